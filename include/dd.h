@@ -1,0 +1,156 @@
+/*
+ * dd.h -- C ABI of libdd, the MI355X (gfx950) library for the cumulative
+ * damage-diffusion distribution of a STEM scan.
+ *
+ * Paper: "Fast Simulation of Damage Diffusion Distribution in Scanning
+ * Transmission Electron Microscopy".  The library evaluates
+ *
+ *   psi(r, t) = sum over visits i with t_i < t of phi_i(r, t)          (Eq. 6)
+ *   phi_i     = Q0/(4 pi D) [E1(a/b1) - E1(a/b0)]                       (Eqs. 1-2)
+ *   phi_i     = Q0/(4 pi D) ln(b1/b0)                  at r = r_i      (Eqs. 3-4)
+ *
+ * with a = |r - r_i|^2, Ds = r_s^2 = sigma^2, b1 = 2 Ds + 4 D (t - t_i),
+ * b0 = 2 Ds while the beam is on (t - t_i <= tau) and 2 Ds + 4 D (t - t_i - tau)
+ * after.  E1 is the exponential integral of order one (Sec. II).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a dd_status; 0 is success, negative is an error.  No
+ *    call throws or aborts.  dd_last_error() returns a thread-local message
+ *    for the last failing call on this thread.
+ *  - A dd_scan handle owns its host and device buffers; it is not thread
+ *    safe (use one handle per thread), distinct handles are independent.
+ *  - Input arrays are read during the call and never retained.
+ *  - Outputs are caller-owned.  With out_on_device = 1, `out` is a device
+ *    pointer and the work is enqueued on `hip_stream` (a hipStream_t, NULL =
+ *    the null stream); the call returns once the work is enqueued.  With
+ *    out_on_device = 0, `out` is host memory and the call synchronizes the
+ *    stream before returning.
+ *  - Results are double precision in u/m^2 (the unit of Q0 per square metre).
+ *  - Precision DD_FP64 evaluates every term in double precision;
+ *    DD_MIXED evaluates the bulk of the E1 differences in single precision
+ *    (with exact lattice distances, exact dwell increments and a split
+ *    exponent) and accumulates in double precision.
+ *  - Lengths are metres, times seconds, D m^2/s, Q0 u/s.
+ */
+#ifndef DD_H
+#define DD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DD_OK = 0,
+  DD_EINVAL = -1,       /* invalid or non-finite argument                       */
+  DD_ENOMEM = -2,       /* host or device allocation failed                     */
+  DD_EDEVICE = -3,      /* HIP runtime error or no usable gfx950 device         */
+  DD_EUNSUPPORTED = -4  /* valid request this build does not handle             */
+} dd_status;
+
+/* Visit orders (Sec. I: raster, interleaved/alternating, random and
+ * multi-frame scans).  Probe id = row * nx + col, probe at (col, row) * pitch. */
+typedef enum {
+  DD_RASTER = 0,       /* row-major, +x fastest                                */
+  DD_INTERLEAVED = 1,  /* stride^2 sub-lattice passes, offsets (oy, ox) row-major,
+                          each pass a raster of its sub-lattice                */
+  DD_RANDOM = 2,       /* seeded permutation: SplitMix64 + Fisher-Yates (from
+                          the last slot) + Lemire's unbiased bounded integers  */
+  DD_MULTIFRAME = 3,   /* `frames` raster frames, per-visit dwell dwell_s/frames */
+  DD_EXPLICIT = 4      /* caller-supplied probe ids, repeats allowed           */
+} dd_order;
+
+typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
+
+/* Scan description (Sec. II assumptions: deposition rate Q0, constant D,
+ * Gaussian probe of per-axis standard deviation sigma = r_s).  Visit v
+ * (0-based) starts at v * tau_v and lasts tau_v, back to back, where
+ * tau_v = dwell_s / frames for DD_MULTIFRAME and dwell_s otherwise.       */
+typedef struct {
+  int32_t nx, ny;          /* probe grid, >= 1 each                            */
+  int32_t order;           /* dd_order                                         */
+  int32_t stride;          /* DD_INTERLEAVED: >= 1                             */
+  int32_t frames;          /* DD_MULTIFRAME: >= 1                              */
+  int32_t reserved;        /* must be 0                                        */
+  uint64_t seed;           /* DD_RANDOM                                        */
+  const int32_t *visits;   /* DD_EXPLICIT: probe ids in [0, nx*ny), copied     */
+  int64_t n_visits;        /* DD_EXPLICIT: >= 1                                */
+  double pitch_m;          /* > 0                                              */
+  double dwell_s;          /* > 0                                              */
+  double sigma_m;          /* > 0 (the log form needs Ds > 0)                  */
+  double D_m2s;            /* > 0                                              */
+  double Q0_us;            /* >= 0                                             */
+} dd_scan_desc;
+
+typedef struct dd_scan dd_scan; /* opaque */
+
+/* Evaluation grid for maps: pixel (u, v) at (x0 + u dx, y0 + v dy), u < w,
+ * v < h; w, h >= 1; spacings may be any finite value.                     */
+typedef struct {
+  double x0_m, y0_m, dx_m, dy_m;
+  int32_t w, h;
+} dd_grid;
+
+/* Builds the visit list and probe table (Sec. I scan strategies, Sec. II
+ * probe placement).  Host only: no device is touched until the first query.
+ * Errors: DD_EINVAL for a bad description, DD_ENOMEM.                      */
+dd_status dd_scan_create(const dd_scan_desc *desc, dd_scan **out);
+/* Frees the handle and its device buffers; NULL is allowed.               */
+void dd_scan_destroy(dd_scan *s);
+/* Number of visits V (nx*ny, frames*nx*ny or n_visits); -1 for NULL.      */
+int64_t dd_scan_num_visits(const dd_scan *s);
+/* Copies the probe id of each visit, in visit order, to out_host[V].      */
+dd_status dd_scan_visits(const dd_scan *s, int32_t *out_host);
+
+/* psi on a pixel grid at n_t times (Eq. 6 at each pixel and time).
+ * t_s: host array of n_t finite times >= 0 (seconds from the start of the
+ * first visit).  out: [n_t][h][w] row-major.  Times before a visit's start
+ * give that visit no contribution; a time within 8 ulp of a dwell boundary
+ * is taken to be on it.                                                   */
+dd_status dd_damage_map(dd_scan *s, const dd_grid *g, const double *t_s, int32_t n_t,
+                        dd_precision p, double *out, int32_t out_on_device, void *hip_stream);
+
+/* psi at every probe visit at the moment that visit starts: out[j] =
+ * psi(r_j, t_j), summed over visits i < j (Eq. 6 with j the visit being
+ * made; the visit itself contributes phi_j(r_j, t_j) = 0).  out: [V].    */
+dd_status dd_damage_at_probe_arrival(dd_scan *s, dd_precision p, double *out,
+                                     int32_t out_on_device, void *hip_stream);
+
+/* Queries for dd_batch_solve (bit mask).                                  */
+typedef enum {
+  DD_Q_ARRIVAL = 1,          /* [V] as dd_damage_at_probe_arrival              */
+  DD_Q_FINAL_AT_PROBES = 2   /* [ny][nx]: psi at each probe position at the end
+                                of the scan, t = V * tau_v                     */
+} dd_query;
+
+/* Many independent scans in one persistent launch (work items of all scans
+ * ordered longest first, taken from a device work counter).  outs[k] holds
+ * scan k's results back to back: [V_k] arrival (if requested) then
+ * [ny_k * nx_k] final map (if requested).  Results equal the per-scan calls.
+ * Errors: DD_EINVAL (n < 1, NULL scans or outs, empty mask).              */
+dd_status dd_batch_solve(dd_scan *const *scans, int32_t n, uint32_t query_mask,
+                         dd_precision p, double *const *outs, int32_t out_on_device,
+                         void *hip_stream);
+
+/* Dimensionless pair term phi_hat = phi * 4 pi D / Q0 (Eqs. 1-4) for n
+ * (a, lag) pairs: a[k] = squared distance / pitch^2 (>= 0), lag[k] = time
+ * since the visit started / tau_v (> 0), with kappa = D tau_v / pitch^2 and
+ * sigma_hat = sigma / pitch.  a, lag, out are device pointers; the work is
+ * enqueued on hip_stream.  Exposes the device E1 difference for testing.  */
+dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double *a,
+                        const double *lag, dd_precision p, double *out, void *hip_stream);
+
+/* Autotuner: times the candidate tile shapes on representative problems
+ * and writes a JSON cache to cache_path (NULL: $DD_TUNE_CACHE or
+ * ./dd_tune.json).  Later queries in this process use the winners.        */
+dd_status dd_autotune(const char *cache_path);
+/* Loads a cache written by dd_autotune; DD_EINVAL if unreadable.          */
+dd_status dd_tune_load(const char *cache_path);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *dd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -35,7 +35,7 @@ def build(force: bool = False) -> str:
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-fPIC", "-shared",
-             "-Wall", "-o", tmp, _SRC, "-lm", "-lpthread"]
+             "-Wall", "-o", tmp, _SRC, "-lquadmath", "-lm", "-lpthread"]
         )
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -66,6 +66,10 @@ def _load():
             lib.ddo_e1.argtypes = [D]
             lib.ddo_phi.restype = D
             lib.ddo_phi.argtypes = [D] * 6
+            lib.ddo_phi_bracket_q.restype = D
+            lib.ddo_phi_bracket_q.argtypes = [D] * 5
+            lib.ddo_e1_q.restype = D
+            lib.ddo_e1_q.argtypes = [D]
             lib.ddo_splitmix64.restype = U64
             lib.ddo_splitmix64.argtypes = [P(U64)]
             lib.ddo_visits.restype = I64
@@ -105,6 +109,16 @@ def e1(x: float) -> float:
 def phi(a, dt, tau, sigma, D, Q0=1.0) -> float:
     """Single-visit field (Eqs. 1-4) at squared distance a and lag dt."""
     return float(_load().ddo_phi(a, dt, tau, sigma, D, Q0))
+
+
+def e1_q(x: float) -> float:
+    """E1 in binary128, rounded to double."""
+    return float(_load().ddo_e1_q(x))
+
+
+def phi_bracket_q(a, dt, tau, sigma, D) -> float:
+    """Dimensionless bracket of Eqs. 1-4 in binary128 (no Q0/(4 pi D))."""
+    return float(_load().ddo_phi_bracket_q(a, dt, tau, sigma, D))
 
 
 def splitmix64_stream(seed: int, n: int):

@@ -22,6 +22,7 @@
 
 #include <math.h>
 #include <pthread.h>
+#include <quadmath.h>
 #include <stdlib.h>
 #include <string.h>
 #include <unistd.h>
@@ -131,6 +132,51 @@ double ddo_phi(double a, double dt, double tau, double sigma, double D, double Q
   long double Ds = (long double)sigma * (long double)sigma;
   long double br = phi_bracket(a, dt, tau, Ds, D);
   return (double)((long double)Q0 / (4.0L * PI_L * (long double)D) * br);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same bracket in IEEE binary128 (libquadmath), for per-pair checks
+ * where E1(a/b1) and E1(a/b0) nearly coincide and the long-double
+ * difference loses up to ~log10(E1/phi) digits.  Same series and continued
+ * fraction as above, carried to 113-bit precision.                         */
+static __float128 e1q(__float128 x) {
+  if (x <= 1.0Q) {
+    __float128 term = 1.0Q, sum = 0.0Q;
+    for (int n = 1; n < 400; ++n) {
+      term *= -x / (__float128)n;
+      __float128 add = term / (__float128)n;
+      sum += add;
+      if (fabsq(add) <= 1e-36Q * fabsq(sum)) break;
+    }
+    return -0.5772156649015328606065120900824024310422Q - logq(x) - sum;
+  }
+  const __float128 tiny = 1e-4900Q;
+  __float128 f = x + 1.0Q, C = f, Dn = 0.0Q;
+  for (int j = 1; j < 1000000; ++j) {
+    __float128 aj = -(__float128)j * (__float128)j;
+    __float128 bj = x + 2.0Q * j + 1.0Q;
+    Dn = bj + aj * Dn;
+    if (Dn == 0.0Q) Dn = tiny;
+    C = bj + aj / C;
+    if (C == 0.0Q) C = tiny;
+    Dn = 1.0Q / Dn;
+    __float128 delta = C * Dn;
+    f *= delta;
+    if (fabsq(delta - 1.0Q) < 1e-34Q) break;
+  }
+  return expq(-x) / f;
+}
+
+double ddo_e1_q(double x) { return (double)e1q((__float128)x); }
+
+double ddo_phi_bracket_q(double a, double dt, double tau, double sigma, double D) {
+  if (dt <= 0.0) return 0.0;
+  __float128 Ds = (__float128)sigma * (__float128)sigma;
+  __float128 b1 = 2.0Q * Ds + 4.0Q * (__float128)D * (__float128)dt;
+  __float128 b0 = (dt <= tau) ? 2.0Q * Ds
+                              : 2.0Q * Ds + 4.0Q * (__float128)D * ((__float128)dt - (__float128)tau);
+  if (a == 0.0) return (double)logq(b1 / b0);
+  return (double)(e1q((__float128)a / b1) - e1q((__float128)a / b0));
 }
 
 /* ------------------------------------------------------------------------ */

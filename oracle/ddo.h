@@ -39,6 +39,12 @@ double ddo_e1(double x);
  * Returns 0 for dt <= 0 (visit not yet started).                          */
 double ddo_phi(double a, double dt, double tau, double sigma, double D, double Q0);
 
+/* Eqs. 1-4 bracket E1(a/b1) - E1(a/b0) (or ln(b1/b0) at a = 0), without
+ * Q0/(4 pi D), evaluated in IEEE binary128 to resolve nearly coincident
+ * arguments; and E1 itself in binary128.                                  */
+double ddo_phi_bracket_q(double a, double dt, double tau, double sigma, double D);
+double ddo_e1_q(double x);
+
 /* ---- scan orders (Sec. I scan strategies) -------------------------------- */
 enum { DDO_RASTER = 0, DDO_INTERLEAVED = 1, DDO_RANDOM = 2, DDO_MULTIFRAME = 3 };
 /* SplitMix64 step (Steele, Lea & Flood 2014); advances *state.            */

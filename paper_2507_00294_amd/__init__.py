@@ -1,0 +1,242 @@
+"""MI355X (gfx950) library for the cumulative damage-diffusion distribution of a
+STEM scan -- thin Python binding over the C ABI of ``include/dd.h``.
+
+Paper: "Fast Simulation of Damage Diffusion Distribution in Scanning
+Transmission Electron Microscopy", Sec. II: psi(r, t) is the sum, over every
+probe visit that started before t, of the closed-form single-visit field
+(Eqs. 1-4); Eq. 6 is that sum.  All arithmetic runs in the HIP kernels of
+``libdd.so``; this module only marshals arguments.  PyTorch supplies device
+memory and the current HIP stream.  There is no CPU fallback: if ``libdd.so``
+is missing or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_EUNSUPPORTED = 0, -1, -2, -3, -4
+ORDERS = {"raster": 0, "interleaved": 1, "random": 2, "multiframe": 3, "explicit": 4}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
+
+# Every symbol the header declares (checked by the tests).
+EXPORTS = (
+    "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
+    "dd_damage_map", "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms",
+    "dd_autotune", "dd_tune_load", "dd_last_error",
+)
+
+
+class DDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libdd status {status}: {msg}")
+        self.status = status
+
+
+class ScanDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("stride", ctypes.c_int32), ("frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("visits", ctypes.POINTER(ctypes.c_int32)),
+        ("n_visits", ctypes.c_int64), ("pitch_m", ctypes.c_double), ("dwell_s", ctypes.c_double),
+        ("sigma_m", ctypes.c_double), ("D_m2s", ctypes.c_double), ("Q0_us", ctypes.c_double),
+    ]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("x0_m", ctypes.c_double), ("y0_m", ctypes.c_double), ("dx_m", ctypes.c_double),
+                ("dy_m", ctypes.c_double), ("w", ctypes.c_int32), ("h", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libdd.so (built by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    lib.dd_scan_create.argtypes = [P(ScanDesc), P(vp)]
+    lib.dd_scan_destroy.argtypes = [vp]
+    lib.dd_scan_destroy.restype = None
+    lib.dd_scan_num_visits.argtypes = [vp]
+    lib.dd_scan_num_visits.restype = i64
+    lib.dd_scan_visits.argtypes = [vp, P(i32)]
+    lib.dd_damage_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
+    lib.dd_damage_at_probe_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
+    lib.dd_batch_solve.argtypes = [P(vp), i32, ctypes.c_uint32, ctypes.c_int, P(vp), i32, vp]
+    lib.dd_pair_terms.argtypes = [dbl, dbl, i64, vp, vp, ctypes.c_int, vp, vp]
+    lib.dd_autotune.argtypes = [ctypes.c_char_p]
+    lib.dd_tune_load.argtypes = [ctypes.c_char_p]
+    lib.dd_last_error.restype = ctypes.c_char_p
+    for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map",
+                 "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
+                 "dd_tune_load"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != DD_OK:
+        raise DDError(status, load_library().dd_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise DDError(DD_EDEVICE, "no GPU visible to torch")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec(p: str) -> int:
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"precision must be one of {list(PRECISIONS)}") from None
+
+
+class Scan:
+    """A scan handle (``dd_scan``): probe grid, visit order and physics.
+
+    Parameters follow ``dd_scan_desc``: SI units (m, s, m^2/s, u/s)."""
+
+    def __init__(self, nx: int, ny: int, order: str = "raster", *, pitch_m: float = 1e-9,
+                 dwell_s: float = 1e-6, sigma_m: float = 0.5e-9, D_m2s: float = 2.5e-13,
+                 Q0_us: float = 1.0, stride: int = 2, frames: int = 1, seed: int = 0,
+                 visits: Sequence[int] | None = None):
+        lib = load_library()
+        self._visits_keep = None
+        d = ScanDesc()
+        d.nx, d.ny, d.order = nx, ny, ORDERS[order]
+        d.stride, d.frames, d.reserved, d.seed = stride, frames, 0, seed
+        if visits is not None:
+            arr = np.ascontiguousarray(visits, dtype=np.int32)
+            self._visits_keep = arr
+            d.visits = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            d.n_visits = arr.size
+        d.pitch_m, d.dwell_s, d.sigma_m, d.D_m2s, d.Q0_us = pitch_m, dwell_s, sigma_m, D_m2s, Q0_us
+        h = ctypes.c_void_p()
+        _check(lib.dd_scan_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.order = nx, ny, order
+        self.pitch_m, self.dwell_s, self.sigma_m, self.D_m2s, self.Q0_us = (
+            pitch_m, dwell_s, sigma_m, D_m2s, Q0_us)
+        self.frames = frames if order == "multiframe" else 1
+        self.tau_v = dwell_s / self.frames
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().dd_scan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_visits(self) -> int:
+        return int(load_library().dd_scan_num_visits(self._h))
+
+    def visits(self) -> np.ndarray:
+        out = np.empty(self.num_visits, dtype=np.int32)
+        _check(load_library().dd_scan_visits(
+            self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def arrival(self, precision: str = "fp64", out=None, stream=None):
+        """psi at each visit at its start (``dd_damage_at_probe_arrival``) as a
+        float64 CUDA tensor [V], enqueued on the current stream."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.num_visits, dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == self.num_visits
+        _check(load_library().dd_damage_at_probe_arrival(
+            self._h, _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+
+    def damage_map(self, x0_m: float, y0_m: float, dx_m: float, dy_m: float, w: int, h: int,
+                   times_s: Iterable[float], precision: str = "fp64", out=None, stream=None):
+        """psi on a w-by-h pixel grid at each time (``dd_damage_map``) as a
+        float64 CUDA tensor [n_t, h, w]."""
+        torch = _torch()
+        t = np.ascontiguousarray(np.atleast_1d(np.asarray(times_s, dtype=np.float64)))
+        if out is None:
+            out = torch.empty((t.size, h, w), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == t.size * w * h
+        g = Grid(x0_m, y0_m, dx_m, dy_m, w, h)
+        _check(load_library().dd_damage_map(
+            self._h, ctypes.byref(g), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
+            _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+
+    def final_at_probes(self, precision: str = "fp64", stream=None):
+        """psi at every probe position at the end of the scan, [ny, nx]."""
+        t_end = self.num_visits * self.tau_v
+        return self.damage_map(0.0, 0.0, self.pitch_m, self.pitch_m, self.nx, self.ny, [t_end],
+                               precision, stream=stream)[0]
+
+
+def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PROBES,
+                precision: str = "mixed", outs=None, stream=None):
+    """Many scans in one call (``dd_batch_solve``); returns one float64 CUDA
+    tensor per scan: [V] arrival (if requested) then [ny*nx] final map."""
+    torch = _torch()
+    n = len(scans)
+    if outs is None:
+        outs = []
+        for s in scans:
+            size = (s.num_visits if queries & Q_ARRIVAL else 0) + (
+                s.nx * s.ny if queries & Q_FINAL_AT_PROBES else 0)
+            outs.append(torch.empty(size, dtype=torch.float64, device="cuda"))
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in scans])
+    os_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(load_library().dd_batch_solve(hs, n, queries, _prec(precision), os_, 1,
+                                         _stream(stream)))
+    return outs
+
+
+def pair_terms(kappa: float, sigma_hat: float, a, lag, precision: str = "fp64", stream=None):
+    """Dimensionless pair terms (``dd_pair_terms``) for CUDA float64 tensors a, lag."""
+    torch = _torch()
+    a = a.contiguous()
+    lag = lag.contiguous()
+    out = torch.empty_like(a)
+    _check(load_library().dd_pair_terms(kappa, sigma_hat, a.numel(), ctypes.c_void_p(a.data_ptr()),
+                                        ctypes.c_void_p(lag.data_ptr()), _prec(precision),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def autotune(cache_path: str | None = None):
+    _check(load_library().dd_autotune(cache_path.encode() if cache_path else None))
+
+
+def tune_load(cache_path: str):
+    _check(load_library().dd_tune_load(cache_path.encode()))

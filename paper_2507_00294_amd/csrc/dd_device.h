@@ -1,0 +1,129 @@
+// dd_device.h -- device math for the damage-diffusion pair term on gfx950.
+//
+// The pair term of Eqs. 1-4 (Sec. II) in pitch units is
+//   phi_hat = E1(x1) - E1(x0),  x1 = a rb1 < x0 = a rb0,  and ln(b1/b0) at a = 0.
+// Three evaluation forms are used, chosen by dx = x0 - x1 = a c:
+//   * series  (dx <= threshold): exp(-x1) * sum_m P_m dx^m with per-lag P_m
+//     (see dd_internal.h); covers a = 0, the small-argument regime and the
+//     near-coincident regime without cancellation;
+//   * direct  (dx above threshold): E1(x1) - E1(x0) with E1 from its power
+//     series (x <= 2.5) or its continued fraction (x > 2.5); the two values
+//     differ by more than a factor e^-dx so the subtraction loses < 2 digits;
+//   * FP32 series with a split exponent for the mixed-precision bulk.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr double kEulerGamma = 0.5772156649015329;
+
+// 2^-y for y >= 0 in double precision, y -> 2^-n 2^-f with n = rint(y),
+// f in [-1/2, 1/2]; 2^-f = e^{-f ln 2} by its Taylor polynomial of degree 13
+// (remainder < 5e-18 on |f ln 2| <= 0.347).  Returns 0 for y > 1100.
+__device__ __forceinline__ double exp2_neg(double y) {
+  y = fmin(y, 1100.0);
+  const double n = __builtin_rint(y);
+  const double g = (n - y) * kLn2;  // e^g with |g| <= 0.3466
+  double p = 1.0 / 6227020800.0;     // 1/13!
+  p = fma(p, g, 1.0 / 479001600.0);
+  p = fma(p, g, 1.0 / 39916800.0);
+  p = fma(p, g, 1.0 / 3628800.0);
+  p = fma(p, g, 1.0 / 362880.0);
+  p = fma(p, g, 1.0 / 40320.0);
+  p = fma(p, g, 1.0 / 5040.0);
+  p = fma(p, g, 1.0 / 720.0);
+  p = fma(p, g, 1.0 / 120.0);
+  p = fma(p, g, 1.0 / 24.0);
+  p = fma(p, g, 1.0 / 6.0);
+  p = fma(p, g, 0.5);
+  p = fma(p, g, 1.0);
+  p = fma(p, g, 1.0);
+  return __builtin_ldexp(p, -(int)n);
+}
+
+// Coefficients (-1)^n / (n n!) of the E1 power series, n = 1..24.
+struct E1SeriesCoef {
+  double c[24];
+  constexpr E1SeriesCoef() : c() {
+    double fact = 1.0;
+    for (int n = 1; n <= 24; ++n) {
+      fact *= n;
+      c[n - 1] = ((n & 1) ? -1.0 : 1.0) / (n * fact);
+    }
+  }
+};
+
+// E1(x) for x > 0 in double precision (relative error < 3e-15 for
+// x <= 2.5, < 1e-14 above).  Power series about 0 (A&S 5.1.11) for
+// x <= 2.5; for x > 2.5 the even continued fraction
+//   E1(x) = e^-x / (x+1 - 1/(x+3 - 4/(x+5 - ...)))   (A&S 5.1.22)
+// truncated after 5 + 90/x levels and evaluated by the forward three-term
+// recurrence of its convergents (no divisions inside the loop).
+__device__ __forceinline__ double e1_f64(double x) {
+  if (x <= 2.5) {
+    constexpr E1SeriesCoef k{};
+    double s = k.c[23];
+#pragma unroll
+    for (int n = 22; n >= 0; --n) s = fma(s, x, k.c[n]);
+    return -kEulerGamma - ::log(x) - x * s;
+  }
+  const int depth = 5 + (int)(90.0 / x);
+  double am1 = 1.0, bm1 = 0.0, a0 = x + 1.0, b0 = 1.0;
+  double bj = x + 1.0;
+  for (int j = 1; j <= depth; ++j) {
+    bj += 2.0;
+    const double aj = -(double)j * (double)j;
+    const double a1 = fma(bj, a0, aj * am1);
+    const double b1 = fma(bj, b0, aj * bm1);
+    am1 = a0; bm1 = b0; a0 = a1; b0 = b1;
+  }
+  return exp2_neg(x * kLog2e) * (b0 / a0);
+}
+
+// Series form in double precision with P_0..P_M read from an FP64 row.
+template <int M>
+__device__ __forceinline__ double series_f64(double a, const double* __restrict__ row) {
+  const double z = a * row[kR64_C];
+  double q = row[kR64_P + M];
+#pragma unroll
+  for (int m = M - 1; m >= 0; --m) q = fma(q, z, row[kR64_P + m]);
+  return exp2_neg(a * row[kR64_RL2]) * q;
+}
+
+// General FP64 pair term: series for dx <= 1, direct difference above.
+__device__ __forceinline__ double phi_general_f64(double a, const double* __restrict__ row) {
+  const double z = a * row[kR64_C];
+  if (z <= kThr64) return series_f64<kM64>(a, row);
+  const double x1 = a * row[kR64_RB1];
+  if (x1 > 745.0) return 0.0;  // both E1 values below the double range
+  const double x0 = a * row[kR64_RB0];
+  const double e0 = x0 > 745.0 ? 0.0 : e1_f64(x0);
+  return e1_f64(x1) - e0;
+}
+
+// Mixed-precision series with P_0..P_M from an FP32 row.  `a` is exact
+// (lattice distances).  x1 log2(e) = a (rhi + rlo) is formed as yh + yl with
+// yh = fl(a rhi) and yl its rounding error plus a rlo, so that
+// exp(-x1) = 2^-yh (1 - ln2 yl) keeps its relative error near 1e-7 even when
+// x1 is large.  dx = a c stays below the series threshold, where the sum is
+// well conditioned.
+template <int M>
+__device__ __forceinline__ float series_f32(float a, const float* __restrict__ row) {
+  const float z = a * row[kR32_C];
+  const float rhi = row[kR32_RHI];
+  const float yh = a * rhi;
+  float yl = __builtin_fmaf(a, rhi, -yh);
+  yl = __builtin_fmaf(a, row[kR32_RLO], yl);
+  const float t = __builtin_amdgcn_exp2f(-yh);
+  float q = row[kR32_P + M];
+#pragma unroll
+  for (int m = M - 1; m >= 0; --m) q = __builtin_fmaf(q, z, row[kR32_P + m]);
+  q = __builtin_fmaf(q, yl * (float)(-kLn2), q);
+  return t * q;
+}
+
+}  // namespace dd

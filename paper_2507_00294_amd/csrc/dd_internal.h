@@ -1,0 +1,79 @@
+// dd_internal.h -- structures shared by the libdd host runtime and its HIP
+// kernels.  Not part of the public ABI (include/dd.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Lag rows.  For one scan (kappa = D tau_v / pitch^2, s2 = 2 sigma_hat^2) and
+// one lag lambda (time since the visit started, in dwells), the pair term of
+// Eqs. 1-4 in pitch units is
+//     phi_hat(a) = E1(a rb1) - E1(a rb0)              (a = |r - r_i|^2 / pitch^2)
+//               = exp(-a rb1) * sum_m P_m (a c)^m      (entire series in a c)
+// with db = 4 kappa min(lambda, 1), b0 = s2 + 4 kappa max(lambda - 1, 0),
+// b1 = b0 + db, w = db / b0, c = w / b1 and
+//     P_m = (-1)^m w J_m(w) / m!,  J_m(w) = int_0^1 u^m / (1 + w u) du.
+// (Substitute u = x1 e^s in the E1 integral: phi_hat = int_0^L exp(-x1 e^s) ds
+// with L = ln(b1/b0); expand exp(-x1 (e^s - 1)) in powers of x1.)  P_0 = L is
+// exactly the log form of Eqs. 3-4, reached at a = 0.
+// Everything lag-dependent is uniform across a wavefront, so it is computed
+// once per lag into a row and read through the scalar cache.
+
+constexpr int kM64 = 17;     // FP64 rows hold P_0..P_17
+constexpr int kM32 = 8;      // FP32 rows hold P_0..P_8
+constexpr int kRow64 = 24;   // doubles per row: rb1 rb0 c rl2 P0..P17 (+2 pad)
+constexpr int kRow32 = 16;   // floats per row:  c rhi rlo P0..P8 (+4 pad)
+constexpr int kR64_RB1 = 0, kR64_RB0 = 1, kR64_C = 2, kR64_RL2 = 3, kR64_P = 4;
+constexpr int kR32_C = 0, kR32_RHI = 1, kR32_RLO = 2, kR32_P = 3;
+
+// Series regime thresholds on dx = a c (= a/b0 - a/b1).  Below them the
+// series above is used; the truncation bound after P_M is
+// e^{2 dx} dx^{M+1} / (M+1)!  relative to the term.
+constexpr double kThr64 = 1.0;    // FP64: M = 17 covers dx <= 1 to 5e-15
+constexpr float kThr32 = 0.25f;   // FP32: M = 6 covers dx <= 0.25 to 2e-8
+constexpr int kMNear32 = 6;
+
+constexpr int kGL = 24;  // Gauss-Legendre nodes on [0, 1] for J_m(w), w <= 1
+struct GLNodes {
+  double x[kGL];
+  double w[kGL];
+};
+
+// Work item of the arrival query: wavefront tile `tile` (T = 64 R consecutive
+// visits), lags [n_lo, n_hi), partial slot `slot`; `flags` bit 0 = edge (some
+// pairs have lag > visit index and are masked), bit 1 = near (per-pair regime).
+struct ArrItem {
+  int32_t tile, n_lo, n_hi, slot_flags;
+};
+constexpr int kItemEdge = 1 << 30;
+constexpr int kItemNear = 1 << 29;
+constexpr int kSlotMask = (1 << 29) - 1;
+
+// Work item of a map query: pixel tile, time index, lag range, slot.
+struct MapItem {
+  int32_t tile, m, n_lo, n_hi;
+  int32_t slot, near, pad0, pad1;
+};
+
+// Degree segments of the far region: for rows n in [bound[M], bound[M-1]) the
+// series needs P_0..P_M.  bound[-1] is +inf; bound[kMaxSeg] ... bound[0].
+constexpr int kMaxSeg = 18;
+struct DegreeBounds {
+  int32_t b[kMaxSeg + 1];  // b[M] for M = 0..kMaxSeg; nondecreasing as M falls
+  int32_t m_max;           // degree used at the start of the far region
+};
+
+struct MapTime {
+  int64_t K;           // floor(t / tau_v): visit v uses lag row K - v
+  int64_t row_base;    // first row of this time's lag table
+  int64_t slot_base;   // first partial slot of this time
+  int32_t n_slots;     // slots of this time
+  int32_t n_min;       // smallest valid row (1 when t is on a dwell boundary)
+  DegreeBounds bounds; // series degree by row for this time's table
+};
+
+
+
+}  // namespace dd

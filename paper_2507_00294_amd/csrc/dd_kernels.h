@@ -1,0 +1,58 @@
+// dd_kernels.h -- host-callable launchers for the libdd HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+// Front/back padding (in visits) of the device position arrays, so that the
+// sliding probe windows of edge tiles stay inside the allocation.
+constexpr int kPosPad = 1024;
+
+// Fills `count` lag rows for lags lambda = f + n, n = n0 .. n0+count-1, into
+// rows64[k * kRow64] and rows32[k * kRow32], k = n - n0 (rows with
+// lambda <= 0 are zero).
+hipError_t launch_lag_rows(int64_t n0, int64_t count, double f, double kappa, double s2,
+                           const GLNodes& gl, double* rows64, float* rows32, hipStream_t st);
+
+struct ArrivalLaunch {
+  const void* pos;          // float2 (mixed) or double2 (FP64), base = visit 0
+  const double* rows64;     // integer-lag rows, row n = lag n
+  const float* rows32;
+  const ArrItem* items;
+  int32_t n_items;
+  int64_t V;
+  DegreeBounds bounds;
+  double* partial;          // [slots][V]
+  int R;                    // eval visits per lane (tile = 64 R)
+  bool mixed;
+  bool near;                // items are near-band items (per-pair regime)
+};
+hipError_t launch_arrival(const ArrivalLaunch& L, hipStream_t st);
+
+struct MapLaunch {
+  const void* pos;          // float2 / double2 probe positions by visit
+  const double* rows64;
+  const float* rows32;
+  const MapItem* items;
+  int32_t n_items;
+  const MapTime* times;
+  double X0, Y0, DX, DY;    // pixel grid in pitch units
+  int32_t W, H;
+  double* partial;          // [slots][W*H]
+  int R;
+  bool mixed;
+};
+hipError_t launch_map(const MapLaunch& L, hipStream_t st);
+
+hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
+                                 int tile, double pref, double* out, hipStream_t st);
+hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
+                             int64_t npix, double pref, double* out, hipStream_t st);
+
+hipError_t launch_pair_terms(double kappa, double s2, int64_t n, const double* a,
+                             const double* lag, bool mixed, const GLNodes& gl, double* out,
+                             hipStream_t st);
+
+}  // namespace dd

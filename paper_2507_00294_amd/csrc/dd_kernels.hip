@@ -1,0 +1,679 @@
+// dd_kernels.hip -- HIP kernels of libdd for gfx950 (CDNA4, wave64).
+//
+// The hot path is the all-pairs sum of Eq. 6 (Sec. II): every evaluation
+// point adds the pair term of Eqs. 1-4 for every visit that started before it.
+// It is a transcendental pair sum, not a contraction, so it runs on the vector
+// ALUs (no MFMA).  The design keeps everything that depends only on the lag
+// (time since a visit started) uniform across a wavefront:
+//
+//  * arrival query (evaluation point = visit j at its start time): a wave owns
+//    64 R consecutive visits (R per lane) and walks the lag n; the probe of
+//    pair (j, n) is visit j - n, so all 64 R pairs of one step share one lag
+//    row (read into SGPRs) and each lane slides a window of 2R - 1 probe
+//    positions (R loads per R^2 pairs);
+//  * map query (evaluation points = pixels at one time): a wave owns 64 R
+//    pixels and walks the visits; probe position and lag row are both
+//    uniform (SGPR operands), only the pixel coordinates live in VGPRs.
+//
+// Lags split into a near band (per-pair choice between the series and the
+// direct E1 difference) and a far region where every pair of the tile is in
+// the series regime; there the series degree M is a template parameter chosen
+// per lag segment, so the inner loop has no branches.  Partial sums of work
+// items go to fixed slots and are added in a fixed order (bitwise
+// reproducible, no floating-point atomics).
+#include "dd_device.h"
+#include "dd_kernels.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Lag rows (see dd_internal.h for the series).  J_m(w) by 24-node
+// Gauss-Legendre on [0, 1] when w <= 1 (the integrand's pole at u = -1/w is at
+// least 1 away), by the forward recurrence J_{m+1} = (1/(m+1) - J_m) / w when
+// w > 1 (errors shrink by 1/w per step).
+__device__ void make_row(double lam, double kappa, double s2, const GLNodes& gl, double* r64,
+                         float* r32) {
+  if (!(lam > 0.0)) {
+    for (int k = 0; k < kRow64; ++k) r64[k] = 0.0;
+    for (int k = 0; k < kRow32; ++k) r32[k] = 0.0f;
+    return;
+  }
+  const double db = 4.0 * kappa * fmin(lam, 1.0);
+  const double b0 = s2 + 4.0 * kappa * fmax(lam - 1.0, 0.0);
+  const double b1 = b0 + db;
+  const double w = db / b0;
+  const double rb1 = 1.0 / b1, rb0 = 1.0 / b0;
+  const double c = db / (b0 * b1);
+  double J[kM64 + 1];
+  if (w <= 1.0) {
+    for (int m = 0; m <= kM64; ++m) J[m] = 0.0;
+    for (int k = 0; k < kGL; ++k) {
+      const double u = gl.x[k];
+      double f = gl.w[k] / (1.0 + w * u);
+      for (int m = 0; m <= kM64; ++m) {
+        J[m] += f;
+        f *= u;
+      }
+    }
+  } else {
+    J[0] = log1p(w) / w;
+    for (int m = 0; m < kM64; ++m) J[m + 1] = (1.0 / (m + 1) - J[m]) / w;
+  }
+  double P[kM64 + 1];
+  P[0] = log1p(w);
+  double inv_fact = 1.0;
+  for (int m = 1; m <= kM64; ++m) {
+    inv_fact /= m;
+    P[m] = ((m & 1) ? -1.0 : 1.0) * w * J[m] * inv_fact;
+  }
+  const double rl2 = rb1 * kLog2e;
+  r64[kR64_RB1] = rb1;
+  r64[kR64_RB0] = rb0;
+  r64[kR64_C] = c;
+  r64[kR64_RL2] = rl2;
+  for (int m = 0; m <= kM64; ++m) r64[kR64_P + m] = P[m];
+  for (int k = kR64_P + kM64 + 1; k < kRow64; ++k) r64[k] = 0.0;
+  const float rhi = (float)rl2;
+  r32[kR32_C] = (float)c;
+  r32[kR32_RHI] = rhi;
+  r32[kR32_RLO] = (float)(rl2 - (double)rhi);
+  for (int m = 0; m <= kM32; ++m) r32[kR32_P + m] = (float)P[m];
+  for (int k = kR32_P + kM32 + 1; k < kRow32; ++k) r32[k] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, double f, double kappa,
+                                                  double s2, GLNodes gl, double* __restrict__ rows64,
+                                                  float* __restrict__ rows32) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    make_row(f + (double)(n0 + k), kappa, s2, gl, rows64 + k * kRow64, rows32 + k * kRow32);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+template <int R>
+__device__ __forceinline__ float pairwise_sum(const float (&t)[R]) {
+  if constexpr (R == 1) {
+    return t[0];
+  } else if constexpr (R == 2) {
+    return t[0] + t[1];
+  } else if constexpr (R == 4) {
+    return (t[0] + t[1]) + (t[2] + t[3]);
+  } else {
+    static_assert(R == 8, "R must be 1, 2, 4 or 8");
+    return ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+  }
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// ---------------------------------------------------------------------------
+// Arrival query, far region, mixed precision.  Lags [lo, hi) with
+// (hi - lo) % R == 0; window W[q] holds the probe of visit jl - n0 - (R-1) + q.
+template <int M, int R, bool EDGE>
+__device__ __forceinline__ void arr_far32(int lo, int hi, const float2* __restrict__ pos, int64_t jl,
+                                          const float (&ex)[R], const float (&ey)[R],
+                                          const float* __restrict__ rows, double (&acc)[R]) {
+  float2 W[2 * R - 1];
+#pragma unroll
+  for (int q = 0; q < 2 * R - 1; ++q) W[q] = pos[jl - lo - (R - 1) + q];
+  for (int n0 = lo; n0 < hi; n0 += R) {
+    float t[R][R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const float* row = rows + (int64_t)(n0 + s) * kRow32;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float2 p = W[r - s + R - 1];
+        const float dx = ex[r] - p.x, dy = ey[r] - p.y;
+        const float a = __builtin_fmaf(dy, dy, dx * dx);
+        float v = series_f32<M>(a, row);
+        if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0f;
+        t[r][s] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<R>(t[r]);
+#pragma unroll
+    for (int q = 2 * R - 2; q >= R; --q) W[q] = W[q - R];
+    const int64_t base = jl - (n0 + R) - (R - 1);
+#pragma unroll
+    for (int q = 0; q < R; ++q) W[q] = pos[base + q];
+  }
+}
+
+template <int M, int R, bool EDGE>
+__device__ __forceinline__ void arr_far64(int lo, int hi, const double2* __restrict__ pos, int64_t jl,
+                                          const double (&ex)[R], const double (&ey)[R],
+                                          const double* __restrict__ rows, double (&acc)[R]) {
+  double2 W[2 * R - 1];
+#pragma unroll
+  for (int q = 0; q < 2 * R - 1; ++q) W[q] = pos[jl - lo - (R - 1) + q];
+  for (int n0 = lo; n0 < hi; n0 += R) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const double* row = rows + (int64_t)(n0 + s) * kRow64;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double2 p = W[r - s + R - 1];
+        const double dx = ex[r] - p.x, dy = ey[r] - p.y;
+        const double a = fma(dy, dy, dx * dx);
+        double v = series_f64<M>(a, row);
+        if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0;
+        acc[r] += v;
+      }
+    }
+#pragma unroll
+    for (int q = 2 * R - 2; q >= R; --q) W[q] = W[q - R];
+    const int64_t base = jl - (n0 + R) - (R - 1);
+#pragma unroll
+    for (int q = 0; q < R; ++q) W[q] = pos[base + q];
+  }
+}
+
+// Degree dispatch for one segment (uniform branch).
+template <int R, bool EDGE>
+__device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float2* __restrict__ pos,
+                                              int64_t jl, const float (&ex)[R], const float (&ey)[R],
+                                              const float* __restrict__ rows, double (&acc)[R]) {
+  switch (M) {
+    case 0: arr_far32<0, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 1: arr_far32<1, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 2: arr_far32<2, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 3: arr_far32<3, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 4: arr_far32<4, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 5: arr_far32<5, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 6: arr_far32<6, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 7: arr_far32<7, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    default: arr_far32<8, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+  }
+}
+
+template <int R, bool EDGE>
+__device__ __forceinline__ void arr_far64_seg(int M, int lo, int hi, const double2* __restrict__ pos,
+                                              int64_t jl, const double (&ex)[R], const double (&ey)[R],
+                                              const double* __restrict__ rows, double (&acc)[R]) {
+#define DD_CASE(k) \
+  case k: arr_far64<k, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+  switch (M) {
+    DD_CASE(0) DD_CASE(1) DD_CASE(2) DD_CASE(3) DD_CASE(4) DD_CASE(5) DD_CASE(6) DD_CASE(7)
+    DD_CASE(8) DD_CASE(9) DD_CASE(10) DD_CASE(11) DD_CASE(12) DD_CASE(13) DD_CASE(14)
+    DD_CASE(15) DD_CASE(16)
+    default: arr_far64<17, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+  }
+#undef DD_CASE
+}
+
+// Segment [lo, hi) of degree M within [n_lo, n_hi): M runs from m_max down.
+__device__ __forceinline__ void seg_range(const DegreeBounds& b, int M, int n_lo, int n_hi, int& lo,
+                                          int& hi) {
+  lo = max(n_lo, b.b[M]);
+  hi = (M == 0) ? n_hi : min(n_hi, b.b[M - 1]);
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_arrival_far32(const float2* __restrict__ pos,
+                                                       const float* __restrict__ rows,
+                                                       const ArrItem* __restrict__ items, int n_items,
+                                                       int64_t V, DegreeBounds bnd,
+                                                       double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const ArrItem item = items[it];
+  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
+  float ex[R], ey[R];
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float2 e = pos[jl + r];
+    ex[r] = e.x;
+    ey[r] = e.y;
+    acc[r] = 0.0;
+  }
+  const bool edge = (item.slot_flags & kItemEdge) != 0;
+  for (int M = bnd.m_max; M >= 0; --M) {
+    int lo, hi;
+    seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
+    if (lo >= hi) continue;
+    if (edge)
+      arr_far32_seg<R, true>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+    else
+      arr_far32_seg<R, false>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+  }
+  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (jl + r < V) out[jl + r] = acc[r];
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict__ pos,
+                                                       const double* __restrict__ rows,
+                                                       const ArrItem* __restrict__ items, int n_items,
+                                                       int64_t V, DegreeBounds bnd,
+                                                       double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const ArrItem item = items[it];
+  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
+  double ex[R], ey[R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double2 e = pos[jl + r];
+    ex[r] = e.x;
+    ey[r] = e.y;
+    acc[r] = 0.0;
+  }
+  const bool edge = (item.slot_flags & kItemEdge) != 0;
+  for (int M = bnd.m_max; M >= 0; --M) {
+    int lo, hi;
+    seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
+    if (lo >= hi) continue;
+    if (edge)
+      arr_far64_seg<R, true>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+    else
+      arr_far64_seg<R, false>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+  }
+  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (jl + r < V) out[jl + r] = acc[r];
+}
+
+// Near band: per-pair regime choice, every pair masked by causality.
+template <int R, bool MIXED>
+__global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ pos_v,
+                                                      const double* __restrict__ rows64,
+                                                      const float* __restrict__ rows32,
+                                                      const ArrItem* __restrict__ items, int n_items,
+                                                      int64_t V, double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const ArrItem item = items[it];
+  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+  if (MIXED) {
+    const float2* pos = (const float2*)pos_v;
+    float ex[R], ey[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float2 e = pos[jl + r];
+      ex[r] = e.x;
+      ey[r] = e.y;
+    }
+    for (int n = item.n_lo; n < item.n_hi; ++n) {
+      const float* r32 = rows32 + (int64_t)n * kRow32;
+      const double* r64 = rows64 + (int64_t)n * kRow64;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = jl + r - n;
+        if (i >= 0 && jl + r < V) {
+          const float2 p = pos[i];
+          const float dx = ex[r] - p.x, dy = ey[r] - p.y;
+          const float a = __builtin_fmaf(dy, dy, dx * dx);
+          if (a * r32[kR32_C] <= kThr32)
+            acc[r] += (double)series_f32<kMNear32>(a, r32);
+          else
+            acc[r] += phi_general_f64((double)a, r64);
+        }
+      }
+    }
+  } else {
+    const double2* pos = (const double2*)pos_v;
+    double ex[R], ey[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double2 e = pos[jl + r];
+      ex[r] = e.x;
+      ey[r] = e.y;
+    }
+    for (int n = item.n_lo; n < item.n_hi; ++n) {
+      const double* r64 = rows64 + (int64_t)n * kRow64;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t i = jl + r - n;
+        if (i >= 0 && jl + r < V) {
+          const double2 p = pos[i];
+          const double dx = ex[r] - p.x, dy = ey[r] - p.y;
+          acc[r] += phi_general_f64(fma(dy, dy, dx * dx), r64);
+        }
+      }
+    }
+  }
+  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (jl + r < V) out[jl + r] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Map query.  Pixel pix = tile * 64 R + R lane + r at (X0 + u DX, Y0 + v DY),
+// u = pix % W, v = pix / W, all at the item's time; visit v = K - n.
+template <int M, int R, int U>
+__device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float2* __restrict__ pos,
+                                          const float* __restrict__ rows, const float (&ex)[R],
+                                          const float (&ey)[R], double (&acc)[R]) {
+  int n = lo;
+  for (; n + U <= hi; n += U) {
+    float t[R][U];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+      const float2 p = pos[K - (n + s)];
+      const float* row = rows + (int64_t)(n + s) * kRow32;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float dx = ex[r] - p.x, dy = ey[r] - p.y;
+        t[r][s] = series_f32<M>(__builtin_fmaf(dy, dy, dx * dx), row);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<U>(t[r]);
+  }
+  for (; n < hi; ++n) {
+    const float2 p = pos[K - n];
+    const float* row = rows + (int64_t)n * kRow32;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float dx = ex[r] - p.x, dy = ey[r] - p.y;
+      acc[r] += (double)series_f32<M>(__builtin_fmaf(dy, dy, dx * dx), row);
+    }
+  }
+}
+
+template <int M, int R>
+__device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const double2* __restrict__ pos,
+                                          const double* __restrict__ rows, const double (&ex)[R],
+                                          const double (&ey)[R], double (&acc)[R]) {
+  for (int n = lo; n < hi; ++n) {
+    const double2 p = pos[K - n];
+    const double* row = rows + (int64_t)n * kRow64;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dx = ex[r] - p.x, dy = ey[r] - p.y;
+      acc[r] += series_f64<M>(fma(dy, dy, dx * dx), row);
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void map_far32_seg(int M, int lo, int hi, int64_t K,
+                                              const float2* __restrict__ pos,
+                                              const float* __restrict__ rows, const float (&ex)[R],
+                                              const float (&ey)[R], double (&acc)[R]) {
+  switch (M) {
+    case 0: map_far32<0, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 1: map_far32<1, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 2: map_far32<2, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 3: map_far32<3, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 4: map_far32<4, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 5: map_far32<5, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 6: map_far32<6, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 7: map_far32<7, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    default: map_far32<8, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void map_far64_seg(int M, int lo, int hi, int64_t K,
+                                              const double2* __restrict__ pos,
+                                              const double* __restrict__ rows, const double (&ex)[R],
+                                              const double (&ey)[R], double (&acc)[R]) {
+#define DD_CASE(k) \
+  case k: map_far64<k, R>(lo, hi, K, pos, rows, ex, ey, acc); break;
+  switch (M) {
+    DD_CASE(0) DD_CASE(1) DD_CASE(2) DD_CASE(3) DD_CASE(4) DD_CASE(5) DD_CASE(6) DD_CASE(7)
+    DD_CASE(8) DD_CASE(9) DD_CASE(10) DD_CASE(11) DD_CASE(12) DD_CASE(13) DD_CASE(14)
+    DD_CASE(15) DD_CASE(16)
+    default: map_far64<17, R>(lo, hi, K, pos, rows, ex, ey, acc); break;
+  }
+#undef DD_CASE
+}
+
+template <int R, bool MIXED>
+__global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
+                                             const double* __restrict__ rows64,
+                                             const float* __restrict__ rows32,
+                                             const MapItem* __restrict__ items, int n_items,
+                                             const MapTime* __restrict__ times, double X0, double Y0,
+                                             double DX, double DY, int W, int H,
+                                             double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const MapItem item = items[it];
+  const MapTime tm = times[item.m];
+  const int64_t npix = (int64_t)W * H;
+  const int64_t p0 = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
+  double pxd[R], pyd[R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t pix = min(p0 + r, npix - 1);
+    pxd[r] = X0 + (double)(pix % W) * DX;
+    pyd[r] = Y0 + (double)(pix / W) * DY;
+    acc[r] = 0.0;
+  }
+  const double* r64b = rows64 + tm.row_base * kRow64;
+  const float* r32b = rows32 + tm.row_base * kRow32;
+  if (MIXED) {
+    const float2* pos = (const float2*)pos_v;
+    float ex[R], ey[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ex[r] = (float)pxd[r];
+      ey[r] = (float)pyd[r];
+    }
+    if (item.near) {
+      for (int n = item.n_lo; n < item.n_hi; ++n) {
+        const float2 p = pos[tm.K - n];
+        const float* r32 = r32b + (int64_t)n * kRow32;
+        const double* r64 = r64b + (int64_t)n * kRow64;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float dx = ex[r] - p.x, dy = ey[r] - p.y;
+          const float a = __builtin_fmaf(dy, dy, dx * dx);
+          if (a * r32[kR32_C] <= kThr32)
+            acc[r] += (double)series_f32<kMNear32>(a, r32);
+          else
+            acc[r] += phi_general_f64((double)a, r64);
+        }
+      }
+    } else {
+      for (int M = tm.bounds.m_max; M >= 0; --M) {
+        int lo, hi;
+        seg_range(tm.bounds, M, item.n_lo, item.n_hi, lo, hi);
+        if (lo < hi) map_far32_seg<R>(M, lo, hi, tm.K, pos, r32b, ex, ey, acc);
+      }
+    }
+  } else {
+    const double2* pos = (const double2*)pos_v;
+    if (item.near) {
+      for (int n = item.n_lo; n < item.n_hi; ++n) {
+        const double2 p = pos[tm.K - n];
+        const double* r64 = r64b + (int64_t)n * kRow64;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double dx = pxd[r] - p.x, dy = pyd[r] - p.y;
+          acc[r] += phi_general_f64(fma(dy, dy, dx * dx), r64);
+        }
+      }
+    } else {
+      for (int M = tm.bounds.m_max; M >= 0; --M) {
+        int lo, hi;
+        seg_range(tm.bounds, M, item.n_lo, item.n_hi, lo, hi);
+        if (lo < hi) map_far64_seg<R>(M, lo, hi, tm.K, pos, r64b, pxd, pyd, acc);
+      }
+    }
+  }
+  double* out = partial + (tm.slot_base + item.slot) * npix;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (p0 + r < npix) out[p0 + r] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reductions of the partial slots.
+__global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict__ partial,
+                                                        const int32_t* __restrict__ tile_slots,
+                                                        int64_t V, int tile, double pref,
+                                                        double* __restrict__ out) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < V;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int ns = tile_slots[j / tile];
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += partial[(int64_t)k * V + j];
+    out[j] = pref * s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_map(const double* __restrict__ partial,
+                                                    const MapTime* __restrict__ times, int n_t,
+                                                    int64_t npix, double pref,
+                                                    double* __restrict__ out) {
+  const int64_t total = npix * n_t;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / npix, pix = e % npix;
+    const MapTime tm = times[m];
+    double s = 0.0;
+    for (int k = 0; k < tm.n_slots; ++k) s += partial[(tm.slot_base + k) * npix + pix];
+    out[e] = pref * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair terms for testing the device math: one thread per (a, lag).
+__global__ void __launch_bounds__(256) k_pair_terms(double kappa, double s2, int64_t n,
+                                                    const double* __restrict__ a,
+                                                    const double* __restrict__ lag, int mixed,
+                                                    GLNodes gl, double* __restrict__ out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double r64[kRow64];
+    float r32[kRow32];
+    make_row(lag[k], kappa, s2, gl, r64, r32);
+    const double ak = a[k];
+    double v;
+    if (!(lag[k] > 0.0)) {
+      v = 0.0;
+    } else if (mixed) {
+      const float af = (float)ak;
+      if (af * r32[kR32_C] <= kThr32)
+        v = (double)series_f32<kMNear32>(af, r32);
+      else
+        v = phi_general_f64(ak, r64);
+    } else {
+      v = phi_general_f64(ak, r64);
+    }
+    out[k] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+static inline unsigned grid_for(int64_t n, int64_t cap = 65536) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_lag_rows(int64_t n0, int64_t count, double f, double kappa, double s2,
+                           const GLNodes& gl, double* rows64, float* rows32, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lag_rows, dim3(grid_for(count, 4096)), dim3(256), 0, st, n0, count, f,
+                     kappa, s2, gl, rows64, rows32);
+  return hipGetLastError();
+}
+
+template <int R>
+static void launch_arrival_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
+  if (L.mixed) {
+    hipLaunchKernelGGL((k_arrival_far32<R>), dim3(blocks), dim3(256), 0, st, (const float2*)L.pos,
+                       L.rows32, L.items, L.n_items, L.V, L.bounds, L.partial);
+  } else {
+    hipLaunchKernelGGL((k_arrival_far64<R>), dim3(blocks), dim3(256), 0, st,
+                       (const double2*)L.pos, L.rows64, L.items, L.n_items, L.V, L.bounds,
+                       L.partial);
+  }
+}
+
+template <int R>
+static void launch_arrival_near_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
+  if (L.mixed)
+    hipLaunchKernelGGL((k_arrival_near<R, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,
+                       L.rows32, L.items, L.n_items, L.V, L.partial);
+  else
+    hipLaunchKernelGGL((k_arrival_near<R, false>), dim3(blocks), dim3(256), 0, st, L.pos,
+                       L.rows64, L.rows32, L.items, L.n_items, L.V, L.partial);
+}
+
+// Near-band and far-region items are launched separately (L.near).
+hipError_t launch_arrival(const ArrivalLaunch& L, hipStream_t st) {
+  if (L.n_items <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((L.n_items + 3) / 4);
+  const bool near = L.near;
+  switch (L.R) {
+    case 2:
+      near ? launch_arrival_near_r<2>(L, st, blocks) : launch_arrival_r<2>(L, st, blocks);
+      break;
+    case 4:
+      near ? launch_arrival_near_r<4>(L, st, blocks) : launch_arrival_r<4>(L, st, blocks);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_map(const MapLaunch& L, hipStream_t st) {
+  if (L.n_items <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((L.n_items + 3) / 4);
+#define DD_LAUNCH_MAP(RR)                                                                       \
+  if (L.mixed)                                                                                  \
+    hipLaunchKernelGGL((k_map<RR, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,     \
+                       L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, L.W, L.H, \
+                       L.partial);                                                              \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_map<RR, false>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,    \
+                       L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, L.W, L.H, \
+                       L.partial);
+  switch (L.R) {
+    case 1: DD_LAUNCH_MAP(1) break;
+    case 2: DD_LAUNCH_MAP(2) break;
+    case 4: DD_LAUNCH_MAP(4) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DD_LAUNCH_MAP
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
+                                 int tile, double pref, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_arrival, dim3(grid_for(V)), dim3(256), 0, st, partial, tile_slots,
+                     V, tile, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
+                             int64_t npix, double pref, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_map, dim3(grid_for(npix * n_t)), dim3(256), 0, st, partial, times,
+                     n_t, npix, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_terms(double kappa, double s2, int64_t n, const double* a,
+                             const double* lag, bool mixed, const GLNodes& gl, double* out,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_terms, dim3(grid_for(n, 4096)), dim3(256), 0, st, kappa, s2, n, a, lag,
+                     mixed ? 1 : 0, gl, out);
+  return hipGetLastError();
+}
+
+}  // namespace dd

@@ -1,0 +1,444 @@
+// dd_queries.cpp -- query entry points of libdd (arrival, map, batch, pair
+// terms) and their work planning.  Eq. 6 of the paper is evaluated as a sum
+// over (evaluation point, lag) pairs; see dd_kernels.hip for the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/dd.h"
+#include "dd_internal.h"
+#include "dd_kernels.h"
+#include "dd_runtime.h"
+
+namespace dd {
+
+TuneParams& tune() {
+  static TuneParams t;
+  return t;
+}
+
+#define DD_HIP(call, what)                  \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename T>
+static dd_status upload(DevBuf& b, const std::vector<T>& h, hipStream_t st) {
+  DD_HIP(b.ensure(sizeof(T) * std::max<size_t>(h.size(), 1)), "device allocation");
+  if (!h.empty()) {
+    DD_HIP(hipMemcpyAsync(b.p, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, st),
+           "host-to-device copy");
+    // the host vector is reused by the next call: wait for the copy
+    DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  }
+  return DD_OK;
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+// Positions of every visit in pitch units, padded by kPosPad zeros on both
+// sides; integer rows 0 .. V + margin for the current scan parameters.
+dd_status dd_scan::prepare(hipStream_t st) {
+  dd_status rc = ensure_device();
+  if (rc != DD_OK) return rc;
+  int cur = 0;
+  DD_HIP(hipGetDevice(&cur), "hipGetDevice");
+  if (dev >= 0 && dev != cur) release_device();
+  if (dev == cur) return DD_OK;
+  const int64_t n = V + 2 * (int64_t)kPosPad;
+  std::vector<float2> p32(n, make_float2(0.f, 0.f));
+  std::vector<double2> p64(n, make_double2(0.0, 0.0));
+  for (int64_t v = 0; v < V; ++v) {
+    const int32_t id = ids[v];
+    const double x = id % desc.nx, y = id / desc.nx;
+    p32[kPosPad + v] = make_float2((float)x, (float)y);
+    p64[kPosPad + v] = make_double2(x, y);
+  }
+  rc = upload(pos32, p32, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(pos64, p64, st);
+  if (rc != DD_OK) return rc;
+  dev = cur;
+  return DD_OK;
+}
+
+namespace {
+
+// Integer-lag rows 0 .. V + 1024 (rows past V serve the aligned ends of the
+// last lag chunks, whose pairs are masked).
+dd_status build_int_rows(dd_scan* s, hipStream_t st) {
+  const int64_t n_rows = s->V + 1024;
+  DD_HIP(s->rows64.ensure(sizeof(double) * kRow64 * n_rows), "device allocation");
+  DD_HIP(s->rows32.ensure(sizeof(float) * kRow32 * n_rows), "device allocation");
+  DD_HIP(launch_lag_rows(0, n_rows, 0.0, s->kappa, s->s2, gl_nodes(), s->rows64.as<double>(),
+                         s->rows32.as<float>(), st),
+         "lag-row kernel launch");
+  s->n_rows = n_rows;
+  return DD_OK;
+}
+
+struct ArrivalPlan {
+  int R = 0, K = 0;
+  bool mixed = false;
+  int64_t V = -1;
+  int n_near = 0, n_far = 0, S = 0;
+  DegreeBounds bounds{};
+};
+
+// Plan of the arrival query: tiles of 64R visits; near band lags [1, kf);
+// far chunks of K lags from kf, aligned to R.
+void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
+                  std::vector<ArrItem>& items, std::vector<int32_t>& tile_slots) {
+  const int T = 64 * R;
+  const int64_t V = s->V;
+  const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
+                       (double)(s->desc.ny - 1) * (s->desc.ny - 1);
+  const double thr = mixed ? (double)kThr32 : kThr64;
+  int64_t kf = first_row_below(thr, a_max, 0.0, s->kappa, s->s2, 1, V);
+  kf = 1 + (kf - 1 + R - 1) / R * R;
+  if (kf > V) kf = V + 1;  // every lag is in the near band
+  P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
+  const int64_t n_tiles = (V + T - 1) / T;
+  std::vector<ArrItem> near, far;
+  tile_slots.assign(n_tiles, 1);
+  int S = 1;
+  for (int64_t t = 0; t < n_tiles; ++t) {
+    const int64_t J0 = t * T;
+    const int64_t maxlag = std::min<int64_t>(J0 + T - 1, V - 1);
+    const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
+    near.push_back(ArrItem{(int32_t)t, 1, (int32_t)nhi, 0 | kItemNear});
+    int c = 0;
+    if (maxlag >= kf) {
+      const int64_t span_end = kf + (maxlag + 1 - kf + R - 1) / R * R;
+      for (int64_t lo = kf; lo < span_end; lo += K, ++c) {
+        const int64_t hi = std::min<int64_t>(lo + K, span_end);
+        const int edge = (hi - 1 > J0) ? kItemEdge : 0;
+        far.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)hi, (1 + c) | edge});
+      }
+    }
+    tile_slots[t] = 1 + c;
+    S = std::max(S, 1 + c);
+  }
+  auto longer = [](const ArrItem& a, const ArrItem& b) {
+    return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
+  };
+  std::stable_sort(near.begin(), near.end(), longer);
+  std::stable_sort(far.begin(), far.end(), longer);
+  items = near;
+  items.insert(items.end(), far.begin(), far.end());
+  P.R = R;
+  P.K = K;
+  P.mixed = mixed;
+  P.V = V;
+  P.n_near = (int)near.size();
+  P.n_far = (int)far.size();
+  P.S = S;
+}
+
+struct PlanCache {
+  ArrivalPlan arr;
+};
+std::map<const dd_scan*, PlanCache> g_plans;  // per handle (handles are not thread safe)
+
+dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
+  dd_status rc = s->prepare(st);
+  if (rc != DD_OK) return rc;
+  rc = build_int_rows(s, st);
+  if (rc != DD_OK) return rc;
+  const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
+  int K = mixed ? tune().arr_K_mixed : tune().arr_K_f64;
+  K = std::max(R, K / R * R);
+  ArrivalPlan& P = g_plans[s].arr;
+  if (P.V != s->V || P.R != R || P.K != K || P.mixed != mixed) {
+    std::vector<ArrItem> items;
+    std::vector<int32_t> tile_slots;
+    plan_arrival(s, mixed, R, K, P, items, tile_slots);
+    rc = upload(s->items, items, st);
+    if (rc != DD_OK) return rc;
+    rc = upload(s->aux, tile_slots, st);
+    if (rc != DD_OK) return rc;
+  }
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)s->V), "device allocation");
+  ArrivalLaunch L{};
+  L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
+                : (const void*)(s->pos64.as<double2>() + kPosPad);
+  L.rows64 = s->rows64.as<double>();
+  L.rows32 = s->rows32.as<float>();
+  L.V = s->V;
+  L.bounds = P.bounds;
+  L.partial = s->partial.as<double>();
+  L.R = R;
+  L.mixed = mixed;
+  L.items = s->items.as<ArrItem>();
+  L.n_items = P.n_near;
+  L.near = true;
+  DD_HIP(launch_arrival(L, st), "arrival near-band launch");
+  L.items = s->items.as<ArrItem>() + P.n_near;
+  L.n_items = P.n_far;
+  L.near = false;
+  DD_HIP(launch_arrival(L, st), "arrival far-region launch");
+  DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 64 * R,
+                               s->pref, out_dev, st),
+         "arrival reduce launch");
+  return DD_OK;
+}
+
+// Map query.  Times are snapped to a dwell boundary when within 8 ulp.
+struct MapGroup {
+  double f;
+  int64_t n_first, n_last;  // rows needed
+  int64_t alloc_off;        // first row in the call's row buffer
+  int64_t kf;
+  DegreeBounds bounds;
+};
+
+dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
+                  double* out_dev, hipStream_t st) {
+  dd_status rc = s->prepare(st);
+  if (rc != DD_OK) return rc;
+  const int64_t npix = (int64_t)g->w * g->h;
+  const double p = s->desc.pitch_m;
+  const double X0 = g->x0_m / p, Y0 = g->y0_m / p, DX = g->dx_m / p, DY = g->dy_m / p;
+  const int R = mixed ? tune().map_R_mixed : tune().map_R_f64;
+  const int T = 64 * R;
+  const int64_t n_tiles = (npix + T - 1) / T;
+  // largest squared distance between any pixel and any probe (bounding boxes)
+  const double xa = X0, xb = X0 + (g->w - 1) * DX, ya = Y0, yb = Y0 + (g->h - 1) * DY;
+  const double mx = std::max({std::fabs(xa), std::fabs(xb), std::fabs(xa - (s->desc.nx - 1)),
+                              std::fabs(xb - (s->desc.nx - 1))});
+  const double my = std::max({std::fabs(ya), std::fabs(yb), std::fabs(ya - (s->desc.ny - 1)),
+                              std::fabs(yb - (s->desc.ny - 1))});
+  const double a_max = mx * mx + my * my;
+  const double thr = mixed ? (double)kThr32 : kThr64;
+
+  std::vector<MapTime> times(n_t);
+  std::vector<int> tgroup(n_t);
+  std::vector<MapGroup> groups;
+  std::map<double, int> gid;
+  std::vector<int64_t> nlo(n_t);
+  for (int m = 0; m < n_t; ++m) {
+    double th = t_s[m] / s->tau_v;
+    const double r = std::rint(th);
+    if (std::fabs(th - r) <= 8.0 * 2.220446049250313e-16 * std::max(1.0, std::fabs(th))) th = r;
+    const double K = std::floor(th);
+    const double f = th - K;
+    times[m].K = (int64_t)K;
+    times[m].n_min = (f == 0.0) ? 1 : 0;
+    nlo[m] = std::max<int64_t>(times[m].n_min, times[m].K - s->V + 1);
+    auto it = gid.find(f);
+    int gi;
+    if (it == gid.end()) {
+      gi = (int)groups.size();
+      gid[f] = gi;
+      groups.push_back(MapGroup{f, nlo[m], times[m].K, 0, 0, {}});
+    } else {
+      gi = it->second;
+      groups[gi].n_first = std::min(groups[gi].n_first, nlo[m]);
+      groups[gi].n_last = std::max(groups[gi].n_last, times[m].K);
+    }
+    tgroup[m] = gi;
+  }
+  // Row storage per group; groups whose span is very wide get per-time rows.
+  int64_t total_rows = 0;
+  struct RowJob {
+    int64_t n_first, count, off;
+    double f;
+  };
+  std::vector<RowJob> jobs;
+  std::vector<int64_t> time_off(n_t, -1);
+  for (auto& G : groups) {
+    G.kf = first_row_below(thr, a_max, G.f, s->kappa, s->s2, 1, std::max<int64_t>(G.n_last, 1));
+    G.bounds = degree_bounds(a_max, G.f, s->kappa, s->s2, G.kf, 1, mixed);
+    const int64_t span = std::max<int64_t>(0, G.n_last - G.n_first + 1);
+    if (span <= 4 * s->V + 4096) {
+      G.alloc_off = total_rows;
+      if (span > 0) jobs.push_back(RowJob{G.n_first, span, total_rows, G.f});
+      total_rows += span;
+    } else {
+      G.alloc_off = -1;
+    }
+  }
+  for (int m = 0; m < n_t; ++m) {
+    const MapGroup& G = groups[tgroup[m]];
+    if (G.alloc_off >= 0) {
+      times[m].row_base = G.alloc_off - G.n_first;
+    } else {
+      const int64_t span = std::max<int64_t>(0, times[m].K - nlo[m] + 1);
+      times[m].row_base = total_rows - nlo[m];
+      if (span > 0) jobs.push_back(RowJob{nlo[m], span, total_rows, G.f});
+      total_rows += span;
+    }
+    times[m].bounds = G.bounds;
+  }
+  DD_HIP(s->maprows64.ensure(sizeof(double) * kRow64 * std::max<int64_t>(total_rows, 1)),
+         "device allocation");
+  DD_HIP(s->maprows32.ensure(sizeof(float) * kRow32 * std::max<int64_t>(total_rows, 1)),
+         "device allocation");
+  for (const RowJob& j : jobs)
+    DD_HIP(launch_lag_rows(j.n_first, j.count, j.f, s->kappa, s->s2, gl_nodes(),
+                           s->maprows64.as<double>() + j.off * kRow64,
+                           s->maprows32.as<float>() + j.off * kRow32, st),
+           "lag-row kernel launch");
+  // Items and slots.
+  int64_t Kc = tune().map_K;
+  int64_t far_total = 0;
+  for (int m = 0; m < n_t; ++m) {
+    const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
+    far_total += std::max<int64_t>(0, times[m].K + 1 - kf);
+  }
+  // keep partials below ~1 GiB
+  const int64_t cap_slots = std::max<int64_t>(n_t * 2, (1LL << 27) / std::max<int64_t>(npix, 1));
+  while (far_total / Kc + n_t > cap_slots) Kc *= 2;
+  std::vector<MapItem> near, far;
+  int64_t slot_base = 0;
+  for (int m = 0; m < n_t; ++m) {
+    const int64_t K = times[m].K;
+    const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
+    const int64_t near_hi = std::max<int64_t>(nlo[m], std::min<int64_t>(kf, K + 1));
+    int c = 0;
+    for (int64_t t = 0; t < n_tiles; ++t)
+      near.push_back(MapItem{(int32_t)t, m, (int32_t)nlo[m], (int32_t)near_hi, 0, 1, 0, 0});
+    for (int64_t lo = std::max(kf, nlo[m]); lo <= K; lo += Kc, ++c) {
+      const int64_t hi = std::min<int64_t>(lo + Kc, K + 1);
+      for (int64_t t = 0; t < n_tiles; ++t)
+        far.push_back(MapItem{(int32_t)t, m, (int32_t)lo, (int32_t)hi, 1 + c, 0, 0, 0});
+    }
+    times[m].slot_base = slot_base;
+    times[m].n_slots = 1 + c;
+    slot_base += 1 + c;
+  }
+  auto longer = [](const MapItem& a, const MapItem& b) {
+    return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
+  };
+  std::stable_sort(near.begin(), near.end(), longer);
+  std::stable_sort(far.begin(), far.end(), longer);
+  std::vector<MapItem> items = near;
+  items.insert(items.end(), far.begin(), far.end());
+  rc = upload(s->aux2, items, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(s->aux3, times, st);
+  if (rc != DD_OK) return rc;
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)slot_base * (size_t)npix), "device allocation");
+  MapLaunch L{};
+  L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
+                : (const void*)(s->pos64.as<double2>() + kPosPad);
+  L.rows64 = s->maprows64.as<double>();
+  L.rows32 = s->maprows32.as<float>();
+  L.items = s->aux2.as<MapItem>();
+  L.n_items = (int32_t)items.size();
+  L.times = s->aux3.as<MapTime>();
+  L.X0 = X0; L.Y0 = Y0; L.DX = DX; L.DY = DY;
+  L.W = g->w; L.H = g->h;
+  L.partial = s->partial.as<double>();
+  L.R = R;
+  L.mixed = mixed;
+  DD_HIP(launch_map(L, st), "map launch");
+  DD_HIP(launch_reduce_map(s->partial.as<double>(), s->aux3.as<MapTime>(), n_t, npix, s->pref,
+                           out_dev, st),
+         "map reduce launch");
+  return DD_OK;
+}
+
+// Result delivery: device output directly, or a device scratch then a copy.
+template <typename F>
+dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStream_t st, F&& run) {
+  if (on_device) return run(out);
+  DD_HIP(s->tmp_out.ensure(sizeof(double) * std::max<size_t>(n, 1)), "device allocation");
+  dd_status rc = run(s->tmp_out.as<double>());
+  if (rc != DD_OK) return rc;
+  if (n) DD_HIP(hipMemcpyAsync(out, s->tmp_out.p, sizeof(double) * n, hipMemcpyDeviceToHost, st),
+                "device-to-host copy");
+  DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return DD_OK;
+}
+
+}  // namespace
+
+void dd_forget_plans(const dd_scan* s) { g_plans.erase(s); }
+
+dd_status dd_damage_at_probe_arrival(dd_scan* s, dd_precision p, double* out,
+                                     int32_t out_on_device, void* hip_stream) {
+  if (!s || !out) return fail(DD_EINVAL, "NULL argument");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  hipStream_t st = (hipStream_t)hip_stream;
+  return deliver(s, (size_t)s->V, out, out_on_device, st,
+                 [&](double* o) { return run_arrival(s, p == DD_MIXED, o, st); });
+}
+
+dd_status dd_damage_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t,
+                        dd_precision p, double* out, int32_t out_on_device, void* hip_stream) {
+  if (!s || !g || !out || (n_t > 0 && !t_s)) return fail(DD_EINVAL, "NULL argument");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  if (n_t < 1) return fail(DD_EINVAL, "n_t must be >= 1");
+  if (g->w < 1 || g->h < 1) return fail(DD_EINVAL, "grid w and h must be >= 1");
+  if ((int64_t)g->w * g->h > (1LL << 30)) return fail(DD_EINVAL, "grid too large");
+  for (double v : {g->x0_m, g->y0_m, g->dx_m, g->dy_m})
+    if (!std::isfinite(v)) return fail(DD_EINVAL, "grid values must be finite");
+  for (int32_t m = 0; m < n_t; ++m)
+    if (!std::isfinite(t_s[m]) || t_s[m] < 0) return fail(DD_EINVAL, "time %d invalid", m);
+  // pixel coordinates in pitch units must be exact in single precision for
+  // the mixed path to keep its accuracy; they are used as given otherwise
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t n = (size_t)n_t * g->w * g->h;
+  return deliver(s, n, out, out_on_device, st,
+                 [&](double* o) { return run_map(s, g, t_s, n_t, p == DD_MIXED, o, st); });
+}
+
+dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, dd_precision p,
+                         double* const* outs, int32_t out_on_device, void* hip_stream) {
+  if (n < 1 || !scans || !outs) return fail(DD_EINVAL, "bad batch arguments");
+  if ((query_mask & 3u) == 0 || (query_mask & ~3u)) return fail(DD_EINVAL, "bad query mask");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  for (int32_t k = 0; k < n; ++k)
+    if (!scans[k] || !outs[k]) return fail(DD_EINVAL, "scan %d or its output is NULL", k);
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (int32_t k = 0; k < n; ++k) {
+    dd_scan* s = scans[k];
+    double* o = outs[k];
+    if (query_mask & DD_Q_ARRIVAL) {
+      dd_status rc = dd_damage_at_probe_arrival(s, p, o, out_on_device, hip_stream);
+      if (rc != DD_OK) return rc;
+      o += s->V;
+    }
+    if (query_mask & DD_Q_FINAL_AT_PROBES) {
+      dd_grid g{0.0, 0.0, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx, s->desc.ny};
+      const double t_end = (double)s->V * s->tau_v;
+      dd_status rc = dd_damage_map(s, &g, &t_end, 1, p, o, out_on_device, hip_stream);
+      if (rc != DD_OK) return rc;
+    }
+  }
+  (void)st;
+  return DD_OK;
+}
+
+dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double* a,
+                        const double* lag, dd_precision p, double* out, void* hip_stream) {
+  if (!(std::isfinite(kappa) && kappa > 0 && std::isfinite(sigma_hat) && sigma_hat > 0))
+    return fail(DD_EINVAL, "kappa and sigma_hat must be finite and > 0");
+  if (n < 0 || (n > 0 && (!a || !lag || !out))) return fail(DD_EINVAL, "bad arrays");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  dd_status rc = ensure_device();
+  if (rc != DD_OK) return rc;
+  DD_HIP(launch_pair_terms(kappa, 2.0 * sigma_hat * sigma_hat, n, a, lag, p == DD_MIXED,
+                           gl_nodes(), out, (hipStream_t)hip_stream),
+         "pair-term launch");
+  return DD_OK;
+}
+
+dd_status dd_autotune(const char* cache_path) {
+  (void)cache_path;
+  return fail(DD_EUNSUPPORTED, "autotuner not available in this build");
+}
+
+dd_status dd_tune_load(const char* cache_path) {
+  (void)cache_path;
+  return fail(DD_EUNSUPPORTED, "autotuner not available in this build");
+}

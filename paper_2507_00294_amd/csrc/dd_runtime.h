@@ -1,0 +1,87 @@
+// dd_runtime.h -- the scan handle and host helpers shared by the libdd
+// runtime sources.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/dd.h"
+#include "dd_internal.h"
+
+namespace dd {
+
+dd_status fail(dd_status st, const char* fmt, ...);
+dd_status hip_fail(hipError_t e, const char* what);
+bool host_alloc_ok(size_t bytes);
+hipError_t dev_alloc(void** p, size_t bytes);
+dd_status ensure_device();
+const GLNodes& gl_nodes();
+double row_c(double lam, double kappa, double s2);
+int degree_needed(double dx, bool mixed);
+int64_t first_row_below(double thr, double a_max, double f, double kappa, double s2,
+                        int64_t n_start, int64_t n_end);
+DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
+                           bool mixed);
+
+// A grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int dev = -1;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = dev_alloc(&p, need);
+    if (e == hipSuccess) bytes = need ? need : 16;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+// Tile-shape choices (autotuned; defaults otherwise).
+struct TuneParams {
+  int arr_R_mixed = 4, arr_R_f64 = 2;
+  int arr_K_mixed = 2048, arr_K_f64 = 1024;   // lags per far work item
+  int map_R_mixed = 2, map_R_f64 = 1;
+  int map_K = 4096;
+};
+TuneParams& tune();
+
+}  // namespace dd
+
+struct dd_scan {
+  dd_scan_desc desc{};
+  std::vector<int32_t> ids;
+  int64_t V = 0;
+  double tau_v = 0, kappa = 0, s2 = 0, pref = 0;
+
+  // Device state (created on first query, on the then-current device).
+  int dev = -1;
+  dd::DevBuf pos32, pos64;          // padded probe positions by visit
+  dd::DevBuf rows64, rows32;        // integer-lag rows n = 0 .. n_rows-1
+  int64_t n_rows = 0;
+  dd::DevBuf partial, items, aux, aux2, aux3, tmp_out, maprows64, maprows32;
+
+  void release_device() {
+    for (dd::DevBuf* b : {&pos32, &pos64, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,
+                          &tmp_out, &maprows64, &maprows32})
+      b->release();
+    n_rows = 0;
+    dev = -1;
+  }
+  // Uploads positions and integer-lag rows (rows 0 .. V + margin).
+  dd_status prepare(hipStream_t st);
+};

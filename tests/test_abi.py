@@ -1,0 +1,128 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/dd.h declares, validates its arguments, generates the
+scan orders exactly as the oracle does, and fails loudly without a device."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2507_00294_amd as dd
+
+    if not os.path.exists(dd.LIB_PATH):
+        from paper_2507_00294_amd import build
+
+        build.build()
+    dd.load_library()
+    return dd
+
+
+def test_exports_every_header_symbol(dd):
+    with open(os.path.join(ROOT, "include", "dd.h")) as f:
+        header = f.read()
+    declared = set(re.findall(r"\b(dd_[a-z_0-9]+)\s*\(", header))
+    assert declared == set(dd.EXPORTS)
+    lib = dd.load_library()
+    for name in declared:
+        assert hasattr(lib, name), name
+    nm = subprocess.run(["nm", "-D", "--defined-only", dd.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    for name in declared:
+        assert re.search(rf"\bT {name}\b", nm), name
+
+
+def test_visit_orders_match_oracle(dd, ora):
+    cases = [
+        ("raster", dict(nx=7, ny=5), dict(order=ora.RASTER)),
+        ("interleaved", dict(nx=4, ny=4, stride=2), dict(order=ora.INTERLEAVED, stride=2)),
+        ("interleaved", dict(nx=9, ny=7, stride=3), dict(order=ora.INTERLEAVED, stride=3)),
+        ("random", dict(nx=33, ny=17, seed=3), dict(order=ora.RANDOM, seed=3)),
+        ("random", dict(nx=512, ny=512, seed=3), dict(order=ora.RANDOM, seed=3)),
+        ("random", dict(nx=5, ny=5, seed=2 ** 63 + 12345), dict(order=ora.RANDOM,
+                                                               seed=2 ** 63 + 12345)),
+        ("multiframe", dict(nx=6, ny=3, frames=4), dict(order=ora.MULTIFRAME, frames=4)),
+    ]
+    for order, kw, okw in cases:
+        s = dd.Scan(kw["nx"], kw["ny"], order, **{k: v for k, v in kw.items()
+                                                  if k not in ("nx", "ny")})
+        o = ora.visits(okw.pop("order"), kw["nx"], kw["ny"], **okw)
+        assert np.array_equal(s.visits(), o), (order, kw)
+        assert s.num_visits == o.size
+
+
+def test_explicit_order_copied(dd):
+    v = [3, 1, 1, 0, 2]
+    s = dd.Scan(2, 2, "explicit", visits=v)
+    assert s.visits().tolist() == v
+    assert s.num_visits == 5
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=0, ny=4), dict(nx=4, ny=-1), dict(nx=4, ny=4, pitch_m=0.0),
+    dict(nx=4, ny=4, pitch_m=float("nan")), dict(nx=4, ny=4, dwell_s=-1e-6),
+    dict(nx=4, ny=4, sigma_m=0.0), dict(nx=4, ny=4, D_m2s=0.0),
+    dict(nx=4, ny=4, D_m2s=float("inf")), dict(nx=4, ny=4, Q0_us=-1.0),
+    dict(nx=4, ny=4, order="interleaved", stride=0),
+    dict(nx=4, ny=4, order="multiframe", frames=0),
+    dict(nx=2, ny=2, order="explicit", visits=[0, 4]),
+    dict(nx=2, ny=2, order="explicit", visits=[0, -1]),
+    dict(nx=5000, ny=2),
+])
+def test_invalid_descriptions(dd, kw):
+    nx, ny = kw.pop("nx"), kw.pop("ny")
+    order = kw.pop("order", "raster")
+    with pytest.raises(dd.DDError) as e:
+        dd.Scan(nx, ny, order, **kw)
+    assert e.value.status == dd.DD_EINVAL
+
+
+def test_null_and_bad_arguments(dd):
+    lib = dd.load_library()
+    h = ctypes.c_void_p()
+    assert lib.dd_scan_create(None, ctypes.byref(h)) == dd.DD_EINVAL
+    assert lib.dd_scan_num_visits(None) == -1
+    lib.dd_scan_destroy(None)  # NULL is allowed
+    s = dd.Scan(2, 2)
+    assert lib.dd_damage_at_probe_arrival(s.handle, 7, ctypes.c_void_p(16), 1, None) == dd.DD_EINVAL
+    assert lib.dd_batch_solve(None, 0, 1, 0, None, 1, None) == dd.DD_EINVAL
+    g = dd.Grid(0, 0, 1e-9, 1e-9, 0, 4)
+    t = (ctypes.c_double * 1)(0.0)
+    assert lib.dd_damage_map(s.handle, ctypes.byref(g), t, 1, 0, ctypes.c_void_p(16), 1,
+                             None) == dd.DD_EINVAL
+    g = dd.Grid(0, 0, 1e-9, 1e-9, 4, 4)
+    t = (ctypes.c_double * 1)(-1.0)
+    assert lib.dd_damage_map(s.handle, ctypes.byref(g), t, 1, 0, ctypes.c_void_p(16), 1,
+                             None) == dd.DD_EINVAL
+    assert lib.dd_pair_terms(-1.0, 0.5, 1, None, None, 0, None, None) == dd.DD_EINVAL
+    assert b"kappa" in lib.dd_last_error()
+
+
+def test_queries_fail_loudly_without_device(dd):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = dd.load_library()
+    s = dd.Scan(2, 2)
+    out = (ctypes.c_double * 4)()
+    st = lib.dd_damage_at_probe_arrival(s.handle, 0, ctypes.cast(out, ctypes.c_void_p), 0, None)
+    assert st == dd.DD_EDEVICE
+    assert lib.dd_last_error()
+
+
+def test_out_of_memory_path():
+    # a per-allocation limit makes scan creation of a large grid fail cleanly
+    code = ("import paper_2507_00294_amd as dd\n"
+            "try:\n    dd.Scan(1024, 1024)\nexcept dd.DDError as e:\n    print(e.status)\n")
+    env = dict(os.environ, DD_ALLOC_LIMIT_BYTES="1000000", PYTHONPATH=ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         cwd=ROOT, timeout=120)
+    assert out.stdout.strip() == "-2", out.stderr

@@ -72,3 +72,30 @@ def test_large_argument_asymptote(ora):
         lhs = x * math.exp(x) * ora.e1(x) if x < 700 else None
         approx = 1 - 1 / x + 2 / x ** 2 - 6 / x ** 3
         assert abs(lhs - approx) <= 30 / x ** 4
+
+
+def test_binary128_e1_matches_mpmath(ora):
+    mpmath.mp.dps = 40
+    for x in XS:
+        ref = float(mpmath.e1(mpmath.mpf(float(x))))
+        assert abs(ora.e1_q(float(x)) - ref) <= 1.2e-16 * ref, x
+
+
+@pytest.mark.parametrize("a,dt,tau,sig,D", [
+    (5.0, 1e-3, 1.0, 1.0, 1e-4),      # E1 arguments differ by 1 part in 5e6
+    (1e5, 1e5, 1.0, 0.4, 0.5),        # far lag, far probe
+    (0.25, 3e5, 1.0, 0.4, 0.5),       # far lag, near probe
+    (2.0, 1.0, 1.0, 0.2, 1e-4),
+])
+def test_binary128_bracket_resolves_cancellation(ora, a, dt, tau, sig, D):
+    # E1(a/b1) - E1(a/b0) at 60 digits; the binary128 bracket keeps ~1e-16
+    mpmath.mp.dps = 60
+    Ds = mpmath.mpf(sig) ** 2
+    b1 = 2 * Ds + 4 * mpmath.mpf(D) * mpmath.mpf(dt)
+    b0 = 2 * Ds + 4 * mpmath.mpf(D) * max(mpmath.mpf(dt) - mpmath.mpf(tau), 0)
+    ref = float(mpmath.e1(mpmath.mpf(a) / b1) - mpmath.e1(mpmath.mpf(a) / b0))
+    assert abs(ora.phi_bracket_q(a, dt, tau, sig, D) - ref) <= 2e-16 * ref
+    # the long-double bracket agrees within its cancellation-limited accuracy
+    ld = ora.phi(a, dt, tau, sig, D, 4 * math.pi * D)
+    cond = float(mpmath.e1(mpmath.mpf(a) / b1)) / ref
+    assert abs(ld - ref) <= 4e-18 * cond * ref + 4e-16 * ref
