@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the damage-diffusion hot path on one MI355X.
+
+Workload: the arrival query (Eq. 6 evaluated at every probe visit at the
+moment it starts) of a 512x512 probe grid scanned in a seeded random order,
+pitch 1 nm, sigma 0.4 nm, dwell 0.5 us, D = 1e-12 m^2/s, in mixed precision:
+262144 visits, 3.436e10 causal pair terms per step.  One step is one full
+query (lag rows, near band, far region, fixed-order reduction) with the probe
+table resident in HBM.  Prints one JSON line.
+
+The dominant kernel (far region) is timed with HIP events on the stream it
+runs on; its algorithmic FLOPs per launch come from the library's plan.  The
+CPU oracle is timed on a seeded sample of the same visits and its values are
+the accuracy check of the GPU result.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pair E1-terms/s at oracle-matched accuracy; surrogate speedup @≤1% L2 err"
+PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X FP32 / FP64 vector peaks
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_query(scan, prec, out, steps, warmup, dd, torch):
+    for _ in range(warmup):
+        scan.arrival(prec, out=out)
+    torch.cuda.synchronize()
+    for k in ("arrival_far", "arrival_near", "lag_rows", "reduce"):
+        dd.profile_read(k, reset=True)
+    dd.profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        scan.arrival(prec, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dd.profiling(False)
+    kern = {k: dd.profile_read(k, reset=True)
+            for k in ("arrival_far", "arrival_near", "lag_rows", "reduce")}
+    return (t1 - t0) / steps, kern
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="mixed", choices=("mixed", "fp64"))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target duration of the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--side", type=int, default=512)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes three times "
+                         "(reference for the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {4 * n} bytes three times")
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_00294_amd as dd
+    from paper_2507_00294_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    dd.load_library()
+    spec = wl.large_random(args.side)
+    scan = dd.Scan(**spec.kwargs())
+    V = scan.num_visits
+    pairs = wl.causal_arrival_pairs(V)
+    out = torch.empty(V, dtype=torch.float64, device="cuda")
+    prec = args.precision
+    log(f"[bench] {args.side}x{args.side} random scan, V={V}, pairs={pairs:.4e}, {prec}")
+
+    sec, kern = time_query(scan, prec, out, args.steps, args.warmup, dd, torch)
+    value = pairs / sec
+    log(f"[bench] {prec}: {sec * 1e3:.3f} ms/step, {value:.4e} pairs/s")
+    far = kern["arrival_far"]
+    far_ms = far["ms"] / max(far["launches"], 1)
+    far_flops = far["flops"] / max(far["launches"], 1)
+    achieved = far_flops / (far_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": "k_arrival_far32" if prec == "mixed" else "k_arrival_far64",
+        "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None,
+        "avg_launch_ms": round(far_ms, 4),
+        "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
+        "flops_per_launch": far_flops,
+    }
+    result = out.cpu().numpy()
+
+    # The other precision on the same workload, for context.
+    other = "fp64" if prec == "mixed" else "mixed"
+    sec_o, _ = time_query(scan, other, out, max(2, args.steps // 4), 1, dd, torch)
+    other_res = out.cpu().numpy()
+    floor = 1e-30 * spec.Q0_us / (4 * math.pi * spec.D_m2s)
+    diff = np.abs(result - other_res) / np.maximum(np.abs(other_res if other == "fp64" else result),
+                                                  floor)
+    log(f"[bench] {other}: {sec_o * 1e3:.3f} ms/step; max rel diff mixed vs fp64 {diff.max():.3e}")
+
+    cpu = None
+    max_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+        ora = oracle.Scan(spec.nx, spec.ny, scan.visits(), spec.pitch_m, spec.tau_v,
+                          spec.sigma_m, spec.D_m2s, spec.Q0_us)
+        # calibrate on a small sample, then size the timed sample to the target
+        cal = wl.sampled_visits(V, 16, seed=101)
+        t0 = time.perf_counter()
+        ora.psi_arrival(cal, nthreads=threads)
+        rate = max(float(cal.sum()), 1.0) / max(time.perf_counter() - t0, 1e-6)
+        n_s = int(max(32, min(V, args.cpu_seconds * rate / (V / 2))))
+        idx = wl.sampled_visits(V, n_s, seed=7)
+        t0 = time.perf_counter()
+        ref = ora.psi_arrival(idx, nthreads=threads)
+        dt = time.perf_counter() - t0
+        s_pairs = float(idx.sum())
+        err = np.abs(result[idx] - ref) / np.maximum(np.abs(ref), floor)
+        max_err = float(err.max())
+        cpu = {"value": s_pairs / dt, "unit": "pair-terms/s", "cores": threads, "kind": "oracle",
+               "sample": f"arrival at {idx.size} seeded visits of the same scan "
+                         f"({s_pairs:.3e} pairs, {dt:.1f} s, long double)"}
+        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {threads} threads; "
+            f"max rel err GPU vs oracle {max_err:.3e}")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "pair-terms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"arrival query, {args.side}x{args.side} random-order scan "
+                               f"(seed 3), pitch 1 nm, sigma 0.4 nm, dwell 0.5 us, D 1e-12 m^2/s",
+                   "visits": V, "pairs_per_step": pairs, "precision": prec},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "max_rel_err_vs_oracle": max_err,
+        "other_precision": {"precision": other, "ms_per_step": sec_o * 1e3,
+                            "value": pairs / sec_o, "max_rel_diff_mixed_vs_fp64": float(diff.max())},
+        "kernels_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in kern.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

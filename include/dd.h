@@ -147,6 +147,25 @@ dd_status dd_autotune(const char *cache_path);
 /* Loads a cache written by dd_autotune; DD_EINVAL if unreadable.          */
 dd_status dd_tune_load(const char *cache_path);
 
+/* Kernel timing for measurement.  While enabled, the library brackets each
+ * launch of its main kernels with HIP events on the stream it launches on
+ * and records the algorithmic work of the launch: pairs is the number of
+ * causal (evaluation point, visit) pairs it evaluates, flops the FP32/FP64
+ * operations of the evaluation form used for them (FMA counted as 2; per
+ * pair 15 + 2M or 17 + 2M in mixed precision and 40 + 2M in FP64 for a
+ * series of degree M).  Kernel names: "arrival_far", "arrival_near", "map",
+ * "batch", "lag_rows", "reduce".                                          */
+typedef struct {
+  double ms;         /* summed event time of the launches                   */
+  int64_t launches;
+  double pairs;      /* summed pairs                                        */
+  double flops;      /* summed algorithmic floating-point operations         */
+} dd_kernel_stats;
+dd_status dd_profiling(int32_t enable);
+/* Synchronizes the recorded events and returns the totals since the last
+ * reset; reset = 1 clears them.  DD_EINVAL for an unknown name.          */
+dd_status dd_profile_read(const char *kernel, dd_kernel_stats *out, int32_t reset);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);
 

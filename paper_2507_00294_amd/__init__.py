@@ -29,7 +29,7 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
     "dd_damage_map", "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms",
-    "dd_autotune", "dd_tune_load", "dd_last_error",
+    "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_last_error",
 )
 
 
@@ -47,6 +47,11 @@ class ScanDesc(ctypes.Structure):
         ("n_visits", ctypes.c_int64), ("pitch_m", ctypes.c_double), ("dwell_s", ctypes.c_double),
         ("sigma_m", ctypes.c_double), ("D_m2s", ctypes.c_double), ("Q0_us", ctypes.c_double),
     ]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("pairs", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 class Grid(ctypes.Structure):
@@ -79,10 +84,12 @@ def load_library():
     lib.dd_pair_terms.argtypes = [dbl, dbl, i64, vp, vp, ctypes.c_int, vp, vp]
     lib.dd_autotune.argtypes = [ctypes.c_char_p]
     lib.dd_tune_load.argtypes = [ctypes.c_char_p]
+    lib.dd_profiling.argtypes = [i32]
+    lib.dd_profile_read.argtypes = [ctypes.c_char_p, P(KernelStats), i32]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map",
                  "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
-                 "dd_tune_load"):
+                 "dd_tune_load", "dd_profiling", "dd_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -240,3 +247,15 @@ def autotune(cache_path: str | None = None):
 
 def tune_load(cache_path: str):
     _check(load_library().dd_tune_load(cache_path.encode()))
+
+
+def profiling(enable: bool = True):
+    """Turn HIP-event timing of the main kernels on or off (``dd_profiling``)."""
+    _check(load_library().dd_profiling(1 if enable else 0))
+
+
+def profile_read(kernel: str, reset: bool = True) -> dict:
+    """Totals for one kernel since the last reset (``dd_profile_read``)."""
+    st = KernelStats()
+    _check(load_library().dd_profile_read(kernel.encode(), ctypes.byref(st), 1 if reset else 0))
+    return {"ms": st.ms, "launches": int(st.launches), "pairs": st.pairs, "flops": st.flops}

@@ -119,11 +119,53 @@ __device__ __forceinline__ float series_f32(float a, const float* __restrict__ r
   float yl = __builtin_fmaf(a, rhi, -yh);
   yl = __builtin_fmaf(a, row[kR32_RLO], yl);
   const float t = __builtin_amdgcn_exp2f(-yh);
-  float q = row[kR32_P + M];
+  float q;
+  if constexpr (M == 0) {
+    q = row[kR32_P0];
+  } else {
+    q = row[kR32_P1 + M - 1];
 #pragma unroll
-  for (int m = M - 1; m >= 0; --m) q = __builtin_fmaf(q, z, row[kR32_P + m]);
+    for (int m = M - 1; m >= 1; --m) q = __builtin_fmaf(q, z, row[kR32_P1 + m - 1]);
+    q = __builtin_fmaf(q, z, row[kR32_P0]);
+  }
   q = __builtin_fmaf(q, yl * (float)(-kLn2), q);
   return t * q;
+}
+
+// Mixed-precision series for degree M <= 3 in powers of a itself,
+//   q = P_0 + PA_1 a + ... + PA_M a^M,   PA_m = P_m c^m,
+// with the exponent's rounding correction folded in: with x1 log2(e) =
+// yh + e2 + a rlo (yh = fl(a rhi), e2 its exact rounding error),
+// exp(-x1) = 2^-yh (1 + eps), eps = -ln2 (e2 + a rlo), and
+// t q (1 + eps) ~= t (q + P_0 eps); the neglected t P_0 eps (q/P_0 - 1) is
+// below |eps| dx / 2, i.e. under 1e-8 of the term at the dx <= 0.01 where
+// degrees <= 3 are used.  P_0 eps enters as -ln2 P_0 rlo added to the linear
+// coefficient (row field PA_1 holds PA_1 - ln2 P_0 rlo) and one fma with e2.
+// `a` is exact.
+template <int M>
+__device__ __forceinline__ float series_f32a(float a, const RowA& w) {
+  static_assert(M <= kMaxA, "degree too high for the a-form");
+  const float yh = a * w.rhi;
+  const float e2 = __builtin_fmaf(a, w.rhi, -yh);
+  const float t = __builtin_amdgcn_exp2f(-yh);
+  float q;
+  if constexpr (M == 0) {
+    q = __builtin_fmaf(w.p0nr, a, w.p0);
+  } else {
+    const float pa[3] = {w.pa1, w.pa2, w.pa3};
+    q = pa[M - 1];
+#pragma unroll
+    for (int m = M - 1; m >= 1; --m) q = __builtin_fmaf(q, a, pa[m - 1]);
+    q = __builtin_fmaf(q, a, w.p0);
+  }
+  q = __builtin_fmaf(w.p0n, e2, q);
+  return t * q;
+}
+
+__device__ __forceinline__ RowA load_rowa(const float* __restrict__ row) {
+  const float4 u = *(const float4*)row;
+  const float4 v = *(const float4*)(row + 4);
+  return RowA{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 }
 
 }  // namespace dd

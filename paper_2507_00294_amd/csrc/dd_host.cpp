@@ -211,8 +211,9 @@ static dd_status validate(const dd_scan_desc* d) {
     default:
       return fail(DD_EINVAL, "unknown order %d", d->order);
   }
-  // Lattice coordinates must stay exact in single precision.
-  if (d->nx > 4096 || d->ny > 4096) return fail(DD_EINVAL, "probe grid side above 4096");
+  // Lattice coordinates and squared distances must stay exact in single
+  // precision (|e|^2 + |p|^2 < 2^24).
+  if (d->nx > 2048 || d->ny > 2048) return fail(DD_EINVAL, "probe grid side above 2048");
   return DD_OK;
 }
 
@@ -351,3 +352,98 @@ dd_status dd_scan_visits(const dd_scan* s, int32_t* out_host) {
 }
 
 const char* dd_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Kernel timing.
+namespace {
+struct ProfRec {
+  std::string kernel;
+  hipEvent_t a, b;
+  double pairs, flops;
+  bool done;
+};
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::map<std::string, dd_kernel_stats> tot;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+ProfState& prof() {
+  static ProfState* p = new ProfState();
+  return *p;
+}
+const char* const kKernelNames[] = {"arrival_far", "arrival_near", "map", "batch", "lag_rows",
+                                    "reduce"};
+}  // namespace
+
+namespace dd {
+ProfToken prof_begin(const char* kernel, hipStream_t st) {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  ProfToken t;
+  if (!P.on) return t;
+  hipEvent_t a = P.get(), b = P.get();
+  if (!a || !b) return t;
+  if (hipEventRecord(a, st) != hipSuccess) return t;
+  P.recs.push_back(ProfRec{kernel, a, b, 0, 0, false});
+  t.slot = (int)P.recs.size() - 1;
+  return t;
+}
+void prof_end(ProfToken tok, hipStream_t st, double pairs, double flops) {
+  if (tok.slot < 0) return;
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (tok.slot >= (int)P.recs.size()) return;
+  ProfRec& r = P.recs[tok.slot];
+  r.pairs = pairs;
+  r.flops = flops;
+  r.done = hipEventRecord(r.b, st) == hipSuccess;
+}
+}  // namespace dd
+
+dd_status dd_profiling(int32_t enable) {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  P.on = enable != 0;
+  return DD_OK;
+}
+
+dd_status dd_profile_read(const char* kernel, dd_kernel_stats* out, int32_t reset) {
+  if (!kernel || !out) return fail(DD_EINVAL, "NULL argument");
+  bool known = false;
+  for (const char* k : kKernelNames) known = known || strcmp(k, kernel) == 0;
+  if (!known) return fail(DD_EINVAL, "unknown kernel name '%s'", kernel);
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  for (ProfRec& r : P.recs) {
+    if (r.done) {
+      if (hipEventSynchronize(r.b) != hipSuccess) return fail(DD_EDEVICE, "event synchronize failed");
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(DD_EDEVICE, "event time failed");
+      dd_kernel_stats& t = P.tot[r.kernel];
+      t.ms += ms;
+      t.launches += 1;
+      t.pairs += r.pairs;
+      t.flops += r.flops;
+    }
+    P.pool.push_back(r.a);
+    P.pool.push_back(r.b);
+  }
+  P.recs.clear();
+  dd_kernel_stats z{0.0, 0, 0.0, 0.0};
+  auto it = P.tot.find(kernel);
+  *out = it == P.tot.end() ? z : it->second;
+  if (reset) P.tot.erase(kernel);
+  return DD_OK;
+}

@@ -22,11 +22,24 @@ namespace dd {
 // once per lag into a row and read through the scalar cache.
 
 constexpr int kM64 = 17;     // FP64 rows hold P_0..P_17
-constexpr int kM32 = 8;      // FP32 rows hold P_0..P_8
+constexpr int kM32 = 6;      // FP32 rows hold P_0..P_6
 constexpr int kRow64 = 24;   // doubles per row: rb1 rb0 c rl2 P0..P17 (+2 pad)
-constexpr int kRow32 = 16;   // floats per row:  c rhi rlo P0..P8 (+4 pad)
+constexpr int kRow32 = 16;   // floats per row, see kR32_*
 constexpr int kR64_RB1 = 0, kR64_RB0 = 1, kR64_C = 2, kR64_RL2 = 3, kR64_P = 4;
-constexpr int kR32_C = 0, kR32_RHI = 1, kR32_RLO = 2, kR32_P = 3;
+// FP32 row.  The first 8 floats are everything the bulk (degree <= 3) path
+// reads, so one 32-byte scalar load fetches them: rb1 log2(e) rounded (rhi),
+// P_0, the series coefficients in powers of a itself (PA_m = P_m c^m,
+// m = 1..3), -ln2 P_0, -ln2 P_0 rlo and c.  Then rlo = rb1 log2(e) - rhi and
+// P_1..P_6 for the degree >= 4 form in powers of dx = a c.
+constexpr int kR32_RHI = 0, kR32_P0 = 1, kR32_PA = 2, kR32_P0N = 5, kR32_P0NR = 6, kR32_C = 7,
+              kR32_RLO = 8, kR32_P1 = 9;
+constexpr int kMaxA = 3;     // highest degree evaluated in powers of a
+static_assert(kR32_PA + kMaxA <= kR32_P0N && kR32_P0NR < kR32_C && kR32_P1 + kM32 - 1 < kRow32,
+              "FP32 row fields overlap");
+// Row fields of the bulk path, loaded together.
+struct RowA {
+  float rhi, p0, pa1, pa2, pa3, p0n, p0nr, c;
+};
 
 // Series regime thresholds on dx = a c (= a/b0 - a/b1).  Below them the
 // series above is used; the truncation bound after P_M is
@@ -34,6 +47,11 @@ constexpr int kR32_C = 0, kR32_RHI = 1, kR32_RLO = 2, kR32_P = 3;
 constexpr double kThr64 = 1.0;    // FP64: M = 17 covers dx <= 1 to 5e-15
 constexpr float kThr32 = 0.25f;   // FP32: M = 6 covers dx <= 0.25 to 2e-8
 constexpr int kMNear32 = 6;
+// Mixed path: terms with x1 = a/b1 > 100 (below e^-100 each, fewer than
+// 2^30 of them) are dropped; they sum to < 4e-35, far below the 1e-30
+// floor of the mixed path's relative-error model.  The test is made on
+// x1 log2(e), the quantity the FP32 rows hold.
+constexpr float kCull32Log2 = 144.26950408889634f;
 
 constexpr int kGL = 24;  // Gauss-Legendre nodes on [0, 1] for J_m(w), w <= 1
 struct GLNodes {
@@ -75,5 +93,33 @@ struct MapTime {
 };
 
 
+// Batched launch: one descriptor per scan and one item list for all scans.
+enum { kBatchArrNear = 0, kBatchArrFar = 1, kBatchMapNear = 2, kBatchMapFar = 3 };
+struct BatchScan {
+  const void* pos;         // float2 (mixed) or double2 (FP64), base = visit 0
+  const float4* pos4;      // (-2x, -2y, x^2+y^2, 0) by visit
+  const double* rows64;    // integer-lag rows of this scan
+  const float* rows32;
+  int64_t V;
+  int32_t nx, ny;
+  DegreeBounds arr_bounds;
+  MapTime map_time;        // the final map at t = V tau_v (K = V, f = 0)
+  double* arr_partial;     // [slots][V]
+  double* map_partial;     // [slots][nx*ny]
+};
+struct BatchItem {
+  int32_t scan, kind, tile, n_lo, n_hi, slot_flags, cost_hi, cost_lo;
+};
+// Reduction work of a batch: one entry per (scan, query).
+struct BatchReduce {
+  const double* partial;
+  const int32_t* tile_slots;  // arrival: slots per tile; map: nullptr
+  int32_t n_slots;            // map: slots of the single time
+  int32_t tile;               // arrival tile width
+  int64_t n;                  // outputs
+  int64_t out_off;            // first output in the flat index space
+  double* out;
+  double pref;
+};
 
 }  // namespace dd

@@ -18,6 +18,7 @@ hipError_t launch_lag_rows(int64_t n0, int64_t count, double f, double kappa, do
 
 struct ArrivalLaunch {
   const void* pos;          // float2 (mixed) or double2 (FP64), base = visit 0
+  const float4* pos4;       // (-2x, -2y, x^2+y^2, 0) by visit, base = visit 0
   const double* rows64;     // integer-lag rows, row n = lag n
   const float* rows32;
   const ArrItem* items;
@@ -33,6 +34,8 @@ hipError_t launch_arrival(const ArrivalLaunch& L, hipStream_t st);
 
 struct MapLaunch {
   const void* pos;          // float2 / double2 probe positions by visit
+  const float4* pos4;       // (-2x, -2y, x^2+y^2, 0) by visit
+  bool lattice;             // pixel/probe coordinates exact small dyadics
   const double* rows64;
   const float* rows32;
   const MapItem* items;
@@ -50,6 +53,12 @@ hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slot
                                  int tile, double pref, double* out, hipStream_t st);
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
                              int64_t npix, double pref, double* out, hipStream_t st);
+
+// Persistent batched launch; `counter` is zeroed on the stream first.
+hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
+                        int* counter, int R, int RN, int RM, bool mixed, hipStream_t st);
+hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
+                               hipStream_t st);
 
 hipError_t launch_pair_terms(double kappa, double s2, int64_t n, const double* a,
                              const double* lag, bool mixed, const GLNodes& gl, double* out,

@@ -21,6 +21,8 @@
 // per lag segment, so the inner loop has no branches.  Partial sums of work
 // items go to fixed slots and are added in a fixed order (bitwise
 // reproducible, no floating-point atomics).
+#include <type_traits>
+
 #include "dd_device.h"
 #include "dd_kernels.h"
 
@@ -74,11 +76,20 @@ __device__ void make_row(double lam, double kappa, double s2, const GLNodes& gl,
   for (int m = 0; m <= kM64; ++m) r64[kR64_P + m] = P[m];
   for (int k = kR64_P + kM64 + 1; k < kRow64; ++k) r64[k] = 0.0;
   const float rhi = (float)rl2;
-  r32[kR32_C] = (float)c;
+  const float rlo = (float)(rl2 - (double)rhi);
   r32[kR32_RHI] = rhi;
-  r32[kR32_RLO] = (float)(rl2 - (double)rhi);
-  for (int m = 0; m <= kM32; ++m) r32[kR32_P + m] = (float)P[m];
-  for (int k = kR32_P + kM32 + 1; k < kRow32; ++k) r32[k] = 0.0f;
+  r32[kR32_P0] = (float)P[0];
+  double cm = 1.0;
+  for (int m = 1; m <= kMaxA; ++m) {
+    cm *= c;
+    r32[kR32_PA + m - 1] = (float)(P[m] * cm + (m == 1 ? -kLn2 * P[0] * (double)rlo : 0.0));
+  }
+  r32[kR32_P0N] = (float)(-kLn2 * P[0]);
+  r32[kR32_P0NR] = (float)(-kLn2 * P[0] * (double)rlo);
+  r32[kR32_C] = (float)c;
+  r32[kR32_RLO] = rlo;
+  for (int m = 1; m <= kM32; ++m) r32[kR32_P1 + m - 1] = (float)P[m];
+  for (int k = kR32_P1 + kM32; k < kRow32; ++k) r32[k] = 0.0f;
 }
 
 __global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, double f, double kappa,
@@ -110,37 +121,94 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 // ---------------------------------------------------------------------------
 // Arrival query, far region, mixed precision.  Lags [lo, hi) with
-// (hi - lo) % R == 0; window W[q] holds the probe of visit jl - n0 - (R-1) + q.
+// (hi - lo) % R == 0; window W[q] holds the probe of visit jl - n0 - (R-1) + q
+// as (-2x, -2y, x^2 + y^2), so that a = |e|^2 + |p|^2 - 2 e.p takes three
+// exact FP32 operations (lattice coordinates below 2048).  For degrees <= 3
+// the rows of the next R lags are fetched (scalar loads) while the current R
+// lags are evaluated.
+template <int M>
+struct RowSel {
+  // degree <= 3: the 8 bulk fields; higher degrees read the row in place
+  using type = typename std::conditional<(M <= kMaxA), RowA, const float*>::type;
+};
+
+template <int M>
+__device__ __forceinline__ typename RowSel<M>::type fetch_row(const float* __restrict__ rows,
+                                                              int64_t n) {
+  if constexpr (M <= kMaxA)
+    return load_rowa(rows + n * kRow32);
+  else
+    return rows + n * kRow32;
+}
+
+template <int M>
+__device__ __forceinline__ float series_row32(float a, const typename RowSel<M>::type& row) {
+  if constexpr (M <= kMaxA)
+    return series_f32a<M>(a, row);
+  else
+    return series_f32<M>(a, row);
+}
+
+// One chunk of R lags n0 .. n0+R-1 against window W (see arr_far32); the R
+// terms of each evaluation point are summed in FP32 by fused multiply-adds
+// (R roundings) and then added to its FP64 accumulator.
 template <int M, int R, bool EDGE>
-__device__ __forceinline__ void arr_far32(int lo, int hi, const float2* __restrict__ pos, int64_t jl,
-                                          const float (&ex)[R], const float (&ey)[R],
-                                          const float* __restrict__ rows, double (&acc)[R]) {
-  float2 W[2 * R - 1];
+__device__ __forceinline__ void arr_chunk32(int n0, int64_t jl, const float4 (&W)[2 * R - 1],
+                                            const float (&ex)[R], const float (&ey)[R],
+                                            const float (&ee)[R],
+                                            const typename RowSel<M>::type (&row)[R],
+                                            double (&acc)[R]) {
+  float part[R];
 #pragma unroll
-  for (int q = 0; q < 2 * R - 1; ++q) W[q] = pos[jl - lo - (R - 1) + q];
-  for (int n0 = lo; n0 < hi; n0 += R) {
-    float t[R][R];
+  for (int s = 0; s < R; ++s) {
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const float* row = rows + (int64_t)(n0 + s) * kRow32;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float2 p = W[r - s + R - 1];
-        const float dx = ex[r] - p.x, dy = ey[r] - p.y;
-        const float a = __builtin_fmaf(dy, dy, dx * dx);
-        float v = series_f32<M>(a, row);
-        if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0f;
-        t[r][s] = v;
-      }
+    for (int r = 0; r < R; ++r) {
+      const float4 p = W[r - s + R - 1];
+      const float a = __builtin_fmaf(ex[r], p.x, __builtin_fmaf(ey[r], p.y, ee[r] + p.z));
+      float v = series_row32<M>(a, row[s]);
+      if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0f;
+      part[r] = (s == 0) ? v : part[r] + v;
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<R>(t[r]);
-#pragma unroll
-    for (int q = 2 * R - 2; q >= R; --q) W[q] = W[q - R];
-    const int64_t base = jl - (n0 + R) - (R - 1);
-#pragma unroll
-    for (int q = 0; q < R; ++q) W[q] = pos[base + q];
   }
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
+}
+
+template <int M, int R, bool EDGE>
+__device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restrict__ pos, int64_t jl,
+                                          const float (&ex)[R], const float (&ey)[R],
+                                          const float (&ee)[R], const float* __restrict__ rows,
+                                          double (&acc)[R]) {
+  using Row = typename RowSel<M>::type;
+  // Two windows alternate so that sliding by R visits needs no register
+  // moves: A covers the chunk at n0, B the chunk at n0 + R.
+  float4 A[2 * R - 1], B[2 * R - 1];
+#pragma unroll
+  for (int q = 0; q < 2 * R - 1; ++q) A[q] = pos[jl - lo - (R - 1) + q];
+  Row cur[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, lo + s);
+  int n0 = lo;
+  for (; n0 + 2 * R <= hi; n0 += 2 * R) {
+    Row nxt[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M>(rows, n0 + R + s);
+#pragma unroll
+    for (int q = R; q < 2 * R - 1; ++q) B[q] = A[q - R];
+    const int64_t b1 = jl - (n0 + R) - (R - 1);
+#pragma unroll
+    for (int q = 0; q < R; ++q) B[q] = pos[b1 + q];
+    arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);
+#pragma unroll
+    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, min(n0 + 2 * R + s, hi - 1));
+#pragma unroll
+    for (int q = R; q < 2 * R - 1; ++q) A[q] = B[q - R];
+    const int64_t b2 = jl - (n0 + 2 * R) - (R - 1);
+#pragma unroll
+    for (int q = 0; q < R; ++q) A[q] = pos[b2 + q];
+    arr_chunk32<M, R, EDGE>(n0 + R, jl, B, ex, ey, ee, nxt, acc);
+  }
+  if (n0 < hi) arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);  // one chunk left
 }
 
 template <int M, int R, bool EDGE>
@@ -174,19 +242,18 @@ __device__ __forceinline__ void arr_far64(int lo, int hi, const double2* __restr
 
 // Degree dispatch for one segment (uniform branch).
 template <int R, bool EDGE>
-__device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float2* __restrict__ pos,
+__device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float4* __restrict__ pos,
                                               int64_t jl, const float (&ex)[R], const float (&ey)[R],
-                                              const float* __restrict__ rows, double (&acc)[R]) {
+                                              const float (&ee)[R], const float* __restrict__ rows,
+                                              double (&acc)[R]) {
   switch (M) {
-    case 0: arr_far32<0, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 1: arr_far32<1, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 2: arr_far32<2, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 3: arr_far32<3, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 4: arr_far32<4, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 5: arr_far32<5, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 6: arr_far32<6, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    case 7: arr_far32<7, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-    default: arr_far32<8, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
+    case 0: arr_far32<0, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 1: arr_far32<1, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 2: arr_far32<2, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 3: arr_far32<3, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 4: arr_far32<4, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 5: arr_far32<5, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    default: arr_far32<6, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
   }
 }
 
@@ -212,24 +279,22 @@ __device__ __forceinline__ void seg_range(const DegreeBounds& b, int M, int n_lo
   hi = (M == 0) ? n_hi : min(n_hi, b.b[M - 1]);
 }
 
+// One wavefront processes one arrival work item (far region).
 template <int R>
-__global__ void __launch_bounds__(256) k_arrival_far32(const float2* __restrict__ pos,
-                                                       const float* __restrict__ rows,
-                                                       const ArrItem* __restrict__ items, int n_items,
-                                                       int64_t V, DegreeBounds bnd,
-                                                       double* __restrict__ partial) {
-  const int it = blockIdx.x * 4 + wave_id();
-  if (it >= n_items) return;
+__device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const float4* __restrict__ pos,
+                                                 const float* __restrict__ rows, int64_t V,
+                                                 const DegreeBounds& bnd,
+                                                 double* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
-  const ArrItem item = items[it];
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
-  float ex[R], ey[R];
+  float ex[R], ey[R], ee[R];
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const float2 e = pos[jl + r];
-    ex[r] = e.x;
-    ey[r] = e.y;
+    const float4 e = pos[jl + r];
+    ex[r] = -0.5f * e.x;
+    ey[r] = -0.5f * e.y;
+    ee[r] = e.z;
     acc[r] = 0.0;
   }
   const bool edge = (item.slot_flags & kItemEdge) != 0;
@@ -238,9 +303,9 @@ __global__ void __launch_bounds__(256) k_arrival_far32(const float2* __restrict_
     seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
     if (lo >= hi) continue;
     if (edge)
-      arr_far32_seg<R, true>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+      arr_far32_seg<R, true>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
     else
-      arr_far32_seg<R, false>(M, lo, hi, pos, jl, ex, ey, rows, acc);
+      arr_far32_seg<R, false>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
   }
   double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
 #pragma unroll
@@ -249,15 +314,11 @@ __global__ void __launch_bounds__(256) k_arrival_far32(const float2* __restrict_
 }
 
 template <int R>
-__global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict__ pos,
-                                                       const double* __restrict__ rows,
-                                                       const ArrItem* __restrict__ items, int n_items,
-                                                       int64_t V, DegreeBounds bnd,
-                                                       double* __restrict__ partial) {
-  const int it = blockIdx.x * 4 + wave_id();
-  if (it >= n_items) return;
+__device__ __forceinline__ void do_arrival_far64(const ArrItem& item, const double2* __restrict__ pos,
+                                                 const double* __restrict__ rows, int64_t V,
+                                                 const DegreeBounds& bnd,
+                                                 double* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
-  const ArrItem item = items[it];
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   double ex[R], ey[R], acc[R];
 #pragma unroll
@@ -285,15 +346,11 @@ __global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict
 
 // Near band: per-pair regime choice, every pair masked by causality.
 template <int R, bool MIXED>
-__global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ pos_v,
-                                                      const double* __restrict__ rows64,
-                                                      const float* __restrict__ rows32,
-                                                      const ArrItem* __restrict__ items, int n_items,
-                                                      int64_t V, double* __restrict__ partial) {
-  const int it = blockIdx.x * 4 + wave_id();
-  if (it >= n_items) return;
+__device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void* __restrict__ pos_v,
+                                                const double* __restrict__ rows64,
+                                                const float* __restrict__ rows32, int64_t V,
+                                                double* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
-  const ArrItem item = items[it];
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   double acc[R];
 #pragma unroll
@@ -319,7 +376,7 @@ __global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ p
           const float a = __builtin_fmaf(dy, dy, dx * dx);
           if (a * r32[kR32_C] <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else
+          else if (a * r32[kR32_RHI] <= kCull32Log2)
             acc[r] += phi_general_f64((double)a, r64);
         }
       }
@@ -355,34 +412,63 @@ __global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ p
 // ---------------------------------------------------------------------------
 // Map query.  Pixel pix = tile * 64 R + R lane + r at (X0 + u DX, Y0 + v DY),
 // u = pix % W, v = pix / W, all at the item's time; visit v = K - n.
-template <int M, int R, int U>
-__device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float2* __restrict__ pos,
+// LAT: pixel and probe coordinates are exact small dyadic numbers, so the
+// three-operation a = |e|^2 + |p|^2 - 2 e.p is exact; otherwise a is formed
+// from the differences (relative error ~1e-7, no cancellation).
+template <bool LAT, int R>
+__device__ __forceinline__ float map_a32(const float4& p, const float (&ex)[R], const float (&ey)[R],
+                                         const float (&ee)[R], int r) {
+  if (LAT) return __builtin_fmaf(ex[r], p.x, __builtin_fmaf(ey[r], p.y, ee[r] + p.z));
+  const float dx = __builtin_fmaf(0.5f, p.x, ex[r]), dy = __builtin_fmaf(0.5f, p.y, ey[r]);
+  return __builtin_fmaf(dy, dy, dx * dx);
+}
+
+template <int M, int R, int U, bool LAT>
+__device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float4* __restrict__ pos,
                                           const float* __restrict__ rows, const float (&ex)[R],
-                                          const float (&ey)[R], double (&acc)[R]) {
+                                          const float (&ey)[R], const float (&ee)[R],
+                                          double (&acc)[R]) {
+  using Row = typename RowSel<M>::type;
   int n = lo;
-  for (; n + U <= hi; n += U) {
-    float t[R][U];
+  if (n + U <= hi) {
+    Row cur[U];
+    float4 pc[U];
 #pragma unroll
     for (int s = 0; s < U; ++s) {
-      const float2 p = pos[K - (n + s)];
-      const float* row = rows + (int64_t)(n + s) * kRow32;
+      cur[s] = fetch_row<M>(rows, n + s);
+      pc[s] = pos[K - (n + s)];
+    }
+    for (; n + U <= hi; n += U) {
+      Row nxt[U];
+      float4 pn[U];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float dx = ex[r] - p.x, dy = ey[r] - p.y;
-        t[r][s] = series_f32<M>(__builtin_fmaf(dy, dy, dx * dx), row);
+      for (int s = 0; s < U; ++s) {
+        const int nn = min(n + U + s, hi - 1);
+        nxt[s] = fetch_row<M>(rows, nn);
+        pn[s] = pos[K - nn];
+      }
+      float t[R][U];
+#pragma unroll
+      for (int s = 0; s < U; ++s) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          t[r][s] = series_row32<M>(map_a32<LAT, R>(pc[s], ex, ey, ee, r), cur[s]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<U>(t[r]);
+#pragma unroll
+      for (int s = 0; s < U; ++s) {
+        cur[s] = nxt[s];
+        pc[s] = pn[s];
       }
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<U>(t[r]);
   }
   for (; n < hi; ++n) {
-    const float2 p = pos[K - n];
-    const float* row = rows + (int64_t)n * kRow32;
+    const float4 p = pos[K - n];
+    const Row row = fetch_row<M>(rows, n);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float dx = ex[r] - p.x, dy = ey[r] - p.y;
-      acc[r] += (double)series_f32<M>(__builtin_fmaf(dy, dy, dx * dx), row);
-    }
+    for (int r = 0; r < R; ++r)
+      acc[r] += (double)series_row32<M>(map_a32<LAT, R>(p, ex, ey, ee, r), row);
   }
 }
 
@@ -401,21 +487,20 @@ __device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const doubl
   }
 }
 
-template <int R>
+template <int R, bool LAT>
 __device__ __forceinline__ void map_far32_seg(int M, int lo, int hi, int64_t K,
-                                              const float2* __restrict__ pos,
+                                              const float4* __restrict__ pos,
                                               const float* __restrict__ rows, const float (&ex)[R],
-                                              const float (&ey)[R], double (&acc)[R]) {
+                                              const float (&ey)[R], const float (&ee)[R],
+                                              double (&acc)[R]) {
   switch (M) {
-    case 0: map_far32<0, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 1: map_far32<1, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 2: map_far32<2, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 3: map_far32<3, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 4: map_far32<4, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 5: map_far32<5, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 6: map_far32<6, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    case 7: map_far32<7, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
-    default: map_far32<8, R, 4>(lo, hi, K, pos, rows, ex, ey, acc); break;
+    case 0: map_far32<0, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 1: map_far32<1, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 2: map_far32<2, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 3: map_far32<3, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 4: map_far32<4, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 5: map_far32<5, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    default: map_far32<6, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
   }
 }
 
@@ -436,18 +521,14 @@ __device__ __forceinline__ void map_far64_seg(int M, int lo, int hi, int64_t K,
 }
 
 template <int R, bool MIXED>
-__global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
-                                             const double* __restrict__ rows64,
-                                             const float* __restrict__ rows32,
-                                             const MapItem* __restrict__ items, int n_items,
-                                             const MapTime* __restrict__ times, double X0, double Y0,
-                                             double DX, double DY, int W, int H,
-                                             double* __restrict__ partial) {
-  const int it = blockIdx.x * 4 + wave_id();
-  if (it >= n_items) return;
+__device__ __forceinline__ void do_map(const MapItem& item, const MapTime& tm,
+                                       const void* __restrict__ pos_v,
+                                       const float4* __restrict__ pos4,
+                                       const double* __restrict__ rows64,
+                                       const float* __restrict__ rows32, double X0, double Y0,
+                                       double DX, double DY, int W, int H, bool lattice,
+                                       double* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
-  const MapItem item = items[it];
-  const MapTime tm = times[item.m];
   const int64_t npix = (int64_t)W * H;
   const int64_t p0 = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   double pxd[R], pyd[R], acc[R];
@@ -462,11 +543,12 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
   const float* r32b = rows32 + tm.row_base * kRow32;
   if (MIXED) {
     const float2* pos = (const float2*)pos_v;
-    float ex[R], ey[R];
+    float ex[R], ey[R], ee[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       ex[r] = (float)pxd[r];
       ey[r] = (float)pyd[r];
+      ee[r] = __builtin_fmaf(ey[r], ey[r], ex[r] * ex[r]);
     }
     if (item.near) {
       for (int n = item.n_lo; n < item.n_hi; ++n) {
@@ -479,7 +561,7 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
           const float a = __builtin_fmaf(dy, dy, dx * dx);
           if (a * r32[kR32_C] <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else
+          else if (a * r32[kR32_RHI] <= kCull32Log2)
             acc[r] += phi_general_f64((double)a, r64);
         }
       }
@@ -487,7 +569,11 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
       for (int M = tm.bounds.m_max; M >= 0; --M) {
         int lo, hi;
         seg_range(tm.bounds, M, item.n_lo, item.n_hi, lo, hi);
-        if (lo < hi) map_far32_seg<R>(M, lo, hi, tm.K, pos, r32b, ex, ey, acc);
+        if (lo >= hi) continue;
+        if (lattice)
+          map_far32_seg<R, true>(M, lo, hi, tm.K, pos4, r32b, ex, ey, ee, acc);
+        else
+          map_far32_seg<R, false>(M, lo, hi, tm.K, pos4, r32b, ex, ey, ee, acc);
       }
     }
   } else {
@@ -517,6 +603,97 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
 }
 
 // ---------------------------------------------------------------------------
+// Grid-mapped kernels: wavefront w of block b takes item 4 b + w.
+template <int R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_arrival_far32(const float4* __restrict__ pos,
+                                                       const float* __restrict__ rows,
+                                                       const ArrItem* __restrict__ items, int n_items,
+                                                       int64_t V, DegreeBounds bnd,
+                                                       double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  do_arrival_far32<R>(items[it], pos, rows, V, bnd, partial);
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict__ pos,
+                                                       const double* __restrict__ rows,
+                                                       const ArrItem* __restrict__ items, int n_items,
+                                                       int64_t V, DegreeBounds bnd,
+                                                       double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  do_arrival_far64<R>(items[it], pos, rows, V, bnd, partial);
+}
+
+template <int R, bool MIXED>
+__global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ pos_v,
+                                                      const double* __restrict__ rows64,
+                                                      const float* __restrict__ rows32,
+                                                      const ArrItem* __restrict__ items, int n_items,
+                                                      int64_t V, double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  do_arrival_near<R, MIXED>(items[it], pos_v, rows64, rows32, V, partial);
+}
+
+template <int R, bool MIXED>
+__global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
+                                             const float4* __restrict__ pos4,
+                                             const double* __restrict__ rows64,
+                                             const float* __restrict__ rows32,
+                                             const MapItem* __restrict__ items, int n_items,
+                                             const MapTime* __restrict__ times, double X0, double Y0,
+                                             double DX, double DY, int W, int H, int lattice,
+                                             double* __restrict__ partial) {
+  const int it = blockIdx.x * 4 + wave_id();
+  if (it >= n_items) return;
+  const MapItem item = items[it];
+  do_map<R, MIXED>(item, times[item.m], pos_v, pos4, rows64, rows32, X0, Y0, DX, DY, W, H,
+                   lattice != 0, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel: many scans, one launch.  Each wavefront takes
+// the next item from a device counter until the list is exhausted (every
+// wave reaches that exit).  The items were sorted longest first on the host;
+// each item runs exactly the per-item code of the per-scan kernels, so batch
+// results equal per-scan results bit for bit.
+template <int R, int RN, int RM, bool MIXED>
+__global__ void __launch_bounds__(256) k_batch(const BatchScan* __restrict__ scans,
+                                               const BatchItem* __restrict__ items, int n_items,
+                                               int* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    const BatchScan& S = scans[bi.scan];
+    if (bi.kind == kBatchArrFar) {
+      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
+      if (MIXED)
+        do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
+      else
+        do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds,
+                            S.arr_partial);
+    } else if (bi.kind == kBatchArrNear) {
+      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
+      do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
+    } else {
+      const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask,
+                       bi.kind == kBatchMapNear ? 1 : 0, 0, 0};
+      do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0, 0.0, 1.0, 1.0,
+                        S.nx, S.ny, true, S.map_partial);
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// ---------------------------------------------------------------------------
 // Fixed-order reductions of the partial slots.
 __global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict__ partial,
                                                         const int32_t* __restrict__ tile_slots,
@@ -543,6 +720,30 @@ __global__ void __launch_bounds__(256) k_reduce_map(const double* __restrict__ p
     double s = 0.0;
     for (int k = 0; k < tm.n_slots; ++k) s += partial[(tm.slot_base + k) * npix + pix];
     out[e] = pref * s;
+  }
+}
+
+// One pass over the outputs of a whole batch; entry found by binary search
+// on the output offsets; slots added in the same order as the per-scan
+// reductions.
+__global__ void __launch_bounds__(256) k_reduce_batch(const BatchReduce* __restrict__ reds,
+                                                      int n_red, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_red - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (reds[mid].out_off <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const BatchReduce& Rd = reds[lo];
+    const int64_t j = e - Rd.out_off;
+    const int ns = Rd.tile_slots ? Rd.tile_slots[j / Rd.tile] : Rd.n_slots;
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += Rd.partial[(int64_t)k * Rd.n + j];
+    Rd.out[j] = Rd.pref * s;
   }
 }
 
@@ -594,7 +795,7 @@ hipError_t launch_lag_rows(int64_t n0, int64_t count, double f, double kappa, do
 template <int R>
 static void launch_arrival_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
   if (L.mixed) {
-    hipLaunchKernelGGL((k_arrival_far32<R>), dim3(blocks), dim3(256), 0, st, (const float2*)L.pos,
+    hipLaunchKernelGGL((k_arrival_far32<R>), dim3(blocks), dim3(256), 0, st, L.pos4,
                        L.rows32, L.items, L.n_items, L.V, L.bounds, L.partial);
   } else {
     hipLaunchKernelGGL((k_arrival_far64<R>), dim3(blocks), dim3(256), 0, st,
@@ -636,13 +837,13 @@ hipError_t launch_map(const MapLaunch& L, hipStream_t st) {
   const unsigned blocks = (unsigned)((L.n_items + 3) / 4);
 #define DD_LAUNCH_MAP(RR)                                                                       \
   if (L.mixed)                                                                                  \
-    hipLaunchKernelGGL((k_map<RR, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,     \
-                       L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, L.W, L.H, \
-                       L.partial);                                                              \
+    hipLaunchKernelGGL((k_map<RR, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.pos4,       \
+                       L.rows64, L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, \
+                       L.W, L.H, L.lattice ? 1 : 0, L.partial);                                 \
   else                                                                                          \
-    hipLaunchKernelGGL((k_map<RR, false>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,    \
-                       L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, L.W, L.H, \
-                       L.partial);
+    hipLaunchKernelGGL((k_map<RR, false>), dim3(blocks), dim3(256), 0, st, L.pos, L.pos4,      \
+                       L.rows64, L.rows32, L.items, L.n_items, L.times, L.X0, L.Y0, L.DX, L.DY, \
+                       L.W, L.H, L.lattice ? 1 : 0, L.partial);
   switch (L.R) {
     case 1: DD_LAUNCH_MAP(1) break;
     case 2: DD_LAUNCH_MAP(2) break;
@@ -664,6 +865,38 @@ hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_
                              int64_t npix, double pref, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_map, dim3(grid_for(npix * n_t)), dim3(256), 0, st, partial, times,
                      n_t, npix, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
+                        int* counter, int R, int RN, int RM, bool mixed, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
+  // persistent grid: enough waves to fill the chip a few times over
+  const unsigned blocks = (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
+#define DD_LAUNCH_BATCH(A, B, C)                                                                 \
+  if (R == A && RN == B && RM == C) {                                                            \
+    if (mixed)                                                                                   \
+      hipLaunchKernelGGL((k_batch<A, B, C, true>), dim3(blocks), dim3(256), 0, st, scans, items, \
+                         n_items, counter);                                                      \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_batch<A, B, C, false>), dim3(blocks), dim3(256), 0, st, scans,       \
+                         items, n_items, counter);                                               \
+    return hipGetLastError();                                                                    \
+  }
+  DD_LAUNCH_BATCH(4, 2, 2)
+  DD_LAUNCH_BATCH(2, 2, 1)
+  DD_LAUNCH_BATCH(4, 2, 1)
+  DD_LAUNCH_BATCH(2, 2, 2)
+  DD_LAUNCH_BATCH(4, 4, 2)
+#undef DD_LAUNCH_BATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
+                               hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_batch, dim3(grid_for(total)), dim3(256), 0, st, reds, n_red, total);
   return hipGetLastError();
 }
 

@@ -56,15 +56,19 @@ dd_status dd_scan::prepare(hipStream_t st) {
   const int64_t n = V + 2 * (int64_t)kPosPad;
   std::vector<float2> p32(n, make_float2(0.f, 0.f));
   std::vector<double2> p64(n, make_double2(0.0, 0.0));
+  std::vector<float4> p4(n, make_float4(0.f, 0.f, 0.f, 0.f));
   for (int64_t v = 0; v < V; ++v) {
     const int32_t id = ids[v];
     const double x = id % desc.nx, y = id / desc.nx;
     p32[kPosPad + v] = make_float2((float)x, (float)y);
     p64[kPosPad + v] = make_double2(x, y);
+    p4[kPosPad + v] = make_float4((float)(-2 * x), (float)(-2 * y), (float)(x * x + y * y), 0.f);
   }
   rc = upload(pos32, p32, st);
   if (rc != DD_OK) return rc;
   rc = upload(pos64, p64, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(pos4, p4, st);
   if (rc != DD_OK) return rc;
   dev = cur;
   return DD_OK;
@@ -86,18 +90,47 @@ dd_status build_int_rows(dd_scan* s, hipStream_t st) {
 }
 
 struct ArrivalPlan {
-  int R = 0, K = 0;
+  int R = 0, RN = 0, K = 0;
   bool mixed = false;
   int64_t V = -1;
   int n_near = 0, n_far = 0, S = 0;
   DegreeBounds bounds{};
+  double near_pairs = 0, near_flops = 0, far_pairs = 0, far_flops = 0;
 };
+
+// Causal pairs of an arrival item: sum over visits j in [A, B) of the lags
+// n in [lo, hi) with n <= j.
+double arrival_pairs(int64_t A, int64_t B, int64_t lo, int64_t hi) {
+  if (hi <= lo || B <= A) return 0.0;
+  const double L = (double)(hi - lo);
+  auto S = [L](double x) {  // sum_{u=0}^{x-1} clamp(u, 0, L), x >= 0
+    if (x <= L + 1) return x * (x - 1) / 2;
+    return L * (L + 1) / 2 + (x - L - 1) * L;
+  };
+  const double u0 = std::max<double>(0, (double)(A + 1 - lo));
+  const double u1 = std::max<double>(0, (double)(B - lo));
+  return S(u1) - S(u0);
+}
+
+// Split [lo, hi) by the degree bounds and add up pairs and flops.
+template <typename PairsFn>
+void count_segments(const DegreeBounds& b, int64_t lo, int64_t hi, bool mixed, PairsFn&& pairs,
+                    double& p_out, double& f_out) {
+  for (int M = b.m_max; M >= 0; --M) {
+    const int64_t a = std::max<int64_t>(lo, b.b[M]);
+    const int64_t e = (M == 0) ? hi : std::min<int64_t>(hi, b.b[M - 1]);
+    if (a >= e) continue;
+    const double pr = pairs(a, e);
+    p_out += pr;
+    f_out += pr * series_flops(M, mixed);
+  }
+}
 
 // Plan of the arrival query: tiles of 64R visits; near band lags [1, kf);
 // far chunks of K lags from kf, aligned to R.
-void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
+void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPlan& P,
                   std::vector<ArrItem>& items, std::vector<int32_t>& tile_slots) {
-  const int T = 64 * R;
+  const int T = 64 * R, TN = 64 * RN;
   const int64_t V = s->V;
   const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
                        (double)(s->desc.ny - 1) * (s->desc.ny - 1);
@@ -106,6 +139,7 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
   kf = 1 + (kf - 1 + R - 1) / R * R;
   if (kf > V) kf = V + 1;  // every lag is in the near band
   P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
+  P.near_pairs = P.near_flops = P.far_pairs = P.far_flops = 0;
   const int64_t n_tiles = (V + T - 1) / T;
   std::vector<ArrItem> near, far;
   tile_slots.assign(n_tiles, 1);
@@ -113,8 +147,7 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
   for (int64_t t = 0; t < n_tiles; ++t) {
     const int64_t J0 = t * T;
     const int64_t maxlag = std::min<int64_t>(J0 + T - 1, V - 1);
-    const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
-    near.push_back(ArrItem{(int32_t)t, 1, (int32_t)nhi, 0 | kItemNear});
+    const int64_t jend = std::min<int64_t>(J0 + T, V);
     int c = 0;
     if (maxlag >= kf) {
       const int64_t span_end = kf + (maxlag + 1 - kf + R - 1) / R * R;
@@ -122,10 +155,23 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
         const int64_t hi = std::min<int64_t>(lo + K, span_end);
         const int edge = (hi - 1 > J0) ? kItemEdge : 0;
         far.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)hi, (1 + c) | edge});
+        count_segments(P.bounds, lo, hi, mixed,
+                       [&](int64_t a, int64_t e) { return arrival_pairs(J0, jend, a, e); },
+                       P.far_pairs, P.far_flops);
       }
     }
     tile_slots[t] = 1 + c;
     S = std::max(S, 1 + c);
+  }
+  // near band: tiles of 64 RN visits, lags [1, kf), slot 0
+  for (int64_t t = 0; t < (V + TN - 1) / TN; ++t) {
+    const int64_t J0 = t * TN;
+    const int64_t maxlag = std::min<int64_t>(J0 + TN - 1, V - 1);
+    const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
+    near.push_back(ArrItem{(int32_t)t, 1, (int32_t)nhi, 0 | kItemNear});
+    const double np_ = arrival_pairs(J0, std::min<int64_t>(J0 + TN, V), 1, nhi);
+    P.near_pairs += np_;
+    P.near_flops += np_ * series_flops(mixed ? kMNear32 : kM64, mixed);
   }
   auto longer = [](const ArrItem& a, const ArrItem& b) {
     return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
@@ -135,12 +181,22 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int K, ArrivalPlan& P,
   items = near;
   items.insert(items.end(), far.begin(), far.end());
   P.R = R;
+  P.RN = RN;
   P.K = K;
   P.mixed = mixed;
   P.V = V;
   P.n_near = (int)near.size();
   P.n_far = (int)far.size();
   P.S = S;
+}
+
+// Lags per far work item: the tuned value, raised so that no tile has more
+// than 64 far slots (bounds the partial buffer at 65 V doubles).
+int arrival_K(int64_t V, int R, bool mixed) {
+  int K = mixed ? tune().arr_K_mixed : tune().arr_K_f64;
+  const int64_t need = (V + 63) / 64;
+  if (need > K) K = (int)std::min<int64_t>(need, 1 << 28);
+  return std::max(R, (K + R - 1) / R * R);
 }
 
 struct PlanCache {
@@ -151,16 +207,18 @@ std::map<const dd_scan*, PlanCache> g_plans;  // per handle (handles are not thr
 dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   dd_status rc = s->prepare(st);
   if (rc != DD_OK) return rc;
+  ProfToken tr = prof_begin("lag_rows", st);
   rc = build_int_rows(s, st);
   if (rc != DD_OK) return rc;
+  prof_end(tr, st, 0, 0);
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
-  int K = mixed ? tune().arr_K_mixed : tune().arr_K_f64;
-  K = std::max(R, K / R * R);
+  const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
+  const int K = arrival_K(s->V, R, mixed);
   ArrivalPlan& P = g_plans[s].arr;
-  if (P.V != s->V || P.R != R || P.K != K || P.mixed != mixed) {
+  if (P.V != s->V || P.R != R || P.RN != RN || P.K != K || P.mixed != mixed) {
     std::vector<ArrItem> items;
     std::vector<int32_t> tile_slots;
-    plan_arrival(s, mixed, R, K, P, items, tile_slots);
+    plan_arrival(s, mixed, R, RN, K, P, items, tile_slots);
     rc = upload(s->items, items, st);
     if (rc != DD_OK) return rc;
     rc = upload(s->aux, tile_slots, st);
@@ -170,6 +228,7 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   ArrivalLaunch L{};
   L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
                 : (const void*)(s->pos64.as<double2>() + kPosPad);
+  L.pos4 = s->pos4.as<float4>() + kPosPad;
   L.rows64 = s->rows64.as<double>();
   L.rows32 = s->rows32.as<float>();
   L.V = s->V;
@@ -180,14 +239,22 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   L.items = s->items.as<ArrItem>();
   L.n_items = P.n_near;
   L.near = true;
+  L.R = RN;
+  ProfToken tn = prof_begin("arrival_near", st);
   DD_HIP(launch_arrival(L, st), "arrival near-band launch");
+  prof_end(tn, st, P.near_pairs, P.near_flops);
   L.items = s->items.as<ArrItem>() + P.n_near;
   L.n_items = P.n_far;
   L.near = false;
+  L.R = R;
+  ProfToken tf = prof_begin("arrival_far", st);
   DD_HIP(launch_arrival(L, st), "arrival far-region launch");
+  prof_end(tf, st, P.far_pairs, P.far_flops);
+  ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 64 * R,
                                s->pref, out_dev, st),
          "arrival reduce launch");
+  prof_end(tq, st, 0, 0);
   return DD_OK;
 }
 
@@ -200,26 +267,66 @@ struct MapGroup {
   DegreeBounds bounds;
 };
 
-dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
-                  double* out_dev, hipStream_t st) {
-  dd_status rc = s->prepare(st);
-  if (rc != DD_OK) return rc;
+struct RowJob {
+  int64_t n_first, count, off;
+  double f;
+};
+
+struct MapPlan {
+  std::vector<MapItem> items;     // near items first, each kind longest first
+  std::vector<MapTime> times;
+  std::vector<RowJob> jobs;       // rows to build (none when int_rows is used)
+  int64_t total_rows = 0, slots = 0, npix = 0;
+  double X0 = 0, Y0 = 0, DX = 0, DY = 0;
+  double pairs = 0, flops = 0;
+  int R = 1;
+  bool lattice = false;
+};
+
+// Pixel coordinates (pitch units) are multiples of 2^-q for some q <= 8 and
+// small enough that |e|^2 + |p|^2 stays an exact single-precision value.
+bool grid_is_lattice(double X0, double Y0, double DX, double DY, int w, int h, int nx, int ny) {
+  for (int q = 0; q <= 8; ++q) {
+    const double sc = std::ldexp(1.0, q);
+    bool ok = true;
+    for (double v : {X0, Y0, DX, DY}) ok = ok && std::rint(v * sc) == v * sc;
+    if (!ok) continue;
+    const double ex = std::max(std::fabs(X0), std::fabs(X0 + (w - 1) * DX));
+    const double ey = std::max(std::fabs(Y0), std::fabs(Y0 + (h - 1) * DY));
+    const double pe = (double)(nx - 1) * (nx - 1) + (double)(ny - 1) * (ny - 1);
+    const double bound = (ex * ex + ey * ey + pe) * sc * sc;
+    return bound < 16777216.0 && (ex + nx) * sc < 4096.0 && (ey + ny) * sc < 4096.0;
+  }
+  return false;
+}
+
+// Plans a map query.  With int_rows, every time must lie on a dwell boundary
+// at or before the end of the scan, and rows are taken from the scan's
+// integer-lag table (row n at offset n) instead of a per-call table.
+void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
+              int R, int64_t Kmap, bool int_rows, MapPlan& P) {
   const int64_t npix = (int64_t)g->w * g->h;
   const double p = s->desc.pitch_m;
-  const double X0 = g->x0_m / p, Y0 = g->y0_m / p, DX = g->dx_m / p, DY = g->dy_m / p;
-  const int R = mixed ? tune().map_R_mixed : tune().map_R_f64;
+  P.X0 = g->x0_m / p;
+  P.Y0 = g->y0_m / p;
+  P.DX = g->dx_m / p;
+  P.DY = g->dy_m / p;
+  P.npix = npix;
+  P.R = R;
   const int T = 64 * R;
   const int64_t n_tiles = (npix + T - 1) / T;
   // largest squared distance between any pixel and any probe (bounding boxes)
-  const double xa = X0, xb = X0 + (g->w - 1) * DX, ya = Y0, yb = Y0 + (g->h - 1) * DY;
+  const double xa = P.X0, xb = P.X0 + (g->w - 1) * P.DX, ya = P.Y0, yb = P.Y0 + (g->h - 1) * P.DY;
   const double mx = std::max({std::fabs(xa), std::fabs(xb), std::fabs(xa - (s->desc.nx - 1)),
                               std::fabs(xb - (s->desc.nx - 1))});
   const double my = std::max({std::fabs(ya), std::fabs(yb), std::fabs(ya - (s->desc.ny - 1)),
                               std::fabs(yb - (s->desc.ny - 1))});
   const double a_max = mx * mx + my * my;
   const double thr = mixed ? (double)kThr32 : kThr64;
+  P.lattice = grid_is_lattice(P.X0, P.Y0, P.DX, P.DY, g->w, g->h, s->desc.nx, s->desc.ny);
 
-  std::vector<MapTime> times(n_t);
+  std::vector<MapTime>& times = P.times;
+  times.assign(n_t, MapTime{});
   std::vector<int> tgroup(n_t);
   std::vector<MapGroup> groups;
   std::map<double, int> gid;
@@ -247,48 +354,38 @@ dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, 
     tgroup[m] = gi;
   }
   // Row storage per group; groups whose span is very wide get per-time rows.
-  int64_t total_rows = 0;
-  struct RowJob {
-    int64_t n_first, count, off;
-    double f;
-  };
-  std::vector<RowJob> jobs;
-  std::vector<int64_t> time_off(n_t, -1);
+  P.total_rows = 0;
+  P.jobs.clear();
   for (auto& G : groups) {
     G.kf = first_row_below(thr, a_max, G.f, s->kappa, s->s2, 1, std::max<int64_t>(G.n_last, 1));
     G.bounds = degree_bounds(a_max, G.f, s->kappa, s->s2, G.kf, 1, mixed);
     const int64_t span = std::max<int64_t>(0, G.n_last - G.n_first + 1);
-    if (span <= 4 * s->V + 4096) {
-      G.alloc_off = total_rows;
-      if (span > 0) jobs.push_back(RowJob{G.n_first, span, total_rows, G.f});
-      total_rows += span;
+    if (int_rows) {
+      G.alloc_off = 0;
+    } else if (span <= 4 * s->V + 4096) {
+      G.alloc_off = P.total_rows;
+      if (span > 0) P.jobs.push_back(RowJob{G.n_first, span, P.total_rows, G.f});
+      P.total_rows += span;
     } else {
       G.alloc_off = -1;
     }
   }
   for (int m = 0; m < n_t; ++m) {
     const MapGroup& G = groups[tgroup[m]];
-    if (G.alloc_off >= 0) {
+    if (int_rows) {
+      times[m].row_base = 0;
+    } else if (G.alloc_off >= 0) {
       times[m].row_base = G.alloc_off - G.n_first;
     } else {
       const int64_t span = std::max<int64_t>(0, times[m].K - nlo[m] + 1);
-      times[m].row_base = total_rows - nlo[m];
-      if (span > 0) jobs.push_back(RowJob{nlo[m], span, total_rows, G.f});
-      total_rows += span;
+      times[m].row_base = P.total_rows - nlo[m];
+      if (span > 0) P.jobs.push_back(RowJob{nlo[m], span, P.total_rows, G.f});
+      P.total_rows += span;
     }
     times[m].bounds = G.bounds;
   }
-  DD_HIP(s->maprows64.ensure(sizeof(double) * kRow64 * std::max<int64_t>(total_rows, 1)),
-         "device allocation");
-  DD_HIP(s->maprows32.ensure(sizeof(float) * kRow32 * std::max<int64_t>(total_rows, 1)),
-         "device allocation");
-  for (const RowJob& j : jobs)
-    DD_HIP(launch_lag_rows(j.n_first, j.count, j.f, s->kappa, s->s2, gl_nodes(),
-                           s->maprows64.as<double>() + j.off * kRow64,
-                           s->maprows32.as<float>() + j.off * kRow32, st),
-           "lag-row kernel launch");
   // Items and slots.
-  int64_t Kc = tune().map_K;
+  int64_t Kc = Kmap;
   int64_t far_total = 0;
   for (int m = 0; m < n_t; ++m) {
     const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
@@ -299,6 +396,7 @@ dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, 
   while (far_total / Kc + n_t > cap_slots) Kc *= 2;
   std::vector<MapItem> near, far;
   int64_t slot_base = 0;
+  P.pairs = P.flops = 0;
   for (int m = 0; m < n_t; ++m) {
     const int64_t K = times[m].K;
     const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
@@ -306,44 +404,78 @@ dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, 
     int c = 0;
     for (int64_t t = 0; t < n_tiles; ++t)
       near.push_back(MapItem{(int32_t)t, m, (int32_t)nlo[m], (int32_t)near_hi, 0, 1, 0, 0});
+    P.pairs += (double)npix * (double)(near_hi - nlo[m]);
+    P.flops += (double)npix * (double)(near_hi - nlo[m]) *
+               series_flops(mixed ? kMNear32 : kM64, mixed);
     for (int64_t lo = std::max(kf, nlo[m]); lo <= K; lo += Kc, ++c) {
       const int64_t hi = std::min<int64_t>(lo + Kc, K + 1);
       for (int64_t t = 0; t < n_tiles; ++t)
         far.push_back(MapItem{(int32_t)t, m, (int32_t)lo, (int32_t)hi, 1 + c, 0, 0, 0});
+      count_segments(times[m].bounds, lo, hi, mixed,
+                     [&](int64_t a, int64_t e) { return (double)npix * (double)(e - a); },
+                     P.pairs, P.flops);
     }
     times[m].slot_base = slot_base;
     times[m].n_slots = 1 + c;
     slot_base += 1 + c;
   }
+  P.slots = slot_base;
   auto longer = [](const MapItem& a, const MapItem& b) {
     return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
   };
   std::stable_sort(near.begin(), near.end(), longer);
   std::stable_sort(far.begin(), far.end(), longer);
-  std::vector<MapItem> items = near;
-  items.insert(items.end(), far.begin(), far.end());
-  rc = upload(s->aux2, items, st);
+  P.items = near;
+  P.items.insert(P.items.end(), far.begin(), far.end());
+}
+
+dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
+                  double* out_dev, hipStream_t st) {
+  dd_status rc = s->prepare(st);
   if (rc != DD_OK) return rc;
-  rc = upload(s->aux3, times, st);
+  const int R = mixed ? tune().map_R_mixed : tune().map_R_f64;
+  MapPlan P;
+  plan_map(s, g, t_s, n_t, mixed, R, tune().map_K, false, P);
+  DD_HIP(s->maprows64.ensure(sizeof(double) * kRow64 * std::max<int64_t>(P.total_rows, 1)),
+         "device allocation");
+  DD_HIP(s->maprows32.ensure(sizeof(float) * kRow32 * std::max<int64_t>(P.total_rows, 1)),
+         "device allocation");
+  ProfToken trw = prof_begin("lag_rows", st);
+  for (const RowJob& j : P.jobs)
+    DD_HIP(launch_lag_rows(j.n_first, j.count, j.f, s->kappa, s->s2, gl_nodes(),
+                           s->maprows64.as<double>() + j.off * kRow64,
+                           s->maprows32.as<float>() + j.off * kRow32, st),
+           "lag-row kernel launch");
+  prof_end(trw, st, 0, 0);
+  rc = upload(s->aux2, P.items, st);
   if (rc != DD_OK) return rc;
-  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)slot_base * (size_t)npix), "device allocation");
+  rc = upload(s->aux3, P.times, st);
+  if (rc != DD_OK) return rc;
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.slots * (size_t)P.npix),
+         "device allocation");
   MapLaunch L{};
   L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
                 : (const void*)(s->pos64.as<double2>() + kPosPad);
+  L.pos4 = s->pos4.as<float4>() + kPosPad;
+  L.lattice = P.lattice;
   L.rows64 = s->maprows64.as<double>();
   L.rows32 = s->maprows32.as<float>();
   L.items = s->aux2.as<MapItem>();
-  L.n_items = (int32_t)items.size();
+  L.n_items = (int32_t)P.items.size();
   L.times = s->aux3.as<MapTime>();
-  L.X0 = X0; L.Y0 = Y0; L.DX = DX; L.DY = DY;
+  L.X0 = P.X0; L.Y0 = P.Y0; L.DX = P.DX; L.DY = P.DY;
   L.W = g->w; L.H = g->h;
   L.partial = s->partial.as<double>();
   L.R = R;
   L.mixed = mixed;
+  ProfToken tm = prof_begin("map", st);
   DD_HIP(launch_map(L, st), "map launch");
-  DD_HIP(launch_reduce_map(s->partial.as<double>(), s->aux3.as<MapTime>(), n_t, npix, s->pref,
+  prof_end(tm, st, P.pairs, P.flops);
+  ProfToken tq = prof_begin("reduce", st);
+  DD_HIP(launch_reduce_map(s->partial.as<double>(), s->aux3.as<MapTime>(), n_t, P.npix, s->pref,
                            out_dev, st),
          "map reduce launch");
+  prof_end(tq, st, 0, 0);
   return DD_OK;
 }
 
@@ -357,6 +489,162 @@ dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStrea
   if (n) DD_HIP(hipMemcpyAsync(out, s->tmp_out.p, sizeof(double) * n, hipMemcpyDeviceToHost, st),
                 "device-to-host copy");
   DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return DD_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched solve: every scan's arrival and final-map items in one persistent
+// launch, then one fixed-order reduction launch.
+struct BatchScratch {
+  DevBuf scans, items, reds, slots, partial, counter, staging;
+};
+static thread_local BatchScratch g_batch;
+
+dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
+                    double* const* outs, int32_t on_device, hipStream_t st) {
+  const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
+  const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
+  const int RM = mixed ? tune().map_R_mixed : tune().map_R_f64;
+  const bool want_arr = (mask & DD_Q_ARRIVAL) != 0, want_map = (mask & DD_Q_FINAL_AT_PROBES) != 0;
+  std::vector<BatchScan> bs(n);
+  std::vector<BatchItem> items;
+  std::vector<BatchReduce> reds;
+  std::vector<int32_t> all_slots;
+  std::vector<int64_t> arr_off(n, 0), map_off(n, 0), slot_off(n, 0), out_off(n, 0);
+  int64_t partial_total = 0, out_total = 0;
+  double pairs = 0, flops = 0;
+  ProfToken trw = prof_begin("lag_rows", st);
+  for (int32_t k = 0; k < n; ++k) {
+    dd_scan* s = scans[k];
+    dd_status rc = s->prepare(st);
+    if (rc != DD_OK) return rc;
+    rc = build_int_rows(s, st);
+    if (rc != DD_OK) return rc;
+  }
+  prof_end(trw, st, 0, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    dd_scan* s = scans[k];
+    BatchScan& B = bs[k];
+    B.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
+                  : (const void*)(s->pos64.as<double2>() + kPosPad);
+    B.pos4 = s->pos4.as<float4>() + kPosPad;
+    B.rows64 = s->rows64.as<double>();
+    B.rows32 = s->rows32.as<float>();
+    B.V = s->V;
+    B.nx = s->desc.nx;
+    B.ny = s->desc.ny;
+    out_off[k] = out_total;
+    if (want_arr) {
+      ArrivalPlan AP;
+      std::vector<ArrItem> ai;
+      std::vector<int32_t> ts;
+      plan_arrival(s, mixed, R, RN, arrival_K(s->V, R, mixed), AP, ai, ts);
+      B.arr_bounds = AP.bounds;
+      arr_off[k] = partial_total;
+      partial_total += (int64_t)AP.S * s->V;
+      slot_off[k] = (int64_t)all_slots.size();
+      all_slots.insert(all_slots.end(), ts.begin(), ts.end());
+      const double near_w = mixed ? 6.0 : 3.0;  // relative cost of a near pair
+      for (size_t q = 0; q < ai.size(); ++q) {
+        const ArrItem& a = ai[q];
+        const bool near_item = (int)q < AP.n_near;
+        const double cost =
+            (double)(a.n_hi - a.n_lo) * 64.0 * (near_item ? RN * near_w : R);
+        const int64_t c = (int64_t)cost;
+        items.push_back(BatchItem{k, near_item ? kBatchArrNear : kBatchArrFar, a.tile, a.n_lo,
+                                  a.n_hi, a.slot_flags, (int32_t)(c >> 31),
+                                  (int32_t)(c & 0x7fffffff)});
+      }
+      reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref});
+      out_total += s->V;
+      pairs += AP.near_pairs + AP.far_pairs;
+      flops += AP.near_flops + AP.far_flops;
+    }
+    if (want_map) {
+      dd_grid g{0.0, 0.0, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx, s->desc.ny};
+      const double t_end = (double)s->V * s->tau_v;
+      MapPlan MP;
+      plan_map(s, &g, &t_end, 1, mixed, RM, tune().map_K, true, MP);
+      B.map_time = MP.times[0];
+      map_off[k] = partial_total;
+      partial_total += MP.slots * MP.npix;
+      const double near_w = mixed ? 6.0 : 3.0;
+      for (const MapItem& m : MP.items) {
+        const int64_t tile_pix = std::min<int64_t>(64 * RM, MP.npix - (int64_t)m.tile * 64 * RM);
+        const double cost = (double)(m.n_hi - m.n_lo) * tile_pix * (m.near ? near_w : 1.0);
+        const int64_t c = (int64_t)cost;
+        items.push_back(BatchItem{k, m.near ? kBatchMapNear : kBatchMapFar, m.tile, m.n_lo, m.n_hi,
+                                  m.slot, (int32_t)(c >> 31), (int32_t)(c & 0x7fffffff)});
+      }
+      reds.push_back(BatchReduce{nullptr, nullptr, MP.times[0].n_slots, 0, MP.npix, out_total,
+                                 nullptr, s->pref});
+      out_total += MP.npix;
+      pairs += MP.pairs;
+      flops += MP.flops;
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) {
+    const int64_t ca = ((int64_t)a.cost_hi << 31) | a.cost_lo;
+    const int64_t cb = ((int64_t)b.cost_hi << 31) | b.cost_lo;
+    return ca > cb;
+  });
+  BatchScratch& W = g_batch;
+  DD_HIP(W.partial.ensure(sizeof(double) * (size_t)std::max<int64_t>(partial_total, 1)),
+         "device allocation");
+  double* part = W.partial.as<double>();
+  DD_HIP(W.slots.ensure(sizeof(int32_t) * std::max<size_t>(all_slots.size(), 1)),
+         "device allocation");
+  if (!on_device) DD_HIP(W.staging.ensure(sizeof(double) * (size_t)std::max<int64_t>(out_total, 1)),
+                         "device allocation");
+  {
+    size_t r = 0;
+    for (int32_t k = 0; k < n; ++k) {
+      double* o = on_device ? outs[k] : W.staging.as<double>() + out_off[k];
+      if (want_arr) {
+        bs[k].arr_partial = part + arr_off[k];
+        reds[r].partial = bs[k].arr_partial;
+        reds[r].tile_slots = W.slots.as<int32_t>() + slot_off[k];
+        reds[r].out = o;
+        o += scans[k]->V;
+        ++r;
+      }
+      if (want_map) {
+        bs[k].map_partial = part + map_off[k];
+        reds[r].partial = bs[k].map_partial;
+        reds[r].out = o;
+        ++r;
+      }
+    }
+  }
+  dd_status rc = upload(W.scans, bs, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(W.items, items, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(W.reds, reds, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(W.slots, all_slots, st);
+  if (rc != DD_OK) return rc;
+  DD_HIP(W.counter.ensure(sizeof(int)), "device allocation");
+  ProfToken tb = prof_begin("batch", st);
+  DD_HIP(launch_batch(W.scans.as<BatchScan>(), W.items.as<BatchItem>(), (int32_t)items.size(),
+                      W.counter.as<int>(), R, RN, RM, mixed, st),
+         "batched launch");
+  prof_end(tb, st, pairs, flops);
+  ProfToken tq = prof_begin("reduce", st);
+  DD_HIP(launch_reduce_batch(W.reds.as<BatchReduce>(), (int32_t)reds.size(), out_total, st),
+         "batched reduce launch");
+  prof_end(tq, st, 0, 0);
+  if (!on_device) {
+    for (int32_t k = 0; k < n; ++k) {
+      const int64_t len = (k + 1 < n ? out_off[k + 1] : out_total) - out_off[k];
+      if (len > 0)
+        DD_HIP(hipMemcpyAsync(outs[k], W.staging.as<double>() + out_off[k], sizeof(double) * len,
+                              hipMemcpyDeviceToHost, st),
+               "device-to-host copy");
+    }
+    DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  }
   return DD_OK;
 }
 
@@ -399,24 +687,8 @@ dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, 
   if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
   for (int32_t k = 0; k < n; ++k)
     if (!scans[k] || !outs[k]) return fail(DD_EINVAL, "scan %d or its output is NULL", k);
-  hipStream_t st = (hipStream_t)hip_stream;
-  for (int32_t k = 0; k < n; ++k) {
-    dd_scan* s = scans[k];
-    double* o = outs[k];
-    if (query_mask & DD_Q_ARRIVAL) {
-      dd_status rc = dd_damage_at_probe_arrival(s, p, o, out_on_device, hip_stream);
-      if (rc != DD_OK) return rc;
-      o += s->V;
-    }
-    if (query_mask & DD_Q_FINAL_AT_PROBES) {
-      dd_grid g{0.0, 0.0, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx, s->desc.ny};
-      const double t_end = (double)s->V * s->tau_v;
-      dd_status rc = dd_damage_map(s, &g, &t_end, 1, p, o, out_on_device, hip_stream);
-      if (rc != DD_OK) return rc;
-    }
-  }
-  (void)st;
-  return DD_OK;
+  return run_batch(scans, n, query_mask, p == DD_MIXED, outs, out_on_device,
+                   (hipStream_t)hip_stream);
 }
 
 dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double* a,

@@ -24,6 +24,23 @@ int64_t first_row_below(double thr, double a_max, double f, double kappa, double
 DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
                            bool mixed);
 
+// Kernel timing (dd_profiling / dd_profile_read): events around a launch on
+// the stream it runs on, plus the launch's algorithmic work.
+struct ProfToken {
+  int slot = -1;
+};
+ProfToken prof_begin(const char* kernel, hipStream_t st);
+void prof_end(ProfToken tok, hipStream_t st, double pairs, double flops);
+
+// Floating-point operations per pair of the evaluation form used (FMA = 2):
+// mixed degree <= 3 (powers of a, folded correction) 15 + 2M, mixed degree
+// >= 4 (powers of dx, exact correction) 17 + 2M, FP64 40 + 2M (13-term
+// exp polynomial).
+inline double series_flops(int M, bool mixed) {
+  if (!mixed) return 40.0 + 2.0 * M;
+  return (M <= kMaxA ? 15.0 : 17.0) + 2.0 * M;
+}
+
 // A grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
@@ -53,7 +70,8 @@ struct DevBuf {
 
 // Tile-shape choices (autotuned; defaults otherwise).
 struct TuneParams {
-  int arr_R_mixed = 4, arr_R_f64 = 2;
+  int arr_R_mixed = 4, arr_R_f64 = 2;      // far-region tile: 64 R visits
+  int arr_RN_mixed = 2, arr_RN_f64 = 2;    // near-band tile
   int arr_K_mixed = 2048, arr_K_f64 = 1024;   // lags per far work item
   int map_R_mixed = 2, map_R_f64 = 1;
   int map_K = 4096;
@@ -70,13 +88,13 @@ struct dd_scan {
 
   // Device state (created on first query, on the then-current device).
   int dev = -1;
-  dd::DevBuf pos32, pos64;          // padded probe positions by visit
+  dd::DevBuf pos32, pos64, pos4;    // padded probe positions by visit
   dd::DevBuf rows64, rows32;        // integer-lag rows n = 0 .. n_rows-1
   int64_t n_rows = 0;
   dd::DevBuf partial, items, aux, aux2, aux3, tmp_out, maprows64, maprows32;
 
   void release_device() {
-    for (dd::DevBuf* b : {&pos32, &pos64, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,
+    for (dd::DevBuf* b : {&pos32, &pos64, &pos4, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,
                           &tmp_out, &maprows64, &maprows32})
       b->release();
     n_rows = 0;

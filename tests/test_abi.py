@@ -74,7 +74,7 @@ def test_explicit_order_copied(dd):
     dict(nx=4, ny=4, order="multiframe", frames=0),
     dict(nx=2, ny=2, order="explicit", visits=[0, 4]),
     dict(nx=2, ny=2, order="explicit", visits=[0, -1]),
-    dict(nx=5000, ny=2),
+    dict(nx=3000, ny=2),
 ])
 def test_invalid_descriptions(dd, kw):
     nx, ny = kw.pop("nx"), kw.pop("ny")

@@ -1,0 +1,78 @@
+"""Batched persistent solve: equal, bit for bit, to the per-scan calls, and
+within tolerance of the oracle on sampled scans of the batched configuration
+(256 scans of side 16..256, four orders, D, dwell and sigma sampled)."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_close, oracle_scan
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_00294_amd as dd
+
+    dd.load_library()
+    return dd
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_2507_00294_amd import workloads
+
+    return workloads
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_equals_per_scan(dd, wl, prec):
+    specs = wl.batch_scans(12, seed=41, side_lo=9, side_hi=70)
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    outs = dd.batch_solve(scans, dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES, prec)
+    for s, o in zip(scans, outs):
+        o = o.cpu().numpy()
+        arr = s.arrival(prec).cpu().numpy()
+        fin = s.final_at_probes(prec).cpu().numpy().ravel()
+        assert np.array_equal(o[:s.num_visits], arr)
+        assert np.array_equal(o[s.num_visits:], fin)
+    # single queries
+    only = dd.batch_solve(scans[:3], dd.Q_FINAL_AT_PROBES, prec)
+    for s, o in zip(scans[:3], only):
+        assert np.array_equal(o.cpu().numpy(), s.final_at_probes(prec).cpu().numpy().ravel())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_small_vs_oracle(dd, ora, wl, prec):
+    specs = wl.batch_scans(8, seed=43, side_lo=5, side_hi=24)
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    outs = dd.batch_solve(scans, dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES, prec)
+    for spec, s, o in zip(specs, scans, outs):
+        o = o.cpu().numpy()
+        ora_s = oracle_scan(ora, spec, s.visits())
+        assert_close(o[:s.num_visits], ora_s.psi_arrival(), spec, prec, f"batch arrival {spec.order}")
+        fin = ora_s.psi_map(0.0, 0.0, spec.pitch_m, spec.pitch_m, spec.nx, spec.ny,
+                            [spec.n_visits * spec.tau_v])[0].ravel()
+        assert_close(o[s.num_visits:], fin, spec, prec, f"batch final {spec.order}")
+
+
+def test_batched_configuration_sampled(dd, ora, wl):
+    """All 256 scans in one call (mixed), 16 of them checked on samples."""
+    specs = wl.batch_scans()
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    outs = dd.batch_solve(scans, dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES, "mixed")
+    rng = np.random.default_rng(17)
+    for k in rng.choice(len(specs), size=16, replace=False):
+        spec, s, o = specs[k], scans[k], outs[k].cpu().numpy()
+        ora_s = oracle_scan(ora, spec, s.visits())
+        idx = wl.sampled_visits(spec.n_visits, 6, seed=int(k))
+        assert_close(o[idx], ora_s.psi_arrival(idx), spec, "mixed", f"scan {k} arrival")
+        pix = rng.choice(spec.nx * spec.ny, size=6, replace=False)
+        x = (pix % spec.nx) * spec.pitch_m
+        y = (pix // spec.nx) * spec.pitch_m
+        t = np.full(pix.size, spec.n_visits * spec.tau_v)
+        assert_close(o[spec.n_visits + pix], ora_s.psi_points(x, y, t), spec, "mixed",
+                     f"scan {k} final")
