@@ -25,11 +25,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pair E1-terms/s at oracle-matched accuracy; surrogate speedup @≤1% L2 err"
+# HBM bytes of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# valid only while the device sources hash to the recorded value.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_arrival_far32_traffic.txt")
+DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip")
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X FP32 / FP64 vector peaks
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def device_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_00294_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(precision, side):
+    """Bytes per launch from the committed counter record, or None when the
+    kernel sources changed since the counters were taken."""
+    if precision != "mixed" or side != 512 or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = {}
+    with open(TRAFFIC_RECORD) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("source_sha256") != device_source_hash():
+        return None
+    return float(rec["fetch_bytes"]) + float(rec["write_bytes"])
 
 
 def time_query(scan, prec, out, steps, warmup, dd, torch):
@@ -107,7 +137,8 @@ def main():
     roofline = {
         "bound": "alu", "kernel": "k_arrival_far32" if prec == "mixed" else "k_arrival_far64",
         "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None,
+        "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+        "traffic": recorded_traffic(prec, args.side),
         "avg_launch_ms": round(far_ms, 4),
         "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
         "flops_per_launch": far_flops,

@@ -1,0 +1,114 @@
+// dd_batch.hip -- the persistent batched kernel of libdd (many scans in one
+// launch) and its fixed-order reduction.
+#include <algorithm>
+
+#include "dd_items.h"
+#include "dd_kernels.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Persistent batched kernel: many scans, one launch.  Each wavefront takes
+// the next item from a device counter until the list is exhausted (every
+// wave reaches that exit).  The items were sorted longest first on the host;
+// each item runs exactly the per-item code of the per-scan kernels, so batch
+// results equal per-scan results bit for bit.
+template <int R, int RN, int RM, bool MIXED>
+__global__ void __launch_bounds__(256) k_batch(const BatchScan* __restrict__ scans,
+                                               const BatchItem* __restrict__ items, int n_items,
+                                               int* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    const BatchScan& S = scans[bi.scan];
+    if (bi.kind == kBatchArrFar) {
+      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
+      if (MIXED)
+        do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
+      else
+        do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds,
+                            S.arr_partial);
+    } else if (bi.kind == kBatchArrNear) {
+      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
+      do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
+    } else {
+      const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask,
+                       bi.kind == kBatchMapNear ? 1 : 0, 0, 0};
+      do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0, 0.0, 1.0, 1.0,
+                        S.nx, S.ny, true, S.map_partial);
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// One pass over the outputs of a whole batch; entry found by binary search
+// on the output offsets; slots added in the same order as the per-scan
+// reductions.
+__global__ void __launch_bounds__(256) k_reduce_batch(const BatchReduce* __restrict__ reds,
+                                                      int n_red, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_red - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (reds[mid].out_off <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const BatchReduce& Rd = reds[lo];
+    const int64_t j = e - Rd.out_off;
+    const int ns = Rd.tile_slots ? Rd.tile_slots[j / Rd.tile] : Rd.n_slots;
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += Rd.partial[(int64_t)k * Rd.n + j];
+    Rd.out[j] = Rd.pref * s;
+  }
+}
+
+static inline unsigned batch_grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
+                        int* counter, int R, int RN, int RM, bool mixed, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
+  // persistent grid: enough waves to fill the chip a few times over
+  const unsigned blocks = (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
+#define DD_LAUNCH_BATCH(A, B, C)                                                                 \
+  if (R == A && RN == B && RM == C) {                                                            \
+    if (mixed)                                                                                   \
+      hipLaunchKernelGGL((k_batch<A, B, C, true>), dim3(blocks), dim3(256), 0, st, scans, items, \
+                         n_items, counter);                                                      \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_batch<A, B, C, false>), dim3(blocks), dim3(256), 0, st, scans,       \
+                         items, n_items, counter);                                               \
+    return hipGetLastError();                                                                    \
+  }
+  // every tile shape the autotuner may choose: R, RN in {2, 4}, RM in {1, 2}
+  DD_LAUNCH_BATCH(4, 2, 2)
+  DD_LAUNCH_BATCH(4, 2, 1)
+  DD_LAUNCH_BATCH(4, 4, 2)
+  DD_LAUNCH_BATCH(4, 4, 1)
+  DD_LAUNCH_BATCH(2, 2, 2)
+  DD_LAUNCH_BATCH(2, 2, 1)
+  DD_LAUNCH_BATCH(2, 4, 2)
+  DD_LAUNCH_BATCH(2, 4, 1)
+#undef DD_LAUNCH_BATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
+                               hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_batch, dim3(batch_grid_for(total)), dim3(256), 0, st, reds, n_red, total);
+  return hipGetLastError();
+}
+
+}  // namespace dd

@@ -21,76 +21,10 @@
 // per lag segment, so the inner loop has no branches.  Partial sums of work
 // items go to fixed slots and are added in a fixed order (bitwise
 // reproducible, no floating-point atomics).
-#include <type_traits>
-
-#include "dd_device.h"
+#include "dd_items.h"
 #include "dd_kernels.h"
 
 namespace dd {
-
-// ---------------------------------------------------------------------------
-// Lag rows (see dd_internal.h for the series).  J_m(w) by 24-node
-// Gauss-Legendre on [0, 1] when w <= 1 (the integrand's pole at u = -1/w is at
-// least 1 away), by the forward recurrence J_{m+1} = (1/(m+1) - J_m) / w when
-// w > 1 (errors shrink by 1/w per step).
-__device__ void make_row(double lam, double kappa, double s2, const GLNodes& gl, double* r64,
-                         float* r32) {
-  if (!(lam > 0.0)) {
-    for (int k = 0; k < kRow64; ++k) r64[k] = 0.0;
-    for (int k = 0; k < kRow32; ++k) r32[k] = 0.0f;
-    return;
-  }
-  const double db = 4.0 * kappa * fmin(lam, 1.0);
-  const double b0 = s2 + 4.0 * kappa * fmax(lam - 1.0, 0.0);
-  const double b1 = b0 + db;
-  const double w = db / b0;
-  const double rb1 = 1.0 / b1, rb0 = 1.0 / b0;
-  const double c = db / (b0 * b1);
-  double J[kM64 + 1];
-  if (w <= 1.0) {
-    for (int m = 0; m <= kM64; ++m) J[m] = 0.0;
-    for (int k = 0; k < kGL; ++k) {
-      const double u = gl.x[k];
-      double f = gl.w[k] / (1.0 + w * u);
-      for (int m = 0; m <= kM64; ++m) {
-        J[m] += f;
-        f *= u;
-      }
-    }
-  } else {
-    J[0] = log1p(w) / w;
-    for (int m = 0; m < kM64; ++m) J[m + 1] = (1.0 / (m + 1) - J[m]) / w;
-  }
-  double P[kM64 + 1];
-  P[0] = log1p(w);
-  double inv_fact = 1.0;
-  for (int m = 1; m <= kM64; ++m) {
-    inv_fact /= m;
-    P[m] = ((m & 1) ? -1.0 : 1.0) * w * J[m] * inv_fact;
-  }
-  const double rl2 = rb1 * kLog2e;
-  r64[kR64_RB1] = rb1;
-  r64[kR64_RB0] = rb0;
-  r64[kR64_C] = c;
-  r64[kR64_RL2] = rl2;
-  for (int m = 0; m <= kM64; ++m) r64[kR64_P + m] = P[m];
-  for (int k = kR64_P + kM64 + 1; k < kRow64; ++k) r64[k] = 0.0;
-  const float rhi = (float)rl2;
-  const float rlo = (float)(rl2 - (double)rhi);
-  r32[kR32_RHI] = rhi;
-  r32[kR32_P0] = (float)P[0];
-  double cm = 1.0;
-  for (int m = 1; m <= kMaxA; ++m) {
-    cm *= c;
-    r32[kR32_PA + m - 1] = (float)(P[m] * cm + (m == 1 ? -kLn2 * P[0] * (double)rlo : 0.0));
-  }
-  r32[kR32_P0N] = (float)(-kLn2 * P[0]);
-  r32[kR32_P0NR] = (float)(-kLn2 * P[0] * (double)rlo);
-  r32[kR32_C] = (float)c;
-  r32[kR32_RLO] = rlo;
-  for (int m = 1; m <= kM32; ++m) r32[kR32_P1 + m - 1] = (float)P[m];
-  for (int k = kR32_P1 + kM32; k < kRow32; ++k) r32[k] = 0.0f;
-}
 
 __global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, double f, double kappa,
                                                   double s2, GLNodes gl, double* __restrict__ rows64,
@@ -99,507 +33,6 @@ __global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, dou
        k += (int64_t)gridDim.x * blockDim.x) {
     make_row(f + (double)(n0 + k), kappa, s2, gl, rows64 + k * kRow64, rows32 + k * kRow32);
   }
-}
-
-// ---------------------------------------------------------------------------
-// Small helpers.
-template <int R>
-__device__ __forceinline__ float pairwise_sum(const float (&t)[R]) {
-  if constexpr (R == 1) {
-    return t[0];
-  } else if constexpr (R == 2) {
-    return t[0] + t[1];
-  } else if constexpr (R == 4) {
-    return (t[0] + t[1]) + (t[2] + t[3]);
-  } else {
-    static_assert(R == 8, "R must be 1, 2, 4 or 8");
-    return ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
-  }
-}
-
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// ---------------------------------------------------------------------------
-// Arrival query, far region, mixed precision.  Lags [lo, hi) with
-// (hi - lo) % R == 0; window W[q] holds the probe of visit jl - n0 - (R-1) + q
-// as (-2x, -2y, x^2 + y^2), so that a = |e|^2 + |p|^2 - 2 e.p takes three
-// exact FP32 operations (lattice coordinates below 2048).  For degrees <= 3
-// the rows of the next R lags are fetched (scalar loads) while the current R
-// lags are evaluated.
-template <int M>
-struct RowSel {
-  // degree <= 3: the 8 bulk fields; higher degrees read the row in place
-  using type = typename std::conditional<(M <= kMaxA), RowA, const float*>::type;
-};
-
-template <int M>
-__device__ __forceinline__ typename RowSel<M>::type fetch_row(const float* __restrict__ rows,
-                                                              int64_t n) {
-  if constexpr (M <= kMaxA)
-    return load_rowa(rows + n * kRow32);
-  else
-    return rows + n * kRow32;
-}
-
-template <int M>
-__device__ __forceinline__ float series_row32(float a, const typename RowSel<M>::type& row) {
-  if constexpr (M <= kMaxA)
-    return series_f32a<M>(a, row);
-  else
-    return series_f32<M>(a, row);
-}
-
-// One chunk of R lags n0 .. n0+R-1 against window W (see arr_far32); the R
-// terms of each evaluation point are summed in FP32 by fused multiply-adds
-// (R roundings) and then added to its FP64 accumulator.
-template <int M, int R, bool EDGE>
-__device__ __forceinline__ void arr_chunk32(int n0, int64_t jl, const float4 (&W)[2 * R - 1],
-                                            const float (&ex)[R], const float (&ey)[R],
-                                            const float (&ee)[R],
-                                            const typename RowSel<M>::type (&row)[R],
-                                            double (&acc)[R]) {
-  float part[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float4 p = W[r - s + R - 1];
-      const float a = __builtin_fmaf(ex[r], p.x, __builtin_fmaf(ey[r], p.y, ee[r] + p.z));
-      float v = series_row32<M>(a, row[s]);
-      if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0f;
-      part[r] = (s == 0) ? v : part[r] + v;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
-}
-
-template <int M, int R, bool EDGE>
-__device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restrict__ pos, int64_t jl,
-                                          const float (&ex)[R], const float (&ey)[R],
-                                          const float (&ee)[R], const float* __restrict__ rows,
-                                          double (&acc)[R]) {
-  using Row = typename RowSel<M>::type;
-  // Two windows alternate so that sliding by R visits needs no register
-  // moves: A covers the chunk at n0, B the chunk at n0 + R.
-  float4 A[2 * R - 1], B[2 * R - 1];
-#pragma unroll
-  for (int q = 0; q < 2 * R - 1; ++q) A[q] = pos[jl - lo - (R - 1) + q];
-  Row cur[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, lo + s);
-  int n0 = lo;
-  for (; n0 + 2 * R <= hi; n0 += 2 * R) {
-    Row nxt[R];
-#pragma unroll
-    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M>(rows, n0 + R + s);
-#pragma unroll
-    for (int q = R; q < 2 * R - 1; ++q) B[q] = A[q - R];
-    const int64_t b1 = jl - (n0 + R) - (R - 1);
-#pragma unroll
-    for (int q = 0; q < R; ++q) B[q] = pos[b1 + q];
-    arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);
-#pragma unroll
-    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, min(n0 + 2 * R + s, hi - 1));
-#pragma unroll
-    for (int q = R; q < 2 * R - 1; ++q) A[q] = B[q - R];
-    const int64_t b2 = jl - (n0 + 2 * R) - (R - 1);
-#pragma unroll
-    for (int q = 0; q < R; ++q) A[q] = pos[b2 + q];
-    arr_chunk32<M, R, EDGE>(n0 + R, jl, B, ex, ey, ee, nxt, acc);
-  }
-  if (n0 < hi) arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);  // one chunk left
-}
-
-template <int M, int R, bool EDGE>
-__device__ __forceinline__ void arr_far64(int lo, int hi, const double2* __restrict__ pos, int64_t jl,
-                                          const double (&ex)[R], const double (&ey)[R],
-                                          const double* __restrict__ rows, double (&acc)[R]) {
-  double2 W[2 * R - 1];
-#pragma unroll
-  for (int q = 0; q < 2 * R - 1; ++q) W[q] = pos[jl - lo - (R - 1) + q];
-  for (int n0 = lo; n0 < hi; n0 += R) {
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const double* row = rows + (int64_t)(n0 + s) * kRow64;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double2 p = W[r - s + R - 1];
-        const double dx = ex[r] - p.x, dy = ey[r] - p.y;
-        const double a = fma(dy, dy, dx * dx);
-        double v = series_f64<M>(a, row);
-        if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0;
-        acc[r] += v;
-      }
-    }
-#pragma unroll
-    for (int q = 2 * R - 2; q >= R; --q) W[q] = W[q - R];
-    const int64_t base = jl - (n0 + R) - (R - 1);
-#pragma unroll
-    for (int q = 0; q < R; ++q) W[q] = pos[base + q];
-  }
-}
-
-// Degree dispatch for one segment (uniform branch).
-template <int R, bool EDGE>
-__device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float4* __restrict__ pos,
-                                              int64_t jl, const float (&ex)[R], const float (&ey)[R],
-                                              const float (&ee)[R], const float* __restrict__ rows,
-                                              double (&acc)[R]) {
-  switch (M) {
-    case 0: arr_far32<0, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 1: arr_far32<1, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 2: arr_far32<2, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 3: arr_far32<3, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 4: arr_far32<4, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 5: arr_far32<5, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    default: arr_far32<6, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-  }
-}
-
-template <int R, bool EDGE>
-__device__ __forceinline__ void arr_far64_seg(int M, int lo, int hi, const double2* __restrict__ pos,
-                                              int64_t jl, const double (&ex)[R], const double (&ey)[R],
-                                              const double* __restrict__ rows, double (&acc)[R]) {
-#define DD_CASE(k) \
-  case k: arr_far64<k, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-  switch (M) {
-    DD_CASE(0) DD_CASE(1) DD_CASE(2) DD_CASE(3) DD_CASE(4) DD_CASE(5) DD_CASE(6) DD_CASE(7)
-    DD_CASE(8) DD_CASE(9) DD_CASE(10) DD_CASE(11) DD_CASE(12) DD_CASE(13) DD_CASE(14)
-    DD_CASE(15) DD_CASE(16)
-    default: arr_far64<17, R, EDGE>(lo, hi, pos, jl, ex, ey, rows, acc); break;
-  }
-#undef DD_CASE
-}
-
-// Segment [lo, hi) of degree M within [n_lo, n_hi): M runs from m_max down.
-__device__ __forceinline__ void seg_range(const DegreeBounds& b, int M, int n_lo, int n_hi, int& lo,
-                                          int& hi) {
-  lo = max(n_lo, b.b[M]);
-  hi = (M == 0) ? n_hi : min(n_hi, b.b[M - 1]);
-}
-
-// One wavefront processes one arrival work item (far region).
-template <int R>
-__device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const float4* __restrict__ pos,
-                                                 const float* __restrict__ rows, int64_t V,
-                                                 const DegreeBounds& bnd,
-                                                 double* __restrict__ partial) {
-  const int lane = threadIdx.x & 63;
-  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
-  float ex[R], ey[R], ee[R];
-  double acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const float4 e = pos[jl + r];
-    ex[r] = -0.5f * e.x;
-    ey[r] = -0.5f * e.y;
-    ee[r] = e.z;
-    acc[r] = 0.0;
-  }
-  const bool edge = (item.slot_flags & kItemEdge) != 0;
-  for (int M = bnd.m_max; M >= 0; --M) {
-    int lo, hi;
-    seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
-    if (lo >= hi) continue;
-    if (edge)
-      arr_far32_seg<R, true>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
-    else
-      arr_far32_seg<R, false>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
-  }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
-}
-
-template <int R>
-__device__ __forceinline__ void do_arrival_far64(const ArrItem& item, const double2* __restrict__ pos,
-                                                 const double* __restrict__ rows, int64_t V,
-                                                 const DegreeBounds& bnd,
-                                                 double* __restrict__ partial) {
-  const int lane = threadIdx.x & 63;
-  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
-  double ex[R], ey[R], acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const double2 e = pos[jl + r];
-    ex[r] = e.x;
-    ey[r] = e.y;
-    acc[r] = 0.0;
-  }
-  const bool edge = (item.slot_flags & kItemEdge) != 0;
-  for (int M = bnd.m_max; M >= 0; --M) {
-    int lo, hi;
-    seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
-    if (lo >= hi) continue;
-    if (edge)
-      arr_far64_seg<R, true>(M, lo, hi, pos, jl, ex, ey, rows, acc);
-    else
-      arr_far64_seg<R, false>(M, lo, hi, pos, jl, ex, ey, rows, acc);
-  }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
-}
-
-// Near band: per-pair regime choice, every pair masked by causality.
-template <int R, bool MIXED>
-__device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void* __restrict__ pos_v,
-                                                const double* __restrict__ rows64,
-                                                const float* __restrict__ rows32, int64_t V,
-                                                double* __restrict__ partial) {
-  const int lane = threadIdx.x & 63;
-  const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
-  double acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0;
-  if (MIXED) {
-    const float2* pos = (const float2*)pos_v;
-    float ex[R], ey[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float2 e = pos[jl + r];
-      ex[r] = e.x;
-      ey[r] = e.y;
-    }
-    for (int n = item.n_lo; n < item.n_hi; ++n) {
-      const float* r32 = rows32 + (int64_t)n * kRow32;
-      const double* r64 = rows64 + (int64_t)n * kRow64;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t i = jl + r - n;
-        if (i >= 0 && jl + r < V) {
-          const float2 p = pos[i];
-          const float dx = ex[r] - p.x, dy = ey[r] - p.y;
-          const float a = __builtin_fmaf(dy, dy, dx * dx);
-          if (a * r32[kR32_C] <= kThr32)
-            acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else if (a * r32[kR32_RHI] <= kCull32Log2)
-            acc[r] += phi_general_f64((double)a, r64);
-        }
-      }
-    }
-  } else {
-    const double2* pos = (const double2*)pos_v;
-    double ex[R], ey[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double2 e = pos[jl + r];
-      ex[r] = e.x;
-      ey[r] = e.y;
-    }
-    for (int n = item.n_lo; n < item.n_hi; ++n) {
-      const double* r64 = rows64 + (int64_t)n * kRow64;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t i = jl + r - n;
-        if (i >= 0 && jl + r < V) {
-          const double2 p = pos[i];
-          const double dx = ex[r] - p.x, dy = ey[r] - p.y;
-          acc[r] += phi_general_f64(fma(dy, dy, dx * dx), r64);
-        }
-      }
-    }
-  }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
-}
-
-// ---------------------------------------------------------------------------
-// Map query.  Pixel pix = tile * 64 R + R lane + r at (X0 + u DX, Y0 + v DY),
-// u = pix % W, v = pix / W, all at the item's time; visit v = K - n.
-// LAT: pixel and probe coordinates are exact small dyadic numbers, so the
-// three-operation a = |e|^2 + |p|^2 - 2 e.p is exact; otherwise a is formed
-// from the differences (relative error ~1e-7, no cancellation).
-template <bool LAT, int R>
-__device__ __forceinline__ float map_a32(const float4& p, const float (&ex)[R], const float (&ey)[R],
-                                         const float (&ee)[R], int r) {
-  if (LAT) return __builtin_fmaf(ex[r], p.x, __builtin_fmaf(ey[r], p.y, ee[r] + p.z));
-  const float dx = __builtin_fmaf(0.5f, p.x, ex[r]), dy = __builtin_fmaf(0.5f, p.y, ey[r]);
-  return __builtin_fmaf(dy, dy, dx * dx);
-}
-
-template <int M, int R, int U, bool LAT>
-__device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float4* __restrict__ pos,
-                                          const float* __restrict__ rows, const float (&ex)[R],
-                                          const float (&ey)[R], const float (&ee)[R],
-                                          double (&acc)[R]) {
-  using Row = typename RowSel<M>::type;
-  int n = lo;
-  if (n + U <= hi) {
-    Row cur[U];
-    float4 pc[U];
-#pragma unroll
-    for (int s = 0; s < U; ++s) {
-      cur[s] = fetch_row<M>(rows, n + s);
-      pc[s] = pos[K - (n + s)];
-    }
-    for (; n + U <= hi; n += U) {
-      Row nxt[U];
-      float4 pn[U];
-#pragma unroll
-      for (int s = 0; s < U; ++s) {
-        const int nn = min(n + U + s, hi - 1);
-        nxt[s] = fetch_row<M>(rows, nn);
-        pn[s] = pos[K - nn];
-      }
-      float t[R][U];
-#pragma unroll
-      for (int s = 0; s < U; ++s) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-          t[r][s] = series_row32<M>(map_a32<LAT, R>(pc[s], ex, ey, ee, r), cur[s]);
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<U>(t[r]);
-#pragma unroll
-      for (int s = 0; s < U; ++s) {
-        cur[s] = nxt[s];
-        pc[s] = pn[s];
-      }
-    }
-  }
-  for (; n < hi; ++n) {
-    const float4 p = pos[K - n];
-    const Row row = fetch_row<M>(rows, n);
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      acc[r] += (double)series_row32<M>(map_a32<LAT, R>(p, ex, ey, ee, r), row);
-  }
-}
-
-template <int M, int R>
-__device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const double2* __restrict__ pos,
-                                          const double* __restrict__ rows, const double (&ex)[R],
-                                          const double (&ey)[R], double (&acc)[R]) {
-  for (int n = lo; n < hi; ++n) {
-    const double2 p = pos[K - n];
-    const double* row = rows + (int64_t)n * kRow64;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double dx = ex[r] - p.x, dy = ey[r] - p.y;
-      acc[r] += series_f64<M>(fma(dy, dy, dx * dx), row);
-    }
-  }
-}
-
-template <int R, bool LAT>
-__device__ __forceinline__ void map_far32_seg(int M, int lo, int hi, int64_t K,
-                                              const float4* __restrict__ pos,
-                                              const float* __restrict__ rows, const float (&ex)[R],
-                                              const float (&ey)[R], const float (&ee)[R],
-                                              double (&acc)[R]) {
-  switch (M) {
-    case 0: map_far32<0, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 1: map_far32<1, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 2: map_far32<2, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 3: map_far32<3, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 4: map_far32<4, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 5: map_far32<5, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    default: map_far32<6, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-  }
-}
-
-template <int R>
-__device__ __forceinline__ void map_far64_seg(int M, int lo, int hi, int64_t K,
-                                              const double2* __restrict__ pos,
-                                              const double* __restrict__ rows, const double (&ex)[R],
-                                              const double (&ey)[R], double (&acc)[R]) {
-#define DD_CASE(k) \
-  case k: map_far64<k, R>(lo, hi, K, pos, rows, ex, ey, acc); break;
-  switch (M) {
-    DD_CASE(0) DD_CASE(1) DD_CASE(2) DD_CASE(3) DD_CASE(4) DD_CASE(5) DD_CASE(6) DD_CASE(7)
-    DD_CASE(8) DD_CASE(9) DD_CASE(10) DD_CASE(11) DD_CASE(12) DD_CASE(13) DD_CASE(14)
-    DD_CASE(15) DD_CASE(16)
-    default: map_far64<17, R>(lo, hi, K, pos, rows, ex, ey, acc); break;
-  }
-#undef DD_CASE
-}
-
-template <int R, bool MIXED>
-__device__ __forceinline__ void do_map(const MapItem& item, const MapTime& tm,
-                                       const void* __restrict__ pos_v,
-                                       const float4* __restrict__ pos4,
-                                       const double* __restrict__ rows64,
-                                       const float* __restrict__ rows32, double X0, double Y0,
-                                       double DX, double DY, int W, int H, bool lattice,
-                                       double* __restrict__ partial) {
-  const int lane = threadIdx.x & 63;
-  const int64_t npix = (int64_t)W * H;
-  const int64_t p0 = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
-  double pxd[R], pyd[R], acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int64_t pix = min(p0 + r, npix - 1);
-    pxd[r] = X0 + (double)(pix % W) * DX;
-    pyd[r] = Y0 + (double)(pix / W) * DY;
-    acc[r] = 0.0;
-  }
-  const double* r64b = rows64 + tm.row_base * kRow64;
-  const float* r32b = rows32 + tm.row_base * kRow32;
-  if (MIXED) {
-    const float2* pos = (const float2*)pos_v;
-    float ex[R], ey[R], ee[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      ex[r] = (float)pxd[r];
-      ey[r] = (float)pyd[r];
-      ee[r] = __builtin_fmaf(ey[r], ey[r], ex[r] * ex[r]);
-    }
-    if (item.near) {
-      for (int n = item.n_lo; n < item.n_hi; ++n) {
-        const float2 p = pos[tm.K - n];
-        const float* r32 = r32b + (int64_t)n * kRow32;
-        const double* r64 = r64b + (int64_t)n * kRow64;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float dx = ex[r] - p.x, dy = ey[r] - p.y;
-          const float a = __builtin_fmaf(dy, dy, dx * dx);
-          if (a * r32[kR32_C] <= kThr32)
-            acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else if (a * r32[kR32_RHI] <= kCull32Log2)
-            acc[r] += phi_general_f64((double)a, r64);
-        }
-      }
-    } else {
-      for (int M = tm.bounds.m_max; M >= 0; --M) {
-        int lo, hi;
-        seg_range(tm.bounds, M, item.n_lo, item.n_hi, lo, hi);
-        if (lo >= hi) continue;
-        if (lattice)
-          map_far32_seg<R, true>(M, lo, hi, tm.K, pos4, r32b, ex, ey, ee, acc);
-        else
-          map_far32_seg<R, false>(M, lo, hi, tm.K, pos4, r32b, ex, ey, ee, acc);
-      }
-    }
-  } else {
-    const double2* pos = (const double2*)pos_v;
-    if (item.near) {
-      for (int n = item.n_lo; n < item.n_hi; ++n) {
-        const double2 p = pos[tm.K - n];
-        const double* r64 = r64b + (int64_t)n * kRow64;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double dx = pxd[r] - p.x, dy = pyd[r] - p.y;
-          acc[r] += phi_general_f64(fma(dy, dy, dx * dx), r64);
-        }
-      }
-    } else {
-      for (int M = tm.bounds.m_max; M >= 0; --M) {
-        int lo, hi;
-        seg_range(tm.bounds, M, item.n_lo, item.n_hi, lo, hi);
-        if (lo < hi) map_far64_seg<R>(M, lo, hi, tm.K, pos, r64b, pxd, pyd, acc);
-      }
-    }
-  }
-  double* out = partial + (tm.slot_base + item.slot) * npix;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (p0 + r < npix) out[p0 + r] = acc[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -655,45 +88,6 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
 }
 
 // ---------------------------------------------------------------------------
-// Persistent batched kernel: many scans, one launch.  Each wavefront takes
-// the next item from a device counter until the list is exhausted (every
-// wave reaches that exit).  The items were sorted longest first on the host;
-// each item runs exactly the per-item code of the per-scan kernels, so batch
-// results equal per-scan results bit for bit.
-template <int R, int RN, int RM, bool MIXED>
-__global__ void __launch_bounds__(256) k_batch(const BatchScan* __restrict__ scans,
-                                               const BatchItem* __restrict__ items, int n_items,
-                                               int* __restrict__ counter) {
-  const int lane = threadIdx.x & 63;
-  for (;;) {
-    int it = 0;
-    if (lane == 0) it = atomicAdd(counter, 1);
-    it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= n_items) break;
-    const BatchItem bi = items[it];
-    const BatchScan& S = scans[bi.scan];
-    if (bi.kind == kBatchArrFar) {
-      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
-      if (MIXED)
-        do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
-      else
-        do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds,
-                            S.arr_partial);
-    } else if (bi.kind == kBatchArrNear) {
-      const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
-      do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
-    } else {
-      const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask,
-                       bi.kind == kBatchMapNear ? 1 : 0, 0, 0};
-      do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0, 0.0, 1.0, 1.0,
-                        S.nx, S.ny, true, S.map_partial);
-    }
-  }
-}
-
-__global__ void k_zero_int(int* p) { *p = 0; }
-
-// ---------------------------------------------------------------------------
 // Fixed-order reductions of the partial slots.
 __global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict__ partial,
                                                         const int32_t* __restrict__ tile_slots,
@@ -720,30 +114,6 @@ __global__ void __launch_bounds__(256) k_reduce_map(const double* __restrict__ p
     double s = 0.0;
     for (int k = 0; k < tm.n_slots; ++k) s += partial[(tm.slot_base + k) * npix + pix];
     out[e] = pref * s;
-  }
-}
-
-// One pass over the outputs of a whole batch; entry found by binary search
-// on the output offsets; slots added in the same order as the per-scan
-// reductions.
-__global__ void __launch_bounds__(256) k_reduce_batch(const BatchReduce* __restrict__ reds,
-                                                      int n_red, int64_t total) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int lo = 0, hi = n_red - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (reds[mid].out_off <= e)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const BatchReduce& Rd = reds[lo];
-    const int64_t j = e - Rd.out_off;
-    const int ns = Rd.tile_slots ? Rd.tile_slots[j / Rd.tile] : Rd.n_slots;
-    double s = 0.0;
-    for (int k = 0; k < ns; ++k) s += Rd.partial[(int64_t)k * Rd.n + j];
-    Rd.out[j] = Rd.pref * s;
   }
 }
 
@@ -865,38 +235,6 @@ hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_
                              int64_t npix, double pref, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_map, dim3(grid_for(npix * n_t)), dim3(256), 0, st, partial, times,
                      n_t, npix, pref, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
-                        int* counter, int R, int RN, int RM, bool mixed, hipStream_t st) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
-  // persistent grid: enough waves to fill the chip a few times over
-  const unsigned blocks = (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
-#define DD_LAUNCH_BATCH(A, B, C)                                                                 \
-  if (R == A && RN == B && RM == C) {                                                            \
-    if (mixed)                                                                                   \
-      hipLaunchKernelGGL((k_batch<A, B, C, true>), dim3(blocks), dim3(256), 0, st, scans, items, \
-                         n_items, counter);                                                      \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_batch<A, B, C, false>), dim3(blocks), dim3(256), 0, st, scans,       \
-                         items, n_items, counter);                                               \
-    return hipGetLastError();                                                                    \
-  }
-  DD_LAUNCH_BATCH(4, 2, 2)
-  DD_LAUNCH_BATCH(2, 2, 1)
-  DD_LAUNCH_BATCH(4, 2, 1)
-  DD_LAUNCH_BATCH(2, 2, 2)
-  DD_LAUNCH_BATCH(4, 4, 2)
-#undef DD_LAUNCH_BATCH
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
-                               hipStream_t st) {
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_batch, dim3(grid_for(total)), dim3(256), 0, st, reds, n_red, total);
   return hipGetLastError();
 }
 

@@ -704,13 +704,3 @@ dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double*
          "pair-term launch");
   return DD_OK;
 }
-
-dd_status dd_autotune(const char* cache_path) {
-  (void)cache_path;
-  return fail(DD_EUNSUPPORTED, "autotuner not available in this build");
-}
-
-dd_status dd_tune_load(const char* cache_path) {
-  (void)cache_path;
-  return fail(DD_EUNSUPPORTED, "autotuner not available in this build");
-}

@@ -126,3 +126,25 @@ def test_out_of_memory_path():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
                          cwd=ROOT, timeout=120)
     assert out.stdout.strip() == "-2", out.stderr
+
+
+def test_tune_cache_load(dd, tmp_path):
+    good = tmp_path / "tune.json"
+    good.write_text('{\n  "arch": "gfx950",\n  "version": 1,\n'
+                    '  "arrival_mixed": {"R": 4, "RN": 2, "K": 2048, "ms": 1.0},\n'
+                    '  "arrival_fp64": {"R": 2, "RN": 2, "K": 1024, "ms": 1.0},\n'
+                    '  "map_mixed": {"R": 2, "K": 4096, "ms": 1.0},\n'
+                    '  "map_fp64": {"R": 1, "K": 4096, "ms": 1.0}\n}\n')
+    dd.tune_load(str(good))
+    bad = tmp_path / "bad.json"
+    bad.write_text(good.read_text().replace('"R": 4', '"R": 3'))
+    with pytest.raises(dd.DDError) as e:
+        dd.tune_load(str(bad))
+    assert e.value.status == dd.DD_EINVAL
+    with pytest.raises(dd.DDError):
+        dd.tune_load(str(tmp_path / "missing.json"))
+    other = tmp_path / "other.json"
+    other.write_text(good.read_text().replace("gfx950", "gfx942"))
+    with pytest.raises(dd.DDError):
+        dd.tune_load(str(other))
+    dd.tune_load(str(good))  # leave the defaults in place
