@@ -166,6 +166,54 @@ dd_status dd_profiling(int32_t enable);
  * reset; reset = 1 clears them.  DD_EINVAL for an unknown name.          */
 dd_status dd_profile_read(const char *kernel, dd_kernel_stats *out, int32_t reset);
 
+/* ---- Learned surrogate --------------------------------------------------
+ * A 4-level U-Net (32, 64, 128, 256 channels at 64^2, 32^2, 16^2, 8^2; two
+ * 3x3 convolutions + SiLU per level, 2x2 average pooling, nearest 2x
+ * upsampling with skip concatenation, 1x1 head) that maps a 64x64 scan's
+ * first-visit-time map t_first/T plus kappa = D dwell/pitch^2 and
+ * sigma/pitch to ln(psi_hat) of the damage map at the end of the scan
+ * (psi_hat = psi 4 pi D / Q0, Eq. 6 at every probe position).  Convolutions
+ * run on BF16 MFMA with FP32 accumulation; master weights, Adam moments and
+ * the output head are FP32.  Parameters are one flat FP32 vector: per
+ * convolution weights [9 ci][co] (k = (3 ky + kx) ci + c) then bias [co], in
+ * forward order, then the head's 32 weights and its bias.
+ * Tensors are device pointers, NHWC: x [B][64][64][3], y and targets
+ * [B][64][64].  Calls enqueue on hip_stream.  One handle per thread.        */
+typedef struct dd_unet dd_unet;
+/* He-normal initialisation from `seed`.  DD_EDEVICE without a gfx950 GPU. */
+dd_status dd_unet_create(uint64_t seed, dd_unet **out);
+void dd_unet_destroy(dd_unet *u);                           /* NULL-safe */
+int64_t dd_unet_num_params(const dd_unet *u);               /* -1 for NULL */
+/* Copies the FP32 master parameters out (host_get) and/or in (host_set). */
+dd_status dd_unet_params(dd_unet *u, float *host_get, const float *host_set);
+/* Copies the gradient of the last backward pass to host_out.            */
+dd_status dd_unet_grads(const dd_unet *u, float *host_out);
+/* Forward pass of a batch (keeps what the backward pass needs).          */
+dd_status dd_unet_forward(dd_unet *u, int32_t batch, const float *x, float *y, void *hip_stream);
+/* Backward pass of the last forward batch for output gradient dy; the
+ * gradient is overwritten (not accumulated).                             */
+dd_status dd_unet_backward(dd_unet *u, const float *dy, void *hip_stream);
+/* Mean squared error over n values and its gradient dy = 2 (y - t) / n;
+ * loss_host (may be NULL) receives the loss (synchronizes).              */
+dd_status dd_unet_mse(dd_unet *u, int64_t n, const float *y, const float *t, float *dy,
+                      double *loss_host, void *hip_stream);
+/* One Adam step (bias-corrected) on the FP32 master weights.             */
+dd_status dd_unet_adam(dd_unet *u, float lr, float beta1, float beta2, float eps,
+                       void *hip_stream);
+/* Network inputs of n 64x64 scans into x [n][64][64][3]: channel 0 the first
+ * visit of each probe over V, 1 (log10 kappa + 1)/3, 2 (sigma/pitch - 0.6)/0.4. */
+dd_status dd_surrogate_inputs(dd_scan *const *scans, int32_t n, float *x, void *hip_stream);
+/* Training targets t = ln(psi 4 pi D / Q0) from exact final maps psi [n][4096]. */
+dd_status dd_surrogate_targets(dd_scan *const *scans, int32_t n, const double *psi, float *t,
+                               void *hip_stream);
+/* Final damage maps psi [n][64*64] (u/m^2) by the network, judged by the
+ * exact kernels: a map is accepted if the relative L2 error of its middle row
+ * against the exact row is <= spot_tol; scans outside the training range
+ * (grid 64x64, kappa in [1e-4, 100], sigma/pitch in [0.2, 1]) and rejected
+ * maps are computed exactly (used_fallback[k] = 1, host array).            */
+dd_status dd_unet_predict(dd_unet *u, dd_scan *const *scans, int32_t n, double spot_tol,
+                          dd_precision p, double *psi, int32_t *used_fallback, void *hip_stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);
 

@@ -29,7 +29,10 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
     "dd_damage_map", "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms",
-    "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_last_error",
+    "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
+    "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
+    "dd_unet_backward", "dd_unet_mse", "dd_unet_adam", "dd_surrogate_inputs",
+    "dd_surrogate_targets", "dd_unet_predict", "dd_last_error",
 )
 
 
@@ -86,10 +89,28 @@ def load_library():
     lib.dd_tune_load.argtypes = [ctypes.c_char_p]
     lib.dd_profiling.argtypes = [i32]
     lib.dd_profile_read.argtypes = [ctypes.c_char_p, P(KernelStats), i32]
+    lib.dd_unet_create.argtypes = [ctypes.c_uint64, P(vp)]
+    lib.dd_unet_destroy.argtypes = [vp]
+    lib.dd_unet_destroy.restype = None
+    lib.dd_unet_num_params.argtypes = [vp]
+    lib.dd_unet_num_params.restype = i64
+    lib.dd_unet_params.argtypes = [vp, vp, vp]
+    lib.dd_unet_grads.argtypes = [vp, vp]
+    lib.dd_unet_forward.argtypes = [vp, i32, vp, vp, vp]
+    lib.dd_unet_backward.argtypes = [vp, vp, vp]
+    lib.dd_unet_mse.argtypes = [vp, i64, vp, vp, vp, P(dbl), vp]
+    lib.dd_unet_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, vp]
+    lib.dd_surrogate_inputs.argtypes = [P(vp), i32, vp, vp]
+    lib.dd_surrogate_targets.argtypes = [P(vp), i32, vp, vp, vp]
+    lib.dd_unet_predict.argtypes = [vp, P(vp), i32, dbl, ctypes.c_int, vp, P(i32), vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map",
                  "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
-                 "dd_tune_load", "dd_profiling", "dd_profile_read"):
+                 "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
+                 "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
+                 "dd_unet_mse", "dd_unet_adam", "dd_surrogate_inputs", "dd_surrogate_targets",
+                 "dd_unet_predict"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -259,3 +280,114 @@ def profile_read(kernel: str, reset: bool = True) -> dict:
     st = KernelStats()
     _check(load_library().dd_profile_read(kernel.encode(), ctypes.byref(st), 1 if reset else 0))
     return {"ms": st.ms, "launches": int(st.launches), "pairs": st.pairs, "flops": st.flops}
+
+
+# ---------------------------------------------------------------------------
+# Learned surrogate (dd_unet_*): U-Net on 64x64 scans, BF16 MFMA kernels.
+SIDE = 64
+
+
+def _handles(scans):
+    return (ctypes.c_void_p * len(scans))(*[s.handle.value for s in scans])
+
+
+def surrogate_inputs(scans, stream=None):
+    """Network inputs [n, 64, 64, 3] (float32 CUDA) of 64x64 scans."""
+    torch = _torch()
+    x = torch.empty((len(scans), SIDE, SIDE, 3), dtype=torch.float32, device="cuda")
+    _check(load_library().dd_surrogate_inputs(_handles(scans), len(scans),
+                                              ctypes.c_void_p(x.data_ptr()), _stream(stream)))
+    return x
+
+
+def surrogate_targets(scans, psi, stream=None):
+    """Training targets ln(psi 4 pi D / Q0) [n, 64, 64] from exact final maps."""
+    torch = _torch()
+    psi = psi.contiguous()
+    assert psi.dtype == torch.float64 and psi.numel() == len(scans) * SIDE * SIDE
+    t = torch.empty((len(scans), SIDE, SIDE), dtype=torch.float32, device="cuda")
+    _check(load_library().dd_surrogate_targets(_handles(scans), len(scans),
+                                               ctypes.c_void_p(psi.data_ptr()),
+                                               ctypes.c_void_p(t.data_ptr()), _stream(stream)))
+    return t
+
+
+class UNet:
+    """The surrogate network (``dd_unet``); see include/dd.h for the layout."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(load_library().dd_unet_create(seed, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().dd_unet_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(load_library().dd_unet_num_params(self._h))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(load_library().dd_unet_params(self._h, ctypes.c_void_p(out.ctypes.data), None))
+        return out
+
+    def set_params(self, p) -> None:
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.num_params
+        _check(load_library().dd_unet_params(self._h, None, ctypes.c_void_p(p.ctypes.data)))
+
+    def grads(self) -> np.ndarray:
+        out = np.empty(self.num_params, dtype=np.float32)
+        _check(load_library().dd_unet_grads(self._h, ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def forward(self, x, stream=None):
+        torch = _torch()
+        x = x.contiguous()
+        assert x.dtype == torch.float32 and x.shape[1:] == (SIDE, SIDE, 3)
+        y = torch.empty((x.shape[0], SIDE, SIDE), dtype=torch.float32, device="cuda")
+        _check(load_library().dd_unet_forward(self._h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        return y
+
+    def backward(self, dy, stream=None):
+        dy = dy.contiguous()
+        _check(load_library().dd_unet_backward(self._h, ctypes.c_void_p(dy.data_ptr()),
+                                               _stream(stream)))
+
+    def mse(self, y, t, want_loss: bool = True, stream=None):
+        """Returns (loss or None, dy)."""
+        torch = _torch()
+        y, t = y.contiguous(), t.contiguous()
+        dy = torch.empty_like(y)
+        loss = ctypes.c_double(0.0)
+        _check(load_library().dd_unet_mse(self._h, y.numel(), ctypes.c_void_p(y.data_ptr()),
+                                          ctypes.c_void_p(t.data_ptr()),
+                                          ctypes.c_void_p(dy.data_ptr()),
+                                          ctypes.byref(loss) if want_loss else None,
+                                          _stream(stream)))
+        return (loss.value if want_loss else None), dy
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None):
+        _check(load_library().dd_unet_adam(self._h, lr, beta1, beta2, eps, _stream(stream)))
+
+    def predict(self, scans, spot_tol: float = 0.02, precision: str = "mixed", stream=None):
+        """Final maps [n, 64, 64] (float64 CUDA, u/m^2) and the fallback flags."""
+        torch = _torch()
+        n = len(scans)
+        psi = torch.empty((n, SIDE, SIDE), dtype=torch.float64, device="cuda")
+        fb = (ctypes.c_int32 * n)()
+        _check(load_library().dd_unet_predict(self._h, _handles(scans), n, spot_tol,
+                                              _prec(precision), ctypes.c_void_p(psi.data_ptr()),
+                                              fb, _stream(stream)))
+        return psi, np.frombuffer(fb, dtype=np.int32).copy()

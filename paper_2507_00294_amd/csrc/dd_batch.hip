@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(256) k_batch(const BatchScan* __restrict__ sca
     } else {
       const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask,
                        bi.kind == kBatchMapNear ? 1 : 0, 0, 0};
-      do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0, 0.0, 1.0, 1.0,
-                        S.nx, S.ny, true, S.map_partial);
+      do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0,
+                        (double)S.map_row0, 1.0, 1.0, S.nx, S.map_rows, true, S.map_partial);
     }
   }
 }

@@ -101,7 +101,8 @@ struct BatchScan {
   const double* rows64;    // integer-lag rows of this scan
   const float* rows32;
   int64_t V;
-  int32_t nx, ny;
+  int32_t nx, ny;          // final map: nx pixels per row
+  int32_t map_row0, map_rows;  // rows [map_row0, map_row0 + map_rows) of the final map
   DegreeBounds arr_bounds;
   MapTime map_time;        // the final map at t = V tau_v (K = V, f = 0)
   double* arr_partial;     // [slots][V]

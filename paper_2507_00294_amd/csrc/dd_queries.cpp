@@ -501,8 +501,13 @@ struct BatchScratch {
 };
 static thread_local BatchScratch g_batch;
 
-dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
-                    double* const* outs, int32_t on_device, hipStream_t st) {
+}  // namespace
+
+// Batched solve; the final map covers rows [row0, row0 + rows) of each probe
+// grid (rows < 0: all rows).
+dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
+                        double* const* outs, int32_t on_device, hipStream_t st, int32_t row0,
+                        int32_t rows) {
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
   const int RM = mixed ? tune().map_R_mixed : tune().map_R_f64;
@@ -534,6 +539,8 @@ dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
     B.V = s->V;
     B.nx = s->desc.nx;
     B.ny = s->desc.ny;
+    B.map_row0 = rows < 0 ? 0 : std::min(row0, s->desc.ny - 1);
+    B.map_rows = rows < 0 ? s->desc.ny : std::min(rows, s->desc.ny - B.map_row0);
     out_off[k] = out_total;
     if (want_arr) {
       ArrivalPlan AP;
@@ -562,7 +569,8 @@ dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
       flops += AP.near_flops + AP.far_flops;
     }
     if (want_map) {
-      dd_grid g{0.0, 0.0, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx, s->desc.ny};
+      dd_grid g{0.0, B.map_row0 * s->desc.pitch_m, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx,
+                B.map_rows};
       const double t_end = (double)s->V * s->tau_v;
       MapPlan MP;
       plan_map(s, &g, &t_end, 1, mixed, RM, tune().map_K, true, MP);
@@ -648,6 +656,7 @@ dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
   return DD_OK;
 }
 
+namespace {
 }  // namespace
 
 void dd_forget_plans(const dd_scan* s) { g_plans.erase(s); }
@@ -687,8 +696,8 @@ dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, 
   if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
   for (int32_t k = 0; k < n; ++k)
     if (!scans[k] || !outs[k]) return fail(DD_EINVAL, "scan %d or its output is NULL", k);
-  return run_batch(scans, n, query_mask, p == DD_MIXED, outs, out_on_device,
-                   (hipStream_t)hip_stream);
+  return dd::run_batch(scans, n, query_mask, p == DD_MIXED, outs, out_on_device,
+                       (hipStream_t)hip_stream, 0, -1);
 }
 
 dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double* a,

@@ -78,6 +78,12 @@ struct TuneParams {
 };
 TuneParams& tune();
 
+// Batched solve of many scans (arrival and/or final map, the final map
+// restricted to rows [row0, row0 + rows) of each grid; rows < 0 = all).
+dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
+                    double* const* outs, int32_t on_device, hipStream_t st, int32_t row0,
+                    int32_t rows);
+
 }  // namespace dd
 
 struct dd_scan {

@@ -1,0 +1,203 @@
+"""Training and evaluation driver of the learned surrogate (``dd_unet``).
+
+The surrogate maps a 64x64 scan's first-visit-time map, kappa = D dwell /
+pitch^2 and sigma / pitch to ln(psi_hat) of its damage map at the end of the
+scan (Eq. 6 at every probe position).  Training data are exact final maps from
+the batched kernel; the network is trained on the GPU with the library's own
+BF16-MFMA forward and backward kernels and Adam; predictions are judged by the
+exact kernel, which also replaces rejected maps.  PyTorch here only holds
+device tensors and gathers mini-batches.
+
+Run ``python -m paper_2507_00294_amd.surrogate --help`` for the full pipeline
+(dataset generation, training, evaluation, weights file).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import (Q_FINAL_AT_PROBES, SIDE, Scan, UNet, batch_solve, surrogate_inputs,
+               surrogate_targets)
+from . import workloads as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "unet64.npy")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def exact_final_maps(scans, precision="mixed"):
+    """Exact final maps [n, 64, 64] (float64 CUDA) by one batched launch."""
+    import torch
+
+    outs = batch_solve(scans, Q_FINAL_AT_PROBES, precision)
+    return torch.stack([o.view(SIDE, SIDE) for o in outs])
+
+
+def generate(specs, precision="mixed", chunk=256, keep_psi=False):
+    """Inputs x [n,64,64,3], targets t [n,64,64] (and psi) for scan specs,
+    built chunk by chunk so that scan handles are released as we go."""
+    import torch
+
+    xs, ts, ps = [], [], []
+    for k in range(0, len(specs), chunk):
+        scans = [Scan(**s.kwargs()) for s in specs[k: k + chunk]]
+        psi = exact_final_maps(scans, precision)
+        xs.append(surrogate_inputs(scans))
+        ts.append(surrogate_targets(scans, psi))
+        if keep_psi:
+            ps.append(psi)
+        for s in scans:
+            s.close()
+    x, t = torch.cat(xs), torch.cat(ts)
+    return (x, t, torch.cat(ps)) if keep_psi else (x, t)
+
+
+def train(net, x, t, steps, batch=32, lr=2e-3, lr_end=2e-5, seed=0, log_every=200,
+          warmup=100):
+    """Adam with linear warm-up and cosine decay; returns the loss history."""
+    import torch
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    n = x.shape[0]
+    hist = []
+    perm = torch.randperm(n, device="cuda", generator=g)
+    pos = 0
+    t0 = time.time()
+    for step in range(steps):
+        if pos + batch > n:
+            perm = torch.randperm(n, device="cuda", generator=g)
+            pos = 0
+        idx = perm[pos: pos + batch]
+        pos += batch
+        xb, tb = x.index_select(0, idx), t.index_select(0, idx)
+        y = net.forward(xb)
+        want = (step % log_every == 0) or step == steps - 1
+        loss, dy = net.mse(y, tb, want_loss=want)
+        net.backward(dy)
+        frac = step / max(steps - 1, 1)
+        rate = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac))
+        if step < warmup:
+            rate *= (step + 1) / warmup
+        net.adam(rate)
+        if want:
+            hist.append((step, loss))
+            log(f"[surrogate] step {step} loss {loss:.4e} lr {rate:.2e} ({time.time() - t0:.1f} s)")
+    return hist
+
+
+def init_head(net, t):
+    """Start the head's bias at the mean target."""
+    p = net.params()
+    p[-1] = float(t.mean().item())
+    net.set_params(p)
+
+
+def rel_l2(pred, exact):
+    """Per-map relative L2 error (float64 CUDA tensors [n,64,64]) -> numpy."""
+    d = (pred - exact).flatten(1).norm(dim=1)
+    return (d / exact.flatten(1).norm(dim=1)).cpu().numpy()
+
+
+def evaluate(net, specs, spot_tol=0.02, precision="mixed", repeats=3):
+    """Surrogate with fallback vs the exact kernel alone on the same scans."""
+    import torch
+
+    scans = [Scan(**s.kwargs()) for s in specs]
+    exact = exact_final_maps(scans, precision)  # also warms the scans' device tables
+    torch.cuda.synchronize()
+    te = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        exact = exact_final_maps(scans, precision)
+        torch.cuda.synchronize()
+        te.append(time.perf_counter() - t0)
+    net.predict(scans[:8], spot_tol, precision)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        psi, fb = net.predict(scans, spot_tol, precision)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    err = rel_l2(psi, exact)
+    raw_ok = fb == 0
+    res = {
+        "maps": len(specs),
+        "exact_s": float(np.median(te)),
+        "surrogate_s": float(np.median(ts)),
+        "speedup": float(np.median(te) / np.median(ts)),
+        "fallback_rate": float(fb.mean()),
+        "rel_l2_mean": float(err.mean()),
+        "rel_l2_p95": float(np.percentile(err, 95)),
+        "rel_l2_max": float(err.max()),
+        "rel_l2_mean_accepted": float(err[raw_ok].mean()) if raw_ok.any() else None,
+        "spot_tol": spot_tol,
+        "precision": precision,
+    }
+    for s in scans:
+        s.close()
+    return res
+
+
+def save_weights(net, path):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.save(path, net.params())
+
+
+def load_weights(net, path=DEFAULT_WEIGHTS):
+    p = np.load(path, allow_pickle=False)
+    net.set_params(p.astype(np.float32))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="train and evaluate the surrogate")
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--test", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=12000)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--spot-tol", type=float, default=0.02)
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--report", default="")
+    args = ap.parse_args(argv)
+    import torch
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    train_specs = wl.surrogate_scans(args.train, seed=5)
+    test_specs = wl.surrogate_scans(args.test, seed=6)
+    x, t = generate(train_specs)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    log(f"[surrogate] generated {args.train} training maps in {gen_s:.1f} s")
+    net = UNet(args.seed)
+    init_head(net, t)
+    t1 = time.time()
+    hist = train(net, x, t, args.steps, args.batch, args.lr, seed=args.seed)
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    save_weights(net, args.weights)
+    res = evaluate(net, test_specs, args.spot_tol)
+    res.update({"train_maps": args.train, "steps": args.steps, "batch": args.batch,
+                "train_s": train_s, "generate_s": gen_s, "final_loss": hist[-1][1],
+                "params": net.num_params})
+    line = json.dumps(res)
+    print(line, flush=True)
+    if args.report:
+        with open(args.report, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()
