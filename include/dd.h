@@ -169,18 +169,29 @@ dd_status dd_profile_read(const char *kernel, dd_kernel_stats *out, int32_t rese
 /* ---- Learned surrogate --------------------------------------------------
  * A 4-level U-Net (32, 64, 128, 256 channels at 64^2, 32^2, 16^2, 8^2; two
  * 3x3 convolutions + SiLU per level, 2x2 average pooling, nearest 2x
- * upsampling with skip concatenation, 1x1 head) that maps a 64x64 scan's
- * first-visit-time map t_first/T plus kappa = D dwell/pitch^2 and
- * sigma/pitch to ln(psi_hat) of the damage map at the end of the scan
- * (psi_hat = psi 4 pi D / Q0, Eq. 6 at every probe position).  Convolutions
- * run on BF16 MFMA with FP32 accumulation; master weights, Adam moments and
- * the output head are FP32.  Parameters are one flat FP32 vector: per
- * convolution weights [9 ci][co] (k = (3 ky + kx) ci + c) then bias [co], in
- * forward order, then the head's 32 weights and its bias.
- * Tensors are device pointers, NHWC: x [B][64][64][3], y and targets
- * [B][64][64].  Calls enqueue on hip_stream.  One handle per thread.        */
+ * upsampling with skip concatenation, FP32 1x1 head) that predicts the
+ * dimensionless damage map psi_hat = psi 4 pi D / Q0 of a 64x64 scan at the
+ * end of the scan (Eq. 6 at every probe position).  Per probe it reads
+ * DD_SURROGATE_CHANNELS inputs:
+ *   0  first visit start / scan duration (the arrival-time map),
+ *   1  (log10 kappa + 1) / 3, kappa = D tau / pitch^2 (tau: one visit's dwell),
+ *   2  (sigma / pitch - 0.6) / 0.4,
+ *   3  ln(lambda_last) / ln(V), lambda_last = V - (index of the last visit),
+ *   4  (ln O + 4) / 4,
+ * where O = sum over the probe's own visits v of ln(b1/b0), b0 = 2 sigma_hat^2
+ * + 4 kappa (V - v - 1), b1 = b0 + 4 kappa (the a = 0 bracket of Eq. 6 at the
+ * end of the scan).  The prediction is psi_hat = O + exp(y), y the network
+ * output.  Convolutions run on BF16 MFMA with FP32 accumulation; activations,
+ * master weights, Adam moments and the head are FP32.  Parameters are one
+ * flat FP32 vector: per convolution weights [9 ci][co] (k = (3 ky + kx) ci +
+ * c) then bias [co], in forward order, then the head's 32 weights and bias.
+ * Tensors are device pointers, NHWC: x [B][64][64][DD_SURROGATE_CHANNELS],
+ * y, own and targets [B][64][64].  Calls enqueue on hip_stream.  One handle
+ * per thread.                                                              */
+#define DD_SURROGATE_CHANNELS 5
 typedef struct dd_unet dd_unet;
-/* He-normal initialisation from `seed`.  DD_EDEVICE without a gfx950 GPU. */
+/* He-normal convolutions from `seed`, zero biases and head.  DD_EDEVICE
+ * without a gfx950 GPU.                                                   */
 dd_status dd_unet_create(uint64_t seed, dd_unet **out);
 void dd_unet_destroy(dd_unet *u);                           /* NULL-safe */
 int64_t dd_unet_num_params(const dd_unet *u);               /* -1 for NULL */
@@ -188,29 +199,48 @@ int64_t dd_unet_num_params(const dd_unet *u);               /* -1 for NULL */
 dd_status dd_unet_params(dd_unet *u, float *host_get, const float *host_set);
 /* Copies the gradient of the last backward pass to host_out.            */
 dd_status dd_unet_grads(const dd_unet *u, float *host_out);
-/* Forward pass of a batch (keeps what the backward pass needs).          */
-dd_status dd_unet_forward(dd_unet *u, int32_t batch, const float *x, float *y, void *hip_stream);
-/* Backward pass of the last forward batch for output gradient dy; the
- * gradient is overwritten (not accumulated).                             */
-dd_status dd_unet_backward(dd_unet *u, const float *dy, void *hip_stream);
-/* Mean squared error over n values and its gradient dy = 2 (y - t) / n;
- * loss_host (may be NULL) receives the loss (synchronizes).              */
-dd_status dd_unet_mse(dd_unet *u, int64_t n, const float *y, const float *t, float *dy,
-                      double *loss_host, void *hip_stream);
-/* One Adam step (bias-corrected) on the FP32 master weights.             */
-dd_status dd_unet_adam(dd_unet *u, float lr, float beta1, float beta2, float eps,
-                       void *hip_stream);
-/* Network inputs of n 64x64 scans into x [n][64][64][3]: channel 0 the first
- * visit of each probe over V, 1 (log10 kappa + 1)/3, 2 (sigma/pitch - 0.6)/0.4. */
-dd_status dd_surrogate_inputs(dd_scan *const *scans, int32_t n, float *x, void *hip_stream);
-/* Training targets t = ln(psi 4 pi D / Q0) from exact final maps psi [n][4096]. */
+/* Forward pass of a batch; train = 1 keeps what the backward pass needs.  */
+dd_status dd_unet_forward(dd_unet *u, int32_t batch, const float *x, float *y, int32_t train,
+                          void *hip_stream);
+/* Backward pass of the last (training) forward batch, whose input was x,
+ * for output gradient dy; the gradient is overwritten (not accumulated).  */
+dd_status dd_unet_backward(dd_unet *u, const float *x, const float *dy, void *hip_stream);
+/* Loss of `maps` predictions own + exp(y) against targets t: loss_host (may
+ * be NULL; synchronizes) receives the mean over maps of |pred - t|^2 / |t|^2
+ * (squared relative L2 error per map); dy is the gradient of that mean plus
+ * the anchor term (anchor / 4096) sum_i (r_i/t_i)^2 (y_i - ln r_i)^2 per map,
+ * r_i = max(t_i - own_i, 1e-6 t_i), whose gradient does not vanish when
+ * exp(y) is far below r.  exp arguments are capped at 80.  maps <= 4096.  */
+dd_status dd_unet_loss(dd_unet *u, int32_t maps, const float *y, const float *own, const float *t,
+                       float anchor, float *dy, double *loss_host, void *hip_stream);
+/* One Adam step (bias-corrected) on the FP32 master weights with the
+ * gradient scaled to global L2 norm <= clip (clip = 0: no clipping; a
+ * non-finite gradient skips the step).  grad_norm_host (may be NULL)
+ * receives the norm before clipping (synchronizes).                       */
+dd_status dd_unet_adam(dd_unet *u, float lr, float beta1, float beta2, float eps, float clip,
+                       float *grad_norm_host, void *hip_stream);
+/* Training mini-batch: slot b <- map idx[b] of (x_all, own_all, t_all; n_all
+ * maps) under the symmetry transform[b] of the square (0..7: transpose if
+ * bit 0, then mirror rows if bit 1, columns if bit 2); idx and transform are
+ * device arrays of nb entries; an idx outside [0, n_all) gives zeros.      */
+dd_status dd_surrogate_batch(const float *x_all, const float *own_all, const float *t_all,
+                             int64_t n_all, const int32_t *idx, const int32_t *transform,
+                             int32_t nb, float *xb, float *ob, float *tb, void *hip_stream);
+/* Network inputs x [n][64][64][DD_SURROGATE_CHANNELS] and the own-visit term
+ * own [n][64][64] of n scans (64x64 grids with every probe visited, else
+ * DD_EINVAL).  The per-scan table is built once and kept with the scan.   */
+dd_status dd_surrogate_inputs(dd_scan *const *scans, int32_t n, float *x, float *own,
+                              void *hip_stream);
+/* Training targets t = psi 4 pi D / Q0 (float) from exact final maps psi
+ * [n][4096] (double).                                                     */
 dd_status dd_surrogate_targets(dd_scan *const *scans, int32_t n, const double *psi, float *t,
                                void *hip_stream);
-/* Final damage maps psi [n][64*64] (u/m^2) by the network, judged by the
- * exact kernels: a map is accepted if the relative L2 error of its middle row
- * against the exact row is <= spot_tol; scans outside the training range
- * (grid 64x64, kappa in [1e-4, 100], sigma/pitch in [0.2, 1]) and rejected
- * maps are computed exactly (used_fallback[k] = 1, host array).            */
+/* Final damage maps psi [n][64*64] (u/m^2, device) by the network, judged by
+ * the exact kernels: a map is accepted if the relative L2 error of its
+ * middle row (row 31) against the exact row is <= spot_tol; scans outside
+ * the training range (64x64 grid, every probe visited, kappa in
+ * [2.5e-5, 100], sigma/pitch in [0.2, 1]) and rejected maps are computed
+ * exactly (used_fallback[k] = 1, host array).  Synchronizes.               */
 dd_status dd_unet_predict(dd_unet *u, dd_scan *const *scans, int32_t n, double spot_tol,
                           dd_precision p, double *psi, int32_t *used_fallback, void *hip_stream);
 

@@ -11,12 +11,18 @@ The network is defined by its parameter layout (one flat vector):
 
 Forward order (each convolution followed by SiLU):
 
-* encoder: two convolutions per level (3->32, 32->32 | 32->64, 64->64 |
+* encoder: two convolutions per level (5->32, 32->32 | 32->64, 64->64 |
   64->128, 128->128 | 128->256, 256->256), 2x2 average pooling between levels;
 * decoder: nearest 2x upsampling, concatenation [upsampled, skip] on channels,
   two convolutions per level (384->128, 128->128 | 192->64, 64->64 |
   96->32, 32->32);
 * head: y = sum_c a_c w_c + b.
+
+The loss of a batch of maps with own-visit terms O and targets t is the mean
+over maps of |O + exp(y) - t|^2 / |t|^2 (the squared relative L2 error of the
+prediction O + exp(y)); the training objective adds, per map, the anchor
+term (anchor / n) sum_i (r_i / t_i)^2 (y_i - ln r_i)^2, r_i = max(t_i - O_i,
+1e-6 t_i), n pixels per map.
 
 Written with plain PyTorch CPU operations in float64 (convolution,
 pooling, interpolation, autograd); any input side divisible by 8 works.
@@ -27,7 +33,8 @@ import numpy as np
 import torch
 import torch.nn.functional as F
 
-CONVS = [(3, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128), (128, 256), (256, 256),
+CIN = 5  # input channels per probe
+CONVS = [(CIN, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128), (128, 256), (256, 256),
          (384, 128), (128, 128), (192, 64), (64, 64), (96, 32), (32, 32)]
 
 
@@ -49,7 +56,7 @@ def unpack(p: torch.Tensor):
 
 
 def forward(p: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    """x [B][H][W][3] -> y [B][H][W] (float64)."""
+    """x [B][H][W][CIN] -> y [B][H][W] (float64)."""
     layers, hw, hb = unpack(p)
     h = x.permute(0, 3, 1, 2)
 
@@ -67,13 +74,31 @@ def forward(p: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
     return (d1 * hw[None, :, None, None]).sum(1) + hb
 
 
-def loss_and_grad(params: np.ndarray, x: np.ndarray, t: np.ndarray):
-    """Mean squared error of forward(params, x) against t and its gradient."""
+def rel_l2_loss(y: torch.Tensor, own: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    """Mean over maps of |own + exp(y) - t|^2 / |t|^2."""
+    d = (own + torch.exp(y) - t).flatten(1)
+    return ((d * d).sum(1) / (t.flatten(1) ** 2).sum(1)).mean()
+
+
+def anchor_term(y: torch.Tensor, own: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    """Mean over maps of (1/n) sum_i (r_i/t_i)^2 (y_i - ln r_i)^2."""
+    r = torch.maximum(t - own, 1e-6 * t)
+    return (((r / t) ** 2 * (y - torch.log(r)) ** 2).flatten(1).mean(1)).mean()
+
+
+def loss_and_grad(params: np.ndarray, x: np.ndarray, own: np.ndarray, t: np.ndarray,
+                  anchor: float = 1.0):
+    """rel_l2_loss of forward(params, x), the network output y, and the
+    gradients of rel_l2_loss + anchor * anchor_term with respect to the
+    parameters and to y."""
     p = torch.tensor(np.asarray(params, dtype=np.float64), requires_grad=True)
     y = forward(p, torch.tensor(np.asarray(x, dtype=np.float64)))
-    loss = ((y - torch.tensor(np.asarray(t, dtype=np.float64))) ** 2).mean()
-    loss.backward()
-    return float(loss.detach()), y.detach().numpy(), p.grad.numpy()
+    y.retain_grad()
+    own_t = torch.tensor(np.asarray(own, dtype=np.float64))
+    t_t = torch.tensor(np.asarray(t, dtype=np.float64))
+    loss = rel_l2_loss(y, own_t, t_t)
+    (loss + anchor * anchor_term(y, own_t, t_t)).backward()
+    return float(loss.detach()), y.detach().numpy(), p.grad.numpy(), y.grad.numpy()
 
 
 def layer_slices():

@@ -31,8 +31,8 @@ EXPORTS = (
     "dd_damage_map", "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
-    "dd_unet_backward", "dd_unet_mse", "dd_unet_adam", "dd_surrogate_inputs",
-    "dd_surrogate_targets", "dd_unet_predict", "dd_last_error",
+    "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
+    "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_last_error",
 )
 
 
@@ -96,12 +96,13 @@ def load_library():
     lib.dd_unet_num_params.restype = i64
     lib.dd_unet_params.argtypes = [vp, vp, vp]
     lib.dd_unet_grads.argtypes = [vp, vp]
-    lib.dd_unet_forward.argtypes = [vp, i32, vp, vp, vp]
-    lib.dd_unet_backward.argtypes = [vp, vp, vp]
-    lib.dd_unet_mse.argtypes = [vp, i64, vp, vp, vp, P(dbl), vp]
-    lib.dd_unet_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
-                                 ctypes.c_float, vp]
-    lib.dd_surrogate_inputs.argtypes = [P(vp), i32, vp, vp]
+    lib.dd_unet_forward.argtypes = [vp, i32, vp, vp, i32, vp]
+    lib.dd_unet_backward.argtypes = [vp, vp, vp, vp]
+    lib.dd_unet_loss.argtypes = [vp, i32, vp, vp, vp, ctypes.c_float, vp, P(dbl), vp]
+    f32 = ctypes.c_float
+    lib.dd_unet_adam.argtypes = [vp, f32, f32, f32, f32, f32, P(f32), vp]
+    lib.dd_surrogate_batch.argtypes = [vp, vp, vp, i64, vp, vp, i32, vp, vp, vp, vp]
+    lib.dd_surrogate_inputs.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_surrogate_targets.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_unet_predict.argtypes = [vp, P(vp), i32, dbl, ctypes.c_int, vp, P(i32), vp]
     lib.dd_last_error.restype = ctypes.c_char_p
@@ -109,8 +110,8 @@ def load_library():
                  "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
-                 "dd_unet_mse", "dd_unet_adam", "dd_surrogate_inputs", "dd_surrogate_targets",
-                 "dd_unet_predict"):
+                 "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
+                 "dd_surrogate_targets", "dd_unet_predict"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -285,31 +286,55 @@ def profile_read(kernel: str, reset: bool = True) -> dict:
 # ---------------------------------------------------------------------------
 # Learned surrogate (dd_unet_*): U-Net on 64x64 scans, BF16 MFMA kernels.
 SIDE = 64
+CHANNELS = 5  # DD_SURROGATE_CHANNELS
 
 
 def _handles(scans):
     return (ctypes.c_void_p * len(scans))(*[s.handle.value for s in scans])
 
 
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def surrogate_inputs(scans, stream=None):
-    """Network inputs [n, 64, 64, 3] (float32 CUDA) of 64x64 scans."""
+    """Network inputs x [n, 64, 64, CHANNELS] and own-visit terms [n, 64, 64]
+    (float32 CUDA) of 64x64 scans."""
     torch = _torch()
-    x = torch.empty((len(scans), SIDE, SIDE, 3), dtype=torch.float32, device="cuda")
-    _check(load_library().dd_surrogate_inputs(_handles(scans), len(scans),
-                                              ctypes.c_void_p(x.data_ptr()), _stream(stream)))
-    return x
+    n = len(scans)
+    x = torch.empty((n, SIDE, SIDE, CHANNELS), dtype=torch.float32, device="cuda")
+    own = torch.empty((n, SIDE, SIDE), dtype=torch.float32, device="cuda")
+    _check(load_library().dd_surrogate_inputs(_handles(scans), n, _ptr(x), _ptr(own),
+                                              _stream(stream)))
+    return x, own
 
 
 def surrogate_targets(scans, psi, stream=None):
-    """Training targets ln(psi 4 pi D / Q0) [n, 64, 64] from exact final maps."""
+    """Training targets psi 4 pi D / Q0 [n, 64, 64] (float32) from exact final maps."""
     torch = _torch()
     psi = psi.contiguous()
     assert psi.dtype == torch.float64 and psi.numel() == len(scans) * SIDE * SIDE
     t = torch.empty((len(scans), SIDE, SIDE), dtype=torch.float32, device="cuda")
-    _check(load_library().dd_surrogate_targets(_handles(scans), len(scans),
-                                               ctypes.c_void_p(psi.data_ptr()),
-                                               ctypes.c_void_p(t.data_ptr()), _stream(stream)))
+    _check(load_library().dd_surrogate_targets(_handles(scans), len(scans), _ptr(psi), _ptr(t),
+                                               _stream(stream)))
     return t
+
+
+def surrogate_batch(x_all, own_all, t_all, idx, transform, stream=None):
+    """Mini-batch (x, own, t) of maps idx under the square's symmetries
+    `transform` (int32 CUDA tensors, values 0..7)."""
+    torch = _torch()
+    nb = int(idx.numel())
+    assert idx.dtype == torch.int32 and transform.dtype == torch.int32 and transform.numel() == nb
+    xb = torch.empty((nb, SIDE, SIDE, CHANNELS), dtype=torch.float32, device="cuda")
+    ob = torch.empty((nb, SIDE, SIDE), dtype=torch.float32, device="cuda")
+    tb = torch.empty_like(ob)
+    assert x_all.shape[0] == own_all.shape[0] == t_all.shape[0]
+    _check(load_library().dd_surrogate_batch(_ptr(x_all), _ptr(own_all), _ptr(t_all),
+                                             x_all.shape[0], _ptr(idx.contiguous()),
+                                             _ptr(transform.contiguous()),
+                                             nb, _ptr(xb), _ptr(ob), _ptr(tb), _stream(stream)))
+    return xb, ob, tb
 
 
 class UNet:
@@ -350,36 +375,43 @@ class UNet:
         _check(load_library().dd_unet_grads(self._h, ctypes.c_void_p(out.ctypes.data)))
         return out
 
-    def forward(self, x, stream=None):
+    def forward(self, x, train: bool = False, stream=None):
         torch = _torch()
         x = x.contiguous()
-        assert x.dtype == torch.float32 and x.shape[1:] == (SIDE, SIDE, 3)
+        assert x.dtype == torch.float32 and x.shape[1:] == (SIDE, SIDE, CHANNELS)
         y = torch.empty((x.shape[0], SIDE, SIDE), dtype=torch.float32, device="cuda")
-        _check(load_library().dd_unet_forward(self._h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
-                                              ctypes.c_void_p(y.data_ptr()), _stream(stream)))
+        _check(load_library().dd_unet_forward(self._h, x.shape[0], _ptr(x), _ptr(y),
+                                              1 if train else 0, _stream(stream)))
+        self._x = x  # the backward pass reads the input again
         return y
 
     def backward(self, dy, stream=None):
         dy = dy.contiguous()
-        _check(load_library().dd_unet_backward(self._h, ctypes.c_void_p(dy.data_ptr()),
-                                               _stream(stream)))
+        _check(load_library().dd_unet_backward(self._h, _ptr(self._x), _ptr(dy), _stream(stream)))
 
-    def mse(self, y, t, want_loss: bool = True, stream=None):
-        """Returns (loss or None, dy)."""
+    def loss(self, y, own, t, anchor: float = 1.0, want_loss: bool = True, stream=None):
+        """Mean squared relative L2 error of own + exp(y) against t per map
+        and the gradient dy of that loss plus the anchor term (include/dd.h);
+        returns (loss or None, dy)."""
         torch = _torch()
-        y, t = y.contiguous(), t.contiguous()
+        y, own, t = y.contiguous(), own.contiguous(), t.contiguous()
         dy = torch.empty_like(y)
         loss = ctypes.c_double(0.0)
-        _check(load_library().dd_unet_mse(self._h, y.numel(), ctypes.c_void_p(y.data_ptr()),
-                                          ctypes.c_void_p(t.data_ptr()),
-                                          ctypes.c_void_p(dy.data_ptr()),
-                                          ctypes.byref(loss) if want_loss else None,
-                                          _stream(stream)))
+        _check(load_library().dd_unet_loss(self._h, y.shape[0], _ptr(y), _ptr(own), _ptr(t),
+                                           anchor, _ptr(dy),
+                                           ctypes.byref(loss) if want_loss else None,
+                                           _stream(stream)))
         return (loss.value if want_loss else None), dy
 
     def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
-             stream=None):
-        _check(load_library().dd_unet_adam(self._h, lr, beta1, beta2, eps, _stream(stream)))
+             clip: float = 0.0, want_norm: bool = False, stream=None):
+        """One Adam step with global-norm clipping; returns the gradient norm
+        when want_norm (synchronizes)."""
+        norm = ctypes.c_float(0.0)
+        _check(load_library().dd_unet_adam(self._h, lr, beta1, beta2, eps, clip,
+                                           ctypes.byref(norm) if want_norm else None,
+                                           _stream(stream)))
+        return norm.value if want_norm else None
 
     def predict(self, scans, spot_tol: float = 0.02, precision: str = "mixed", stream=None):
         """Final maps [n, 64, 64] (float64 CUDA, u/m^2) and the fallback flags."""

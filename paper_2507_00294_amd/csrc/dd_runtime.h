@@ -98,11 +98,17 @@ struct dd_scan {
   dd::DevBuf rows64, rows32;        // integer-lag rows n = 0 .. n_rows-1
   int64_t n_rows = 0;
   dd::DevBuf partial, items, aux, aux2, aux3, tmp_out, maprows64, maprows32;
+  // Surrogate input table (per probe: the network inputs, then the own-visit
+  // term), built on first use; sur_state 0 = not built, 1 = built, -1 = the
+  // scan is outside what the surrogate accepts.
+  dd::DevBuf sur;
+  int sur_state = 0;
 
   void release_device() {
     for (dd::DevBuf* b : {&pos32, &pos64, &pos4, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,
-                          &tmp_out, &maprows64, &maprows32})
+                          &tmp_out, &maprows64, &maprows32, &sur})
       b->release();
+    sur_state = 0;
     n_rows = 0;
     dev = -1;
   }

@@ -1,4 +1,5 @@
-// unet_kernels.h -- launchers of the surrogate's HIP kernels (unet_kernels.hip).
+// unet_kernels.h -- launchers of the surrogate's HIP kernels (unet_conv.hip,
+// unet_kernels.hip).  All activations are NHWC FP32; GEMM operands BF16.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -7,18 +8,39 @@
 namespace dd {
 namespace nn {
 
-// C = A B on BF16 MFMA (FP32 accumulation); ta/tb select transposed storage
-// (see k_gemm); with ksplit > 1, gemm_splits() partial matrices are written at
+// One convolution layer for the weight-layout kernel.
+struct ConvDesc {
+  int ci, co, kpad, has_dgrad;  // kpad: row length of the forward layout (>= 9 ci)
+  int64_t w_off, wf_off, wd_off;  // FP32 master, BF16 forward [co][kpad], BF16 dgrad [ci][9 co]
+};
+constexpr int kMaxConv = 16;
+struct ConvTable {
+  int n;
+  ConvDesc l[kMaxConv];
+};
+constexpr int kNormBlocks = 256;  // partial sums of the gradient norm
+
+// Implicit-GEMM 3x3 convolution (unet_conv.hip) of x [B][side][side][ci],
+// side = 2^lg, with weights wt [co][9 ci] (k = tap ci + c):
+//   conv3_silu:  z = conv + bias, act = SiLU(z) (z stored when non-NULL);
+//   conv3_plain: out = conv (the data gradient uses it with the dgrad layout).
+// ci and co must be multiples of 32.
+hipError_t conv3_silu(const float* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
+                      float* act, float* z, int co, hipStream_t st);
+hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, float* out, int co,
+                       hipStream_t st);
+// The same GEMM over explicit BF16 rows a [M][k] (k a multiple of 32).
+hipError_t rows_silu(const __bf16* a, int M, int k, const __bf16* wt, const float* bias, float* act,
+                     float* z, int co, hipStream_t st);
+
+// C = A B on BF16 MFMA (FP32 accumulation); ta/tb select transposed storage;
+// with ksplit > 1 the partial matrices (gemm_splits() of them) are written at
 // C + s*M*ldc and must be added by sum_splits.
 hipError_t gemm(const __bf16* A, int lda, bool ta, const __bf16* B, int ldb, bool tb, float* C,
                 int ldc, int M, int N, int K, int ksplit, hipStream_t st);
 int gemm_splits(int M, int K, int ksplit);
-// act = SiLU(A B + bias), z = A B + bias.
-hipError_t gemm_bias_silu(const __bf16* A, int lda, const __bf16* B, int ldb, float* act, float* z,
-                          int ldc, const float* bias, int M, int N, int K, hipStream_t st);
 hipError_t sum_splits(const float* part, int splits, int64_t n, float* out, hipStream_t st);
-hipError_t im2col(const float* x, int B, int H, int W, int C, __bf16* col, hipStream_t st);
-hipError_t col2im(const float* dcol, int B, int H, int W, int C, float* dx, hipStream_t st);
+hipError_t im2col(const float* x, int B, int H, int W, int C, int ld, __bf16* col, hipStream_t st);
 hipError_t silu_bwd(const float* dA, const float* Z, int64_t n, float* dZ, __bf16* dZb,
                     hipStream_t st);
 hipError_t colsum_add(const float* dZ, int M, int N, float* db, hipStream_t st);
@@ -32,16 +54,31 @@ hipError_t head_fwd(const float* a, int64_t M, int C, const float* w, const floa
                     hipStream_t st);
 hipError_t head_bwd(const float* dy, const float* a, int64_t M, int C, const float* w, float* da,
                     float* dw, hipStream_t st);
-hipError_t mse(const float* y, const float* t, int64_t n, float* dy, double* partial, int nblocks,
-               hipStream_t st);
-hipError_t adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                float eps, float bc1, float bc2, __bf16* wb, hipStream_t st);
-hipError_t to_bf16(const float* x, int64_t n, __bf16* y, hipStream_t st);
-hipError_t fill(float* x, int64_t n, float v, hipStream_t st);
-hipError_t exp_out(const float* y, int64_t n, int64_t per_map, const double* pref, double* psi,
-                   hipStream_t st);
-hipError_t log_target(const double* psi, int64_t n, int64_t per_map, const double* pref, float* t,
+// Squared relative L2 error per map (loss_map[b]) of prediction own + exp(y)
+// against t; dy of the mean over maps of that error plus the anchor term
+// (anchor / npx) sum (r/t)^2 (y - ln r)^2, r = max(t - own, 1e-6 t).
+hipError_t rel_l2(const float* y, const float* own, const float* t, int maps, int npx, float anchor,
+                  float* dy, double* loss_map, hipStream_t st);
+// scale_norm[0] = clipping factor of g (global norm), scale_norm[1] = |g|;
+// partial holds kNormBlocks doubles.
+hipError_t clip_scale(const float* g, int64_t n, float clip, double* partial, float* scale_norm,
                       hipStream_t st);
+hipError_t adam(float* w, float* m, float* v, const float* g, const float* scale, int64_t n,
+                float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st);
+hipError_t prep_weights(const float* w, const ConvTable& tab, __bf16* wf, __bf16* wd,
+                        hipStream_t st);
+hipError_t gather_batch(const float* x_all, const float* own_all, const float* t_all,
+                        int64_t n_all, int cin, int side, const int32_t* idx, const int32_t* tf,
+                        int nb, float* xb, float* ob, float* tb, hipStream_t st);
+hipError_t gather_features(const float* const* feat, int nb, int cin, int npx, float* x,
+                           float* own, hipStream_t st);
+hipError_t output(const float* y, const float* own, int nb, int npx, const double* pref,
+                  double* const* out, hipStream_t st);
+hipError_t target(const double* psi, int64_t n, int64_t per_map, const double* pref, float* t,
+                  hipStream_t st);
+hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int row,
+                double* rel, hipStream_t st);
+hipError_t fill(float* x, int64_t n, float v, hipStream_t st);
 
 }  // namespace nn
 }  // namespace dd

@@ -1,13 +1,12 @@
-// unet_kernels.hip -- kernels of the learned surrogate: a U-Net trained and
-// run with BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation) on gfx950.
-//
-// A 3x3 convolution is an im2col (activations FP32 -> BF16 columns) followed by
-// a GEMM Z = Xcol W (M = pixels, N = output channels, K = 9 input channels).
-// Backward: dW = Xcol^T dZ (split over M, partials added in a fixed order),
-// dXcol = dZ W^T, then col2im (a gather, no atomics).  Elementwise kernels
-// cover bias + SiLU, 2x2 average pooling, nearest 2x upsampling, the channel
-// concatenation of skip connections, the 1x1 output head (FP32), the loss and
-// Adam with FP32 master weights.
+// unet_kernels.hip -- kernels of the learned surrogate other than the
+// implicit-GEMM convolution (unet_conv.hip): the weight-gradient GEMM on BF16
+// MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation) over im2col columns, the
+// first layer's im2col, SiLU backward, bias gradients, 2x2 average pooling,
+// nearest 2x upsampling with the skip concatenation, the FP32 1x1 head, the
+// relative-L2 loss, gradient-norm clipping, Adam with FP32 master weights and
+// the rearrangement of the weights into the convolution's BF16 layouts, the
+// dihedral mini-batch gather of training, and the surrogate's input gather,
+// output transform and spot-check.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -132,46 +131,25 @@ __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-// im2col for a 3x3 convolution with zero padding 1 (NHWC, FP32 -> BF16):
+// im2col for a 3x3 convolution with zero padding 1 (NHWC, FP32 -> BF16), rows
+// of ld >= 9 C columns (columns past 9 C are zero):
 // col[m][(ky*3+kx)*C + c] = x[n][y+ky-1][x+kx-1][c], m = (n*H + y)*W + x.
 __global__ void __launch_bounds__(256) k_im2col(const float* __restrict__ x, int B, int H, int W,
-                                                int C, __bf16* __restrict__ col) {
-  const int64_t K = 9 * (int64_t)C, total = (int64_t)B * H * W * K;
+                                                int C, int ld, __bf16* __restrict__ col) {
+  const int64_t K = 9 * (int64_t)C, total = (int64_t)B * H * W * ld;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t m = e / K;
-    const int k = (int)(e % K);
-    const int tap = k / C, c = k % C;
-    const int ky = tap / 3, kx = tap % 3;
-    const int xx = (int)(m % W), yy = (int)((m / W) % H), n = (int)(m / ((int64_t)W * H));
-    const int sy = yy + ky - 1, sx = xx + kx - 1;
+    const int64_t m = e / ld;
+    const int k = (int)(e % ld);
     float v = 0.f;
-    if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = x[(((int64_t)n * H + sy) * W + sx) * C + c];
+    if (k < K) {
+      const int tap = k / C, c = k % C;
+      const int ky = tap / 3, kx = tap % 3;
+      const int xx = (int)(m % W), yy = (int)((m / W) % H), n = (int)(m / ((int64_t)W * H));
+      const int sy = yy + ky - 1, sx = xx + kx - 1;
+      if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = x[(((int64_t)n * H + sy) * W + sx) * C + c];
+    }
     col[e] = (__bf16)v;
-  }
-}
-
-// col2im (the adjoint of k_im2col): dx[n][y][x][c] = sum over taps of
-// dcol[m'][(ky*3+kx)*C + c] with m' the pixel (y-ky+1, x-kx+1); a gather in
-// fixed tap order.
-__global__ void __launch_bounds__(256) k_col2im(const float* __restrict__ dcol, int B, int H,
-                                                int W, int C, float* __restrict__ dx) {
-  const int64_t total = (int64_t)B * H * W * C, K = 9 * (int64_t)C;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % C);
-    const int64_t p = e / C;
-    const int xx = (int)(p % W), yy = (int)((p / W) % H), n = (int)(p / ((int64_t)W * H));
-    float s = 0.f;
-#pragma unroll
-    for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const int ty = yy - ky + 1, tx = xx - kx + 1;
-        if (ty >= 0 && ty < H && tx >= 0 && tx < W)
-          s += dcol[(((int64_t)n * H + ty) * W + tx) * K + (ky * 3 + kx) * C + c];
-      }
-    dx[e] = s;
   }
 }
 
@@ -315,19 +293,66 @@ __global__ void __launch_bounds__(256) k_head_bwd_w(const float* __restrict__ dy
   if (threadIdx.x == 0) dw[c] = red[0];
 }
 
-// Mean squared error over masked elements: per-block partial sums (fixed
-// order) and the gradient dy = 2 (y - t) / count.
-__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const float* __restrict__ t,
-                                             int64_t n, float inv_n, float* __restrict__ dy,
-                                             double* __restrict__ partial) {
+// Loss of a batch of maps (one block per map of n pixels).  The prediction
+// is own + exp(y) (exp argument capped at 80); map b's loss is its squared
+// relative L2 error |pred - t|^2 / |t|^2, written to loss_map[b].  The
+// objective whose gradient dy is returned (for the mean over maps) adds the
+// anchor (anchor / n) sum_i (r_i / t_i)^2 (y_i - ln r_i)^2 with r_i = max(t_i
+// - own_i, 1e-6 t_i): the same per-pixel weight as the relative error, but a
+// gradient that does not vanish when exp(y) is far below r.  Sums are in
+// double, in a fixed order.
+__global__ void __launch_bounds__(256) k_rel_l2(const float* __restrict__ y,
+                                                const float* __restrict__ own,
+                                                const float* __restrict__ t, int n, float inv_maps,
+                                                float anchor, float* __restrict__ dy,
+                                                double* __restrict__ loss_map) {
+  __shared__ double red[256];
+  const int64_t base = (int64_t)blockIdx.x * n;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double ti = t[base + i];
+    s += ti * ti;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double den = red[0] > 0.0 ? red[0] : 1.0;
+  __syncthreads();
+  const float scale = (float)(2.0 / den) * inv_maps;
+  const float ascale = 2.0f * anchor / (float)n * inv_maps;
+  double num = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const float yi = y[base + i], ti = t[base + i], oi = own[base + i];
+    const float e = __expf(fminf(yi, 80.0f));
+    const float d = oi + e - ti;
+    num += (double)d * d;
+    float g = scale * d * e;
+    if (ti > 0.f) {
+      const float r = fmaxf(ti - oi, 1e-6f * ti), wr = r / ti;
+      g += ascale * wr * wr * (yi - __logf(r));
+    }
+    dy[base + i] = g;
+  }
+  red[threadIdx.x] = num;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_map[blockIdx.x] = red[0] / den;
+}
+
+// Sum of squares of g: one partial per block (the grid has kNormBlocks blocks).
+__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ g, int64_t n,
+                                               double* __restrict__ partial) {
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const float d = y[e] - t[e];
-    dy[e] = 2.0f * d * inv_n;
-    s += (double)d * d;
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    s += (double)g[e] * g[e];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -337,30 +362,176 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ y, const 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// Adam with FP32 master weights (bias-corrected), then the BF16 copy used by
-// the GEMMs.  bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+// scale_norm[0] = min(1, clip / |g|) (1 when clip <= 0, 0 when |g| is not
+// finite, which skips the update); scale_norm[1] = |g|.
+__global__ void __launch_bounds__(256) k_clip_scale(const double* __restrict__ partial, float clip,
+                                                    float* __restrict__ scale_norm) {
+  __shared__ double red[256];
+  red[threadIdx.x] = partial[threadIdx.x];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double norm = sqrt(red[0]);
+    double sc = 1.0;
+    if (clip > 0.f && norm > clip) sc = clip / norm;
+    if (!(norm <= 1e300)) sc = 0.0;
+    scale_norm[0] = (float)sc;
+    scale_norm[1] = (float)norm;
+  }
+}
+
+// Adam with FP32 master weights (bias-corrected) on the scaled gradient
+// g * scale[0].  bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, float* __restrict__ m,
                                               float* __restrict__ v, const float* __restrict__ g,
-                                              int64_t n, float lr, float b1, float b2, float eps,
-                                              float bc1, float bc2, __bf16* __restrict__ wb) {
+                                              const float* __restrict__ scale, int64_t n, float lr,
+                                              float b1, float b2, float eps, float bc1, float bc2) {
+  const float sc = scale[0];
+  if (sc == 0.f) return;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[e];
+    const float gi = g[e] * sc;
     const float mi = b1 * m[e] + (1.0f - b1) * gi;
     const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
     m[e] = mi;
     v[e] = vi;
-    const float wi = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-    w[e] = wi;
-    wb[e] = (__bf16)wi;
+    w[e] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   }
 }
 
-__global__ void __launch_bounds__(256) k_to_bf16(const float* __restrict__ x, int64_t n,
-                                                 __bf16* __restrict__ y) {
+// BF16 weight layouts of the convolutions from the FP32 master vector (layer
+// blockIdx.y), whose weights W[k][j] (k = tap ci + c) start at w_off:
+//   forward  wf[j][k], k < kpad (zero for k >= 9 ci);
+//   dgrad    wd[c][t co + j] = W[(8 - t) ci + c][j] (mirrored taps).
+__global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ w, ConvTable tab,
+                                                      __bf16* __restrict__ wf,
+                                                      __bf16* __restrict__ wd) {
+  const ConvDesc L = tab.l[blockIdx.y];
+  const int64_t nf = (int64_t)L.co * L.kpad, nd = L.has_dgrad ? 9LL * L.ci * L.co : 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nf + nd;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nf) {
+      const int j = (int)(e / L.kpad), k = (int)(e % L.kpad);
+      wf[L.wf_off + e] = k < 9 * L.ci ? (__bf16)w[L.w_off + (int64_t)k * L.co + j] : (__bf16)0.f;
+    } else {
+      const int64_t f = e - nf;
+      const int K2 = 9 * L.co;
+      const int c = (int)(f / K2), r = (int)(f % K2);
+      const int t = r / L.co, j = r % L.co;
+      wd[L.wd_off + f] = (__bf16)w[L.w_off + ((int64_t)(8 - t) * L.ci + c) * L.co + j];
+    }
+  }
+}
+
+// Dihedral transform of a side x side map: destination pixel (i, j) reads
+// source pixel T_f(i, j), f in 0..7: transpose if f & 1, then mirror rows if
+// f & 2 and columns if f & 4.
+__device__ __forceinline__ int dihedral_src(int i, int j, int f, int side) {
+  if (f & 1) {
+    const int t = i;
+    i = j;
+    j = t;
+  }
+  if (f & 2) i = side - 1 - i;
+  if (f & 4) j = side - 1 - j;
+  return i * side + j;
+}
+
+// Training mini-batch: map idx[b] of (x_all [cin channels], own_all, t_all;
+// n_all maps) under the dihedral transform tf[b], into slot b of (xb, ob,
+// tb); an index outside [0, n_all) gives a zero slot.
+__global__ void __launch_bounds__(256) k_gather_batch(
+    const float* __restrict__ x_all, const float* __restrict__ own_all,
+    const float* __restrict__ t_all, int64_t n_all, int cin, int side,
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ tf, int nb,
+    float* __restrict__ xb, float* __restrict__ ob, float* __restrict__ tb) {
+  const int npx = side * side;
+  const int64_t total = (int64_t)nb * npx;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / npx), p = (int)(e % npx);
+    const int64_t m = idx[b];
+    if (m < 0 || m >= n_all) {
+      for (int c = 0; c < cin; ++c) xb[e * cin + c] = 0.f;
+      ob[e] = 0.f;
+      tb[e] = 0.f;
+      continue;
+    }
+    const int64_t src = m * npx + dihedral_src(p / side, p % side, tf[b] & 7, side);
+    for (int c = 0; c < cin; ++c) xb[e * cin + c] = x_all[src * cin + c];
+    ob[e] = own_all[src];
+    tb[e] = t_all[src];
+  }
+}
+
+// Inference inputs of map b from its scan's cached table feat[b] (cin inputs,
+// then the own-visit term, per pixel).
+__global__ void __launch_bounds__(256) k_gather_features(const float* const* __restrict__ feat,
+                                                         int nb, int cin, int npx,
+                                                         float* __restrict__ x,
+                                                         float* __restrict__ own) {
+  const int64_t total = (int64_t)nb * npx;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / npx), p = (int)(e % npx);
+    const float* f = feat[b] + (int64_t)p * (cin + 1);
+    for (int c = 0; c < cin; ++c) x[e * cin + c] = f[c];
+    own[e] = f[cin];
+  }
+}
+
+// Prediction output: map b, psi = pref[b] (own + exp(y)) in double, written to
+// out[b] (npx values).
+__global__ void __launch_bounds__(256) k_output(const float* __restrict__ y,
+                                                const float* __restrict__ own, int nb, int npx,
+                                                const double* __restrict__ pref,
+                                                double* const* __restrict__ out) {
+  const int64_t total = (int64_t)nb * npx;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / npx), p = (int)(e % npx);
+    out[b][p] = pref[b] * ((double)own[e] + exp((double)fminf(y[e], 80.0f)));
+  }
+}
+
+// Training target: the dimensionless map psi / pref (float).
+__global__ void __launch_bounds__(256) k_target(const double* __restrict__ psi, int64_t n,
+                                                int64_t per_map, const double* __restrict__ pref,
+                                                float* __restrict__ t) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
-    y[e] = (__bf16)x[e];
+    t[e] = (float)(psi[e] / pref[e / per_map]);
+}
+
+// Spot check of map b: relative L2 distance between row `row` of pred[b]
+// (side x side) and the exact row exact[b side ..]; one wave per map,
+// fixed-order sums.
+__global__ void __launch_bounds__(64) k_spot(const double* const* __restrict__ pred,
+                                             const double* __restrict__ exact, int side, int row,
+                                             double* __restrict__ rel) {
+  __shared__ double a[64], b[64];
+  const int m = blockIdx.x;
+  double num = 0.0, den = 0.0;
+  for (int c = threadIdx.x; c < side; c += 64) {
+    const double e = exact[(int64_t)m * side + c];
+    const double d = pred[m][(int64_t)row * side + c] - e;
+    num += d * d;
+    den += e * e;
+  }
+  a[threadIdx.x] = num;
+  b[threadIdx.x] = den;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      a[threadIdx.x] += a[threadIdx.x + w];
+      b[threadIdx.x] += b[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rel[m] = b[0] > 0 ? sqrt(a[0] / b[0]) : (a[0] > 0 ? 1.0 : 0.0);
 }
 
 __global__ void __launch_bounds__(256) k_fill(float* __restrict__ x, int64_t n, float v) {
@@ -369,23 +540,6 @@ __global__ void __launch_bounds__(256) k_fill(float* __restrict__ x, int64_t n, 
     x[e] = v;
 }
 
-// Surrogate output transform: psi = exp(y) * pref_k for map k (maps of
-// `per_map` pixels), in double; and the training target log(psi / pref_k).
-__global__ void __launch_bounds__(256) k_exp_out(const float* __restrict__ y, int64_t n,
-                                                 int64_t per_map, const double* __restrict__ pref,
-                                                 double* __restrict__ psi) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    psi[e] = exp((double)y[e]) * pref[e / per_map];
-}
-
-__global__ void __launch_bounds__(256) k_log_target(const double* __restrict__ psi, int64_t n,
-                                                    int64_t per_map, const double* __restrict__ pref,
-                                                    float* __restrict__ t) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    t[e] = (float)log(fmax(psi[e] / pref[e / per_map], 1e-300));
-}
 
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(int64_t n) {
@@ -423,28 +577,15 @@ int gemm_splits(int M, int K, int ksplit) {
   return (K + kchunk - 1) / kchunk;
 }
 
-hipError_t gemm_bias_silu(const __bf16* A, int lda, const __bf16* B, int ldb, float* act, float* z,
-                          int ldc, const float* bias, int M, int N, int K, hipStream_t st) {
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, 1);
-  hipLaunchKernelGGL((k_gemm<false, false, EPI_BIAS_SILU>), grid, dim3(256), 0, st, A, lda, B, ldb,
-                     act, ldc, z, bias, M, N, K, ((K + BK - 1) / BK) * BK);
-  return hipGetLastError();
-}
-
 hipError_t sum_splits(const float* part, int splits, int64_t n, float* out, hipStream_t st) {
   hipLaunchKernelGGL(k_sum_splits, dim3(blocks_for(n)), dim3(256), 0, st, part, splits, n, out);
   return hipGetLastError();
 }
 
-hipError_t im2col(const float* x, int B, int H, int W, int C, __bf16* col, hipStream_t st) {
-  hipLaunchKernelGGL(k_im2col, dim3(blocks_for((int64_t)B * H * W * 9 * C)), dim3(256), 0, st, x,
-                     B, H, W, C, col);
-  return hipGetLastError();
-}
-
-hipError_t col2im(const float* dcol, int B, int H, int W, int C, float* dx, hipStream_t st) {
-  hipLaunchKernelGGL(k_col2im, dim3(blocks_for((int64_t)B * H * W * C)), dim3(256), 0, st, dcol, B,
-                     H, W, C, dx);
+hipError_t im2col(const float* x, int B, int H, int W, int C, int ld, __bf16* col, hipStream_t st) {
+  if (ld < 9 * C) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_im2col, dim3(blocks_for((int64_t)B * H * W * ld)), dim3(256), 0, st, x, B,
+                     H, W, C, ld, col);
   return hipGetLastError();
 }
 
@@ -499,38 +640,76 @@ hipError_t head_bwd(const float* dy, const float* a, int64_t M, int C, const flo
   return hipGetLastError();
 }
 
-hipError_t mse(const float* y, const float* t, int64_t n, float* dy, double* partial, int nblocks,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_mse, dim3(nblocks), dim3(256), 0, st, y, t, n, 1.0f / (float)n, dy, partial);
+hipError_t rel_l2(const float* y, const float* own, const float* t, int maps, int npx, float anchor,
+                  float* dy, double* loss_map, hipStream_t st) {
+  hipLaunchKernelGGL(k_rel_l2, dim3(maps), dim3(256), 0, st, y, own, t, npx, 1.0f / (float)maps,
+                     anchor, dy, loss_map);
   return hipGetLastError();
 }
 
-hipError_t adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
-                float eps, float bc1, float bc2, __bf16* wb, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, st, w, m, v, g, n, lr, b1, b2, eps,
-                     bc1, bc2, wb);
+hipError_t clip_scale(const float* g, int64_t n, float clip, double* partial, float* scale_norm,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(kNormBlocks), dim3(256), 0, st, g, n, partial);
+  hipLaunchKernelGGL(k_clip_scale, dim3(1), dim3(kNormBlocks), 0, st, partial, clip, scale_norm);
   return hipGetLastError();
 }
 
-hipError_t to_bf16(const float* x, int64_t n, __bf16* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(256), 0, st, x, n, y);
+hipError_t adam(float* w, float* m, float* v, const float* g, const float* scale, int64_t n,
+                float lr, float b1, float b2, float eps, float bc1, float bc2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, st, w, m, v, g, scale, n, lr, b1, b2,
+                     eps, bc1, bc2);
+  return hipGetLastError();
+}
+
+hipError_t prep_weights(const float* w, const ConvTable& tab, __bf16* wf, __bf16* wd,
+                        hipStream_t st) {
+  int64_t most = 0;
+  for (int l = 0; l < tab.n; ++l) {
+    const ConvDesc& L = tab.l[l];
+    const int64_t n = (int64_t)L.co * L.kpad + (L.has_dgrad ? 9LL * L.ci * L.co : 0);
+    most = n > most ? n : most;
+  }
+  hipLaunchKernelGGL(k_prep_weights, dim3(blocks_for(most), tab.n), dim3(256), 0, st, w, tab, wf,
+                     wd);
+  return hipGetLastError();
+}
+
+hipError_t gather_batch(const float* x_all, const float* own_all, const float* t_all,
+                        int64_t n_all, int cin, int side, const int32_t* idx, const int32_t* tf,
+                        int nb, float* xb, float* ob, float* tb, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_batch, dim3(blocks_for((int64_t)nb * side * side)), dim3(256), 0, st,
+                     x_all, own_all, t_all, n_all, cin, side, idx, tf, nb, xb, ob, tb);
+  return hipGetLastError();
+}
+
+hipError_t gather_features(const float* const* feat, int nb, int cin, int npx, float* x,
+                           float* own, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_features, dim3(blocks_for((int64_t)nb * npx)), dim3(256), 0, st,
+                     feat, nb, cin, npx, x, own);
+  return hipGetLastError();
+}
+
+hipError_t output(const float* y, const float* own, int nb, int npx, const double* pref,
+                  double* const* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_output, dim3(blocks_for((int64_t)nb * npx)), dim3(256), 0, st, y, own, nb,
+                     npx, pref, out);
+  return hipGetLastError();
+}
+
+hipError_t target(const double* psi, int64_t n, int64_t per_map, const double* pref, float* t,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_target, dim3(blocks_for(n)), dim3(256), 0, st, psi, n, per_map, pref, t);
+  return hipGetLastError();
+}
+
+hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int row,
+                double* rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_spot, dim3(maps), dim3(64), 0, st, pred, exact, side, row, rel);
   return hipGetLastError();
 }
 
 hipError_t fill(float* x, int64_t n, float v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, x, n, v);
-  return hipGetLastError();
-}
-
-hipError_t exp_out(const float* y, int64_t n, int64_t per_map, const double* pref, double* psi,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_exp_out, dim3(blocks_for(n)), dim3(256), 0, st, y, n, per_map, pref, psi);
-  return hipGetLastError();
-}
-
-hipError_t log_target(const double* psi, int64_t n, int64_t per_map, const double* pref, float* t,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_log_target, dim3(blocks_for(n)), dim3(256), 0, st, psi, n, per_map, pref, t);
   return hipGetLastError();
 }
 

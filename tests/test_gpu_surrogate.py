@@ -1,6 +1,8 @@
-"""Learned surrogate on the GPU: the BF16-MFMA U-Net forward pass and
-gradients against the CPU float64 reference network, the input and target
-definitions, and an end-to-end training run of the library's own kernels."""
+"""Learned surrogate on the GPU: the BF16-MFMA U-Net forward pass, loss and
+gradients against the CPU float64 reference network, the input table against
+its definition (the own-visit term against the oracle's Eq. 6 bracket), the
+symmetry gather of training batches, a short training run of the library's own
+kernels, and the exact fallback."""
 import math
 
 import numpy as np
@@ -21,7 +23,8 @@ def dd():
     return dd
 
 
-def test_forward_and_gradients_match_reference(dd):
+@pytest.mark.parametrize("batch", [3])
+def test_forward_loss_and_gradients_match_reference(dd, batch):
     import torch
 
     from oracle import unet_ref
@@ -29,29 +32,65 @@ def test_forward_and_gradients_match_reference(dd):
     net = dd.UNet(seed=3)
     assert net.num_params == unet_ref.num_params()
     p = net.params()
-    p[-1] = 0.3
+    p[-1] = -0.5
     net.set_params(p)
     rng = np.random.default_rng(7)
-    x = rng.random((2, 64, 64, 3)).astype(np.float32)
-    t = rng.normal(size=(2, 64, 64)).astype(np.float32)
-    y = net.forward(torch.tensor(x, device="cuda"))
-    loss, dy = net.mse(y, torch.tensor(t, device="cuda"))
+    x = rng.random((batch, 64, 64, dd.CHANNELS)).astype(np.float32)
+    own = rng.random((batch, 64, 64)).astype(np.float32)
+    t = (own + 0.6 + 0.2 * rng.random((batch, 64, 64))).astype(np.float32)
+    dev = lambda a: torch.tensor(a, device="cuda")
+    y = net.forward(dev(x), train=True)
+    loss, dy = net.loss(y, dev(own), dev(t))
     net.backward(dy)
     g = net.grads()
-    ref_loss, ref_y, ref_g = unet_ref.loss_and_grad(p.astype(np.float64), x, t)
-    y = y.cpu().numpy()
+    ref_loss, ref_y, ref_g, ref_dy = unet_ref.loss_and_grad(p.astype(np.float64), x, own, t)
+    y, dy = y.cpu().numpy(), dy.cpu().numpy()
     # BF16 operands (8-bit mantissa) with FP32 accumulation
     assert np.linalg.norm(y - ref_y) <= 2e-2 * np.linalg.norm(ref_y)
-    assert abs(loss - ref_loss) <= 2e-2 * ref_loss
+    assert abs(loss - ref_loss) <= 5e-2 * ref_loss
+    assert np.linalg.norm(dy - ref_dy) <= 5e-2 * np.linalg.norm(ref_dy)
     for name, s in unet_ref.layer_slices():
         gn = np.linalg.norm(ref_g[s])
         if gn == 0:
             continue
         err = np.linalg.norm(g[s] - ref_g[s]) / gn
         assert err <= 6e-2, (name, err)
-    # the gradient points the same way overall
     cos = float(np.dot(g, ref_g) / (np.linalg.norm(g) * np.linalg.norm(ref_g)))
     assert cos > 0.999
+
+
+def test_inference_forward_equals_training_forward(dd):
+    import torch
+
+    net = dd.UNet(seed=1)
+    x = torch.rand((5, 64, 64, dd.CHANNELS), device="cuda")
+    a = net.forward(x, train=True)
+    b = net.forward(x, train=False)
+    assert torch.equal(a, b)
+
+
+def _expected_table(spec, ids):
+    """Inputs and own-visit term from their definitions; O from the oracle."""
+    import oracle as ora
+
+    V = ids.size
+    tau = spec.dwell_s / spec.frames if spec.order == "multiframe" else spec.dwell_s
+    kap = spec.D_m2s * tau / spec.pitch_m ** 2
+    first = np.full(4096, -1)
+    last = np.full(4096, -1)
+    own = np.zeros(4096)
+    for v, pid in enumerate(ids):
+        if first[pid] < 0:
+            first[pid] = v
+        last[pid] = v
+        own[pid] += ora.phi_bracket_q(0.0, (V - v) * tau, tau, spec.sigma_m, spec.D_m2s)
+    x = np.empty((64, 64, 5))
+    x[..., 0] = (first / V).reshape(64, 64)
+    x[..., 1] = (math.log10(kap) + 1) / 3
+    x[..., 2] = (spec.sigma_m / spec.pitch_m - 0.6) / 0.4
+    x[..., 3] = (np.log(V - last) / np.log(V)).reshape(64, 64)
+    x[..., 4] = ((np.log(own) + 4) / 4).reshape(64, 64)
+    return x, own.reshape(64, 64)
 
 
 def test_inputs_and_targets(dd):
@@ -59,44 +98,71 @@ def test_inputs_and_targets(dd):
 
     from paper_2507_00294_amd import workloads as wl
 
-    specs = wl.surrogate_scans(3, seed=11)
+    specs = wl.surrogate_scans(8, seed=11)
+    assert {s.order for s in specs} >= {"multiframe"}  # covers frames > 1
     scans = [dd.Scan(**s.kwargs()) for s in specs]
-    x = dd.surrogate_inputs(scans).cpu().numpy()
+    x, own = dd.surrogate_inputs(scans)
+    x, own = x.cpu().numpy(), own.cpu().numpy()
     for k, (spec, s) in enumerate(zip(specs, scans)):
-        v = s.visits()
-        first = np.full(64 * 64, -1)
-        for j, pid in enumerate(v):
-            if first[pid] < 0:
-                first[pid] = j
-        assert np.allclose(x[k, :, :, 0].ravel(), first / v.size, rtol=0, atol=1e-7)
-        kap = spec.D_m2s * spec.dwell_s / spec.pitch_m ** 2
-        assert np.allclose(x[k, :, :, 1], (math.log10(kap) + 1) / 3, atol=1e-6)
-        assert np.allclose(x[k, :, :, 2], (spec.sigma_m / spec.pitch_m - 0.6) / 0.4, atol=1e-6)
+        ex, eo = _expected_table(spec, s.visits())
+        np.testing.assert_allclose(x[k], ex, rtol=2e-6, atol=2e-7)
+        np.testing.assert_allclose(own[k], eo, rtol=2e-6, atol=0)
     outs = dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, "fp64")
     psi = torch.stack([o.view(64, 64) for o in outs])
     t = dd.surrogate_targets(scans, psi).cpu().numpy()
     for k, spec in enumerate(specs):
         hat = psi[k].cpu().numpy() * 4 * math.pi * spec.D_m2s / spec.Q0_us
-        assert np.allclose(t[k], np.log(hat), rtol=0, atol=2e-5)
+        np.testing.assert_allclose(t[k], hat, rtol=1e-6)
+        assert np.all(t[k] >= own[k] * (1 - 1e-5))  # the own visits are part of the sum
+
+
+def test_batch_gather_applies_square_symmetries(dd):
+    import torch
+
+    n = 3
+    x = torch.rand((n, 64, 64, dd.CHANNELS), device="cuda")
+    own = torch.rand((n, 64, 64), device="cuda")
+    t = torch.rand((n, 64, 64), device="cuda")
+    idx = torch.tensor([2, 0, 1, 2, 1, 0, 2, 1], dtype=torch.int32, device="cuda")
+    tf = torch.arange(8, dtype=torch.int32, device="cuda")
+    xb, ob, tb = dd.surrogate_batch(x, own, t, idx, tf)
+    xn, on, tn = x.cpu().numpy(), own.cpu().numpy(), t.cpu().numpy()
+
+    def apply(a, f):  # destination (i, j) reads source T_f(i, j)
+        i, j = np.meshgrid(np.arange(64), np.arange(64), indexing="ij")
+        if f & 1:
+            i, j = j, i
+        if f & 2:
+            i = 63 - i
+        if f & 4:
+            j = 63 - j
+        return a[i, j]
+
+    for b in range(8):
+        src = int(idx[b])
+        assert np.array_equal(xb[b].cpu().numpy(), apply(xn[src], b))
+        assert np.array_equal(ob[b].cpu().numpy(), apply(on[src], b))
+        assert np.array_equal(tb[b].cpu().numpy(), apply(tn[src], b))
+    # all eight transforms of one map are distinct and include the identity
+    forms = {apply(np.arange(4096).reshape(64, 64), f).tobytes() for f in range(8)}
+    assert len(forms) == 8
 
 
 def test_training_reduces_loss(dd):
     from paper_2507_00294_amd import surrogate as sg
     from paper_2507_00294_amd import workloads as wl
 
-    x, t = sg.generate(wl.surrogate_scans(256, seed=12))
+    x, own, t = sg.generate(wl.surrogate_scans(256, seed=12))
     net = dd.UNet(seed=0)
-    sg.init_head(net, t)
-    hist = sg.train(net, x, t, steps=120, batch=16, lr=2e-3, log_every=40, warmup=20)
-    assert hist[-1][1] < 0.5 * hist[0][1], hist
+    sg.init_head(net, own, t)
+    hist = sg.train(net, x, own, t, steps=150, batch=16, lr=1e-3, log_every=50, warmup=20)
     assert all(np.isfinite(l) for _, l in hist)
+    assert hist[-1][1] < 0.5 * hist[0][1], hist
 
 
 def test_predict_fallback_is_exact(dd):
-    """With spot_tol = 0 every map is rejected and computed exactly; scans
+    """spot_tol = 0 rejects every map, which is then computed exactly; scans
     outside the training range always fall back."""
-    import torch
-
     from paper_2507_00294_amd import workloads as wl
 
     net = dd.UNet(seed=0)
@@ -110,3 +176,7 @@ def test_predict_fallback_is_exact(dd):
     odd = dd.Scan(64, 64, "raster", D_m2s=1e-9)  # kappa far outside the training range
     psi2, fb2 = net.predict([odd], spot_tol=1.0, precision="mixed")
     assert fb2.tolist() == [1]
+    # with an infinite tolerance every in-range map is the network's
+    psi3, fb3 = net.predict(scans, spot_tol=1e300, precision="mixed")
+    assert fb3.tolist() == [0, 0, 0, 0]
+    assert np.all(np.isfinite(psi3.cpu().numpy()))

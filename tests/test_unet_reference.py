@@ -1,5 +1,6 @@
 """Pins for the CPU float64 reference of the surrogate network: its autograd
-gradient against central finite differences, and its parameter layout."""
+gradient against central finite differences, its loss against a direct
+evaluation, and its parameter layout."""
 import numpy as np
 import pytest
 import torch
@@ -9,13 +10,19 @@ def test_layout_matches_library_count():
     from oracle import unet_ref
 
     # 14 convolutions (weights + biases) and the 33-value head
-    assert unet_ref.num_params() == 1_946_881
+    assert unet_ref.num_params() == 1_947_457
     sl = unet_ref.layer_slices()
     assert sl[-1][1].stop == unet_ref.num_params()
 
 
-@pytest.mark.parametrize("seed", [0, 1])
-def test_reference_gradient_against_finite_differences(seed):
+def _objective(unet_ref, p, x, own, t, anchor):
+    y = unet_ref.forward(torch.tensor(p), torch.tensor(x))
+    own_t, t_t = torch.tensor(own), torch.tensor(t)
+    return float(unet_ref.rel_l2_loss(y, own_t, t_t) + anchor * unet_ref.anchor_term(y, own_t, t_t))
+
+
+@pytest.mark.parametrize("seed,anchor", [(0, 0.0), (1, 1.0)])
+def test_reference_gradient_against_finite_differences(seed, anchor):
     from oracle import unet_ref
 
     rng = np.random.default_rng(seed)
@@ -29,9 +36,10 @@ def test_reference_gradient_against_finite_differences(seed):
             p[s] = rng.normal(0, 0.2, 33)
         else:
             p[s] = rng.normal(0, 0.05, s.stop - s.start)
-    x = rng.random((1, 16, 16, 3))
-    t = rng.normal(size=(1, 16, 16))
-    _, _, g = unet_ref.loss_and_grad(p, x, t)
+    x = rng.random((1, 16, 16, unet_ref.CIN))
+    own = rng.random((1, 16, 16))
+    t = own + rng.random((1, 16, 16)) + 0.5
+    _, _, g, _ = unet_ref.loss_and_grad(p, x, own, t, anchor=anchor)
     # a few parameters from several layers, central differences in float64
     picks = [unet_ref.layer_slices()[k][1].start + 3 for k in (0, 5, 14, 20, 27)]
     picks.append(n - 1)  # head bias
@@ -40,7 +48,30 @@ def test_reference_gradient_against_finite_differences(seed):
         pp, pm = p.copy(), p.copy()
         pp[i] += h
         pm[i] -= h
-        lp, _, _ = unet_ref.loss_and_grad(pp, x, t)
-        lm, _, _ = unet_ref.loss_and_grad(pm, x, t)
+        lp = _objective(unet_ref, pp, x, own, t, anchor)
+        lm = _objective(unet_ref, pm, x, own, t, anchor)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, (i, fd, g[i])
+
+
+def test_loss_is_mean_squared_relative_l2():
+    from oracle import unet_ref
+
+    rng = np.random.default_rng(3)
+    y = rng.normal(size=(3, 8, 8))
+    own = rng.random((3, 8, 8))
+    t = own + rng.random((3, 8, 8))
+    got = float(unet_ref.rel_l2_loss(torch.tensor(y), torch.tensor(own), torch.tensor(t)))
+    want = np.mean([np.sum((own[b] + np.exp(y[b]) - t[b]) ** 2) / np.sum(t[b] ** 2)
+                    for b in range(3)])
+    assert got == pytest.approx(want, rel=1e-14)
+    # an exact prediction has zero loss and zero anchor term
+    ye = torch.tensor(np.log(t - own))
+    assert float(unet_ref.rel_l2_loss(ye, torch.tensor(own), torch.tensor(t))) < 1e-28
+    assert float(unet_ref.anchor_term(ye, torch.tensor(own), torch.tensor(t))) < 1e-28
+    # the anchor term weighs pixel i by (r_i / t_i)^2
+    y0 = torch.zeros(1, 1, 2, dtype=torch.float64)
+    own2 = torch.tensor([[[1.0, 0.0]]], dtype=torch.float64)
+    t2 = torch.tensor([[[2.0, 4.0]]], dtype=torch.float64)
+    want2 = 0.5 * ((0.5 ** 2) * (0 - np.log(1.0)) ** 2 + 1.0 * (0 - np.log(4.0)) ** 2)
+    assert float(unet_ref.anchor_term(y0, own2, t2)) == pytest.approx(want2, rel=1e-12)
