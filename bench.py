@@ -5,13 +5,16 @@ Workload: the arrival query (Eq. 6 evaluated at every probe visit at the
 moment it starts) of a 512x512 probe grid scanned in a seeded random order,
 pitch 1 nm, sigma 0.4 nm, dwell 0.5 us, D = 1e-12 m^2/s, in mixed precision:
 262144 visits, 3.436e10 causal pair terms per step.  One step is one full
-query (lag rows, near band, far region, fixed-order reduction) with the probe
-table resident in HBM.  Prints one JSON line.
+query (near band, far region, fixed-order reduction) with the scan's probe
+and lag-row tables resident in HBM (the first query builds them).  Prints
+one JSON line.
 
 The dominant kernel (far region) is timed with HIP events on the stream it
 runs on; its algorithmic FLOPs per launch come from the library's plan.  The
 CPU oracle is timed on a seeded sample of the same visits and its values are
-the accuracy check of the GPU result.
+the accuracy check of the GPU result.  The learned surrogate is measured
+against the exact batched kernel on 2000 held-out 64x64 scans (speedup at its
+relative L2 error, with its exact judge and fallback).
 """
 import argparse
 import json
@@ -91,6 +94,9 @@ def main():
                     help="target duration of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--side", type=int, default=512)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate-versus-exact measurement")
+    ap.add_argument("--surrogate-maps", type=int, default=2000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM byte counters) and exit")
@@ -154,6 +160,33 @@ def main():
                                                   floor)
     log(f"[bench] {other}: {sec_o * 1e3:.3f} ms/step; max rel diff mixed vs fp64 {diff.max():.3e}")
 
+    # Learned surrogate against the exact batched kernel on the held-out 64x64
+    # test scans (both timed end to end, scans' device tables built first).
+    sur = None
+    if not args.no_surrogate:
+        from paper_2507_00294_amd import surrogate as sg
+
+        if os.path.exists(sg.DEFAULT_WEIGHTS):
+            net = dd.UNet(0)
+            sg.load_weights(net)
+            res = sg.evaluate(net, wl.surrogate_scans(args.surrogate_maps, seed=6), 0.02, "mixed",
+                              repeats=3)
+            net.close()
+            sur = {"metric": "surrogate speedup over the exact batched kernel at <= 1% mean "
+                             "relative L2 error", "speedup": res["speedup"],
+                   "rel_l2_mean": res["rel_l2_mean"], "rel_l2_p95": res["rel_l2_p95"],
+                   "rel_l2_max": res["rel_l2_max"], "fallback_rate": res["fallback_rate"],
+                   "exact_ms": res["exact_s"] * 1e3, "surrogate_ms": res["surrogate_s"] * 1e3,
+                   "network_only_ms": res["network_only_s"] * 1e3,
+                   "network_only_rel_l2_mean": res["network_only_rel_l2_mean"],
+                   "maps": res["maps"], "spot_tol": res["spot_tol"],
+                   "workload": "final damage maps of 64x64 scans, batched-config sampling "
+                               "(seed 6), mixed precision exact path"}
+            log(f"[bench] surrogate: x{sur['speedup']:.2f} at rel L2 {sur['rel_l2_mean']:.4f} "
+                f"(fallback {sur['fallback_rate']:.3f})")
+        else:
+            log("[bench] surrogate weights missing; surrogate measurement skipped")
+
     cpu = None
     max_err = None
     if not args.no_cpu_baseline:
@@ -196,6 +229,7 @@ def main():
         "other_precision": {"precision": other, "ms_per_step": sec_o * 1e3,
                             "value": pairs / sec_o, "max_rel_diff_mixed_vs_fp64": float(diff.max())},
         "kernels_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in kern.items()},
+        "surrogate": sur,
     }
     print(json.dumps(line), flush=True)
 

@@ -77,9 +77,11 @@ dd_status dd_scan::prepare(hipStream_t st) {
 namespace {
 
 // Integer-lag rows 0 .. V + 1024 (rows past V serve the aligned ends of the
-// last lag chunks, whose pairs are masked).
+// last lag chunks, whose pairs are masked).  They depend on the scan alone
+// (kappa, sigma, V), so they are built by the scan's first query and kept.
 dd_status build_int_rows(dd_scan* s, hipStream_t st) {
   const int64_t n_rows = s->V + 1024;
+  if (s->n_rows == n_rows) return DD_OK;
   DD_HIP(s->rows64.ensure(sizeof(double) * kRow64 * n_rows), "device allocation");
   DD_HIP(s->rows32.ensure(sizeof(float) * kRow32 * n_rows), "device allocation");
   DD_HIP(launch_lag_rows(0, n_rows, 0.0, s->kappa, s->s2, gl_nodes(), s->rows64.as<double>(),

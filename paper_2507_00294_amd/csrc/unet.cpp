@@ -11,9 +11,12 @@
 // (the logarithm of) what the other probes contribute.  Training minimises
 // the per-map relative L2 error, the accuracy measure of the surrogate.
 //
-// Kernels: implicit-GEMM 3x3 convolutions on BF16 MFMA (unet_conv.hip) for the
-// forward pass and the data gradient, im2col + split-K MFMA GEMM for the
-// weight gradient, FP32 elementwise kernels and Adam (unet_kernels.hip).
+// Kernels: 3x3 convolutions on BF16 MFMA over LDS halo tiles (unet_conv.hip)
+// for the forward pass and the data gradient -- the decoder's upsampling and
+// skip concatenation are read directly by its first convolution, and the
+// output head is reduced in the last convolution's epilogue -- im2col +
+// split-K MFMA GEMM for the weight gradient, FP32 elementwise kernels and Adam
+// (unet_kernels.hip).
 // Predictions are judged by the exact kernels (one exact row per map) and
 // replaced by the exact map when the judge rejects them or the scan lies
 // outside the training range.
@@ -62,7 +65,7 @@ struct dd_unet {
   int64_t step = 0;
   int capB = 0, capB_train = 0, B = 0;
   bool last_train = false;
-  DevBuf col0, p1, p2, p3, c3, c2, c1, y;
+  DevBuf p1, p2, p3, y, col0;
   DevBuf col, dA0, dA1, dZ, dZb, ds1, ds2, ds3, part, loss_map, norm_part, scale_norm;
   size_t part_elems = 0;
 };
@@ -119,21 +122,23 @@ int wgrad_splits(const Conv& c, int64_t M) {
 // pass needs.
 dd_status ensure_capacity(dd_unet& u, int B, bool train) {
   const int64_t M64 = (int64_t)B * NPX, M32 = M64 / 4, M16 = M64 / 16, M8 = M64 / 64;
+  const size_t nL = u.L.size();
   if (B > u.capB) {
-    for (Conv& c : u.L)
+    // the last layer's activation is only kept for training
+    for (size_t l = 0; l + 1 < nL; ++l) {
+      Conv& c = u.L[l];
       UN_HIP(c.A.ensure(sizeof(float) * (int64_t)B * c.H * c.H * c.co), "device allocation");
-    UN_HIP(u.col0.ensure(sizeof(__bf16) * M64 * KPAD0), "device allocation");
+    }
     UN_HIP(u.p1.ensure(sizeof(float) * M32 * 32), "device allocation");
     UN_HIP(u.p2.ensure(sizeof(float) * M16 * 64), "device allocation");
     UN_HIP(u.p3.ensure(sizeof(float) * M8 * 128), "device allocation");
-    UN_HIP(u.c3.ensure(sizeof(float) * M16 * 384), "device allocation");
-    UN_HIP(u.c2.ensure(sizeof(float) * M32 * 192), "device allocation");
-    UN_HIP(u.c1.ensure(sizeof(float) * M64 * 96), "device allocation");
     UN_HIP(u.y.ensure(sizeof(float) * M64), "device allocation");
     u.capB = B;
   }
   if (train && B > u.capB_train) {
     size_t max_mco = 0, max_mci = 0, max_col = 0, max_part = 0;
+    UN_HIP(u.L[nL - 1].A.ensure(sizeof(float) * M64 * u.L[nL - 1].co), "device allocation");
+    UN_HIP(u.col0.ensure(sizeof(__bf16) * M64 * KPAD0), "device allocation");
     for (Conv& c : u.L) {
       const int64_t M = (int64_t)B * c.H * c.H;
       UN_HIP(c.Z.ensure(sizeof(float) * M * c.co), "device allocation");
@@ -159,37 +164,56 @@ dd_status ensure_capacity(dd_unet& u, int B, bool train) {
   return DD_OK;
 }
 
-dd_status conv_fwd(dd_unet& u, Conv& c, const float* in, bool train, hipStream_t st) {
-  const int64_t M = M_of(u, c);
+// Input of a convolution: a plain activation, or (coarse != NULL) the
+// decoder's concatenation [nearest-2x upsampling of coarse (c1 channels),
+// x (the skip map)].
+struct In {
+  const float* x;
+  const float* coarse = nullptr;
+  int c1 = 0;
+};
+
+dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st) {
+  Conv& c = u.L[l];
   const __bf16* wt = u.wf.as<__bf16>() + c.wf_off;
   const float* bias = u.w.as<float>() + c.b_off;
   float* z = train ? c.Z.as<float>() : nullptr;
-  if (c.ci % 32 == 0) {
-    UN_HIP(nn::conv3_silu(in, u.B, c.lg, c.ci, wt, bias, c.A.as<float>(), z, c.co, st), "conv");
-  } else {
-    UN_HIP(nn::im2col(in, u.B, c.H, c.H, c.ci, KPAD0, u.col0.as<__bf16>(), st), "im2col");
-    UN_HIP(nn::rows_silu(u.col0.as<__bf16>(), (int)M, KPAD0, wt, bias, c.A.as<float>(), z, c.co, st),
+  if (c.ci % 32 != 0) {
+    UN_HIP(nn::conv3_first_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<float>(), z, st), "conv");
+  } else if (in.coarse) {
+    UN_HIP(nn::conv3_upcat_silu(in.coarse, in.c1, in.x, c.ci - in.c1, u.B, c.lg, wt, bias,
+                                c.A.as<float>(), z, c.co, st),
            "conv");
+  } else if (l + 1 == u.L.size()) {
+    UN_HIP(nn::conv3_silu_head(in.x, u.B, c.lg, c.ci, wt, bias, u.w.as<float>() + u.head_w,
+                               train ? c.A.as<float>() : nullptr, z, u.y.as<float>(), st),
+           "conv");
+  } else {
+    UN_HIP(nn::conv3_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<float>(), z, c.co, st), "conv");
   }
   return DD_OK;
 }
 
 // Backward of one convolution: from dA (gradient of its activation) and its
-// input `in`, the gradients of its weights and bias, and dX (the gradient of
-// its input) when requested.
-dd_status conv_bwd(dd_unet& u, Conv& c, const float* in, const float* dA, float* dX,
-                   hipStream_t st) {
+// input, the gradients of its weights and bias, and dX (the gradient of its
+// input, of the concatenation for a decoder input) when requested.
+dd_status conv_bwd(dd_unet& u, Conv& c, In in, const float* dA, float* dX, hipStream_t st) {
   const int64_t M = M_of(u, c);
   UN_HIP(nn::silu_bwd(dA, c.Z.as<float>(), M * c.co, u.dZ.as<float>(), u.dZb.as<__bf16>(), st),
          "SiLU backward");
   UN_HIP(nn::colsum_add(u.dZ.as<float>(), (int)M, c.co, u.g.as<float>() + c.b_off, st),
          "bias gradient");
-  const __bf16* col = u.col0.as<__bf16>();
-  int ld = KPAD0;
-  if (c.ci % 32 == 0) {
-    UN_HIP(nn::im2col(in, u.B, c.H, c.H, c.ci, 9 * c.ci, u.col.as<__bf16>(), st), "im2col");
-    col = u.col.as<__bf16>();
-    ld = 9 * c.ci;
+  const __bf16* col = u.col.as<__bf16>();
+  int ld = 9 * c.ci;
+  if (c.ci % 32 != 0) {
+    UN_HIP(nn::im2col(in.x, u.B, c.H, c.H, c.ci, KPAD0, u.col0.as<__bf16>(), st), "im2col");
+    col = u.col0.as<__bf16>();
+    ld = KPAD0;
+  } else if (in.coarse) {
+    UN_HIP(nn::im2col_upcat(in.coarse, in.c1, in.x, c.ci - in.c1, u.B, c.H, u.col.as<__bf16>(), st),
+           "im2col");
+  } else {
+    UN_HIP(nn::im2col(in.x, u.B, c.H, c.H, c.ci, ld, u.col.as<__bf16>(), st), "im2col");
   }
   const int want = wgrad_splits(c, M);
   const int sp = nn::gemm_splits(9 * c.ci, (int)M, want);
@@ -205,6 +229,25 @@ dd_status conv_bwd(dd_unet& u, Conv& c, const float* in, const float* dA, float*
   return DD_OK;
 }
 
+// The input of every layer, in forward order.
+std::vector<In> layer_inputs(dd_unet& u, const float* x) {
+  auto A = [&](int l) { return (const float*)u.L[l].A.as<float>(); };
+  return {In{x},
+          In{A(0)},
+          In{u.p1.as<float>()},
+          In{A(2)},
+          In{u.p2.as<float>()},
+          In{A(4)},
+          In{u.p3.as<float>()},
+          In{A(6)},
+          In{A(5), A(7), 256},  // [up(8^2 x 256), skip 16^2 x 128]
+          In{A(8)},
+          In{A(3), A(9), 128},  // [up(16^2 x 128), skip 32^2 x 64]
+          In{A(10)},
+          In{A(1), A(11), 64},  // [up(32^2 x 64), skip 64^2 x 32]
+          In{A(12)}};
+}
+
 #define STEP(expr) \
   if ((rc = (expr)) != DD_OK) return rc
 
@@ -213,35 +256,17 @@ dd_status forward(dd_unet& u, const float* x, bool train, hipStream_t st) {
   const int B = u.B;
   dd_status rc;
   u.last_train = train;
-  STEP(conv_fwd(u, L[0], x, train, st));
-  STEP(conv_fwd(u, L[1], L[0].A.as<float>(), train, st));
+  const std::vector<In> in = layer_inputs(u, x);
+  STEP(conv_fwd(u, 0, in[0], train, st));
+  STEP(conv_fwd(u, 1, in[1], train, st));
   UN_HIP(nn::pool_fwd(L[1].A.as<float>(), B, 64, 64, 32, u.p1.as<float>(), st), "pool");
-  STEP(conv_fwd(u, L[2], u.p1.as<float>(), train, st));
-  STEP(conv_fwd(u, L[3], L[2].A.as<float>(), train, st));
+  STEP(conv_fwd(u, 2, in[2], train, st));
+  STEP(conv_fwd(u, 3, in[3], train, st));
   UN_HIP(nn::pool_fwd(L[3].A.as<float>(), B, 32, 32, 64, u.p2.as<float>(), st), "pool");
-  STEP(conv_fwd(u, L[4], u.p2.as<float>(), train, st));
-  STEP(conv_fwd(u, L[5], L[4].A.as<float>(), train, st));
+  STEP(conv_fwd(u, 4, in[4], train, st));
+  STEP(conv_fwd(u, 5, in[5], train, st));
   UN_HIP(nn::pool_fwd(L[5].A.as<float>(), B, 16, 16, 128, u.p3.as<float>(), st), "pool");
-  STEP(conv_fwd(u, L[6], u.p3.as<float>(), train, st));
-  STEP(conv_fwd(u, L[7], L[6].A.as<float>(), train, st));
-  UN_HIP(nn::up_concat(L[7].A.as<float>(), B, 8, 8, 256, L[5].A.as<float>(), 128, u.c3.as<float>(),
-                       st),
-         "upsample");
-  STEP(conv_fwd(u, L[8], u.c3.as<float>(), train, st));
-  STEP(conv_fwd(u, L[9], L[8].A.as<float>(), train, st));
-  UN_HIP(nn::up_concat(L[9].A.as<float>(), B, 16, 16, 128, L[3].A.as<float>(), 64, u.c2.as<float>(),
-                       st),
-         "upsample");
-  STEP(conv_fwd(u, L[10], u.c2.as<float>(), train, st));
-  STEP(conv_fwd(u, L[11], L[10].A.as<float>(), train, st));
-  UN_HIP(nn::up_concat(L[11].A.as<float>(), B, 32, 32, 64, L[1].A.as<float>(), 32, u.c1.as<float>(),
-                       st),
-         "upsample");
-  STEP(conv_fwd(u, L[12], u.c1.as<float>(), train, st));
-  STEP(conv_fwd(u, L[13], L[12].A.as<float>(), train, st));
-  UN_HIP(nn::head_fwd(L[13].A.as<float>(), (int64_t)B * NPX, 32, u.w.as<float>() + u.head_w,
-                      u.w.as<float>() + u.head_w + 32, u.y.as<float>(), st),
-         "head");
+  for (size_t l = 6; l < L.size(); ++l) STEP(conv_fwd(u, l, in[l], train, st));
   return DD_OK;
 }
 
@@ -252,32 +277,33 @@ dd_status backward(dd_unet& u, const float* x, const float* dy, hipStream_t st) 
   float* a0 = u.dA0.as<float>();
   float* a1 = u.dA1.as<float>();
   dd_status rc;
+  const std::vector<In> in = layer_inputs(u, x);
   UN_HIP(nn::fill(u.ds1.as<float>(), M64 * 32, 0.f, st), "fill");
   UN_HIP(nn::fill(u.ds2.as<float>(), M32 * 64, 0.f, st), "fill");
   UN_HIP(nn::fill(u.ds3.as<float>(), M16 * 128, 0.f, st), "fill");
   UN_HIP(nn::head_bwd(dy, L[13].A.as<float>(), M64, 32, u.w.as<float>() + u.head_w, a0,
                       u.g.as<float>() + u.head_w, st),
          "head backward");
-  STEP(conv_bwd(u, L[13], L[12].A.as<float>(), a0, a1, st));
-  STEP(conv_bwd(u, L[12], u.c1.as<float>(), a1, a0, st));  // a0 = d c1 [64^2][96]
+  STEP(conv_bwd(u, L[13], in[13], a0, a1, st));
+  STEP(conv_bwd(u, L[12], in[12], a1, a0, st));  // a0 = d[up, skip] at 64^2 x 96
   UN_HIP(nn::up_concat_bwd(a0, B, 32, 32, 64, 32, a1, u.ds1.as<float>(), st), "upsample backward");
-  STEP(conv_bwd(u, L[11], L[10].A.as<float>(), a1, a0, st));
-  STEP(conv_bwd(u, L[10], u.c2.as<float>(), a0, a1, st));  // a1 = d c2 [32^2][192]
+  STEP(conv_bwd(u, L[11], in[11], a1, a0, st));
+  STEP(conv_bwd(u, L[10], in[10], a0, a1, st));  // a1 = d[up, skip] at 32^2 x 192
   UN_HIP(nn::up_concat_bwd(a1, B, 16, 16, 128, 64, a0, u.ds2.as<float>(), st), "upsample backward");
-  STEP(conv_bwd(u, L[9], L[8].A.as<float>(), a0, a1, st));
-  STEP(conv_bwd(u, L[8], u.c3.as<float>(), a1, a0, st));  // a0 = d c3 [16^2][384]
+  STEP(conv_bwd(u, L[9], in[9], a0, a1, st));
+  STEP(conv_bwd(u, L[8], in[8], a1, a0, st));  // a0 = d[up, skip] at 16^2 x 384
   UN_HIP(nn::up_concat_bwd(a0, B, 8, 8, 256, 128, a1, u.ds3.as<float>(), st), "upsample backward");
-  STEP(conv_bwd(u, L[7], L[6].A.as<float>(), a1, a0, st));
-  STEP(conv_bwd(u, L[6], u.p3.as<float>(), a0, a1, st));  // a1 = d p3 [8^2][128]
+  STEP(conv_bwd(u, L[7], in[7], a1, a0, st));
+  STEP(conv_bwd(u, L[6], in[6], a0, a1, st));  // a1 = d p3 [8^2][128]
   UN_HIP(nn::pool_bwd_add(a1, B, 16, 16, 128, u.ds3.as<float>(), st), "pool backward");
-  STEP(conv_bwd(u, L[5], L[4].A.as<float>(), u.ds3.as<float>(), a0, st));
-  STEP(conv_bwd(u, L[4], u.p2.as<float>(), a0, a1, st));  // a1 = d p2 [16^2][64]
+  STEP(conv_bwd(u, L[5], in[5], u.ds3.as<float>(), a0, st));
+  STEP(conv_bwd(u, L[4], in[4], a0, a1, st));  // a1 = d p2 [16^2][64]
   UN_HIP(nn::pool_bwd_add(a1, B, 32, 32, 64, u.ds2.as<float>(), st), "pool backward");
-  STEP(conv_bwd(u, L[3], L[2].A.as<float>(), u.ds2.as<float>(), a0, st));
-  STEP(conv_bwd(u, L[2], u.p1.as<float>(), a0, a1, st));  // a1 = d p1 [32^2][32]
+  STEP(conv_bwd(u, L[3], in[3], u.ds2.as<float>(), a0, st));
+  STEP(conv_bwd(u, L[2], in[2], a0, a1, st));  // a1 = d p1 [32^2][32]
   UN_HIP(nn::pool_bwd_add(a1, B, 64, 64, 32, u.ds1.as<float>(), st), "pool backward");
-  STEP(conv_bwd(u, L[1], L[0].A.as<float>(), u.ds1.as<float>(), a0, st));
-  STEP(conv_bwd(u, L[0], x, a0, nullptr, st));
+  STEP(conv_bwd(u, L[1], in[1], u.ds1.as<float>(), a0, st));
+  STEP(conv_bwd(u, L[0], in[0], a0, nullptr, st));
   return DD_OK;
 }
 #undef STEP
@@ -418,7 +444,7 @@ dd_status dd_unet_create(uint64_t seed, dd_unet** out) {
 void dd_unet_destroy(dd_unet* u) {
   if (!u) return;
   for (DevBuf* b : {&u->w, &u->wf, &u->wd, &u->g, &u->m, &u->v, &u->col0, &u->p1, &u->p2, &u->p3,
-                    &u->c3, &u->c2, &u->c1, &u->y, &u->col, &u->dA0, &u->dA1, &u->dZ, &u->dZb,
+                    &u->y, &u->col, &u->dA0, &u->dA1, &u->dZ, &u->dZb,
                     &u->ds1, &u->ds2, &u->ds3, &u->part, &u->loss_map, &u->norm_part,
                     &u->scale_norm})
     b->release();

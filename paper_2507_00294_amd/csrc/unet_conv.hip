@@ -1,24 +1,32 @@
-// unet_conv.hip -- implicit-GEMM 3x3 convolution on BF16 MFMA for gfx950.
+// unet_conv.hip -- 3x3 convolutions of the surrogate on BF16 MFMA for gfx950.
 //
 // out[m][n] = sum_k A[m][k] Wt[n][k] (+ bias, SiLU), with m a pixel of an
-// NHWC activation (B images of side x side), n an output channel and
-// k = tap * ci + c, tap = 3 ky + kx, the input pixel (y + ky - 1, x + kx - 1)
-// (zero outside the image).  A is never materialised: each K step of 32 is
-// one tap and 32 consecutive input channels, read straight from the FP32
-// activation (one 16-byte load per 4 channels), rounded to BF16 and staged in
-// LDS.  With TAPS = 1 the input is a plain BF16 row-major matrix [M][ci] (the
-// first layer, whose 5-channel im2col is padded to 64 columns).
+// NHWC activation (B images of side x side, side = 2^lg), n an output channel
+// and k = tap ci + c, tap = 3 ky + kx, reading input pixel (y + ky - 1,
+// x + kx - 1) (zero outside the image).  A is never materialised.
 //
-// Block: 256 threads = 4 waves, block tile 256 pixels x BN channels; wave w
-// owns rows 64 w .. 64 w + 63 = 4 x (BN / 16) tiles of
-// v_mfma_f32_16x16x32_bf16.  Fragment layout of that instruction (lane l):
-// A row l % 16, k = 8 (l / 16) .. +7; B column l % 16, same k; D element v at
-// row 4 (l / 16) + v, column l % 16.  LDS rows are padded to 40 BF16 (80 B) so
-// that the 16-byte fragment reads of 16 consecutive rows hit distinct banks.
-// The next K step's global loads are issued before the current step's MFMAs.
+// k_conv_halo (ci a multiple of 32): a block computes 256 consecutive output
+// pixels -- 256 / side whole rows of one image, or 4 whole 8x8 images -- for
+// BN output channels.  For each chunk of 32 input channels it stages the
+// tile's input pixels plus a one-pixel halo (at most 400 pixels) in LDS as
+// BF16, once, and all nine taps then read their A fragments from that tile
+// (the nine-fold reuse of every input value stays on chip).  The B fragments
+// (weights, [N][9 ci], L2-resident) are loaded straight into registers one
+// tap ahead.  Input modes: a plain activation, or the decoder's virtual
+// concatenation [nearest-2x-upsampled coarse map, skip map] read directly
+// from its two sources.  Epilogues: plain (the data gradient), bias + SiLU,
+// and bias + SiLU followed by the 32 -> 1 output head reduced across lanes.
 //
-// The same kernel computes the data gradient of a convolution: dX = conv3(dZ)
-// with the taps mirrored and the weights rearranged to [ci][tap' co + j].
+// k_conv_first (the 5-channel input layer): K = 45 padded to 64, A gathered
+// element by element into LDS (two K steps).
+//
+// Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l): A row l % 16,
+// k = 8 (l / 16) .. +7; B column l % 16, same k; D element v at row
+// 4 (l / 16) + v, column l % 16.  LDS rows hold 32 BF16 channels padded to 40
+// (80 B), so 16 lanes reading 16 consecutive pixels hit distinct banks.
+//
+// The data gradient of a convolution is the same operation on dZ with the
+// taps mirrored and the weights rearranged to [ci][tap' co + j].
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -34,77 +42,135 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int CBM = 256, CLDK = 40;
-// Widest channel tile: 128 needs 270 registers per lane (1 wave per SIMD), 64
-// leaves room for 3.
-constexpr int kMaxBN = 64;
+constexpr int CBM = 256;    // output pixels per block
+constexpr int CLDK = 40;    // LDS row: 32 channels + 8 padding (BF16)
+constexpr int HPMAX = 400;  // halo-tile pixels: 6 x 66, 10 x 34, 18 x 18 or 4 x 10 x 10
+constexpr int SLOTS = (HPMAX * 8 + 255) / 256;  // 16-byte staging slots per thread
+
+enum { IN_PLAIN = 0, IN_UPCAT = 1 };
+enum { EPI_PLAIN = 0, EPI_SILU = 1, EPI_HEAD = 2 };
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
 
-template <typename TIn>
-struct AQuad;
-template <>
-struct AQuad<float> {
-  typedef f32x4 T;
-  static __device__ __forceinline__ T zero() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
-  static __device__ __forceinline__ bf16x4 cvt(T v) {
-    return bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-  }
-};
-template <>
-struct AQuad<__bf16> {
-  typedef bf16x4 T;
-  static __device__ __forceinline__ T zero() {
-    return bf16x4{(__bf16)0.f, (__bf16)0.f, (__bf16)0.f, (__bf16)0.f};
-  }
-  static __device__ __forceinline__ bf16x4 cvt(T v) { return v; }
+__device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
+  return bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+}
+
+struct ConvArgs {
+  const float* x;    // IN_PLAIN: input [M][ci]; IN_UPCAT: skip map [M][ci - c1]
+  const float* xc;   // IN_UPCAT: coarse map [M / 4][c1]
+  int c1;            // IN_UPCAT: channels taken from the coarse map
+  int M, lg, ci;     // output pixels, log2 side, input channels
+  const __bf16* wt;  // [N][9 ci]
+  const float* bias;
+  float* out;        // [M][N]; may be NULL with EPI_HEAD
+  float* z;          // pre-activation [M][N] or NULL
+  const float* hw;   // EPI_HEAD: 32 weights, then the bias
+  float* y;          // EPI_HEAD: [M]
+  int N;
 };
 
-// EPI 0: out = acc.  EPI 1: z = acc + bias; out = SiLU(z); z stored if zout.
-template <typename TIn, int TAPS, int BN, int EPI>
-__global__ void __launch_bounds__(256) k_conv(const TIn* __restrict__ x, int M, int lg, int ci,
-                                              const __bf16* __restrict__ wt,
-                                              const float* __restrict__ bias,
-                                              float* __restrict__ out, float* __restrict__ zout,
-                                              int N) {
-  typedef typename AQuad<TIn>::T Q;
-  __shared__ __attribute__((aligned(16))) __bf16 As[CBM][CLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][CLDK];
+// Epilogue of the block's accumulators: rows m0 + wave 64 + a 16 +
+// 4 (lane / 16) + v, columns n0 + b 16 + lane % 16.
+template <int NB, int EPI>
+__device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB], int m0, int n0,
+                                         int wave, int lane) {
+  if (EPI == EPI_HEAD) {
+    // N = 32 = BN: each row's 32 channels sit in the 16 lanes of one lane
+    // group (two columns per lane); SiLU, weight, then reduce over the group.
+    const int c0 = lane & 15;
+    const float w0 = p.hw[c0], w1 = p.hw[16 + c0], hb = p.hw[32];
+    const float b0 = p.bias[c0], b1 = p.bias[16 + c0];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wave * 64 + a * 16 + 4 * (lane >> 4) + v;
+        const float z0 = acc[a][0][v] + b0, z1 = acc[a][1][v] + b1;
+        const float a0 = silu(z0), a1 = silu(z1);
+        if (row < p.M) {
+          const int64_t o = (int64_t)row * 32 + c0;
+          if (p.out) {
+            p.out[o] = a0;
+            p.out[o + 16] = a1;
+          }
+          if (p.z) {
+            p.z[o] = z0;
+            p.z[o + 16] = z1;
+          }
+        }
+        float s = a0 * w0 + a1 * w1;
+        s += __shfl_xor(s, 1, 16);
+        s += __shfl_xor(s, 2, 16);
+        s += __shfl_xor(s, 4, 16);
+        s += __shfl_xor(s, 8, 16);
+        if (c0 == 0 && row < p.M) p.y[row] = s + hb;
+      }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int col = n0 + b * 16 + (lane & 15);
+      const float bs = EPI == EPI_SILU ? p.bias[col] : 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wave * 64 + a * 16 + 4 * (lane >> 4) + v;
+        if (row < p.M) {
+          const int64_t o = (int64_t)row * p.N + col;
+          if (EPI == EPI_SILU) {
+            const float zz = acc[a][b][v] + bs;
+            if (p.z) p.z[o] = zz;
+            p.out[o] = silu(zz);
+          } else {
+            p.out[o] = acc[a][b][v];
+          }
+        }
+      }
+    }
+}
+
+template <int IN, int BN, int EPI>
+__global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[HPMAX][CLDK];
   constexpr int NB = BN / 16;
-  constexpr int BLOADS = BN * 4;  // 16-byte pieces of the B tile
-  constexpr int BPT = (BLOADS + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * CBM, n0 = blockIdx.y * BN;
-  const int side = 1 << lg, K = TAPS * ci, cchunks = ci >> 5, nsteps = TAPS * cchunks;
-  const int q = tid & 7, r0 = tid >> 3;
+  const int lg = p.lg, W = 1 << lg, ci = p.ci, K = 9 * ci;
+  // tile geometry: G image slices of R rows x W columns, halo (R+2) x (W+2)
+  const int lgR = lg >= 4 ? 8 - lg : lg;  // rows per slice: 256 / W, or W for W = 8
+  const int R = 1 << lgR, lgRW = lgR + lg;
+  const int HW2 = W + 2, slice = (R + 2) * HW2;
+  const int G = CBM >> lgRW, HP = G * slice;
+  const int img0 = m0 >> (2 * lg), y0 = (m0 >> lg) & (W - 1);
 
-  Q areg[8];
-  bf16x8 breg[BPT];
-  auto load = [&](int s) {
-    const int tap = s / cchunks, cc = s - tap * cchunks;
-    const int dy = TAPS == 9 ? tap / 3 - 1 : 0, dx = TAPS == 9 ? tap % 3 - 1 : 0;
+  // source pixel of every staging slot (fixed over the channel chunks)
+  int src[SLOTS];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
-      const int m = m0 + r0 + 32 * p;
-      bool ok = m < M;
-      if (TAPS == 9) {
-        const int yy = ((m >> lg) & (side - 1)) + dy, xx = (m & (side - 1)) + dx;
-        ok = ok && yy >= 0 && yy < side && xx >= 0 && xx < side;
-      }
-      areg[p] = AQuad<TIn>::zero();
-      if (ok)
-        areg[p] = *reinterpret_cast<const Q*>(x + (int64_t)(m + dy * side + dx) * ci + cc * 32 +
-                                              4 * q);
-    }
-#pragma unroll
-    for (int e = 0; e < BPT; ++e) {
-      const int idx = tid + 256 * e;
-      if (idx < BLOADS) {
-        const int j = idx >> 2, part = idx & 3;
-        breg[e] = *reinterpret_cast<const bf16x8*>(wt + (int64_t)(n0 + j) * K + s * 32 + part * 8);
+  for (int i = 0; i < SLOTS; ++i) {
+    const int idx = tid + 256 * i, px = idx >> 3;
+    int s = -1;
+    if (px < HP) {
+      const int g = px / slice, rem = px - g * slice;
+      const int hr = rem / HW2, hc = rem - hr * HW2;
+      const int yy = y0 + hr - 1, xx = hc - 1;
+      if (yy >= 0 && yy < W && xx >= 0 && xx < W) {
+        const int m = (((img0 + g) << lg) + yy) * W + xx;
+        if (m < p.M) s = m;
       }
     }
-  };
+    src[i] = s;
+  }
+  // halo-tile pixel of each of this lane's 4 A-fragment rows at tap (0, 0)
+  int hbase[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int o = wave * 64 + a * 16 + (lane & 15);
+    const int g = o >> lgRW, r = (o >> lg) & (R - 1), x = o & (W - 1);
+    hbase[a] = g * slice + r * HW2 + x;
+  }
+  const __bf16* wlane = p.wt + (int64_t)(n0 + (lane & 15)) * K + 8 * (lane >> 4);
 
   f32x4 acc[4][NB];
 #pragma unroll
@@ -112,94 +178,172 @@ __global__ void __launch_bounds__(256) k_conv(const TIn* __restrict__ x, int M, 
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  load(0);
-  for (int s = 0; s < nsteps; ++s) {
+  const int chunks = ci >> 5;
+  for (int cc = 0; cc < chunks; ++cc) {
+    // stage the halo tile of channels 32 cc .. 32 cc + 31
 #pragma unroll
-    for (int p = 0; p < 8; ++p)
-      *reinterpret_cast<bf16x4*>(&As[r0 + 32 * p][4 * q]) = AQuad<TIn>::cvt(areg[p]);
+    for (int i = 0; i < SLOTS; ++i) {
+      const int idx = tid + 256 * i, px = idx >> 3, q = idx & 7;
+      if (px < HP) {
+        f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int s = src[i];
+        if (s >= 0) {
+          if (IN == IN_UPCAT && cc * 32 < p.c1) {
+            const int im = s >> (2 * lg), yy = (s >> lg) & (W - 1), xx = s & (W - 1);
+            const int sc = (((im << (lg - 1)) + (yy >> 1)) << (lg - 1)) + (xx >> 1);
+            v = *reinterpret_cast<const f32x4*>(p.xc + (int64_t)sc * p.c1 + cc * 32 + 4 * q);
+          } else if (IN == IN_UPCAT) {
+            const int c2 = ci - p.c1;
+            v = *reinterpret_cast<const f32x4*>(p.x + (int64_t)s * c2 + (cc * 32 - p.c1) + 4 * q);
+          } else {
+            v = *reinterpret_cast<const f32x4*>(p.x + (int64_t)s * ci + cc * 32 + 4 * q);
+          }
+        }
+        *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
+      }
+    }
+    bf16x8 bcur[NB];
 #pragma unroll
-    for (int e = 0; e < BPT; ++e) {
-      const int idx = tid + 256 * e;
-      if (idx < BLOADS) *reinterpret_cast<bf16x8*>(&Bs[idx >> 2][(idx & 3) * 8]) = breg[e];
+    for (int b = 0; b < NB; ++b)
+      bcur[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + cc * 32);
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      bf16x8 bnext[NB];
+      if (tap < 8) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          bnext[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + (tap + 1) * ci +
+                                                      cc * 32);
+      }
+      const int toff = (tap / 3) * HW2 + (tap % 3);
+      bf16x8 af[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        af[a] = *reinterpret_cast<const bf16x8*>(&As[hbase[a] + toff][8 * (lane >> 4)]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bcur[b], acc[a][b], 0, 0, 0);
+      if (tap < 8) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bcur[b] = bnext[b];
+      }
     }
     __syncthreads();
-    if (s + 1 < nsteps) load(s + 1);
+  }
+  epilogue<NB, EPI>(p, acc, m0, n0, wave, lane);
+}
+
+// First layer: ci < 32 input channels, K = 9 ci <= 64 padded to 64; N = 32.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[CBM][72];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[32][72];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * CBM;
+  const int lg = p.lg, W = 1 << lg, ci = p.ci, K9 = 9 * ci;
+  // A: pixel m0 + tid, all 64 k values
+  {
+    const int m = m0 + tid;
+    const int yy = (m >> lg) & (W - 1), xx = m & (W - 1);
+#pragma unroll 4
+    for (int k = 0; k < 64; ++k) {
+      float v = 0.f;
+      if (k < K9 && m < p.M) {
+        const int tap = k / ci, c = k - tap * ci;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int sy = yy + dy, sx = xx + dx;
+        if (sy >= 0 && sy < W && sx >= 0 && sx < W) v = p.x[(int64_t)(m + dy * W + dx) * ci + c];
+      }
+      As[tid][k] = (__bf16)v;
+    }
+  }
+  // B: wt [32][64]
+  {
+    const int j = tid >> 3, part = tid & 7;
+    *reinterpret_cast<bf16x8*>(&Bs[j][part * 8]) =
+        *reinterpret_cast<const bf16x8*>(p.wt + (int64_t)j * 64 + part * 8);
+  }
+  __syncthreads();
+  f32x4 acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
     bf16x8 af[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
-      af[a] = *reinterpret_cast<const bf16x8*>(&As[wave * 64 + a * 16 + (lane & 15)][8 * (lane >> 4)]);
+      af[a] = *reinterpret_cast<const bf16x8*>(
+          &As[wave * 64 + a * 16 + (lane & 15)][ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const bf16x8 bfr = *reinterpret_cast<const bf16x8*>(&Bs[b * 16 + (lane & 15)][8 * (lane >> 4)]);
+    for (int b = 0; b < 2; ++b) {
+      const bf16x8 bfr =
+          *reinterpret_cast<const bf16x8*>(&Bs[b * 16 + (lane & 15)][ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr, acc[a][b], 0, 0, 0);
     }
-    __syncthreads();
   }
-
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int col = n0 + b * 16 + (lane & 15);
-      const float bs = EPI == 1 ? bias[col] : 0.f;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wave * 64 + a * 16 + 4 * (lane >> 4) + v;
-        if (row < M) {
-          const int64_t o = (int64_t)row * N + col;
-          if (EPI == 1) {
-            const float z = acc[a][b][v] + bs;
-            if (zout) zout[o] = z;
-            out[o] = silu(z);
-          } else {
-            out[o] = acc[a][b][v];
-          }
-        }
-      }
-    }
+  epilogue<2, EPI>(p, acc, m0, 0, wave, lane);
 }
 
-template <typename TIn, int TAPS, int EPI>
-hipError_t launch(const TIn* x, int M, int lg, int ci, const __bf16* wt, const float* bias,
-                  float* out, float* z, int N, hipStream_t st) {
-  const int bn = (kMaxBN >= 128 && N % 128 == 0) ? 128 : (N % 64 == 0) ? 64 : 32;
-  dim3 grid((M + CBM - 1) / CBM, N / bn);
-  if (bn == 128)
-    hipLaunchKernelGGL((k_conv<TIn, TAPS, 128, EPI>), grid, dim3(256), 0, st, x, M, lg, ci, wt,
-                       bias, out, z, N);
-  else if (bn == 64)
-    hipLaunchKernelGGL((k_conv<TIn, TAPS, 64, EPI>), grid, dim3(256), 0, st, x, M, lg, ci, wt,
-                       bias, out, z, N);
+template <int IN, int EPI>
+hipError_t launch_halo(const ConvArgs& p, hipStream_t st) {
+  const int bn = (EPI == EPI_HEAD) ? 32 : (p.N % 64 == 0) ? 64 : 32;
+  dim3 grid((p.M + CBM - 1) / CBM, p.N / bn);
+  if (bn == 64)
+    hipLaunchKernelGGL((k_conv_halo<IN, 64, EPI>), grid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL((k_conv<TIn, TAPS, 32, EPI>), grid, dim3(256), 0, st, x, M, lg, ci, wt,
-                       bias, out, z, N);
+    hipLaunchKernelGGL((k_conv_halo<IN, 32, EPI>), grid, dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
-bool shape_ok(int M, int ci, int N) { return M > 0 && ci > 0 && ci % 32 == 0 && N > 0 && N % 32 == 0; }
+bool halo_ok(int M, int lg, int ci, int N) {
+  return M > 0 && lg >= 3 && lg <= 6 && ci > 0 && ci % 32 == 0 && N > 0 && N % 32 == 0;
+}
 
 }  // namespace
 
 hipError_t conv3_silu(const float* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
                       float* act, float* z, int co, hipStream_t st) {
-  const int M = B << (2 * lg);
-  if (!shape_ok(M, ci, co)) return hipErrorInvalidValue;
-  return launch<float, 9, 1>(x, M, lg, ci, wt, bias, act, z, co, st);
+  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, co};
+  if (!halo_ok(p.M, lg, ci, co) || !act) return hipErrorInvalidValue;
+  return launch_halo<IN_PLAIN, EPI_SILU>(p, st);
+}
+
+hipError_t conv3_upcat_silu(const float* coarse, int c1, const float* skip, int c2, int B, int lg,
+                            const __bf16* wt, const float* bias, float* act, float* z, int co,
+                            hipStream_t st) {
+  ConvArgs p{skip, coarse, c1, B << (2 * lg), lg, c1 + c2, wt, bias, act, z, nullptr, nullptr, co};
+  if (!halo_ok(p.M, lg, p.ci, co) || c1 % 32 != 0 || lg < 4 || !act) return hipErrorInvalidValue;
+  return launch_halo<IN_UPCAT, EPI_SILU>(p, st);
+}
+
+hipError_t conv3_silu_head(const float* x, int B, int lg, int ci, const __bf16* wt,
+                           const float* bias, const float* head, float* act, float* z, float* y,
+                           hipStream_t st) {
+  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, head, y, 32};
+  if (!halo_ok(p.M, lg, ci, 32) || !y || !head) return hipErrorInvalidValue;
+  return launch_halo<IN_PLAIN, EPI_HEAD>(p, st);
 }
 
 hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, float* out, int co,
                        hipStream_t st) {
-  const int M = B << (2 * lg);
-  if (!shape_ok(M, ci, co)) return hipErrorInvalidValue;
-  return launch<float, 9, 0>(x, M, lg, ci, wt, nullptr, out, nullptr, co, st);
+  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, nullptr, out, nullptr, nullptr, nullptr, co};
+  if (!halo_ok(p.M, lg, ci, co) || !out) return hipErrorInvalidValue;
+  return launch_halo<IN_PLAIN, EPI_PLAIN>(p, st);
 }
 
-hipError_t rows_silu(const __bf16* a, int M, int k, const __bf16* wt, const float* bias, float* act,
-                     float* z, int co, hipStream_t st) {
-  if (!shape_ok(M, k, co)) return hipErrorInvalidValue;
-  return launch<__bf16, 1, 1>(a, M, 0, k, wt, bias, act, z, co, st);
+hipError_t conv3_first_silu(const float* x, int B, int lg, int ci, const __bf16* wt,
+                            const float* bias, float* act, float* z, hipStream_t st) {
+  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, 32};
+  if (p.M <= 0 || ci < 1 || 9 * ci > 64 || lg < 3 || lg > 6 || !act) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_conv_first<EPI_SILU>), dim3((p.M + CBM - 1) / CBM), dim3(256), 0, st, p);
+  return hipGetLastError();
 }
 
 }  // namespace nn

@@ -153,6 +153,30 @@ __global__ void __launch_bounds__(256) k_im2col(const float* __restrict__ x, int
   }
 }
 
+// im2col of the decoder input: channel c < c1 of pixel (n, y, x) is channel c
+// of the coarse map at (n, y/2, x/2), channel c1 + c' is channel c' of skip;
+// rows of 9 (c1 + c2) columns.
+__global__ void __launch_bounds__(256) k_im2col_upcat(const float* __restrict__ coarse, int c1,
+                                                      const float* __restrict__ skip, int c2,
+                                                      int B, int H, __bf16* __restrict__ col) {
+  const int C = c1 + c2, h = H / 2;
+  const int64_t K = 9 * (int64_t)C, total = (int64_t)B * H * H * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / K;
+    const int k = (int)(e % K);
+    const int tap = k / C, c = k % C;
+    const int ky = tap / 3, kx = tap % 3;
+    const int xx = (int)(m % H), yy = (int)((m / H) % H), n = (int)(m / ((int64_t)H * H));
+    const int sy = yy + ky - 1, sx = xx + kx - 1;
+    float v = 0.f;
+    if (sy >= 0 && sy < H && sx >= 0 && sx < H)
+      v = c < c1 ? coarse[(((int64_t)n * h + sy / 2) * h + sx / 2) * c1 + c]
+                 : skip[(((int64_t)n * H + sy) * H + sx) * c2 + (c - c1)];
+    col[e] = (__bf16)v;
+  }
+}
+
 // dZ = dA * SiLU'(Z); also its BF16 copy for the MFMA GEMMs.
 __global__ void __launch_bounds__(256) k_silu_bwd(const float* __restrict__ dA,
                                                   const float* __restrict__ Z, int64_t n,
@@ -210,26 +234,9 @@ __global__ void __launch_bounds__(256) k_pool_bwd(const float* __restrict__ dy, 
   }
 }
 
-// Nearest 2x upsampling of x [B][h][w][C1] written into channels [0, C1) of
-// a [B][2h][2w][Ct] buffer, and the copy of skip [B][2h][2w][C2] into
-// channels [C1, C1+C2): the decoder's concatenation input.
-__global__ void __launch_bounds__(256) k_up_concat(const float* __restrict__ x, int B, int h, int w,
-                                                   int C1, const float* __restrict__ skip, int C2,
-                                                   float* __restrict__ out) {
-  const int H = 2 * h, W = 2 * w, Ct = C1 + C2;
-  const int64_t total = (int64_t)B * H * W * Ct;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % Ct);
-    const int64_t p = e / Ct;
-    const int xx = (int)(p % W), yy = (int)((p / W) % H), n = (int)(p / ((int64_t)W * H));
-    out[e] = c < C1 ? x[(((int64_t)n * h + yy / 2) * w + xx / 2) * C1 + c]
-                    : skip[p * C2 + (c - C1)];
-  }
-}
-
-// Adjoint of k_up_concat: dx [B][h][w][C1] = sum of the 4 children (overwrite);
-// dskip += the skip channels.
+// Adjoint of the decoder input [nearest-2x upsampling of x [B][h][w][C1],
+// skip [B][2h][2w][C2]] (channel concatenation): dx = sum of the 4 children
+// (overwrite); dskip += the skip channels.
 __global__ void __launch_bounds__(256) k_up_concat_bwd(const float* __restrict__ dout, int B, int h,
                                                        int w, int C1, int C2,
                                                        float* __restrict__ dx,
@@ -250,19 +257,6 @@ __global__ void __launch_bounds__(256) k_up_concat_bwd(const float* __restrict__
       const int64_t p = f / C2;
       dskip[f] += dout[p * Ct + C1 + c];
     }
-  }
-}
-
-// 1x1 output head in FP32: y[m] = sum_c a[m][c] w[c] + b.
-__global__ void __launch_bounds__(256) k_head_fwd(const float* __restrict__ a, int64_t M, int C,
-                                                  const float* __restrict__ w,
-                                                  const float* __restrict__ b,
-                                                  float* __restrict__ y) {
-  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < M;
-       m += (int64_t)gridDim.x * blockDim.x) {
-    float s = b[0];
-    for (int c = 0; c < C; ++c) s = fmaf(a[m * C + c], w[c], s);
-    y[m] = s;
   }
 }
 
@@ -589,6 +583,13 @@ hipError_t im2col(const float* x, int B, int H, int W, int C, int ld, __bf16* co
   return hipGetLastError();
 }
 
+hipError_t im2col_upcat(const float* coarse, int c1, const float* skip, int c2, int B, int H,
+                        __bf16* col, hipStream_t st) {
+  hipLaunchKernelGGL(k_im2col_upcat, dim3(blocks_for((int64_t)B * H * H * 9 * (c1 + c2))), dim3(256),
+                     0, st, coarse, c1, skip, c2, B, H, col);
+  return hipGetLastError();
+}
+
 hipError_t silu_bwd(const float* dA, const float* Z, int64_t n, float* dZ, __bf16* dZb,
                     hipStream_t st) {
   hipLaunchKernelGGL(k_silu_bwd, dim3(blocks_for(n)), dim3(256), 0, st, dA, Z, n, dZ, dZb);
@@ -612,24 +613,11 @@ hipError_t pool_bwd_add(const float* dy, int B, int H, int W, int C, float* dx, 
   return hipGetLastError();
 }
 
-hipError_t up_concat(const float* x, int B, int h, int w, int C1, const float* skip, int C2,
-                     float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_up_concat, dim3(blocks_for((int64_t)B * 4 * h * w * (C1 + C2))), dim3(256),
-                     0, st, x, B, h, w, C1, skip, C2, out);
-  return hipGetLastError();
-}
-
 hipError_t up_concat_bwd(const float* dout, int B, int h, int w, int C1, int C2, float* dx,
                          float* dskip, hipStream_t st) {
   const int64_t n = (int64_t)B * h * w * C1 + (int64_t)B * 4 * h * w * C2;
   hipLaunchKernelGGL(k_up_concat_bwd, dim3(blocks_for(n)), dim3(256), 0, st, dout, B, h, w, C1, C2,
                      dx, dskip);
-  return hipGetLastError();
-}
-
-hipError_t head_fwd(const float* a, int64_t M, int C, const float* w, const float* b, float* y,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_head_fwd, dim3(blocks_for(M)), dim3(256), 0, st, a, M, C, w, b, y);
   return hipGetLastError();
 }
 

@@ -204,10 +204,22 @@ def main(argv=None):
     ap.add_argument("--spot-tol", type=float, default=0.02)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--report", default="")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="load --weights and only evaluate on the test maps")
     args = ap.parse_args(argv)
     import torch
 
     torch.cuda.set_device(0)
+    if args.eval_only:
+        net = UNet(args.seed)
+        load_weights(net, args.weights)
+        res = evaluate(net, wl.surrogate_scans(args.test, seed=6), args.spot_tol)
+        line = json.dumps(res)
+        print(line, flush=True)
+        if args.report:
+            with open(args.report, "w") as f:
+                f.write(line + "\n")
+        return
     t0 = time.time()
     train_specs = wl.surrogate_scans(args.train, seed=5)
     test_specs = wl.surrogate_scans(args.test, seed=6)
