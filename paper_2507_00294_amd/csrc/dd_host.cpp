@@ -226,6 +226,15 @@ double row_c(double lam, double kappa, double s2) {
   return db / (b0 * (b0 + db));
 }
 
+// Largest dx = a c at lag lam over the pairs that are not culled:
+// min(a_max c, cull w), w = db / b0, since a <= cull b1 for those pairs and
+// b1 c = w.
+double row_dx_bound(double lam, double a_max, double cull, double kappa, double s2) {
+  const double db = 4.0 * kappa * std::min(lam, 1.0);
+  const double b0 = s2 + 4.0 * kappa * std::max(lam - 1.0, 0.0);
+  return std::min(a_max * db / (b0 * (b0 + db)), cull * db / b0);
+}
+
 int degree_needed(double dx, bool mixed) {
   // smallest M with e^{2 dx} dx^{M+1} / (M+1)! below the precision's target
   const double tol = mixed ? 2e-8 : 5e-15;
@@ -239,12 +248,14 @@ int degree_needed(double dx, bool mixed) {
   return mmax;
 }
 
-// First row n >= n_start (n >= 1) with a_max * c(f + n) <= thr; c decreases
-// for lags >= 1, so binary search applies.
-int64_t first_row_below(double thr, double a_max, double f, double kappa, double s2, int64_t n_start,
-                        int64_t n_end) {
+// First row n >= n_start (n >= 1) whose dx bound (row_dx_bound) is <= thr;
+// the bound decreases for lags >= 1, so binary search applies.
+int64_t first_row_below(double thr, double a_max, double cull, double f, double kappa, double s2,
+                        int64_t n_start, int64_t n_end) {
   if (a_max <= 0) return n_start;
-  auto ok = [&](int64_t n) { return a_max * row_c(f + (double)n, kappa, s2) <= thr; };
+  auto ok = [&](int64_t n) {
+    return row_dx_bound(f + (double)n, a_max, cull, kappa, s2) <= thr;
+  };
   if (ok(n_start)) return n_start;
   int64_t lo = n_start, hi = std::max(n_end, n_start + 1);
   while (!ok(hi)) {
@@ -268,7 +279,8 @@ DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int6
                            bool mixed) {
   DegreeBounds b;
   const int mmax = mixed ? kM32 : kM64;
-  const double dx0 = a_max * row_c(f + (double)kf, kappa, s2);
+  const double cull = mixed ? kCullX32 : kCullX64;
+  const double dx0 = row_dx_bound(f + (double)kf, a_max, cull, kappa, s2);
   b.m_max = std::min(degree_needed(dx0, mixed), mmax);
   const double tol = mixed ? 2e-8 : 5e-15;
   for (int M = 0; M <= kMaxSeg; ++M) b.b[M] = (int32_t)kf;
@@ -281,7 +293,7 @@ DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int6
       for (int k = 1; k <= M + 1; ++k) t *= mid / k;
       (t <= tol ? lo : hi) = mid;
     }
-    int64_t n = first_row_below(lo, a_max, f, kappa, s2, kf, kf + 1);
+    int64_t n = first_row_below(lo, a_max, cull, f, kappa, s2, kf, kf + 1);
     if (align > 1) n = kf + (n - kf + align - 1) / align * align;
     b.b[M] = (int32_t)std::min<int64_t>(n, (int64_t)1 << 30);
   }

@@ -52,6 +52,14 @@ constexpr int kMNear32 = 6;
 // floor of the mixed path's relative-error model.  The test is made on
 // x1 log2(e), the quantity the FP32 rows hold.
 constexpr float kCull32Log2 = 144.26950408889634f;
+// The x1 beyond which a pair's term is negligible, per path (FP64: both E1
+// values are below the double range).  The planner bounds a pair's dx by
+// min(a_max c, cull w) with w = db/b0 (= b1 c): a term with x1 above the
+// cull contributes nothing whatever its dx, so it needs no near-band form;
+// evaluated by the far-region series it is below L e^{-x1 (1 - w)}, which is
+// zero in the path's precision since w <= thr / cull there.
+constexpr double kCullX32 = 100.0;
+constexpr double kCullX64 = 745.0;
 
 constexpr int kGL = 24;  // Gauss-Legendre nodes on [0, 1] for J_m(w), w <= 1
 struct GLNodes {

@@ -137,7 +137,8 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
   const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
                        (double)(s->desc.ny - 1) * (s->desc.ny - 1);
   const double thr = mixed ? (double)kThr32 : kThr64;
-  int64_t kf = first_row_below(thr, a_max, 0.0, s->kappa, s->s2, 1, V);
+  const double cull = mixed ? kCullX32 : kCullX64;
+  int64_t kf = first_row_below(thr, a_max, cull, 0.0, s->kappa, s->s2, 1, V);
   kf = 1 + (kf - 1 + R - 1) / R * R;
   if (kf > V) kf = V + 1;  // every lag is in the near band
   P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
@@ -359,7 +360,8 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
   P.total_rows = 0;
   P.jobs.clear();
   for (auto& G : groups) {
-    G.kf = first_row_below(thr, a_max, G.f, s->kappa, s->s2, 1, std::max<int64_t>(G.n_last, 1));
+    G.kf = first_row_below(thr, a_max, mixed ? kCullX32 : kCullX64, G.f, s->kappa, s->s2, 1,
+                           std::max<int64_t>(G.n_last, 1));
     G.bounds = degree_bounds(a_max, G.f, s->kappa, s->s2, G.kf, 1, mixed);
     const int64_t span = std::max<int64_t>(0, G.n_last - G.n_first + 1);
     if (int_rows) {

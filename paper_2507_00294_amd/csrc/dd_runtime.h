@@ -19,7 +19,8 @@ dd_status ensure_device();
 const GLNodes& gl_nodes();
 double row_c(double lam, double kappa, double s2);
 int degree_needed(double dx, bool mixed);
-int64_t first_row_below(double thr, double a_max, double f, double kappa, double s2,
+double row_dx_bound(double lam, double a_max, double cull, double kappa, double s2);
+int64_t first_row_below(double thr, double a_max, double cull, double f, double kappa, double s2,
                         int64_t n_start, int64_t n_end);
 DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
                            bool mixed);
