@@ -273,6 +273,28 @@ int64_t first_row_below(double thr, double a_max, double cull, double f, double 
   return hi;
 }
 
+// Largest dx that the series of degree M covers: e^{2dx} dx^{M+1}/(M+1)! = tol
+// (bisection), for M = 0 .. kMaxSeg; the same for every scan, computed once.
+static const double* dx_cover(bool mixed) {
+  struct Table {
+    double v[kMaxSeg + 1];
+    explicit Table(double tol) {
+      for (int M = 0; M <= kMaxSeg; ++M) {
+        double lo = 0, hi = 1.0;
+        for (int it = 0; it < 80; ++it) {
+          const double mid = 0.5 * (lo + hi);
+          double t = std::exp(2 * mid);
+          for (int k = 1; k <= M + 1; ++k) t *= mid / k;
+          (t <= tol ? lo : hi) = mid;
+        }
+        v[M] = lo;
+      }
+    }
+  };
+  static const Table t32(2e-8), t64(5e-15);
+  return mixed ? t32.v : t64.v;
+}
+
 // Degree bounds for the far region starting at row kf (aligned so that
 // kf + k*align are the only segment starts).
 DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
@@ -282,18 +304,11 @@ DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int6
   const double cull = mixed ? kCullX32 : kCullX64;
   const double dx0 = row_dx_bound(f + (double)kf, a_max, cull, kappa, s2);
   b.m_max = std::min(degree_needed(dx0, mixed), mmax);
-  const double tol = mixed ? 2e-8 : 5e-15;
+  const double* cover = dx_cover(mixed);
   for (int M = 0; M <= kMaxSeg; ++M) b.b[M] = (int32_t)kf;
   for (int M = 0; M < b.m_max; ++M) {
-    // largest dx that degree M covers: solve e^{2dx} dx^{M+1}/(M+1)! = tol
-    double lo = 0, hi = 1.0;
-    for (int it = 0; it < 80; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      double t = std::exp(2 * mid);
-      for (int k = 1; k <= M + 1; ++k) t *= mid / k;
-      (t <= tol ? lo : hi) = mid;
-    }
-    int64_t n = first_row_below(lo, a_max, cull, f, kappa, s2, kf, kf + 1);
+    // first row whose dx bound degree M covers
+    int64_t n = first_row_below(cover[M], a_max, cull, f, kappa, s2, kf, kf + 1);
     if (align > 1) n = kf + (n - kf + align - 1) / align * align;
     b.b[M] = (int32_t)std::min<int64_t>(n, (int64_t)1 << 30);
   }

@@ -74,7 +74,7 @@ struct TuneParams {
   int arr_R_mixed = 4, arr_R_f64 = 2;      // far-region tile: 64 R visits
   int arr_RN_mixed = 2, arr_RN_f64 = 2;    // near-band tile
   int arr_K_mixed = 2048, arr_K_f64 = 1024;   // lags per far work item
-  int map_R_mixed = 2, map_R_f64 = 1;
+  int map_R_mixed = 4, map_R_f64 = 1;
   int map_K = 4096;
 };
 TuneParams& tune();

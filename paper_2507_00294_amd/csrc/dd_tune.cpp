@@ -116,7 +116,7 @@ bool read_int(const std::string& txt, const char* obj, const char* field, int& o
 
 bool valid(const TuneParams& t) {
   auto r_ok = [](int r) { return r == 2 || r == 4; };
-  auto rm_ok = [](int r) { return r == 1 || r == 2; };
+  auto rm_ok = [](int r) { return r == 1 || r == 2 || r == 4; };
   auto k_ok = [](int k) { return k >= 64 && k <= (1 << 24); };
   return r_ok(t.arr_R_mixed) && r_ok(t.arr_R_f64) && r_ok(t.arr_RN_mixed) && r_ok(t.arr_RN_f64) &&
          k_ok(t.arr_K_mixed) && k_ok(t.arr_K_f64) && rm_ok(t.map_R_mixed) && rm_ok(t.map_R_f64) &&
@@ -224,7 +224,7 @@ dd_status dd_autotune(const char* cache_path) {
   FreeGuard fg2{mout};
   for (int mixed = 1; mixed >= 0; --mixed) {
     double bms = 1e30;
-    for (int R : {1, 2})
+    for (int R : {1, 2, 4})
       for (int K : {1024, 4096, 16384}) {
         TuneParams t = best;
         (mixed ? t.map_R_mixed : t.map_R_f64) = R;
