@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the surrogate-versus-exact measurement")
     ap.add_argument("--surrogate-maps", type=int, default=2000)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-configuration measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM byte counters) and exit")
@@ -159,6 +161,35 @@ def main():
     diff = np.abs(result - other_res) / np.maximum(np.abs(other_res if other == "fp64" else result),
                                                   floor)
     log(f"[bench] {other}: {sec_o * 1e3:.3f} ms/step; max rel diff mixed vs fp64 {diff.max():.3e}")
+
+    # Batched configuration: 256 scans of uneven size, order and physics in one
+    # call (arrival at every visit and the final map at the probes).
+    bat = None
+    if not args.no_batched:
+        specs_b = wl.batch_scans()
+        scans_b = [dd.Scan(**sp.kwargs()) for sp in specs_b]
+        mask = dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES
+        dd.batch_solve(scans_b, mask, prec)  # builds the scans' device tables
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            dd.batch_solve(scans_b, mask, prec)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t_b = float(np.median(ts))
+        vs = [sb.num_visits for sb in scans_b]
+        pairs_b = float(sum(wl.causal_arrival_pairs(v) + sp.nx * sp.ny * v
+                            for v, sp in zip(vs, specs_b)))
+        bat = {"value": pairs_b / t_b, "unit": "pair-terms/s", "ms_per_call": t_b * 1e3,
+               "pairs_per_call": pairs_b, "precision": prec, "scans": len(scans_b),
+               "workload": "256 scans (seed 4): side U{16..256}, order uniform over raster / "
+                           "interleaved / random / 4-frame, dwell 10^U(-7,-5) s, D 10^U(-15,-11) "
+                           "m^2/s, sigma U[0.2,1] nm; arrival at every visit + final map at the "
+                           "probes, one call"}
+        log(f"[bench] batched: {t_b * 1e3:.1f} ms/call, {bat['value']:.4e} pairs/s")
+        for sb in scans_b:
+            sb.close()
 
     # Learned surrogate against the exact batched kernel on the held-out 64x64
     # test scans (both timed end to end, scans' device tables built first).
@@ -229,6 +260,7 @@ def main():
         "other_precision": {"precision": other, "ms_per_step": sec_o * 1e3,
                             "value": pairs / sec_o, "max_rel_diff_mixed_vs_fp64": float(diff.max())},
         "kernels_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in kern.items()},
+        "batched": bat,
         "surrogate": sur,
     }
     print(json.dumps(line), flush=True)
