@@ -9,16 +9,16 @@ namespace dd {
 
 // ---------------------------------------------------------------------------
 // Persistent batched kernels: many scans, one launch per item kind (arrival
-// items, then map items, so that each kernel has the register budget of its
-// own code).  Each wavefront takes the next item from a device counter until
+// far region, arrival near band, map far region, map near band), so that
+// each kernel has the register budget of its own code.  Each wavefront takes the next item from a device counter until
 // the list is exhausted (every wave reaches that exit).  The items were
 // sorted longest first on the host; each item runs exactly the per-item code
 // of the per-scan kernels, so batch results equal per-scan results bit for
 // bit.
-template <int R, int RN, bool MIXED>
-__global__ void __launch_bounds__(256) k_batch_arrival(const BatchScan* __restrict__ scans,
-                                                       const BatchItem* __restrict__ items,
-                                                       int n_items, int* __restrict__ counter) {
+template <int R, bool MIXED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MIXED && R == 4 ? 3 : 1, 8)))
+k_batch_arrival_far(const BatchScan* __restrict__ scans, const BatchItem* __restrict__ items,
+                    int n_items, int* __restrict__ counter) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     int it = 0;
@@ -28,19 +28,33 @@ __global__ void __launch_bounds__(256) k_batch_arrival(const BatchScan* __restri
     const BatchItem bi = items[it];
     const BatchScan& S = scans[bi.scan];
     const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
-    if (bi.kind == kBatchArrFar) {
-      if (MIXED)
-        do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
-      else
-        do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds,
-                            S.arr_partial);
-    } else {
-      do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
-    }
+    if (MIXED)
+      do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
+    else
+      do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds, S.arr_partial);
   }
 }
 
-template <int RM, bool MIXED>
+template <int RN, bool MIXED>
+__global__ void __launch_bounds__(256) k_batch_arrival_near(const BatchScan* __restrict__ scans,
+                                                            const BatchItem* __restrict__ items,
+                                                            int n_items, int* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(counter, 1);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    const BatchScan& S = scans[bi.scan];
+    const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
+    do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
+  }
+}
+
+// Map items; NEAR selects the near-band items (per-pair regimes) or the
+// far-region items (degree segments).
+template <int RM, bool MIXED, bool NEAR>
 __global__ void __launch_bounds__(256) k_batch_map(const BatchScan* __restrict__ scans,
                                                    const BatchItem* __restrict__ items,
                                                    int n_items, int* __restrict__ counter) {
@@ -52,8 +66,7 @@ __global__ void __launch_bounds__(256) k_batch_map(const BatchScan* __restrict__
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const BatchScan& S = scans[bi.scan];
-    const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask,
-                     bi.kind == kBatchMapNear ? 1 : 0, 0, 0};
+    const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask, NEAR ? 1 : 0, 0, 0};
     do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0,
                       (double)S.map_row0, 1.0, 1.0, S.nx, S.map_rows, true, S.map_partial);
   }
@@ -90,51 +103,82 @@ static inline unsigned batch_grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
+// Persistent grid: enough waves to fill the chip a few times over.
+static unsigned persistent_blocks(int32_t n_items) {
+  return (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
+}
+
 hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
-                        int* counter, int R, int RN, bool mixed, hipStream_t st) {
+                        int* counter, int R, bool mixed, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
-  // persistent grid: enough waves to fill the chip a few times over
-  const unsigned blocks = (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
-#define DD_LAUNCH_BATCH(A, B)                                                                      \
-  if (R == A && RN == B) {                                                                         \
-    if (mixed)                                                                                     \
-      hipLaunchKernelGGL((k_batch_arrival<A, B, true>), dim3(blocks), dim3(256), 0, st, scans,     \
-                         items, n_items, counter);                                                 \
-    else                                                                                           \
-      hipLaunchKernelGGL((k_batch_arrival<A, B, false>), dim3(blocks), dim3(256), 0, st, scans,    \
-                         items, n_items, counter);                                                 \
-    return hipGetLastError();                                                                      \
+  const unsigned blocks = persistent_blocks(n_items);
+#define DD_LAUNCH(A)                                                                            \
+  if (R == A) {                                                                                 \
+    if (mixed)                                                                                  \
+      hipLaunchKernelGGL((k_batch_arrival_far<A, true>), dim3(blocks), dim3(256), 0, st, scans, \
+                         items, n_items, counter);                                              \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_batch_arrival_far<A, false>), dim3(blocks), dim3(256), 0, st,       \
+                         scans, items, n_items, counter);                                       \
+    return hipGetLastError();                                                                   \
   }
-  // every tile shape the autotuner may choose: R, RN in {2, 4}
-  DD_LAUNCH_BATCH(4, 2)
-  DD_LAUNCH_BATCH(4, 4)
-  DD_LAUNCH_BATCH(2, 2)
-  DD_LAUNCH_BATCH(2, 4)
-#undef DD_LAUNCH_BATCH
+  DD_LAUNCH(4)
+  DD_LAUNCH(2)
+#undef DD_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_near(const BatchScan* scans, const BatchItem* items, int32_t n_items,
+                             int* counter, int RN, bool mixed, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
+  const unsigned blocks = persistent_blocks(n_items);
+#define DD_LAUNCH(B)                                                                             \
+  if (RN == B) {                                                                                 \
+    if (mixed)                                                                                   \
+      hipLaunchKernelGGL((k_batch_arrival_near<B, true>), dim3(blocks), dim3(256), 0, st, scans, \
+                         items, n_items, counter);                                               \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_batch_arrival_near<B, false>), dim3(blocks), dim3(256), 0, st,       \
+                         scans, items, n_items, counter);                                        \
+    return hipGetLastError();                                                                    \
+  }
+  DD_LAUNCH(2)
+  DD_LAUNCH(4)
+#undef DD_LAUNCH
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_map(const BatchScan* scans, const BatchItem* items, int32_t n_items,
-                            int* counter, int RM, bool mixed, hipStream_t st) {
+                            int* counter, int RM, bool mixed, bool near, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, st, counter);
-  const unsigned blocks = (unsigned)std::min<int64_t>((n_items + 3) / 4, 256 * 8);
-#define DD_LAUNCH_BATCH_MAP(C)                                                                    \
-  if (RM == C) {                                                                                  \
-    if (mixed)                                                                                    \
-      hipLaunchKernelGGL((k_batch_map<C, true>), dim3(blocks), dim3(256), 0, st, scans, items,    \
-                         n_items, counter);                                                       \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_batch_map<C, false>), dim3(blocks), dim3(256), 0, st, scans, items,   \
-                         n_items, counter);                                                       \
-    return hipGetLastError();                                                                     \
+  const unsigned blocks = persistent_blocks(n_items);
+#define DD_LAUNCH_ONE(C, MX, NR)                                                                 \
+  hipLaunchKernelGGL((k_batch_map<C, MX, NR>), dim3(blocks), dim3(256), 0, st, scans, items,     \
+                     n_items, counter)
+#define DD_LAUNCH_BATCH_MAP(C)                                                                   \
+  if (RM == C) {                                                                                 \
+    if (mixed) {                                                                                 \
+      if (near)                                                                                  \
+        DD_LAUNCH_ONE(C, true, true);                                                            \
+      else                                                                                       \
+        DD_LAUNCH_ONE(C, true, false);                                                           \
+    } else {                                                                                     \
+      if (near)                                                                                  \
+        DD_LAUNCH_ONE(C, false, true);                                                           \
+      else                                                                                       \
+        DD_LAUNCH_ONE(C, false, false);                                                          \
+    }                                                                                            \
+    return hipGetLastError();                                                                    \
   }
   // every tile shape the autotuner may choose: RM in {1, 2, 4}
   DD_LAUNCH_BATCH_MAP(4)
   DD_LAUNCH_BATCH_MAP(2)
   DD_LAUNCH_BATCH_MAP(1)
 #undef DD_LAUNCH_BATCH_MAP
+#undef DD_LAUNCH_ONE
   return hipErrorInvalidValue;
 }
 

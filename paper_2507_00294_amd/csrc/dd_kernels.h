@@ -54,12 +54,15 @@ hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slot
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
                              int64_t npix, double pref, double* out, hipStream_t st);
 
-// Persistent batched launches (arrival items; map items); `counter` is
-// zeroed on the stream first.
+// Persistent batched launches (arrival far-region items; arrival near-band
+// items; map far-region or near-band items); `counter` is zeroed on the
+// stream first.
 hipError_t launch_batch(const BatchScan* scans, const BatchItem* items, int32_t n_items,
-                        int* counter, int R, int RN, bool mixed, hipStream_t st);
+                        int* counter, int R, bool mixed, hipStream_t st);
+hipError_t launch_batch_near(const BatchScan* scans, const BatchItem* items, int32_t n_items,
+                             int* counter, int RN, bool mixed, hipStream_t st);
 hipError_t launch_batch_map(const BatchScan* scans, const BatchItem* items, int32_t n_items,
-                            int* counter, int RM, bool mixed, hipStream_t st);
+                            int* counter, int RM, bool mixed, bool near, hipStream_t st);
 hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
                                hipStream_t st);
 

@@ -501,7 +501,8 @@ dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStrea
 // Batched solve: every scan's arrival and final-map items in one persistent
 // launch, then one fixed-order reduction launch.
 struct BatchScratch {
-  DevBuf scans, items, map_items, reds, slots, partial, counter, staging;
+  DevBuf scans, items, near_items, map_items, map_near_items, reds, slots, partial, counter,
+      staging;
 };
 static thread_local BatchScratch g_batch;
 
@@ -517,7 +518,7 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   const int RM = mixed ? tune().map_R_mixed : tune().map_R_f64;
   const bool want_arr = (mask & DD_Q_ARRIVAL) != 0, want_map = (mask & DD_Q_FINAL_AT_PROBES) != 0;
   std::vector<BatchScan> bs(n);
-  std::vector<BatchItem> items, map_items;
+  std::vector<BatchItem> items, near_items, map_items, map_near_items;
   std::vector<BatchReduce> reds;
   std::vector<int32_t> all_slots;
   std::vector<int64_t> arr_off(n, 0), map_off(n, 0), slot_off(n, 0), out_off(n, 0);
@@ -563,9 +564,10 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
         const double cost =
             (double)(a.n_hi - a.n_lo) * 64.0 * (near_item ? RN * near_w : R);
         const int64_t c = (int64_t)cost;
-        items.push_back(BatchItem{k, near_item ? kBatchArrNear : kBatchArrFar, a.tile, a.n_lo,
-                                  a.n_hi, a.slot_flags, (int32_t)(c >> 31),
-                                  (int32_t)(c & 0x7fffffff)});
+        (near_item ? near_items : items)
+            .push_back(BatchItem{k, near_item ? kBatchArrNear : kBatchArrFar, a.tile, a.n_lo,
+                                 a.n_hi, a.slot_flags, (int32_t)(c >> 31),
+                                 (int32_t)(c & 0x7fffffff)});
       }
       reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref});
       out_total += s->V;
@@ -586,9 +588,9 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
         const int64_t tile_pix = std::min<int64_t>(64 * RM, MP.npix - (int64_t)m.tile * 64 * RM);
         const double cost = (double)(m.n_hi - m.n_lo) * tile_pix * (m.near ? near_w : 1.0);
         const int64_t c = (int64_t)cost;
-        map_items.push_back(BatchItem{k, m.near ? kBatchMapNear : kBatchMapFar, m.tile, m.n_lo,
-                                      m.n_hi, m.slot, (int32_t)(c >> 31),
-                                      (int32_t)(c & 0x7fffffff)});
+        (m.near ? map_near_items : map_items)
+            .push_back(BatchItem{k, m.near ? kBatchMapNear : kBatchMapFar, m.tile, m.n_lo, m.n_hi,
+                                 m.slot, (int32_t)(c >> 31), (int32_t)(c & 0x7fffffff)});
       }
       reds.push_back(BatchReduce{nullptr, nullptr, MP.times[0].n_slots, 0, MP.npix, out_total,
                                  nullptr, s->pref});
@@ -603,7 +605,9 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     return ca > cb;
   };
   std::stable_sort(items.begin(), items.end(), longer);
+  std::stable_sort(near_items.begin(), near_items.end(), longer);
   std::stable_sort(map_items.begin(), map_items.end(), longer);
+  std::stable_sort(map_near_items.begin(), map_near_items.end(), longer);
   BatchScratch& W = g_batch;
   DD_HIP(W.partial.ensure(sizeof(double) * (size_t)std::max<int64_t>(partial_total, 1)),
          "device allocation");
@@ -636,20 +640,31 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   if (rc != DD_OK) return rc;
   rc = upload(W.items, items, st);
   if (rc != DD_OK) return rc;
+  rc = upload(W.near_items, near_items, st);
+  if (rc != DD_OK) return rc;
   rc = upload(W.map_items, map_items, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(W.map_near_items, map_near_items, st);
   if (rc != DD_OK) return rc;
   rc = upload(W.reds, reds, st);
   if (rc != DD_OK) return rc;
   rc = upload(W.slots, all_slots, st);
   if (rc != DD_OK) return rc;
-  DD_HIP(W.counter.ensure(2 * sizeof(int)), "device allocation");
+  DD_HIP(W.counter.ensure(4 * sizeof(int)), "device allocation");
   ProfToken tb = prof_begin("batch", st);
   DD_HIP(launch_batch(W.scans.as<BatchScan>(), W.items.as<BatchItem>(), (int32_t)items.size(),
-                      W.counter.as<int>(), R, RN, mixed, st),
+                      W.counter.as<int>(), R, mixed, st),
          "batched launch");
+  DD_HIP(launch_batch_near(W.scans.as<BatchScan>(), W.near_items.as<BatchItem>(),
+                           (int32_t)near_items.size(), W.counter.as<int>() + 1, RN, mixed, st),
+         "batched near-band launch");
   DD_HIP(launch_batch_map(W.scans.as<BatchScan>(), W.map_items.as<BatchItem>(),
-                          (int32_t)map_items.size(), W.counter.as<int>() + 1, RM, mixed, st),
+                          (int32_t)map_items.size(), W.counter.as<int>() + 2, RM, mixed, false, st),
          "batched map launch");
+  DD_HIP(launch_batch_map(W.scans.as<BatchScan>(), W.map_near_items.as<BatchItem>(),
+                          (int32_t)map_near_items.size(), W.counter.as<int>() + 3, RM, mixed, true,
+                          st),
+         "batched map near-band launch");
   prof_end(tb, st, pairs, flops);
   ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_batch(W.reds.as<BatchReduce>(), (int32_t)reds.size(), out_total, st),
