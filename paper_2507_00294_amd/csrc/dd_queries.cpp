@@ -515,8 +515,20 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
                         int32_t rows) {
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
-  const int RM = mixed ? tune().map_R_mixed : tune().map_R_f64;
   const bool want_arr = (mask & DD_Q_ARRIVAL) != 0, want_map = (mask & DD_Q_FINAL_AT_PROBES) != 0;
+  // map tile width: the tuned one, narrowed while a narrower tile still covers
+  // the largest map of the call (a one-row map fills one 64-pixel tile)
+  int RM = mixed ? tune().map_R_mixed : tune().map_R_f64;
+  if (want_map) {
+    int64_t most = 0;
+    for (int32_t k = 0; k < n; ++k) {
+      const int64_t r = rows < 0 ? scans[k]->desc.ny
+                                 : std::min<int64_t>(rows, scans[k]->desc.ny -
+                                                               std::min(row0, scans[k]->desc.ny - 1));
+      most = std::max<int64_t>(most, r * scans[k]->desc.nx);
+    }
+    while (RM > 1 && 64LL * (RM / 2) >= most) RM /= 2;
+  }
   std::vector<BatchScan> bs(n);
   std::vector<BatchItem> items, near_items, map_items, map_near_items;
   std::vector<BatchReduce> reds;

@@ -68,6 +68,10 @@ struct dd_unet {
   DevBuf p1, p2, p3, y, col0;
   DevBuf col, dA0, dA1, dZ, dZb, ds1, ds2, ds3, part, loss_map, norm_part, scale_norm;
   size_t part_elems = 0;
+  // second stream (default priority, non-blocking) on which predict runs the
+  // exact judge while the network runs on the caller's stream
+  hipStream_t judge_stream = nullptr;
+  hipEvent_t judge_done = nullptr;
 };
 
 namespace {
@@ -452,6 +456,8 @@ void dd_unet_destroy(dd_unet* u) {
     c.Z.release();
     c.A.release();
   }
+  if (u->judge_done) (void)hipEventDestroy(u->judge_done);
+  if (u->judge_stream) (void)hipStreamDestroy(u->judge_stream);
   delete u;
 }
 
@@ -635,6 +641,13 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
     UN_HIP(x.ensure(sizeof(float) * chunk * NPX * CIN), "device allocation");
     UN_HIP(own.ensure(sizeof(float) * chunk * NPX), "device allocation");
     if ((rc = ensure_capacity(*u, chunk, false)) != DD_OK) return rc;
+    UN_HIP(spot.ensure(sizeof(double) * nok * S), "device allocation");
+    UN_HIP(rel.ensure(sizeof(double) * nok), "device allocation");
+    if (!u->judge_stream)
+      UN_HIP(hipStreamCreateWithFlags(&u->judge_stream, hipStreamNonBlocking), "stream creation");
+    if (!u->judge_done)
+      UN_HIP(hipEventCreateWithFlags(&u->judge_done, hipEventDisableTiming), "event creation");
+    // the network, enqueued on the caller's stream
     for (size_t b0 = 0; b0 < nok; b0 += chunk) {
       const int nb = (int)std::min<size_t>(chunk, nok - b0);
       UN_HIP(nn::gather_features(d_feat.as<const float*>() + b0, nb, CIN, NPX, x.as<float>(),
@@ -646,17 +659,18 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
                         d_out.as<double*>() + b0, st),
              "prediction output");
     }
-    // 2. judge: the exact middle row (row 31) of every predicted map
+    // 2. judge: the exact middle row (row 31) of every predicted map, planned
+    // on the host and run on the judge stream while the network runs
     const int row = 31;
     std::vector<dd_scan*> sub(nok);
     for (size_t q = 0; q < nok; ++q) sub[q] = scans[ok_idx[q]];
-    UN_HIP(spot.ensure(sizeof(double) * nok * S), "device allocation");
-    UN_HIP(rel.ensure(sizeof(double) * nok), "device allocation");
     std::vector<double*> rows(nok);
     for (size_t q = 0; q < nok; ++q) rows[q] = spot.as<double>() + q * S;
-    rc = run_batch(sub.data(), (int32_t)nok, DD_Q_FINAL_AT_PROBES, mixed, rows.data(), 1, st, row,
-                   1);
+    rc = run_batch(sub.data(), (int32_t)nok, DD_Q_FINAL_AT_PROBES, mixed, rows.data(), 1,
+                   u->judge_stream, row, 1);
     if (rc != DD_OK) return rc;
+    UN_HIP(hipEventRecord(u->judge_done, u->judge_stream), "event record");
+    UN_HIP(hipStreamWaitEvent(st, u->judge_done, 0), "stream wait");
     UN_HIP(nn::spot(d_out.as<const double*>(), spot.as<double>(), (int)nok, S, row,
                     rel.as<double>(), st),
            "spot check");

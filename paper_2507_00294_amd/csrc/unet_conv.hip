@@ -17,8 +17,8 @@
 // from its two sources.  Epilogues: plain (the data gradient), bias + SiLU,
 // and bias + SiLU followed by the 32 -> 1 output head reduced across lanes.
 //
-// k_conv_first (the 5-channel input layer): K = 45 padded to 64, A gathered
-// element by element into LDS (two K steps).
+// k_conv_first (the 5-channel input layer): K = 45 padded to 64; each thread
+// gathers its pixel's row into registers and stores it to LDS (two K steps).
 //
 // Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l): A row l % 16,
 // k = 8 (l / 16) .. +7; B column l % 16, same k; D element v at row
@@ -236,28 +236,38 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   epilogue<NB, EPI>(p, acc, m0, n0, wave, lane);
 }
 
-// First layer: ci < 32 input channels, K = 9 ci <= 64 padded to 64; N = 32.
-template <int EPI>
+// First layer: CI (< 32) input channels, K = 9 CI <= 64 padded to 64; N = 32.
+// Each thread gathers its pixel's 9 CI values into registers (indices fixed at
+// compile time) and writes its LDS row with 16-byte stores.
+template <int CI, int EPI>
 __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
+  static_assert(9 * CI <= 64, "first layer: 9 CI must fit in 64 columns");
   __shared__ __attribute__((aligned(16))) __bf16 As[CBM][72];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[32][72];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * CBM;
-  const int lg = p.lg, W = 1 << lg, ci = p.ci, K9 = 9 * ci;
-  // A: pixel m0 + tid, all 64 k values
+  const int lg = p.lg, W = 1 << lg;
+  // A: pixel m0 + tid, k = tap CI + c
   {
     const int m = m0 + tid;
     const int yy = (m >> lg) & (W - 1), xx = m & (W - 1);
-#pragma unroll 4
-    for (int k = 0; k < 64; ++k) {
-      float v = 0.f;
-      if (k < K9 && m < p.M) {
-        const int tap = k / ci, c = k - tap * ci;
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const int sy = yy + dy, sx = xx + dx;
-        if (sy >= 0 && sy < W && sx >= 0 && sx < W) v = p.x[(int64_t)(m + dy * W + dx) * ci + c];
-      }
-      As[tid][k] = (__bf16)v;
+    float v[64];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const bool ok = m < p.M && yy + dy >= 0 && yy + dy < W && xx + dx >= 0 && xx + dx < W;
+      const float* src = p.x + (int64_t)(ok ? m + dy * W + dx : 0) * CI;
+#pragma unroll
+      for (int c = 0; c < CI; ++c) v[tap * CI + c] = ok ? src[c] : 0.f;
+    }
+#pragma unroll
+    for (int k = 9 * CI; k < 64; ++k) v[k] = 0.f;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      bf16x8 b;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) b[e] = (__bf16)v[8 * g + e];
+      *reinterpret_cast<bf16x8*>(&As[tid][8 * g]) = b;
     }
   }
   // B: wt [32][64]
@@ -341,8 +351,13 @@ hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, 
 hipError_t conv3_first_silu(const float* x, int B, int lg, int ci, const __bf16* wt,
                             const float* bias, float* act, float* z, hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, 32};
-  if (p.M <= 0 || ci < 1 || 9 * ci > 64 || lg < 3 || lg > 6 || !act) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_conv_first<EPI_SILU>), dim3((p.M + CBM - 1) / CBM), dim3(256), 0, st, p);
+  if (p.M <= 0 || lg < 3 || lg > 6 || !act) return hipErrorInvalidValue;
+  const dim3 grid((p.M + CBM - 1) / CBM);
+  switch (ci) {  // the input channel counts the network uses
+    case 5: hipLaunchKernelGGL((k_conv_first<5, EPI_SILU>), grid, dim3(256), 0, st, p); break;
+    case 3: hipLaunchKernelGGL((k_conv_first<3, EPI_SILU>), grid, dim3(256), 0, st, p); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
