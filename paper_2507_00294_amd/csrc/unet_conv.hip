@@ -10,9 +10,9 @@
 // BN output channels.  For each chunk of 32 input channels it stages the
 // tile's input pixels plus a one-pixel halo (at most 400 pixels) in LDS as
 // BF16, once, and all nine taps then read their A fragments from that tile
-// (the nine-fold reuse of every input value stays on chip).  The B fragments
-// (weights, [N][9 ci], L2-resident) are loaded straight into registers one
-// tap ahead.  Input modes: a plain activation, or the decoder's virtual
+// (the nine-fold reuse of every input value stays on chip).  The chunk's
+// weights (9 taps x BN columns x 32, from [N][9 ci]) are staged in LDS once
+// per block beside it, so the four waves share them.  Input modes: a plain activation, or the decoder's virtual
 // concatenation [nearest-2x-upsampled coarse map, skip map] read directly
 // from its two sources.  Epilogues: plain (the data gradient), bias + SiLU,
 // and bias + SiLU followed by the 32 -> 1 output head reduced across lanes.
@@ -134,7 +134,10 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
 template <int IN, int BN, int EPI>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   __shared__ __attribute__((aligned(16))) __bf16 As[HPMAX][CLDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[9][BN][CLDK];
   constexpr int NB = BN / 16;
+  constexpr int BPIECES = 9 * BN * 4;  // 16-byte pieces of the chunk's weights
+  constexpr int BSLOTS = (BPIECES + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * CBM, n0 = blockIdx.y * BN;
   const int lg = p.lg, W = 1 << lg, ci = p.ci, K = 9 * ci;
@@ -170,7 +173,6 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
     const int g = o >> lgRW, r = (o >> lg) & (R - 1), x = o & (W - 1);
     hbase[a] = g * slice + r * HW2 + x;
   }
-  const __bf16* wlane = p.wt + (int64_t)(n0 + (lane & 15)) * K + 8 * (lane >> 4);
 
   f32x4 acc[4][NB];
 #pragma unroll
@@ -180,7 +182,18 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
 
   const int chunks = ci >> 5;
   for (int cc = 0; cc < chunks; ++cc) {
-    // stage the halo tile of channels 32 cc .. 32 cc + 31
+    // stage the chunk's weights (9 taps x BN columns x 32 k) ...
+#pragma unroll
+    for (int i = 0; i < BSLOTS; ++i) {
+      const int piece = tid + 256 * i;
+      if (piece < BPIECES) {
+        const int tap = piece / (BN * 4), rem = piece - tap * (BN * 4);
+        const int n = rem >> 2, part = rem & 3;
+        *reinterpret_cast<bf16x8*>(&Bs[tap][n][part * 8]) = *reinterpret_cast<const bf16x8*>(
+            p.wt + (int64_t)(n0 + n) * K + tap * ci + cc * 32 + part * 8);
+      }
+    }
+    // ... and the halo tile of channels 32 cc .. 32 cc + 31
 #pragma unroll
     for (int i = 0; i < SLOTS; ++i) {
       const int idx = tid + 256 * i, px = idx >> 3, q = idx & 7;
@@ -202,33 +215,21 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
         *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
       }
     }
-    bf16x8 bcur[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      bcur[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + cc * 32);
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      bf16x8 bnext[NB];
-      if (tap < 8) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-          bnext[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + (tap + 1) * ci +
-                                                      cc * 32);
-      }
       const int toff = (tap / 3) * HW2 + (tap % 3);
       bf16x8 af[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         af[a] = *reinterpret_cast<const bf16x8*>(&As[hbase[a] + toff][8 * (lane >> 4)]);
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+      for (int b = 0; b < NB; ++b) {
+        const bf16x8 bf =
+            *reinterpret_cast<const bf16x8*>(&Bs[tap][b * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bcur[b], acc[a][b], 0, 0, 0);
-      if (tap < 8) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) bcur[b] = bnext[b];
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf, acc[a][b], 0, 0, 0);
       }
     }
     __syncthreads();
