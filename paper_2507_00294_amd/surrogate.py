@@ -196,7 +196,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="train and evaluate the surrogate")
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--test", type=int, default=2000)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=40000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--clip", type=float, default=1.0)
