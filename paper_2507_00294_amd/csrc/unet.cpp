@@ -369,17 +369,21 @@ bool in_training_range(const dd_scan* s) {
 dd_status ensure_table(dd_scan* s, hipStream_t st, bool& ok) {
   ok = false;
   if (s->sur_state == 0) {
-    s->sur_state = -1;
+    std::vector<float> h;
     if (s->desc.nx == S && s->desc.ny == S && s->V >= NPX) {
-      std::vector<float> h((size_t)NPX * (CIN + 1));
-      if (scan_table(s, h.data())) {
-        UN_HIP(s->sur.ensure(sizeof(float) * h.size()), "device allocation");
-        UN_HIP(hipMemcpyAsync(s->sur.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice,
-                              st),
-               "copy");
-        UN_HIP(hipStreamSynchronize(st), "synchronize");
-        s->sur_state = 1;
-      }
+      h.resize((size_t)NPX * (CIN + 1));
+      if (!scan_table(s, h.data())) h.clear();
+    }
+    if (h.empty()) {
+      s->sur_state = -1;  // the scan itself is outside what the surrogate accepts
+    } else {
+      // a device error leaves the state unset, so a later call retries
+      UN_HIP(s->sur.ensure(sizeof(float) * h.size()), "device allocation");
+      UN_HIP(hipMemcpyAsync(s->sur.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice,
+                            st),
+             "copy");
+      UN_HIP(hipStreamSynchronize(st), "synchronize");
+      s->sur_state = 1;
     }
   }
   ok = s->sur_state == 1;

@@ -10,9 +10,11 @@
 // BN output channels.  For each chunk of 32 input channels it stages the
 // tile's input pixels plus a one-pixel halo (at most 400 pixels) in LDS as
 // BF16, once, and all nine taps then read their A fragments from that tile
-// (the nine-fold reuse of every input value stays on chip).  The chunk's
-// weights (9 taps x BN columns x 32, from [N][9 ci]) are staged in LDS once
-// per block beside it, so the four waves share them.  Input modes: a plain activation, or the decoder's virtual
+// (the nine-fold reuse of every input value stays on chip).  With BN = 64 the
+// chunk's weights (9 taps x BN columns x 32, from [N][9 ci]) are staged in LDS
+// once per block beside it, so the four waves share them; with BN = 32 each
+// wave reads its weight fragments from L2 one tap ahead, which keeps the LDS
+// footprint (and so the occupancy) of the 64^2 layers low.  Input modes: a plain activation, or the decoder's virtual
 // concatenation [nearest-2x-upsampled coarse map, skip map] read directly
 // from its two sources.  Epilogues: plain (the data gradient), bias + SiLU,
 // and bias + SiLU followed by the 32 -> 1 output head reduced across lanes.
@@ -133,8 +135,11 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
 
 template <int IN, int BN, int EPI>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
+  // weights staged in LDS for BN = 64; for BN = 32 (the one-chunk layers at
+  // 64^2, which depend on occupancy) each wave reads them from L2, one tap ahead
+  constexpr bool BLDS = BN >= 64;
   __shared__ __attribute__((aligned(16))) __bf16 As[HPMAX][CLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[9][BN][CLDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BLDS ? 9 : 1][BLDS ? BN : 1][CLDK];
   constexpr int NB = BN / 16;
   constexpr int BPIECES = 9 * BN * 4;  // 16-byte pieces of the chunk's weights
   constexpr int BSLOTS = (BPIECES + 255) / 256;
@@ -180,13 +185,14 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  const __bf16* wlane = p.wt + (int64_t)(n0 + (lane & 15)) * K + 8 * (lane >> 4);
   const int chunks = ci >> 5;
   for (int cc = 0; cc < chunks; ++cc) {
     // stage the chunk's weights (9 taps x BN columns x 32 k) ...
 #pragma unroll
     for (int i = 0; i < BSLOTS; ++i) {
       const int piece = tid + 256 * i;
-      if (piece < BPIECES) {
+      if (BLDS && piece < BPIECES) {
         const int tap = piece / (BN * 4), rem = piece - tap * (BN * 4);
         const int n = rem >> 2, part = rem & 3;
         *reinterpret_cast<bf16x8*>(&Bs[tap][n][part * 8]) = *reinterpret_cast<const bf16x8*>(
@@ -215,10 +221,23 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
         *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
       }
     }
+    bf16x8 bcur[NB];
+    if (!BLDS) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        bcur[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + cc * 32);
+    }
     __syncthreads();
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int toff = (tap / 3) * HW2 + (tap % 3);
+      bf16x8 bnext[NB];
+      if (!BLDS && tap < 8) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          bnext[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + (tap + 1) * ci +
+                                                      cc * 32);
+      }
       bf16x8 af[4];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -226,10 +245,16 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const bf16x8 bf =
-            *reinterpret_cast<const bf16x8*>(&Bs[tap][b * 16 + (lane & 15)][8 * (lane >> 4)]);
+            BLDS ? *reinterpret_cast<const bf16x8*>(
+                       &Bs[BLDS ? tap : 0][BLDS ? b * 16 + (lane & 15) : 0][8 * (lane >> 4)])
+                 : bcur[b];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf, acc[a][b], 0, 0, 0);
+      }
+      if (!BLDS && tap < 8) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) bcur[b] = bnext[b];
       }
     }
     __syncthreads();

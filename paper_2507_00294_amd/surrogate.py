@@ -206,10 +206,31 @@ def main(argv=None):
     ap.add_argument("--report", default="")
     ap.add_argument("--eval-only", action="store_true",
                     help="load --weights and only evaluate on the test maps")
+    ap.add_argument("--forward-bench", type=int, default=0, metavar="N",
+                    help="only time the network's forward pass on N test maps")
     args = ap.parse_args(argv)
     import torch
 
     torch.cuda.set_device(0)
+    if args.forward_bench:
+        net = UNet(args.seed)
+        load_weights(net, args.weights)
+        specs = wl.surrogate_scans(args.forward_bench, seed=6)
+        scans = [Scan(**s.kwargs()) for s in specs]
+        x, _ = surrogate_inputs(scans)
+        for _ in range(2):
+            net.forward(x)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            net.forward(x)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = float(np.median(ts)) * 1e3
+        print(json.dumps({"maps": args.forward_bench, "forward_ms": ms,
+                          "maps_per_s": args.forward_bench / ms * 1e3}), flush=True)
+        return
     if args.eval_only:
         net = UNet(args.seed)
         load_weights(net, args.weights)
