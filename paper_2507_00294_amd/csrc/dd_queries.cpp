@@ -500,9 +500,17 @@ dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStrea
 // ---------------------------------------------------------------------------
 // Batched solve: every scan's arrival and final-map items in one persistent
 // launch, then one fixed-order reduction launch.
+// Scratch of the batched solve, shared by the calls of one host thread.  A
+// call may run on another stream than the previous one (the surrogate runs
+// its exact judge on a second stream): each call records `done` after its
+// last launch and the next call makes its stream wait for it before its
+// uploads overwrite the scratch.  (Reallocation is safe: hipFree waits for
+// the device.)
 struct BatchScratch {
   DevBuf scans, items, near_items, map_items, map_near_items, reds, slots, partial, counter,
       staging;
+  hipEvent_t done = nullptr;  // kept until the process ends
+  bool pending = false;
 };
 static thread_local BatchScratch g_batch;
 
@@ -611,6 +619,8 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       flops += MP.flops;
     }
   }
+  BatchScratch& W = g_batch;
+  if (W.pending) DD_HIP(hipStreamWaitEvent(st, W.done, 0), "stream wait");
   auto longer = [](const BatchItem& a, const BatchItem& b) {
     const int64_t ca = ((int64_t)a.cost_hi << 31) | a.cost_lo;
     const int64_t cb = ((int64_t)b.cost_hi << 31) | b.cost_lo;
@@ -620,7 +630,6 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   std::stable_sort(near_items.begin(), near_items.end(), longer);
   std::stable_sort(map_items.begin(), map_items.end(), longer);
   std::stable_sort(map_near_items.begin(), map_near_items.end(), longer);
-  BatchScratch& W = g_batch;
   DD_HIP(W.partial.ensure(sizeof(double) * (size_t)std::max<int64_t>(partial_total, 1)),
          "device allocation");
   double* part = W.partial.as<double>();
@@ -682,6 +691,9 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   DD_HIP(launch_reduce_batch(W.reds.as<BatchReduce>(), (int32_t)reds.size(), out_total, st),
          "batched reduce launch");
   prof_end(tq, st, 0, 0);
+  if (!W.done) DD_HIP(hipEventCreateWithFlags(&W.done, hipEventDisableTiming), "event creation");
+  DD_HIP(hipEventRecord(W.done, st), "event record");
+  W.pending = true;
   if (!on_device) {
     for (int32_t k = 0; k < n; ++k) {
       const int64_t len = (k + 1 < n ? out_off[k + 1] : out_total) - out_off[k];

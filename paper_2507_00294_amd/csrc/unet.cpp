@@ -46,7 +46,7 @@ constexpr int kPredictChunk = 1024;  // maps per inference forward pass
 struct Conv {
   int H, lg, ci, co, kpad;
   int64_t w_off, b_off, wf_off, wd_off;
-  DevBuf Z, A;  // pre-activation (training only), activation (FP32 NHWC)
+  DevBuf Z, A;  // pre-activation (FP32, training only), activation (BF16 NHWC)
 };
 
 #define UN_HIP(call, what)                           \
@@ -131,17 +131,17 @@ dd_status ensure_capacity(dd_unet& u, int B, bool train) {
     // the last layer's activation is only kept for training
     for (size_t l = 0; l + 1 < nL; ++l) {
       Conv& c = u.L[l];
-      UN_HIP(c.A.ensure(sizeof(float) * (int64_t)B * c.H * c.H * c.co), "device allocation");
+      UN_HIP(c.A.ensure(sizeof(__bf16) * (int64_t)B * c.H * c.H * c.co), "device allocation");
     }
-    UN_HIP(u.p1.ensure(sizeof(float) * M32 * 32), "device allocation");
-    UN_HIP(u.p2.ensure(sizeof(float) * M16 * 64), "device allocation");
-    UN_HIP(u.p3.ensure(sizeof(float) * M8 * 128), "device allocation");
+    UN_HIP(u.p1.ensure(sizeof(__bf16) * M32 * 32), "device allocation");
+    UN_HIP(u.p2.ensure(sizeof(__bf16) * M16 * 64), "device allocation");
+    UN_HIP(u.p3.ensure(sizeof(__bf16) * M8 * 128), "device allocation");
     UN_HIP(u.y.ensure(sizeof(float) * M64), "device allocation");
     u.capB = B;
   }
   if (train && B > u.capB_train) {
     size_t max_mco = 0, max_mci = 0, max_col = 0, max_part = 0;
-    UN_HIP(u.L[nL - 1].A.ensure(sizeof(float) * M64 * u.L[nL - 1].co), "device allocation");
+    UN_HIP(u.L[nL - 1].A.ensure(sizeof(__bf16) * M64 * u.L[nL - 1].co), "device allocation");
     UN_HIP(u.col0.ensure(sizeof(__bf16) * M64 * KPAD0), "device allocation");
     for (Conv& c : u.L) {
       const int64_t M = (int64_t)B * c.H * c.H;
@@ -168,13 +168,14 @@ dd_status ensure_capacity(dd_unet& u, int B, bool train) {
   return DD_OK;
 }
 
-// Input of a convolution: a plain activation, or (coarse != NULL) the
-// decoder's concatenation [nearest-2x upsampling of coarse (c1 channels),
-// x (the skip map)].
+// Input of a convolution: the network input x0 (first layer, FP32), a plain
+// activation x, or (coarse != NULL) the decoder's concatenation
+// [nearest-2x upsampling of coarse (c1 channels), x (the skip map)].
 struct In {
-  const float* x;
-  const float* coarse = nullptr;
+  const __bf16* x = nullptr;
+  const __bf16* coarse = nullptr;
   int c1 = 0;
+  const float* x0 = nullptr;
 };
 
 dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st) {
@@ -183,17 +184,17 @@ dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st) {
   const float* bias = u.w.as<float>() + c.b_off;
   float* z = train ? c.Z.as<float>() : nullptr;
   if (c.ci % 32 != 0) {
-    UN_HIP(nn::conv3_first_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<float>(), z, st), "conv");
+    UN_HIP(nn::conv3_first_silu(in.x0, u.B, c.lg, c.ci, wt, bias, c.A.as<__bf16>(), z, st), "conv");
   } else if (in.coarse) {
     UN_HIP(nn::conv3_upcat_silu(in.coarse, in.c1, in.x, c.ci - in.c1, u.B, c.lg, wt, bias,
-                                c.A.as<float>(), z, c.co, st),
+                                c.A.as<__bf16>(), z, c.co, st),
            "conv");
   } else if (l + 1 == u.L.size()) {
     UN_HIP(nn::conv3_silu_head(in.x, u.B, c.lg, c.ci, wt, bias, u.w.as<float>() + u.head_w,
-                               train ? c.A.as<float>() : nullptr, z, u.y.as<float>(), st),
+                               train ? c.A.as<__bf16>() : nullptr, z, u.y.as<float>(), st),
            "conv");
   } else {
-    UN_HIP(nn::conv3_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<float>(), z, c.co, st), "conv");
+    UN_HIP(nn::conv3_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<__bf16>(), z, c.co, st), "conv");
   }
   return DD_OK;
 }
@@ -210,7 +211,7 @@ dd_status conv_bwd(dd_unet& u, Conv& c, In in, const float* dA, float* dX, hipSt
   const __bf16* col = u.col.as<__bf16>();
   int ld = 9 * c.ci;
   if (c.ci % 32 != 0) {
-    UN_HIP(nn::im2col(in.x, u.B, c.H, c.H, c.ci, KPAD0, u.col0.as<__bf16>(), st), "im2col");
+    UN_HIP(nn::im2col(in.x0, u.B, c.H, c.H, c.ci, KPAD0, u.col0.as<__bf16>(), st), "im2col");
     col = u.col0.as<__bf16>();
     ld = KPAD0;
   } else if (in.coarse) {
@@ -235,14 +236,16 @@ dd_status conv_bwd(dd_unet& u, Conv& c, In in, const float* dA, float* dX, hipSt
 
 // The input of every layer, in forward order.
 std::vector<In> layer_inputs(dd_unet& u, const float* x) {
-  auto A = [&](int l) { return (const float*)u.L[l].A.as<float>(); };
-  return {In{x},
+  auto A = [&](int l) { return (const __bf16*)u.L[l].A.as<__bf16>(); };
+  In first;
+  first.x0 = x;
+  return {first,
           In{A(0)},
-          In{u.p1.as<float>()},
+          In{u.p1.as<__bf16>()},
           In{A(2)},
-          In{u.p2.as<float>()},
+          In{u.p2.as<__bf16>()},
           In{A(4)},
-          In{u.p3.as<float>()},
+          In{u.p3.as<__bf16>()},
           In{A(6)},
           In{A(5), A(7), 256},  // [up(8^2 x 256), skip 16^2 x 128]
           In{A(8)},
@@ -263,13 +266,13 @@ dd_status forward(dd_unet& u, const float* x, bool train, hipStream_t st) {
   const std::vector<In> in = layer_inputs(u, x);
   STEP(conv_fwd(u, 0, in[0], train, st));
   STEP(conv_fwd(u, 1, in[1], train, st));
-  UN_HIP(nn::pool_fwd(L[1].A.as<float>(), B, 64, 64, 32, u.p1.as<float>(), st), "pool");
+  UN_HIP(nn::pool_fwd(L[1].A.as<__bf16>(), B, 64, 64, 32, u.p1.as<__bf16>(), st), "pool");
   STEP(conv_fwd(u, 2, in[2], train, st));
   STEP(conv_fwd(u, 3, in[3], train, st));
-  UN_HIP(nn::pool_fwd(L[3].A.as<float>(), B, 32, 32, 64, u.p2.as<float>(), st), "pool");
+  UN_HIP(nn::pool_fwd(L[3].A.as<__bf16>(), B, 32, 32, 64, u.p2.as<__bf16>(), st), "pool");
   STEP(conv_fwd(u, 4, in[4], train, st));
   STEP(conv_fwd(u, 5, in[5], train, st));
-  UN_HIP(nn::pool_fwd(L[5].A.as<float>(), B, 16, 16, 128, u.p3.as<float>(), st), "pool");
+  UN_HIP(nn::pool_fwd(L[5].A.as<__bf16>(), B, 16, 16, 128, u.p3.as<__bf16>(), st), "pool");
   for (size_t l = 6; l < L.size(); ++l) STEP(conv_fwd(u, l, in[l], train, st));
   return DD_OK;
 }
@@ -285,7 +288,7 @@ dd_status backward(dd_unet& u, const float* x, const float* dy, hipStream_t st) 
   UN_HIP(nn::fill(u.ds1.as<float>(), M64 * 32, 0.f, st), "fill");
   UN_HIP(nn::fill(u.ds2.as<float>(), M32 * 64, 0.f, st), "fill");
   UN_HIP(nn::fill(u.ds3.as<float>(), M16 * 128, 0.f, st), "fill");
-  UN_HIP(nn::head_bwd(dy, L[13].A.as<float>(), M64, 32, u.w.as<float>() + u.head_w, a0,
+  UN_HIP(nn::head_bwd(dy, L[13].A.as<__bf16>(), M64, 32, u.w.as<float>() + u.head_w, a0,
                       u.g.as<float>() + u.head_w, st),
          "head backward");
   STEP(conv_bwd(u, L[13], in[13], a0, a1, st));

@@ -18,6 +18,8 @@
 // concatenation [nearest-2x-upsampled coarse map, skip map] read directly
 // from its two sources.  Epilogues: plain (the data gradient), bias + SiLU,
 // and bias + SiLU followed by the 32 -> 1 output head reduced across lanes.
+// Activations are stored in BF16 (the MFMA operand precision; every consumer
+// rounds its input to BF16 anyway); pre-activations and gradients are FP32.
 //
 // k_conv_first (the 5-channel input layer): K = 45 padded to 64; each thread
 // gathers its pixel's row into registers and stores it to LDS (two K steps).
@@ -47,7 +49,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int CBM = 256;    // output pixels per block
 constexpr int CLDK = 40;    // LDS row: 32 channels + 8 padding (BF16)
 constexpr int HPMAX = 400;  // halo-tile pixels: 6 x 66, 10 x 34, 18 x 18 or 4 x 10 x 10
-constexpr int SLOTS = (HPMAX * 8 + 255) / 256;  // 16-byte staging slots per thread
 
 enum { IN_PLAIN = 0, IN_UPCAT = 1 };
 enum { EPI_PLAIN = 0, EPI_SILU = 1, EPI_HEAD = 2 };
@@ -58,14 +59,17 @@ __device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
   return bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
 }
 
+// Activations (inputs of IN_PLAIN / IN_UPCAT with TIn = __bf16, outputs of
+// EPI_SILU / EPI_HEAD) are BF16; the data gradient reads and writes FP32.
 struct ConvArgs {
-  const float* x;    // IN_PLAIN: input [M][ci]; IN_UPCAT: skip map [M][ci - c1]
-  const float* xc;   // IN_UPCAT: coarse map [M / 4][c1]
+  const void* x;     // IN_PLAIN: input [M][ci]; IN_UPCAT: skip map [M][ci - c1]
+  const void* xc;    // IN_UPCAT: coarse map [M / 4][c1]
   int c1;            // IN_UPCAT: channels taken from the coarse map
   int M, lg, ci;     // output pixels, log2 side, input channels
   const __bf16* wt;  // [N][9 ci]
   const float* bias;
-  float* out;        // [M][N]; may be NULL with EPI_HEAD
+  void* out;         // [M][N]: BF16 activation (EPI_SILU, EPI_HEAD; may be NULL
+                     // with EPI_HEAD) or FP32 (EPI_PLAIN)
   float* z;          // pre-activation [M][N] or NULL
   const float* hw;   // EPI_HEAD: 32 weights, then the bias
   float* y;          // EPI_HEAD: [M]
@@ -93,8 +97,9 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
         if (row < p.M) {
           const int64_t o = (int64_t)row * 32 + c0;
           if (p.out) {
-            p.out[o] = a0;
-            p.out[o + 16] = a1;
+            __bf16* act = static_cast<__bf16*>(p.out);
+            act[o] = (__bf16)a0;
+            act[o + 16] = (__bf16)a1;
           }
           if (p.z) {
             p.z[o] = z0;
@@ -124,16 +129,16 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
           if (EPI == EPI_SILU) {
             const float zz = acc[a][b][v] + bs;
             if (p.z) p.z[o] = zz;
-            p.out[o] = silu(zz);
+            static_cast<__bf16*>(p.out)[o] = (__bf16)silu(zz);
           } else {
-            p.out[o] = acc[a][b][v];
+            static_cast<float*>(p.out)[o] = acc[a][b][v];
           }
         }
       }
     }
 }
 
-template <int IN, int BN, int EPI>
+template <typename TIn, int IN, int BN, int EPI>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   // weights staged in LDS for BN = 64; for BN = 32 (the one-chunk layers at
   // 64^2, which depend on occupancy) each wave reads them from L2, one tap ahead
@@ -152,12 +157,17 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   const int HW2 = W + 2, slice = (R + 2) * HW2;
   const int G = CBM >> lgRW, HP = G * slice;
   const int img0 = m0 >> (2 * lg), y0 = (m0 >> lg) & (W - 1);
+  // staging: 16-byte slots of CPQ channels, QPP slots per pixel and chunk
+  constexpr int CPQ = 16 / (int)sizeof(TIn), LGQ = CPQ == 8 ? 2 : 3, QPP = 1 << LGQ;
+  constexpr int NSLOT = (HPMAX * QPP + 255) / 256;
+  const TIn* xin = static_cast<const TIn*>(p.x);
+  const TIn* xco = static_cast<const TIn*>(p.xc);
 
   // source pixel of every staging slot (fixed over the channel chunks)
-  int src[SLOTS];
+  int src[NSLOT];
 #pragma unroll
-  for (int i = 0; i < SLOTS; ++i) {
-    const int idx = tid + 256 * i, px = idx >> 3;
+  for (int i = 0; i < NSLOT; ++i) {
+    const int idx = tid + 256 * i, px = idx >> LGQ;
     int s = -1;
     if (px < HP) {
       const int g = px / slice, rem = px - g * slice;
@@ -201,24 +211,31 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
     }
     // ... and the halo tile of channels 32 cc .. 32 cc + 31
 #pragma unroll
-    for (int i = 0; i < SLOTS; ++i) {
-      const int idx = tid + 256 * i, px = idx >> 3, q = idx & 7;
+    for (int i = 0; i < NSLOT; ++i) {
+      const int idx = tid + 256 * i, px = idx >> LGQ, q = idx & (QPP - 1);
       if (px < HP) {
-        f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
         const int s = src[i];
+        const TIn* from = nullptr;
         if (s >= 0) {
           if (IN == IN_UPCAT && cc * 32 < p.c1) {
             const int im = s >> (2 * lg), yy = (s >> lg) & (W - 1), xx = s & (W - 1);
             const int sc = (((im << (lg - 1)) + (yy >> 1)) << (lg - 1)) + (xx >> 1);
-            v = *reinterpret_cast<const f32x4*>(p.xc + (int64_t)sc * p.c1 + cc * 32 + 4 * q);
+            from = xco + (int64_t)sc * p.c1 + cc * 32 + CPQ * q;
           } else if (IN == IN_UPCAT) {
-            const int c2 = ci - p.c1;
-            v = *reinterpret_cast<const f32x4*>(p.x + (int64_t)s * c2 + (cc * 32 - p.c1) + 4 * q);
+            from = xin + (int64_t)s * (ci - p.c1) + (cc * 32 - p.c1) + CPQ * q;
           } else {
-            v = *reinterpret_cast<const f32x4*>(p.x + (int64_t)s * ci + cc * 32 + 4 * q);
+            from = xin + (int64_t)s * ci + cc * 32 + CPQ * q;
           }
         }
-        *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
+        if constexpr (CPQ == 8) {
+          bf16x8 v = bf16x8{};
+          if (from) v = *reinterpret_cast<const bf16x8*>(from);
+          *reinterpret_cast<bf16x8*>(&As[px][8 * q]) = v;
+        } else {
+          f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (from) v = *reinterpret_cast<const f32x4*>(from);
+          *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
+        }
       }
     }
     bf16x8 bcur[NB];
@@ -282,7 +299,7 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
       const bool ok = m < p.M && yy + dy >= 0 && yy + dy < W && xx + dx >= 0 && xx + dx < W;
-      const float* src = p.x + (int64_t)(ok ? m + dy * W + dx : 0) * CI;
+      const float* src = static_cast<const float*>(p.x) + (int64_t)(ok ? m + dy * W + dx : 0) * CI;
 #pragma unroll
       for (int c = 0; c < CI; ++c) v[tap * CI + c] = ok ? src[c] : 0.f;
     }
@@ -327,14 +344,14 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
   epilogue<2, EPI>(p, acc, m0, 0, wave, lane);
 }
 
-template <int IN, int EPI>
+template <typename TIn, int IN, int EPI>
 hipError_t launch_halo(const ConvArgs& p, hipStream_t st) {
   const int bn = (EPI == EPI_HEAD) ? 32 : (p.N % 64 == 0) ? 64 : 32;
   dim3 grid((p.M + CBM - 1) / CBM, p.N / bn);
   if (bn == 64)
-    hipLaunchKernelGGL((k_conv_halo<IN, 64, EPI>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_conv_halo<TIn, IN, 64, EPI>), grid, dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL((k_conv_halo<IN, 32, EPI>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_conv_halo<TIn, IN, 32, EPI>), grid, dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
@@ -344,38 +361,38 @@ bool halo_ok(int M, int lg, int ci, int N) {
 
 }  // namespace
 
-hipError_t conv3_silu(const float* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
-                      float* act, float* z, int co, hipStream_t st) {
+hipError_t conv3_silu(const __bf16* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
+                      __bf16* act, float* z, int co, hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, co};
   if (!halo_ok(p.M, lg, ci, co) || !act) return hipErrorInvalidValue;
-  return launch_halo<IN_PLAIN, EPI_SILU>(p, st);
+  return launch_halo<__bf16, IN_PLAIN, EPI_SILU>(p, st);
 }
 
-hipError_t conv3_upcat_silu(const float* coarse, int c1, const float* skip, int c2, int B, int lg,
-                            const __bf16* wt, const float* bias, float* act, float* z, int co,
-                            hipStream_t st) {
+hipError_t conv3_upcat_silu(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B,
+                            int lg, const __bf16* wt, const float* bias, __bf16* act, float* z,
+                            int co, hipStream_t st) {
   ConvArgs p{skip, coarse, c1, B << (2 * lg), lg, c1 + c2, wt, bias, act, z, nullptr, nullptr, co};
   if (!halo_ok(p.M, lg, p.ci, co) || c1 % 32 != 0 || lg < 4 || !act) return hipErrorInvalidValue;
-  return launch_halo<IN_UPCAT, EPI_SILU>(p, st);
+  return launch_halo<__bf16, IN_UPCAT, EPI_SILU>(p, st);
 }
 
-hipError_t conv3_silu_head(const float* x, int B, int lg, int ci, const __bf16* wt,
-                           const float* bias, const float* head, float* act, float* z, float* y,
+hipError_t conv3_silu_head(const __bf16* x, int B, int lg, int ci, const __bf16* wt,
+                           const float* bias, const float* head, __bf16* act, float* z, float* y,
                            hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, head, y, 32};
   if (!halo_ok(p.M, lg, ci, 32) || !y || !head) return hipErrorInvalidValue;
-  return launch_halo<IN_PLAIN, EPI_HEAD>(p, st);
+  return launch_halo<__bf16, IN_PLAIN, EPI_HEAD>(p, st);
 }
 
 hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, float* out, int co,
                        hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, nullptr, out, nullptr, nullptr, nullptr, co};
   if (!halo_ok(p.M, lg, ci, co) || !out) return hipErrorInvalidValue;
-  return launch_halo<IN_PLAIN, EPI_PLAIN>(p, st);
+  return launch_halo<float, IN_PLAIN, EPI_PLAIN>(p, st);
 }
 
 hipError_t conv3_first_silu(const float* x, int B, int lg, int ci, const __bf16* wt,
-                            const float* bias, float* act, float* z, hipStream_t st) {
+                            const float* bias, __bf16* act, float* z, hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, 32};
   if (p.M <= 0 || lg < 3 || lg > 6 || !act) return hipErrorInvalidValue;
   const dim3 grid((p.M + CBM - 1) / CBM);

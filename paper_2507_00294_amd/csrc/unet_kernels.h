@@ -31,18 +31,18 @@ constexpr int kNormBlocks = 256;  // partial sums of the gradient norm
 //   conv3_plain:       out = conv (the data gradient, with the dgrad layout);
 //   conv3_first_silu:  ci < 32 with 9 ci <= 64, co = 32, weights [32][64].
 // ci, c1 and co must be multiples of 32 except in conv3_first_silu.
-hipError_t conv3_silu(const float* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
-                      float* act, float* z, int co, hipStream_t st);
-hipError_t conv3_upcat_silu(const float* coarse, int c1, const float* skip, int c2, int B, int lg,
-                            const __bf16* wt, const float* bias, float* act, float* z, int co,
-                            hipStream_t st);
-hipError_t conv3_silu_head(const float* x, int B, int lg, int ci, const __bf16* wt,
-                           const float* bias, const float* head, float* act, float* z, float* y,
+hipError_t conv3_silu(const __bf16* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
+                      __bf16* act, float* z, int co, hipStream_t st);
+hipError_t conv3_upcat_silu(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B,
+                            int lg, const __bf16* wt, const float* bias, __bf16* act, float* z,
+                            int co, hipStream_t st);
+hipError_t conv3_silu_head(const __bf16* x, int B, int lg, int ci, const __bf16* wt,
+                           const float* bias, const float* head, __bf16* act, float* z, float* y,
                            hipStream_t st);
 hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, float* out, int co,
                        hipStream_t st);
 hipError_t conv3_first_silu(const float* x, int B, int lg, int ci, const __bf16* wt,
-                            const float* bias, float* act, float* z, hipStream_t st);
+                            const float* bias, __bf16* act, float* z, hipStream_t st);
 
 // C = A B on BF16 MFMA (FP32 accumulation); ta/tb select transposed storage;
 // with ksplit > 1 the partial matrices (gemm_splits() of them) are written at
@@ -52,17 +52,19 @@ hipError_t gemm(const __bf16* A, int lda, bool ta, const __bf16* B, int ldb, boo
 int gemm_splits(int M, int K, int ksplit);
 hipError_t sum_splits(const float* part, int splits, int64_t n, float* out, hipStream_t st);
 hipError_t im2col(const float* x, int B, int H, int W, int C, int ld, __bf16* col, hipStream_t st);
+hipError_t im2col(const __bf16* x, int B, int H, int W, int C, int ld, __bf16* col,
+                  hipStream_t st);
 // im2col of the virtual concatenation [upsampled coarse (c1), skip (c2)].
-hipError_t im2col_upcat(const float* coarse, int c1, const float* skip, int c2, int B, int H,
+hipError_t im2col_upcat(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B, int H,
                         __bf16* col, hipStream_t st);
 hipError_t silu_bwd(const float* dA, const float* Z, int64_t n, float* dZ, __bf16* dZb,
                     hipStream_t st);
 hipError_t colsum_add(const float* dZ, int M, int N, float* db, hipStream_t st);
-hipError_t pool_fwd(const float* x, int B, int H, int W, int C, float* y, hipStream_t st);
+hipError_t pool_fwd(const __bf16* x, int B, int H, int W, int C, __bf16* y, hipStream_t st);
 hipError_t pool_bwd_add(const float* dy, int B, int H, int W, int C, float* dx, hipStream_t st);
 hipError_t up_concat_bwd(const float* dout, int B, int h, int w, int C1, int C2, float* dx,
                          float* dskip, hipStream_t st);
-hipError_t head_bwd(const float* dy, const float* a, int64_t M, int C, const float* w, float* da,
+hipError_t head_bwd(const float* dy, const __bf16* a, int64_t M, int C, const float* w, float* da,
                     float* dw, hipStream_t st);
 // Squared relative L2 error per map (loss_map[b]) of prediction own + exp(y)
 // against t; dy of the mean over maps of that error plus the anchor term

@@ -134,7 +134,8 @@ __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ pa
 // im2col for a 3x3 convolution with zero padding 1 (NHWC, FP32 -> BF16), rows
 // of ld >= 9 C columns (columns past 9 C are zero):
 // col[m][(ky*3+kx)*C + c] = x[n][y+ky-1][x+kx-1][c], m = (n*H + y)*W + x.
-__global__ void __launch_bounds__(256) k_im2col(const float* __restrict__ x, int B, int H, int W,
+template <typename T>
+__global__ void __launch_bounds__(256) k_im2col(const T* __restrict__ x, int B, int H, int W,
                                                 int C, int ld, __bf16* __restrict__ col) {
   const int64_t K = 9 * (int64_t)C, total = (int64_t)B * H * W * ld;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -147,7 +148,8 @@ __global__ void __launch_bounds__(256) k_im2col(const float* __restrict__ x, int
       const int ky = tap / 3, kx = tap % 3;
       const int xx = (int)(m % W), yy = (int)((m / W) % H), n = (int)(m / ((int64_t)W * H));
       const int sy = yy + ky - 1, sx = xx + kx - 1;
-      if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = x[(((int64_t)n * H + sy) * W + sx) * C + c];
+      if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+        v = (float)x[(((int64_t)n * H + sy) * W + sx) * C + c];
     }
     col[e] = (__bf16)v;
   }
@@ -156,8 +158,8 @@ __global__ void __launch_bounds__(256) k_im2col(const float* __restrict__ x, int
 // im2col of the decoder input: channel c < c1 of pixel (n, y, x) is channel c
 // of the coarse map at (n, y/2, x/2), channel c1 + c' is channel c' of skip;
 // rows of 9 (c1 + c2) columns.
-__global__ void __launch_bounds__(256) k_im2col_upcat(const float* __restrict__ coarse, int c1,
-                                                      const float* __restrict__ skip, int c2,
+__global__ void __launch_bounds__(256) k_im2col_upcat(const __bf16* __restrict__ coarse, int c1,
+                                                      const __bf16* __restrict__ skip, int c2,
                                                       int B, int H, __bf16* __restrict__ col) {
   const int C = c1 + c2, h = H / 2;
   const int64_t K = 9 * (int64_t)C, total = (int64_t)B * H * H * K;
@@ -169,11 +171,11 @@ __global__ void __launch_bounds__(256) k_im2col_upcat(const float* __restrict__ 
     const int ky = tap / 3, kx = tap % 3;
     const int xx = (int)(m % H), yy = (int)((m / H) % H), n = (int)(m / ((int64_t)H * H));
     const int sy = yy + ky - 1, sx = xx + kx - 1;
-    float v = 0.f;
+    __bf16 v = (__bf16)0.f;
     if (sy >= 0 && sy < H && sx >= 0 && sx < H)
       v = c < c1 ? coarse[(((int64_t)n * h + sy / 2) * h + sx / 2) * c1 + c]
                  : skip[(((int64_t)n * H + sy) * H + sx) * c2 + (c - c1)];
-    col[e] = (__bf16)v;
+    col[e] = v;
   }
 }
 
@@ -206,9 +208,10 @@ __global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dZ, in
   if (threadIdx.x == 0) db[j] = red[0];
 }
 
-// 2x2 average pooling (NHWC) and its adjoint (which accumulates).
-__global__ void __launch_bounds__(256) k_pool_fwd(const float* __restrict__ x, int B, int H, int W,
-                                                  int C, float* __restrict__ y) {
+// 2x2 average pooling (NHWC, BF16 activations, summed in FP32) and its
+// adjoint on FP32 gradients (which accumulates).
+__global__ void __launch_bounds__(256) k_pool_fwd(const __bf16* __restrict__ x, int B, int H, int W,
+                                                  int C, __bf16* __restrict__ y) {
   const int Ho = H / 2, Wo = W / 2;
   const int64_t total = (int64_t)B * Ho * Wo * C;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -217,7 +220,8 @@ __global__ void __launch_bounds__(256) k_pool_fwd(const float* __restrict__ x, i
     const int64_t p = e / C;
     const int xo = (int)(p % Wo), yo = (int)((p / Wo) % Ho), n = (int)(p / ((int64_t)Wo * Ho));
     const int64_t base = (((int64_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
-    y[e] = 0.25f * (x[base] + x[base + C] + x[base + (int64_t)W * C] + x[base + (int64_t)W * C + C]);
+    y[e] = (__bf16)(0.25f * ((float)x[base] + (float)x[base + C] + (float)x[base + (int64_t)W * C] +
+                             (float)x[base + (int64_t)W * C + C]));
   }
 }
 
@@ -272,12 +276,12 @@ __global__ void __launch_bounds__(256) k_head_bwd_data(const float* __restrict__
 // Head weight gradient: dw[c] = sum_m dy[m] a[m][c] (c < C), db = sum_m dy[m]
 // (slot C); one block per output, fixed order.
 __global__ void __launch_bounds__(256) k_head_bwd_w(const float* __restrict__ dy,
-                                                    const float* __restrict__ a, int64_t M, int C,
+                                                    const __bf16* __restrict__ a, int64_t M, int C,
                                                     float* __restrict__ dw) {
   __shared__ float red[256];
   const int c = blockIdx.x;
   float s = 0.f;
-  for (int64_t m = threadIdx.x; m < M; m += 256) s += dy[m] * (c < C ? a[m * C + c] : 1.0f);
+  for (int64_t m = threadIdx.x; m < M; m += 256) s += dy[m] * (c < C ? (float)a[m * C + c] : 1.0f);
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -578,12 +582,20 @@ hipError_t sum_splits(const float* part, int splits, int64_t n, float* out, hipS
 
 hipError_t im2col(const float* x, int B, int H, int W, int C, int ld, __bf16* col, hipStream_t st) {
   if (ld < 9 * C) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_im2col, dim3(blocks_for((int64_t)B * H * W * ld)), dim3(256), 0, st, x, B,
-                     H, W, C, ld, col);
+  hipLaunchKernelGGL(k_im2col<float>, dim3(blocks_for((int64_t)B * H * W * ld)), dim3(256), 0, st,
+                     x, B, H, W, C, ld, col);
   return hipGetLastError();
 }
 
-hipError_t im2col_upcat(const float* coarse, int c1, const float* skip, int c2, int B, int H,
+hipError_t im2col(const __bf16* x, int B, int H, int W, int C, int ld, __bf16* col,
+                  hipStream_t st) {
+  if (ld < 9 * C) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_im2col<__bf16>, dim3(blocks_for((int64_t)B * H * W * ld)), dim3(256), 0, st,
+                     x, B, H, W, C, ld, col);
+  return hipGetLastError();
+}
+
+hipError_t im2col_upcat(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B, int H,
                         __bf16* col, hipStream_t st) {
   hipLaunchKernelGGL(k_im2col_upcat, dim3(blocks_for((int64_t)B * H * H * 9 * (c1 + c2))), dim3(256),
                      0, st, coarse, c1, skip, c2, B, H, col);
@@ -601,7 +613,7 @@ hipError_t colsum_add(const float* dZ, int M, int N, float* db, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t pool_fwd(const float* x, int B, int H, int W, int C, float* y, hipStream_t st) {
+hipError_t pool_fwd(const __bf16* x, int B, int H, int W, int C, __bf16* y, hipStream_t st) {
   hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((int64_t)B * H * W * C / 4)), dim3(256), 0, st, x,
                      B, H, W, C, y);
   return hipGetLastError();
@@ -621,7 +633,7 @@ hipError_t up_concat_bwd(const float* dout, int B, int h, int w, int C1, int C2,
   return hipGetLastError();
 }
 
-hipError_t head_bwd(const float* dy, const float* a, int64_t M, int C, const float* w, float* da,
+hipError_t head_bwd(const float* dy, const __bf16* a, int64_t M, int C, const float* w, float* da,
                     float* dw, hipStream_t st) {
   hipLaunchKernelGGL(k_head_bwd_data, dim3(blocks_for(M * C)), dim3(256), 0, st, dy, M, C, w, da);
   hipLaunchKernelGGL(k_head_bwd_w, dim3(C + 1), dim3(256), 0, st, dy, a, M, C, dw);

@@ -180,3 +180,24 @@ def test_predict_fallback_is_exact(dd):
     psi3, fb3 = net.predict(scans, spot_tol=1e300, precision="mixed")
     assert fb3.tolist() == [0, 0, 0, 0]
     assert np.all(np.isfinite(psi3.cpu().numpy()))
+
+
+def test_predict_right_after_batched_solve(dd):
+    """predict runs its exact judge on a second stream: a batched solve still
+    queued on the caller's stream when predict starts keeps its results, and
+    so does the judge (the batched solve's scratch is ordered across streams)."""
+    import torch
+
+    from paper_2507_00294_amd import workloads as wl
+
+    scans = [dd.Scan(**s.kwargs()) for s in wl.surrogate_scans(48, seed=14)]
+    ref = [o.clone() for o in dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, "mixed")]
+    torch.cuda.synchronize()
+    net = dd.UNet(seed=0)
+    outs = dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, "mixed")  # not synchronized
+    psi, fb = net.predict(scans, spot_tol=0.0, precision="mixed")  # every map falls back
+    torch.cuda.synchronize()
+    assert fb.tolist() == [1] * len(scans)
+    for k, r in enumerate(ref):
+        assert torch.equal(outs[k], r)
+        assert torch.equal(psi[k].flatten(), r)
