@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "unet_kernels.h"
 
@@ -197,47 +198,70 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
 
   const __bf16* wlane = p.wt + (int64_t)(n0 + (lane & 15)) * K + 8 * (lane >> 4);
   const int chunks = ci >> 5;
-  for (int cc = 0; cc < chunks; ++cc) {
-    // stage the chunk's weights (9 taps x BN columns x 32 k) ...
+  // Staging registers of one chunk: the weights (BN = 64) and the halo tile.
+  // With BF16 activations and BN = 64 the next chunk's loads are issued before the
+  // current chunk's MFMAs and stored to LDS after them (register prefetch);
+  // the FP32 input of the data gradient is loaded and stored in one step.
+  constexpr bool PIPE = CPQ == 8 && BLDS;
+  using AReg = typename std::conditional<CPQ == 8, bf16x8, f32x4>::type;
+  AReg ar[NSLOT];
+  bf16x8 br[BLDS ? BSLOTS : 1];
+  auto fetch = [&](int cc) {
 #pragma unroll
     for (int i = 0; i < BSLOTS; ++i) {
       const int piece = tid + 256 * i;
       if (BLDS && piece < BPIECES) {
         const int tap = piece / (BN * 4), rem = piece - tap * (BN * 4);
         const int n = rem >> 2, part = rem & 3;
-        *reinterpret_cast<bf16x8*>(&Bs[tap][n][part * 8]) = *reinterpret_cast<const bf16x8*>(
-            p.wt + (int64_t)(n0 + n) * K + tap * ci + cc * 32 + part * 8);
+        br[BLDS ? i : 0] = *reinterpret_cast<const bf16x8*>(p.wt + (int64_t)(n0 + n) * K +
+                                                            tap * ci + cc * 32 + part * 8);
       }
     }
-    // ... and the halo tile of channels 32 cc .. 32 cc + 31
+#pragma unroll
+    for (int i = 0; i < NSLOT; ++i) {
+      const int idx = tid + 256 * i, px = idx >> LGQ, q = idx & (QPP - 1);
+      ar[i] = AReg{};
+      const int s = src[i];
+      if (px < HP && s >= 0) {
+        const TIn* from;
+        if (IN == IN_UPCAT && cc * 32 < p.c1) {
+          const int im = s >> (2 * lg), yy = (s >> lg) & (W - 1), xx = s & (W - 1);
+          const int sc = (((im << (lg - 1)) + (yy >> 1)) << (lg - 1)) + (xx >> 1);
+          from = xco + (int64_t)sc * p.c1 + cc * 32 + CPQ * q;
+        } else if (IN == IN_UPCAT) {
+          from = xin + (int64_t)s * (ci - p.c1) + (cc * 32 - p.c1) + CPQ * q;
+        } else {
+          from = xin + (int64_t)s * ci + cc * 32 + CPQ * q;
+        }
+        ar[i] = *reinterpret_cast<const AReg*>(from);
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < BSLOTS; ++i) {
+      const int piece = tid + 256 * i;
+      if (BLDS && piece < BPIECES) {
+        const int tap = piece / (BN * 4), rem = piece - tap * (BN * 4);
+        *reinterpret_cast<bf16x8*>(&Bs[BLDS ? tap : 0][BLDS ? rem >> 2 : 0][(rem & 3) * 8]) =
+            br[BLDS ? i : 0];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < NSLOT; ++i) {
       const int idx = tid + 256 * i, px = idx >> LGQ, q = idx & (QPP - 1);
       if (px < HP) {
-        const int s = src[i];
-        const TIn* from = nullptr;
-        if (s >= 0) {
-          if (IN == IN_UPCAT && cc * 32 < p.c1) {
-            const int im = s >> (2 * lg), yy = (s >> lg) & (W - 1), xx = s & (W - 1);
-            const int sc = (((im << (lg - 1)) + (yy >> 1)) << (lg - 1)) + (xx >> 1);
-            from = xco + (int64_t)sc * p.c1 + cc * 32 + CPQ * q;
-          } else if (IN == IN_UPCAT) {
-            from = xin + (int64_t)s * (ci - p.c1) + (cc * 32 - p.c1) + CPQ * q;
-          } else {
-            from = xin + (int64_t)s * ci + cc * 32 + CPQ * q;
-          }
-        }
-        if constexpr (CPQ == 8) {
-          bf16x8 v = bf16x8{};
-          if (from) v = *reinterpret_cast<const bf16x8*>(from);
-          *reinterpret_cast<bf16x8*>(&As[px][8 * q]) = v;
-        } else {
-          f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (from) v = *reinterpret_cast<const f32x4*>(from);
-          *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(v);
-        }
+        if constexpr (CPQ == 8)
+          *reinterpret_cast<bf16x8*>(&As[px][8 * q]) = ar[i];
+        else
+          *reinterpret_cast<bf16x4*>(&As[px][4 * q]) = to_bf16x4(ar[i]);
       }
     }
+  };
+  if (PIPE) fetch(0);
+  for (int cc = 0; cc < chunks; ++cc) {
+    if (!PIPE) fetch(cc);
+    store();
     bf16x8 bcur[NB];
     if (!BLDS) {
 #pragma unroll
@@ -245,6 +269,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
         bcur[b] = *reinterpret_cast<const bf16x8*>(wlane + (int64_t)b * 16 * K + cc * 32);
     }
     __syncthreads();
+    if (PIPE && cc + 1 < chunks) fetch(cc + 1);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int toff = (tap / 3) * HW2 + (tap % 3);
