@@ -21,8 +21,9 @@
 // Activations are stored in BF16 (the MFMA operand precision; every consumer
 // rounds its input to BF16 anyway); pre-activations and gradients are FP32.
 //
-// k_conv_first (the 5-channel input layer): K = 45 padded to 64; each thread
-// gathers its pixel's row into registers and stores it to LDS (two K steps).
+// k_conv_first (the 5-channel input layer): K = 45 padded to 64; the input
+// halo tile is staged in LDS (FP32), each thread assembles its pixel's row of
+// A from it (two K steps).
 //
 // Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l): A row l % 16,
 // k = 8 (l / 16) .. +7; B column l % 16, same k; D element v at row
@@ -305,28 +306,47 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
 }
 
 // First layer: CI (< 32) input channels, K = 9 CI <= 64 padded to 64; N = 32.
-// Each thread gathers its pixel's 9 CI values into registers (indices fixed at
-// compile time) and writes its LDS row with 16-byte stores.
+// The tile's input pixels plus a one-pixel halo (the geometry of
+// k_conv_halo) are staged in LDS as FP32 with coalesced loads; each thread
+// then assembles its pixel's 9 CI values (indices fixed at compile time) and
+// writes its BF16 row of A with 16-byte stores.
 template <int CI, int EPI>
 __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
   static_assert(9 * CI <= 64, "first layer: 9 CI must fit in 64 columns");
+  __shared__ float Xs[HPMAX][CI];
   __shared__ __attribute__((aligned(16))) __bf16 As[CBM][72];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[32][72];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * CBM;
   const int lg = p.lg, W = 1 << lg;
-  // A: pixel m0 + tid, k = tap CI + c
+  const int lgR = lg >= 4 ? 8 - lg : lg, R = 1 << lgR, lgRW = lgR + lg;
+  const int HW2 = W + 2, slice = (R + 2) * HW2, HP = (CBM >> lgRW) * slice;
+  const int img0 = m0 >> (2 * lg), y0 = (m0 >> lg) & (W - 1);
+  const float* x = static_cast<const float*>(p.x);
+  // halo tile, one pixel per thread and pass
+  for (int px = tid; px < HP; px += 256) {
+    const int g = px / slice, rem = px - g * slice;
+    const int hr = rem / HW2, hc = rem - hr * HW2;
+    const int yy = y0 + hr - 1, xx = hc - 1;
+    int m = -1;
+    if (yy >= 0 && yy < W && xx >= 0 && xx < W) {
+      m = (((img0 + g) << lg) + yy) * W + xx;
+      if (m >= p.M) m = -1;
+    }
+#pragma unroll
+    for (int c = 0; c < CI; ++c) Xs[px][c] = m >= 0 ? x[(int64_t)m * CI + c] : 0.f;
+  }
+  __syncthreads();
+  // A: pixel o = tid of the tile, k = tap CI + c
   {
-    const int m = m0 + tid;
-    const int yy = (m >> lg) & (W - 1), xx = m & (W - 1);
+    const int o = tid;
+    const int hb = (o >> lgRW) * slice + ((o >> lg) & (R - 1)) * HW2 + (o & (W - 1));
     float v[64];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const bool ok = m < p.M && yy + dy >= 0 && yy + dy < W && xx + dx >= 0 && xx + dx < W;
-      const float* src = static_cast<const float*>(p.x) + (int64_t)(ok ? m + dy * W + dx : 0) * CI;
+      const int h = hb + (tap / 3) * HW2 + (tap % 3);
 #pragma unroll
-      for (int c = 0; c < CI; ++c) v[tap * CI + c] = ok ? src[c] : 0.f;
+      for (int c = 0; c < CI; ++c) v[tap * CI + c] = Xs[h][c];
     }
 #pragma unroll
     for (int k = 9 * CI; k < 64; ++k) v[k] = 0.f;
