@@ -33,6 +33,8 @@ METRIC = "pair E1-terms/s at oracle-matched accuracy; surrogate speedup @≤1% L
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_arrival_far32_traffic.txt")
 DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip")
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X FP32 / FP64 vector peaks
+FP32_NONPACKED_TFLOPS = 78.6  # FP32 vector peak without packed instructions
+VALU_ISSUE_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: one VALU op per lane per clock
 
 
 def log(*a):
@@ -49,9 +51,10 @@ def device_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(precision, side):
-    """Bytes per launch from the committed counter record, or None when the
-    kernel sources changed since the counters were taken."""
+def counter_record(precision, side):
+    """The committed counter record of the dominant kernel (HBM bytes and VALU
+    lane-instructions per pair), or None when the kernel sources changed since
+    the counters were taken or the workload is not the recorded one."""
     if precision != "mixed" or side != 512 or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = {}
@@ -62,7 +65,13 @@ def recorded_traffic(precision, side):
                 rec[k.strip()] = v.strip()
     if rec.get("source_sha256") != device_source_hash():
         return None
-    return float(rec["fetch_bytes"]) + float(rec["write_bytes"])
+    return rec
+
+
+def recorded_traffic(precision, side):
+    """Bytes per launch from the committed counter record, or None."""
+    rec = counter_record(precision, side)
+    return None if rec is None else float(rec["fetch_bytes"]) + float(rec["write_bytes"])
 
 
 def time_query(scan, prec, out, steps, warmup, dd, torch):
@@ -151,6 +160,18 @@ def main():
         "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
         "flops_per_launch": far_flops,
     }
+    if prec == "mixed":
+        # this build does not emit packed FP32, so 78.6 TFLOP/s is the FLOP
+        # ceiling; the VALU issue rate comes from the recorded instructions
+        # per pair (rocprofv3 SQ_INSTS_VALU) times the live pair rate
+        roofline["frac_of_fp32_nonpacked"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
+        rec = counter_record(prec, args.side)
+        if rec is not None and "valu_lane_instructions_per_pair" in rec:
+            ipp = float(rec["valu_lane_instructions_per_pair"])
+            rate = roofline["pairs_per_launch"] / (far_ms * 1e-3) * ipp
+            roofline["valu_issue"] = {"lane_instructions_per_pair": ipp, "achieved": rate,
+                                      "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
+                                      "frac": round(rate / VALU_ISSUE_PEAK, 4)}
     result = out.cpu().numpy()
 
     # The other precision on the same workload, for context.
