@@ -233,22 +233,45 @@ class Scan:
 
 
 def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PROBES,
-                precision: str = "mixed", outs=None, stream=None):
-    """Many scans in one call (``dd_batch_solve``); returns one float64 CUDA
-    tensor per scan: [V] arrival (if requested) then [ny*nx] final map."""
+                precision: str = "mixed", outs=None, stream=None, out=None):
+    """Many scans in one call (``dd_batch_solve``).  Per scan the result is
+    [V] arrival (if requested) then [ny*nx] final map, float64 on the GPU.
+
+    By default one buffer holds every scan's result back to back and the call
+    returns one view of it per scan.  ``outs`` gives one tensor per scan
+    instead; ``out`` gives the single buffer (contiguous float64 of the total
+    size, any shape), and the call then returns ``out`` itself."""
     torch = _torch()
     n = len(scans)
-    if outs is None:
-        outs = []
-        for s in scans:
-            size = (s.num_visits if queries & Q_ARRIVAL else 0) + (
-                s.nx * s.ny if queries & Q_FINAL_AT_PROBES else 0)
-            outs.append(torch.empty(size, dtype=torch.float64, device="cuda"))
     hs = (ctypes.c_void_p * n)(*[s.handle.value for s in scans])
-    os_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    if outs is not None:
+        ptrs = np.array([o.data_ptr() for o in outs], dtype=np.uint64)
+    else:
+        arr = (queries & Q_ARRIVAL) != 0
+        fin = (queries & Q_FINAL_AT_PROBES) != 0
+        sizes = np.array([(s.num_visits if arr else 0) + (s.nx * s.ny if fin else 0) for s in scans],
+                         dtype=np.int64)
+        total = int(sizes.sum())
+        if out is None:
+            flat = torch.empty(total, dtype=torch.float64, device="cuda")
+        else:
+            if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous() or \
+                    out.numel() != total:
+                raise ValueError(f"out must be a contiguous float64 CUDA tensor of {total} elements")
+            flat = out
+        offs = np.zeros(n, dtype=np.int64)
+        if n > 1:
+            np.cumsum(sizes[:-1], out=offs[1:])
+        ptrs = (np.uint64(flat.data_ptr()) + offs.astype(np.uint64) * np.uint64(8))
+    os_ = (ctypes.c_void_p * n).from_buffer(np.ascontiguousarray(ptrs, dtype=np.uint64)) if n \
+        else (ctypes.c_void_p * 0)()
     _check(load_library().dd_batch_solve(hs, n, queries, _prec(precision), os_, 1,
                                          _stream(stream)))
-    return outs
+    if outs is not None:
+        return outs
+    if out is not None:
+        return out
+    return list(torch.split(flat.view(-1), sizes.tolist()))
 
 
 def pair_terms(kappa: float, sigma_hat: float, a, lag, precision: str = "fp64", stream=None):

@@ -427,6 +427,11 @@ ProfToken prof_begin(const char* kernel, hipStream_t st) {
   t.slot = (int)P.recs.size() - 1;
   return t;
 }
+bool prof_on() {
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  return P.on;
+}
 void prof_end(ProfToken tok, hipStream_t st, double pairs, double flops) {
   if (tok.slot < 0) return;
   ProfState& P = prof();

@@ -430,7 +430,10 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
           t[r][s] = series_row32<M>(map_a32<LAT, R>(pc[s], ex, ey, ee, r), cur[s]);
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += (double)pairwise_sum<U>(t[r]);
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < U; q += 4)  // groups of four, whatever the unroll
+          acc[r] += (double)((t[r][q] + t[r][q + 1]) + (t[r][q + 2] + t[r][q + 3]));
 #pragma unroll
       for (int s = 0; s < U; ++s) {
         cur[s] = nxt[s];
@@ -462,21 +465,38 @@ __device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const doubl
   }
 }
 
+template <int R, int U, bool LAT>
+__device__ __forceinline__ void map_far32_u(int M, int lo, int hi, int64_t K,
+                                            const float4* __restrict__ pos,
+                                            const float* __restrict__ rows, const float (&ex)[R],
+                                            const float (&ey)[R], const float (&ee)[R],
+                                            double (&acc)[R]) {
+  switch (M) {
+    case 0: map_far32<0, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 1: map_far32<1, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 2: map_far32<2, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 3: map_far32<3, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 4: map_far32<4, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    case 5: map_far32<5, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+    default: map_far32<6, R, U, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+  }
+}
+
 template <int R, bool LAT>
 __device__ __forceinline__ void map_far32_seg(int M, int lo, int hi, int64_t K,
                                               const float4* __restrict__ pos,
                                               const float* __restrict__ rows, const float (&ex)[R],
                                               const float (&ey)[R], const float (&ee)[R],
                                               double (&acc)[R]) {
-  switch (M) {
-    case 0: map_far32<0, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 1: map_far32<1, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 2: map_far32<2, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 3: map_far32<3, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 4: map_far32<4, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    case 5: map_far32<5, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
-    default: map_far32<6, R, 4, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); break;
+  // One pixel per lane: eight lags per step for more loads in flight.  The sum
+  // still runs over groups of four in lag order, so the result does not
+  // depend on the tile width.
+  if constexpr (R == 1) {
+    const int mid = lo + ((hi - lo) & ~7);
+    map_far32_u<R, 8, LAT>(M, lo, mid, K, pos, rows, ex, ey, ee, acc);
+    lo = mid;
   }
+  map_far32_u<R, 4, LAT>(M, lo, hi, K, pos, rows, ex, ey, ee, acc);
 }
 
 template <int R>

@@ -130,8 +130,11 @@ void count_segments(const DegreeBounds& b, int64_t lo, int64_t hi, bool mixed, P
 
 // Plan of the arrival query: tiles of 64R visits; near band lags [1, kf);
 // far chunks of K lags from kf, aligned to R.
+// The near items go to `near` and the far items to `far`, both in planning
+// order.  Pair and flop counts (for the profiler) are formed only if `count`.
 void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPlan& P,
-                  std::vector<ArrItem>& items, std::vector<int32_t>& tile_slots) {
+                  std::vector<ArrItem>& near, std::vector<ArrItem>& far,
+                  std::vector<int32_t>& tile_slots, bool count) {
   const int T = 64 * R, TN = 64 * RN;
   const int64_t V = s->V;
   const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
@@ -144,7 +147,8 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
   P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
   P.near_pairs = P.near_flops = P.far_pairs = P.far_flops = 0;
   const int64_t n_tiles = (V + T - 1) / T;
-  std::vector<ArrItem> near, far;
+  near.clear();
+  far.clear();
   tile_slots.assign(n_tiles, 1);
   int S = 1;
   for (int64_t t = 0; t < n_tiles; ++t) {
@@ -158,9 +162,10 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
         const int64_t hi = std::min<int64_t>(lo + K, span_end);
         const int edge = (hi - 1 > J0) ? kItemEdge : 0;
         far.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)hi, (1 + c) | edge});
-        count_segments(P.bounds, lo, hi, mixed,
-                       [&](int64_t a, int64_t e) { return arrival_pairs(J0, jend, a, e); },
-                       P.far_pairs, P.far_flops);
+        if (count)
+          count_segments(P.bounds, lo, hi, mixed,
+                         [&](int64_t a, int64_t e) { return arrival_pairs(J0, jend, a, e); },
+                         P.far_pairs, P.far_flops);
       }
     }
     tile_slots[t] = 1 + c;
@@ -172,17 +177,12 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
     const int64_t maxlag = std::min<int64_t>(J0 + TN - 1, V - 1);
     const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
     near.push_back(ArrItem{(int32_t)t, 1, (int32_t)nhi, 0 | kItemNear});
-    const double np_ = arrival_pairs(J0, std::min<int64_t>(J0 + TN, V), 1, nhi);
-    P.near_pairs += np_;
-    P.near_flops += np_ * series_flops(mixed ? kMNear32 : kM64, mixed);
+    if (count) {
+      const double np_ = arrival_pairs(J0, std::min<int64_t>(J0 + TN, V), 1, nhi);
+      P.near_pairs += np_;
+      P.near_flops += np_ * series_flops(mixed ? kMNear32 : kM64, mixed);
+    }
   }
-  auto longer = [](const ArrItem& a, const ArrItem& b) {
-    return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
-  };
-  std::stable_sort(near.begin(), near.end(), longer);
-  std::stable_sort(far.begin(), far.end(), longer);
-  items = near;
-  items.insert(items.end(), far.begin(), far.end());
   P.R = R;
   P.RN = RN;
   P.K = K;
@@ -219,9 +219,15 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   const int K = arrival_K(s->V, R, mixed);
   ArrivalPlan& P = g_plans[s].arr;
   if (P.V != s->V || P.R != R || P.RN != RN || P.K != K || P.mixed != mixed) {
-    std::vector<ArrItem> items;
+    std::vector<ArrItem> items, far;
     std::vector<int32_t> tile_slots;
-    plan_arrival(s, mixed, R, RN, K, P, items, tile_slots);
+    plan_arrival(s, mixed, R, RN, K, P, items, far, tile_slots, true);
+    auto longer = [](const ArrItem& a, const ArrItem& b) {
+      return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
+    };
+    std::stable_sort(items.begin(), items.end(), longer);
+    std::stable_sort(far.begin(), far.end(), longer);
+    items.insert(items.end(), far.begin(), far.end());  // near items first
     rc = upload(s->items, items, st);
     if (rc != DD_OK) return rc;
     rc = upload(s->aux, tile_slots, st);
@@ -307,7 +313,8 @@ bool grid_is_lattice(double X0, double Y0, double DX, double DY, int w, int h, i
 // at or before the end of the scan, and rows are taken from the scan's
 // integer-lag table (row n at offset n) instead of a per-call table.
 void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
-              int R, int64_t Kmap, bool int_rows, MapPlan& P) {
+              int R, int64_t Kmap, bool int_rows, MapPlan& P, bool sort_items = true,
+              bool count = true) {
   const int64_t npix = (int64_t)g->w * g->h;
   const double p = s->desc.pitch_m;
   P.X0 = g->x0_m / p;
@@ -395,6 +402,13 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
     const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
     far_total += std::max<int64_t>(0, times[m].K + 1 - kf);
   }
+  // A small map splits its far lags into shorter chunks (down to 512) until it
+  // alone yields about 64 work items of 256 pixels, so that a call holding few
+  // small maps still spreads over the chip.  The chunk length depends only on
+  // this map (grid and times), never on the rest of a batched call, so batched
+  // and single-map results stay the same bit for bit.
+  const int64_t units = (npix + 255) / 256;
+  while (Kc > 512 && units * ((far_total + Kc - 1) / Kc) < 64) Kc /= 2;
   // keep partials below ~1 GiB
   const int64_t cap_slots = std::max<int64_t>(n_t * 2, (1LL << 27) / std::max<int64_t>(npix, 1));
   while (far_total / Kc + n_t > cap_slots) Kc *= 2;
@@ -408,16 +422,19 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
     int c = 0;
     for (int64_t t = 0; t < n_tiles; ++t)
       near.push_back(MapItem{(int32_t)t, m, (int32_t)nlo[m], (int32_t)near_hi, 0, 1, 0, 0});
-    P.pairs += (double)npix * (double)(near_hi - nlo[m]);
-    P.flops += (double)npix * (double)(near_hi - nlo[m]) *
-               series_flops(mixed ? kMNear32 : kM64, mixed);
+    if (count) {
+      P.pairs += (double)npix * (double)(near_hi - nlo[m]);
+      P.flops += (double)npix * (double)(near_hi - nlo[m]) *
+                 series_flops(mixed ? kMNear32 : kM64, mixed);
+    }
     for (int64_t lo = std::max(kf, nlo[m]); lo <= K; lo += Kc, ++c) {
       const int64_t hi = std::min<int64_t>(lo + Kc, K + 1);
       for (int64_t t = 0; t < n_tiles; ++t)
         far.push_back(MapItem{(int32_t)t, m, (int32_t)lo, (int32_t)hi, 1 + c, 0, 0, 0});
-      count_segments(times[m].bounds, lo, hi, mixed,
-                     [&](int64_t a, int64_t e) { return (double)npix * (double)(e - a); },
-                     P.pairs, P.flops);
+      if (count)
+        count_segments(times[m].bounds, lo, hi, mixed,
+                       [&](int64_t a, int64_t e) { return (double)npix * (double)(e - a); },
+                       P.pairs, P.flops);
     }
     times[m].slot_base = slot_base;
     times[m].n_slots = 1 + c;
@@ -427,8 +444,10 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
   auto longer = [](const MapItem& a, const MapItem& b) {
     return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
   };
-  std::stable_sort(near.begin(), near.end(), longer);
-  std::stable_sort(far.begin(), far.end(), longer);
+  if (sort_items) {
+    std::stable_sort(near.begin(), near.end(), longer);
+    std::stable_sort(far.begin(), far.end(), longer);
+  }
   P.items = near;
   P.items.insert(P.items.end(), far.begin(), far.end());
 }
@@ -506,13 +525,79 @@ dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStrea
 // last launch and the next call makes its stream wait for it before its
 // uploads overwrite the scratch.  (Reallocation is safe: hipFree waits for
 // the device.)
+// The call's tables (scans, four item lists, reductions, tile slots) travel
+// in one pinned host block and one copy; the next call waits for that copy
+// (`copied`) before it rewrites the block.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    const size_t want = std::max(need, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+};
+
 struct BatchScratch {
-  DevBuf scans, items, near_items, map_items, map_near_items, reds, slots, partial, counter,
-      staging;
-  hipEvent_t done = nullptr;  // kept until the process ends
-  bool pending = false;
+  DevBuf block, partial, counter, staging;
+  PinnedBuf host_block;
+  std::vector<BatchScan> h_scans;
+  std::vector<BatchItem> h_items, h_near_items, h_map_items, h_map_near_items, h_tmp;
+  std::vector<BatchReduce> h_reds;
+  std::vector<int32_t> h_slots, h_tile_slots;
+  std::vector<ArrItem> h_arr_near, h_arr_far;
+  std::vector<uint64_t> h_ka, h_kb;
+  hipEvent_t done = nullptr, copied = nullptr;  // kept until the process ends
+  bool pending = false, copy_pending = false;
 };
 static thread_local BatchScratch g_batch;
+
+int64_t item_cost(const BatchItem& a) { return ((int64_t)a.cost_hi << 31) | a.cost_lo; }
+
+// Items longest first.  A stable LSD radix sort on (largest cost - cost):
+// equal costs keep their planned order, as with a stable comparison sort, at
+// linear cost for the long item lists of a large batch.  The sort runs on
+// 8-byte (key, index) words; the items move once at the end.
+void sort_longest_first(std::vector<BatchItem>& v, std::vector<BatchItem>& tmp,
+                        std::vector<uint64_t>& ka, std::vector<uint64_t>& kb) {
+  const size_t n = v.size();
+  if (n < 2) return;
+  int64_t top = 0;
+  for (const BatchItem& a : v) top = std::max(top, item_cost(a));
+  if (top == 0) return;
+  constexpr int kBits = 11;
+  constexpr uint64_t kMask = (1u << kBits) - 1;
+  // keys above 2^32 - 1 are clamped: the order among items that long is
+  // then their planned order, which an LPT schedule does not need to refine
+  const uint64_t span = std::min<uint64_t>((uint64_t)top, 0xffffffffULL);
+  ka.resize(n);
+  kb.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    const uint64_t key = std::min<uint64_t>((uint64_t)(top - item_cost(v[i])), span);
+    ka[i] = (key << 32) | (uint64_t)i;
+  }
+  size_t count[(size_t)1 << kBits];
+  for (int shift = 32; shift < 64 && (span >> (shift - 32)) != 0; shift += kBits) {
+    std::fill(count, count + ((size_t)1 << kBits), 0);
+    for (size_t i = 0; i < n; ++i) ++count[(ka[i] >> shift) & kMask];
+    size_t sum = 0;
+    for (size_t& c : count) {
+      const size_t here = c;
+      c = sum;
+      sum += here;
+    }
+    for (size_t i = 0; i < n; ++i) kb[count[(ka[i] >> shift) & kMask]++] = ka[i];
+    ka.swap(kb);
+  }
+  tmp.resize(n);
+  for (size_t i = 0; i < n; ++i) tmp[i] = v[ka[i] & 0xffffffffULL];
+  v.swap(tmp);
+}
 
 }  // namespace
 
@@ -537,10 +622,23 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     }
     while (RM > 1 && 64LL * (RM / 2) >= most) RM /= 2;
   }
-  std::vector<BatchScan> bs(n);
-  std::vector<BatchItem> items, near_items, map_items, map_near_items;
-  std::vector<BatchReduce> reds;
-  std::vector<int32_t> all_slots;
+  // host tables, kept by the thread between calls (no reallocation per call)
+  BatchScratch& W = g_batch;
+  const bool count = prof_on();
+  std::vector<BatchScan>& bs = W.h_scans;
+  std::vector<BatchItem>& items = W.h_items;
+  std::vector<BatchItem>& near_items = W.h_near_items;
+  std::vector<BatchItem>& map_items = W.h_map_items;
+  std::vector<BatchItem>& map_near_items = W.h_map_near_items;
+  std::vector<BatchReduce>& reds = W.h_reds;
+  std::vector<int32_t>& all_slots = W.h_slots;
+  bs.assign(n, BatchScan{});
+  items.clear();
+  near_items.clear();
+  map_items.clear();
+  map_near_items.clear();
+  reds.clear();
+  all_slots.clear();
   std::vector<int64_t> arr_off(n, 0), map_off(n, 0), slot_off(n, 0), out_off(n, 0);
   int64_t partial_total = 0, out_total = 0;
   double pairs = 0, flops = 0;
@@ -569,26 +667,26 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     out_off[k] = out_total;
     if (want_arr) {
       ArrivalPlan AP;
-      std::vector<ArrItem> ai;
-      std::vector<int32_t> ts;
-      plan_arrival(s, mixed, R, RN, arrival_K(s->V, R, mixed), AP, ai, ts);
+      std::vector<ArrItem>& an = W.h_arr_near;
+      std::vector<ArrItem>& af = W.h_arr_far;
+      std::vector<int32_t>& ts = W.h_tile_slots;
+      plan_arrival(s, mixed, R, RN, arrival_K(s->V, R, mixed), AP, an, af, ts, count);
       B.arr_bounds = AP.bounds;
       arr_off[k] = partial_total;
       partial_total += (int64_t)AP.S * s->V;
       slot_off[k] = (int64_t)all_slots.size();
       all_slots.insert(all_slots.end(), ts.begin(), ts.end());
       const double near_w = mixed ? 6.0 : 3.0;  // relative cost of a near pair
-      for (size_t q = 0; q < ai.size(); ++q) {
-        const ArrItem& a = ai[q];
-        const bool near_item = (int)q < AP.n_near;
-        const double cost =
-            (double)(a.n_hi - a.n_lo) * 64.0 * (near_item ? RN * near_w : R);
-        const int64_t c = (int64_t)cost;
-        (near_item ? near_items : items)
-            .push_back(BatchItem{k, near_item ? kBatchArrNear : kBatchArrFar, a.tile, a.n_lo,
-                                 a.n_hi, a.slot_flags, (int32_t)(c >> 31),
-                                 (int32_t)(c & 0x7fffffff)});
-      }
+      auto add = [&](std::vector<BatchItem>& dst, const std::vector<ArrItem>& src, int kind,
+                     double per_lag) {
+        for (const ArrItem& a : src) {
+          const int64_t c = (int64_t)((double)(a.n_hi - a.n_lo) * per_lag);
+          dst.push_back(BatchItem{k, kind, a.tile, a.n_lo, a.n_hi, a.slot_flags,
+                                  (int32_t)(c >> 31), (int32_t)(c & 0x7fffffff)});
+        }
+      };
+      add(near_items, an, kBatchArrNear, 64.0 * RN * near_w);
+      add(items, af, kBatchArrFar, 64.0 * R);
       reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref});
       out_total += s->V;
       pairs += AP.near_pairs + AP.far_pairs;
@@ -599,7 +697,7 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
                 B.map_rows};
       const double t_end = (double)s->V * s->tau_v;
       MapPlan MP;
-      plan_map(s, &g, &t_end, 1, mixed, RM, tune().map_K, true, MP);
+      plan_map(s, &g, &t_end, 1, mixed, RM, tune().map_K, true, MP, false, count);
       B.map_time = MP.times[0];
       map_off[k] = partial_total;
       partial_total += MP.slots * MP.npix;
@@ -619,32 +717,42 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       flops += MP.flops;
     }
   }
-  BatchScratch& W = g_batch;
   if (W.pending) DD_HIP(hipStreamWaitEvent(st, W.done, 0), "stream wait");
-  auto longer = [](const BatchItem& a, const BatchItem& b) {
-    const int64_t ca = ((int64_t)a.cost_hi << 31) | a.cost_lo;
-    const int64_t cb = ((int64_t)b.cost_hi << 31) | b.cost_lo;
-    return ca > cb;
+  for (std::vector<BatchItem>* v : {&items, &near_items, &map_items, &map_near_items})
+    sort_longest_first(*v, W.h_tmp, W.h_ka, W.h_kb);
+  // tables: scans, far/near arrival items, far/near map items, reductions, slots
+  struct Table {
+    const void* src;
+    size_t bytes, off;
   };
-  std::stable_sort(items.begin(), items.end(), longer);
-  std::stable_sort(near_items.begin(), near_items.end(), longer);
-  std::stable_sort(map_items.begin(), map_items.end(), longer);
-  std::stable_sort(map_near_items.begin(), map_near_items.end(), longer);
+  Table tab[7] = {{bs.data(), sizeof(BatchScan) * bs.size(), 0},
+                  {items.data(), sizeof(BatchItem) * items.size(), 0},
+                  {near_items.data(), sizeof(BatchItem) * near_items.size(), 0},
+                  {map_items.data(), sizeof(BatchItem) * map_items.size(), 0},
+                  {map_near_items.data(), sizeof(BatchItem) * map_near_items.size(), 0},
+                  {reds.data(), sizeof(BatchReduce) * reds.size(), 0},
+                  {all_slots.data(), sizeof(int32_t) * all_slots.size(), 0}};
+  size_t block_bytes = 0;
+  for (Table& t : tab) {
+    t.off = block_bytes;
+    block_bytes += (t.bytes + 255) & ~(size_t)255;
+  }
+  DD_HIP(W.block.ensure(block_bytes), "device allocation");
+  char* blk = (char*)W.block.p;
   DD_HIP(W.partial.ensure(sizeof(double) * (size_t)std::max<int64_t>(partial_total, 1)),
          "device allocation");
   double* part = W.partial.as<double>();
-  DD_HIP(W.slots.ensure(sizeof(int32_t) * std::max<size_t>(all_slots.size(), 1)),
-         "device allocation");
   if (!on_device) DD_HIP(W.staging.ensure(sizeof(double) * (size_t)std::max<int64_t>(out_total, 1)),
                          "device allocation");
   {
+    const int32_t* d_slots = (const int32_t*)(blk + tab[6].off);
     size_t r = 0;
     for (int32_t k = 0; k < n; ++k) {
       double* o = on_device ? outs[k] : W.staging.as<double>() + out_off[k];
       if (want_arr) {
         bs[k].arr_partial = part + arr_off[k];
         reds[r].partial = bs[k].arr_partial;
-        reds[r].tile_slots = W.slots.as<int32_t>() + slot_off[k];
+        reds[r].tile_slots = d_slots + slot_off[k];
         reds[r].out = o;
         o += scans[k]->V;
         ++r;
@@ -657,38 +765,37 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       }
     }
   }
-  dd_status rc = upload(W.scans, bs, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.items, items, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.near_items, near_items, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.map_items, map_items, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.map_near_items, map_near_items, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.reds, reds, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(W.slots, all_slots, st);
-  if (rc != DD_OK) return rc;
+  if (W.copy_pending) DD_HIP(hipEventSynchronize(W.copied), "event synchronize");
+  W.copy_pending = false;
+  DD_HIP(W.host_block.ensure(block_bytes), "pinned host allocation");
+  for (const Table& t : tab)
+    if (t.bytes) std::memcpy((char*)W.host_block.p + t.off, t.src, t.bytes);
+  if (!W.copied)
+    DD_HIP(hipEventCreateWithFlags(&W.copied, hipEventDisableTiming), "event creation");
+  DD_HIP(hipMemcpyAsync(blk, W.host_block.p, block_bytes, hipMemcpyHostToDevice, st),
+         "host-to-device copy");
+  DD_HIP(hipEventRecord(W.copied, st), "event record");
+  W.copy_pending = true;
+  const BatchScan* d_scans = (const BatchScan*)(blk + tab[0].off);
   DD_HIP(W.counter.ensure(4 * sizeof(int)), "device allocation");
   ProfToken tb = prof_begin("batch", st);
-  DD_HIP(launch_batch(W.scans.as<BatchScan>(), W.items.as<BatchItem>(), (int32_t)items.size(),
+  DD_HIP(launch_batch(d_scans, (const BatchItem*)(blk + tab[1].off), (int32_t)items.size(),
                       W.counter.as<int>(), R, mixed, st),
          "batched launch");
-  DD_HIP(launch_batch_near(W.scans.as<BatchScan>(), W.near_items.as<BatchItem>(),
+  DD_HIP(launch_batch_near(d_scans, (const BatchItem*)(blk + tab[2].off),
                            (int32_t)near_items.size(), W.counter.as<int>() + 1, RN, mixed, st),
          "batched near-band launch");
-  DD_HIP(launch_batch_map(W.scans.as<BatchScan>(), W.map_items.as<BatchItem>(),
-                          (int32_t)map_items.size(), W.counter.as<int>() + 2, RM, mixed, false, st),
+  DD_HIP(launch_batch_map(d_scans, (const BatchItem*)(blk + tab[3].off), (int32_t)map_items.size(),
+                          W.counter.as<int>() + 2, RM, mixed, false, st),
          "batched map launch");
-  DD_HIP(launch_batch_map(W.scans.as<BatchScan>(), W.map_near_items.as<BatchItem>(),
+  DD_HIP(launch_batch_map(d_scans, (const BatchItem*)(blk + tab[4].off),
                           (int32_t)map_near_items.size(), W.counter.as<int>() + 3, RM, mixed, true,
                           st),
          "batched map near-band launch");
   prof_end(tb, st, pairs, flops);
   ProfToken tq = prof_begin("reduce", st);
-  DD_HIP(launch_reduce_batch(W.reds.as<BatchReduce>(), (int32_t)reds.size(), out_total, st),
+  DD_HIP(launch_reduce_batch((const BatchReduce*)(blk + tab[5].off), (int32_t)reds.size(),
+                             out_total, st),
          "batched reduce launch");
   prof_end(tq, st, 0, 0);
   if (!W.done) DD_HIP(hipEventCreateWithFlags(&W.done, hipEventDisableTiming), "event creation");

@@ -32,6 +32,7 @@ struct ProfToken {
 };
 ProfToken prof_begin(const char* kernel, hipStream_t st);
 void prof_end(ProfToken tok, hipStream_t st, double pairs, double flops);
+bool prof_on();  // whether kernel timing is being recorded
 
 // Floating-point operations per pair of the evaluation form used (FMA = 2):
 // mixed degree <= 3 (powers of a, folded correction) 15 + 2M, mixed degree

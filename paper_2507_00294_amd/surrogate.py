@@ -42,8 +42,8 @@ def exact_final_maps(scans, precision="mixed"):
     """Exact final maps [n, 64, 64] (float64 CUDA) by one batched launch."""
     import torch
 
-    outs = batch_solve(scans, Q_FINAL_AT_PROBES, precision)
-    return torch.stack([o.view(SIDE, SIDE) for o in outs])
+    out = torch.empty((len(scans), SIDE, SIDE), dtype=torch.float64, device="cuda")
+    return batch_solve(scans, Q_FINAL_AT_PROBES, precision, out=out)
 
 
 def generate(specs, precision="mixed", chunk=256, keep_psi=False):
