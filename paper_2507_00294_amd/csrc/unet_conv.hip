@@ -27,7 +27,9 @@
 //
 // Fragment layout of v_mfma_f32_16x16x32_bf16 (lane l): A row l % 16,
 // k = 8 (l / 16) .. +7; B column l % 16, same k; D element v at row
-// 4 (l / 16) + v, column l % 16.  LDS rows hold 32 BF16 channels padded to 40
+// 4 (l / 16) + v, column l % 16.  The weights are the A operand and the
+// activations the B operand, so D rows are output channels and columns
+// pixels.  LDS rows hold 32 BF16 channels padded to 40
 // (80 B), so 16 lanes reading 16 consecutive pixels hit distinct banks.
 //
 // The data gradient of a convolution is the same operation on dZ with the
@@ -55,8 +57,6 @@ constexpr int HPMAX = 400;  // halo-tile pixels: 6 x 66, 10 x 34, 18 x 18 or 4 x
 enum { IN_PLAIN = 0, IN_UPCAT = 1 };
 enum { EPI_PLAIN = 0, EPI_SILU = 1, EPI_HEAD = 2 };
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
-
 __device__ __forceinline__ bf16x4 to_bf16x4(f32x4 v) {
   return bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
 }
@@ -78,69 +78,79 @@ struct ConvArgs {
   int N;
 };
 
-// Epilogue of the block's accumulators: rows m0 + wave 64 + a 16 +
-// 4 (lane / 16) + v, columns n0 + b 16 + lane % 16.
+// Epilogue of the block's accumulators.  The MFMAs take the weights as their
+// first operand, so acc[a][b][v] is output channel n0 + b 16 + 4 (lane / 16)
+// + v of pixel m0 + wave 64 + a 16 + lane % 16: every lane holds four
+// consecutive channels of one pixel and stores them with one 8-byte (BF16)
+// or 16-byte (FP32) store.
+__device__ __forceinline__ float silu(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
 template <int NB, int EPI>
 __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB], int m0, int n0,
                                          int wave, int lane) {
+  const int c4 = 4 * (lane >> 4);
   if (EPI == EPI_HEAD) {
-    // N = 32 = BN: each row's 32 channels sit in the 16 lanes of one lane
-    // group (two columns per lane); SiLU, weight, then reduce over the group.
-    const int c0 = lane & 15;
-    const float w0 = p.hw[c0], w1 = p.hw[16 + c0], hb = p.hw[32];
-    const float b0 = p.bias[c0], b1 = p.bias[16 + c0];
+    // N = 32 = BN: this lane holds channels c4..c4+3 and 16+c4..16+c4+3 of its
+    // pixel; SiLU, weight, then the sum over the pixel's four lanes.
+    f32x4 w[2], bb[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 2; ++b) {
+      w[b] = *reinterpret_cast<const f32x4*>(p.hw + 16 * b + c4);
+      bb[b] = *reinterpret_cast<const f32x4*>(p.bias + 16 * b + c4);
+    }
+    const float hb = p.hw[32];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wave * 64 + a * 16 + 4 * (lane >> 4) + v;
-        const float z0 = acc[a][0][v] + b0, z1 = acc[a][1][v] + b1;
-        const float a0 = silu(z0), a1 = silu(z1);
-        if (row < p.M) {
-          const int64_t o = (int64_t)row * 32 + c0;
-          if (p.out) {
-            __bf16* act = static_cast<__bf16*>(p.out);
-            act[o] = (__bf16)a0;
-            act[o + 16] = (__bf16)a1;
-          }
-          if (p.z) {
-            p.z[o] = z0;
-            p.z[o + 16] = z1;
-          }
+    for (int a = 0; a < 4; ++a) {
+      const int row = m0 + wave * 64 + a * 16 + (lane & 15);
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        f32x4 z, act;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          z[v] = acc[a][b][v] + bb[b][v];
+          act[v] = silu(z[v]);
+          s = __builtin_fmaf(act[v], w[b][v], s);
         }
-        float s = a0 * w0 + a1 * w1;
-        s += __shfl_xor(s, 1, 16);
-        s += __shfl_xor(s, 2, 16);
-        s += __shfl_xor(s, 4, 16);
-        s += __shfl_xor(s, 8, 16);
-        if (c0 == 0 && row < p.M) p.y[row] = s + hb;
+        if (row < p.M) {
+          const int64_t o = (int64_t)row * 32 + 16 * b + c4;
+          if (p.out) *reinterpret_cast<bf16x4*>(static_cast<__bf16*>(p.out) + o) = to_bf16x4(act);
+          if (p.z) *reinterpret_cast<f32x4*>(p.z + o) = z;
+        }
       }
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (c4 == 0 && row < p.M) p.y[row] = s + hb;
+    }
     return;
   }
+  f32x4 bs[NB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int b = 0; b < NB; ++b)
+    bs[b] = EPI == EPI_SILU ? *reinterpret_cast<const f32x4*>(p.bias + n0 + 16 * b + c4)
+                            : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = m0 + wave * 64 + a * 16 + (lane & 15);
+    if (row >= p.M) continue;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int col = n0 + b * 16 + (lane & 15);
-      const float bs = EPI == EPI_SILU ? p.bias[col] : 0.f;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wave * 64 + a * 16 + 4 * (lane >> 4) + v;
-        if (row < p.M) {
-          const int64_t o = (int64_t)row * p.N + col;
-          if (EPI == EPI_SILU) {
-            const float zz = acc[a][b][v] + bs;
-            if (p.z) p.z[o] = zz;
-            static_cast<__bf16*>(p.out)[o] = (__bf16)silu(zz);
-          } else {
-            static_cast<float*>(p.out)[o] = acc[a][b][v];
-          }
-        }
+      const int64_t o = (int64_t)row * p.N + n0 + 16 * b + c4;
+      if (EPI == EPI_SILU) {
+        const f32x4 z = acc[a][b] + bs[b];
+        if (p.z) *reinterpret_cast<f32x4*>(p.z + o) = z;
+        const f32x4 act{silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3])};
+        *reinterpret_cast<bf16x4*>(static_cast<__bf16*>(p.out) + o) = to_bf16x4(act);
+      } else {
+        *reinterpret_cast<f32x4*>(static_cast<float*>(p.out) + o) = acc[a][b];
       }
     }
+  }
 }
 
-template <typename TIn, int IN, int BN, int EPI>
+template <typename TIn, int IN, int BN, int EPI, int LG>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   // weights staged in LDS for BN = 64; for BN = 32 (the one-chunk layers at
   // 64^2, which depend on occupancy) each wave reads them from L2, one tap ahead
@@ -152,12 +162,15 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   constexpr int BSLOTS = (BPIECES + 255) / 256;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * CBM, n0 = blockIdx.y * BN;
-  const int lg = p.lg, W = 1 << lg, ci = p.ci, K = 9 * ci;
+  // the image side is a template parameter, so that the tile geometry below
+  // is constant and its divisions are multiplications
+  constexpr int lg = LG, W = 1 << lg;
+  const int ci = p.ci, K = 9 * ci;
   // tile geometry: G image slices of R rows x W columns, halo (R+2) x (W+2)
-  const int lgR = lg >= 4 ? 8 - lg : lg;  // rows per slice: 256 / W, or W for W = 8
-  const int R = 1 << lgR, lgRW = lgR + lg;
-  const int HW2 = W + 2, slice = (R + 2) * HW2;
-  const int G = CBM >> lgRW, HP = G * slice;
+  constexpr int lgR = lg >= 4 ? 8 - lg : lg;  // rows per slice: 256 / W, or W for W = 8
+  constexpr int R = 1 << lgR, lgRW = lgR + lg;
+  constexpr int HW2 = W + 2, slice = (R + 2) * HW2;
+  constexpr int G = CBM >> lgRW, HP = G * slice;
   const int img0 = m0 >> (2 * lg), y0 = (m0 >> lg) & (W - 1);
   // staging: 16-byte slots of CPQ channels, QPP slots per pixel and chunk
   constexpr int CPQ = 16 / (int)sizeof(TIn), LGQ = CPQ == 8 ? 2 : 3, QPP = 1 << LGQ;
@@ -293,7 +306,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
                  : bcur[b];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf, af[a], acc[a][b], 0, 0, 0);
       }
       if (!BLDS && tap < 8) {
 #pragma unroll
@@ -383,20 +396,31 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
           *reinterpret_cast<const bf16x8*>(&Bs[b * 16 + (lane & 15)][ks * 32 + 8 * (lane >> 4)]);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr, acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr, af[a], acc[a][b], 0, 0, 0);
     }
   }
   epilogue<2, EPI>(p, acc, m0, 0, wave, lane);
 }
 
+template <typename TIn, int IN, int BN, int EPI>
+void launch_halo_bn(const ConvArgs& p, dim3 grid, hipStream_t st) {
+  switch (p.lg) {
+    case 3: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 3>), grid, dim3(256), 0, st, p); break;
+    case 4: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 4>), grid, dim3(256), 0, st, p); break;
+    case 5: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 5>), grid, dim3(256), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 6>), grid, dim3(256), 0, st, p); break;
+  }
+}
+
+// Callers have checked 3 <= lg <= 6 (halo_ok).
 template <typename TIn, int IN, int EPI>
 hipError_t launch_halo(const ConvArgs& p, hipStream_t st) {
   const int bn = (EPI == EPI_HEAD) ? 32 : (p.N % 64 == 0) ? 64 : 32;
   dim3 grid((p.M + CBM - 1) / CBM, p.N / bn);
   if (bn == 64)
-    hipLaunchKernelGGL((k_conv_halo<TIn, IN, 64, EPI>), grid, dim3(256), 0, st, p);
+    launch_halo_bn<TIn, IN, 64, EPI>(p, grid, st);
   else
-    hipLaunchKernelGGL((k_conv_halo<TIn, IN, 32, EPI>), grid, dim3(256), 0, st, p);
+    launch_halo_bn<TIn, IN, 32, EPI>(p, grid, st);
   return hipGetLastError();
 }
 
