@@ -85,13 +85,23 @@ __device__ __forceinline__ double e1_f64(double x) {
 }
 
 // Series form in double precision with P_0..P_M read from an FP64 row.
+// The two factors of the term: returns q and sets t = exp(-x1) (term = t q).
 template <int M>
-__device__ __forceinline__ double series_f64(double a, const double* __restrict__ row) {
+__device__ __forceinline__ double series_f64_q(double a, const double* __restrict__ row,
+                                               double& t) {
   const double z = a * row[kR64_C];
   double q = row[kR64_P + M];
 #pragma unroll
   for (int m = M - 1; m >= 0; --m) q = fma(q, z, row[kR64_P + m]);
-  return exp2_neg(a * row[kR64_RL2]) * q;
+  t = exp2_neg(a * row[kR64_RL2]);
+  return q;
+}
+
+template <int M>
+__device__ __forceinline__ double series_f64(double a, const double* __restrict__ row) {
+  double t;
+  const double q = series_f64_q<M>(a, row, t);
+  return t * q;
 }
 
 // General FP64 pair term: series for dx <= 1, direct difference above.
@@ -111,14 +121,15 @@ __device__ __forceinline__ double phi_general_f64(double a, const double* __rest
 // exp(-x1) = 2^-yh (1 - ln2 yl) keeps its relative error near 1e-7 even when
 // x1 is large.  dx = a c stays below the series threshold, where the sum is
 // well conditioned.
+// The two factors of the term: returns q and sets t = 2^-yh (term = t q).
 template <int M>
-__device__ __forceinline__ float series_f32(float a, const float* __restrict__ row) {
+__device__ __forceinline__ float series_f32_q(float a, const float* __restrict__ row, float& t) {
   const float z = a * row[kR32_C];
   const float rhi = row[kR32_RHI];
   const float yh = a * rhi;
   float yl = __builtin_fmaf(a, rhi, -yh);
   yl = __builtin_fmaf(a, row[kR32_RLO], yl);
-  const float t = __builtin_amdgcn_exp2f(-yh);
+  t = __builtin_amdgcn_exp2f(-yh);
   float q;
   if constexpr (M == 0) {
     q = row[kR32_P0];
@@ -128,7 +139,13 @@ __device__ __forceinline__ float series_f32(float a, const float* __restrict__ r
     for (int m = M - 1; m >= 1; --m) q = __builtin_fmaf(q, z, row[kR32_P1 + m - 1]);
     q = __builtin_fmaf(q, z, row[kR32_P0]);
   }
-  q = __builtin_fmaf(q, yl * (float)(-kLn2), q);
+  return __builtin_fmaf(q, yl * (float)(-kLn2), q);
+}
+
+template <int M>
+__device__ __forceinline__ float series_f32(float a, const float* __restrict__ row) {
+  float t;
+  const float q = series_f32_q<M>(a, row, t);
   return t * q;
 }
 
@@ -143,11 +160,11 @@ __device__ __forceinline__ float series_f32(float a, const float* __restrict__ r
 // coefficient (row field PA_1 holds PA_1 - ln2 P_0 rlo) and one fma with e2.
 // `a` is exact.
 template <int M>
-__device__ __forceinline__ float series_f32a(float a, const RowA& w) {
+__device__ __forceinline__ float series_f32a_q(float a, const RowA& w, float& t) {
   static_assert(M <= kMaxA, "degree too high for the a-form");
   const float yh = a * w.rhi;
   const float e2 = __builtin_fmaf(a, w.rhi, -yh);
-  const float t = __builtin_amdgcn_exp2f(-yh);
+  t = __builtin_amdgcn_exp2f(-yh);
   float q;
   if constexpr (M == 0) {
     q = __builtin_fmaf(w.p0nr, a, w.p0);
@@ -158,7 +175,13 @@ __device__ __forceinline__ float series_f32a(float a, const RowA& w) {
     for (int m = M - 1; m >= 1; --m) q = __builtin_fmaf(q, a, pa[m - 1]);
     q = __builtin_fmaf(q, a, w.p0);
   }
-  q = __builtin_fmaf(w.p0n, e2, q);
+  return __builtin_fmaf(w.p0n, e2, q);
+}
+
+template <int M>
+__device__ __forceinline__ float series_f32a(float a, const RowA& w) {
+  float t;
+  const float q = series_f32a_q<M>(a, w, t);
   return t * q;
 }
 

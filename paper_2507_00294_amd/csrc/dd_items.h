@@ -124,6 +124,17 @@ __device__ __forceinline__ float series_row32(float a, const typename RowSel<M>:
     return series_f32<M>(a, row);
 }
 
+// The term as its two factors (q returned, t set), for sums that must not
+// depend on how the compiler fuses products into additions.
+template <int M>
+__device__ __forceinline__ float series_row32_q(float a, const typename RowSel<M>::type& row,
+                                                float& t) {
+  if constexpr (M <= kMaxA)
+    return series_f32a_q<M>(a, row, t);
+  else
+    return series_f32_q<M>(a, row, t);
+}
+
 // One chunk of R lags n0 .. n0+R-1 against window W (see arr_far32); the R
 // terms of each evaluation point are summed in FP32 by fused multiply-adds
 // (R roundings) and then added to its FP64 accumulator.
@@ -422,18 +433,26 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
         nxt[s] = fetch_row<M>(rows, nn);
         pn[s] = pos[K - nn];
       }
-      float t[R][U];
+      float t[R][U], qv[R][U];
 #pragma unroll
       for (int s = 0; s < U; ++s) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          t[r][s] = series_row32<M>(map_a32<LAT, R>(pc[s], ex, ey, ee, r), cur[s]);
+          qv[r][s] = series_row32_q<M>(map_a32<LAT, R>(pc[s], ex, ey, ee, r), cur[s], t[r][s]);
       }
+      // Groups of four lags in lag order, each summed by an explicit chain
+      // of fused multiply-adds: the arithmetic of a pixel is then the same
+      // for every tile width and unroll depth.
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int q = 0; q < U; q += 4)  // groups of four, whatever the unroll
-          acc[r] += (double)((t[r][q] + t[r][q + 1]) + (t[r][q + 2] + t[r][q + 3]));
+        for (int q = 0; q < U; q += 4) {
+          float g = t[r][q] * qv[r][q];
+          g = __builtin_fmaf(t[r][q + 1], qv[r][q + 1], g);
+          g = __builtin_fmaf(t[r][q + 2], qv[r][q + 2], g);
+          g = __builtin_fmaf(t[r][q + 3], qv[r][q + 3], g);
+          acc[r] += (double)g;
+        }
 #pragma unroll
       for (int s = 0; s < U; ++s) {
         cur[s] = nxt[s];
@@ -460,7 +479,9 @@ __device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const doubl
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const double dx = ex[r] - p.x, dy = ey[r] - p.y;
-      acc[r] += series_f64<M>(fma(dy, dy, dx * dx), row);
+      double t;
+      const double q = series_f64_q<M>(fma(dy, dy, dx * dx), row, t);
+      acc[r] = fma(t, q, acc[r]);  // explicit: the same for every tile width
     }
   }
 }

@@ -549,13 +549,13 @@ struct BatchScratch {
   std::vector<BatchScan> h_scans;
   std::vector<BatchItem> h_items, h_near_items, h_map_items, h_map_near_items, h_tmp;
   std::vector<BatchReduce> h_reds;
-  std::vector<int32_t> h_slots, h_tile_slots;
-  std::vector<ArrItem> h_arr_near, h_arr_far;
+  std::vector<int32_t> h_slots;
   std::vector<uint64_t> h_ka, h_kb;
   hipEvent_t done = nullptr, copied = nullptr;  // kept until the process ends
   bool pending = false, copy_pending = false;
 };
 static thread_local BatchScratch g_batch;
+static thread_local uint64_t g_plan_clock = 0;  // recency of the handles' cached map plans
 
 int64_t item_cost(const BatchItem& a) { return ((int64_t)a.cost_hi << 31) | a.cost_lo; }
 
@@ -621,6 +621,24 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       most = std::max<int64_t>(most, r * scans[k]->desc.nx);
     }
     while (RM > 1 && 64LL * (RM / 2) >= most) RM /= 2;
+    // A small call (the surrogate's fallback) yields too few far items to
+    // fill the chip with 4-pixel tiles; 2-pixel tiles double them.  The tile
+    // width does not change any pixel's sum.  The estimate takes every lag
+    // as far and the chunk length of plan_map.
+    if (RM == 4) {
+      double est = 0;
+      for (int32_t k = 0; k < n; ++k) {
+        const int64_t r = rows < 0 ? scans[k]->desc.ny
+                                   : std::min<int64_t>(rows, scans[k]->desc.ny -
+                                                                 std::min(row0, scans[k]->desc.ny - 1));
+        const int64_t npix = r * scans[k]->desc.nx, V = scans[k]->V;
+        const int64_t units = (npix + 255) / 256;
+        int64_t Kc = tune().map_K;
+        while (Kc > 512 && units * ((V + Kc - 1) / Kc) < 64) Kc /= 2;
+        est += (double)((npix + 255) / 256) * (double)((V + Kc - 1) / Kc);
+      }
+      if (est < 6144) RM = 2;
+    }
   }
   // host tables, kept by the thread between calls (no reallocation per call)
   BatchScratch& W = g_batch;
@@ -666,16 +684,31 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     B.map_rows = rows < 0 ? s->desc.ny : std::min(rows, s->desc.ny - B.map_row0);
     out_off[k] = out_total;
     if (want_arr) {
-      ArrivalPlan AP;
-      std::vector<ArrItem>& an = W.h_arr_near;
-      std::vector<ArrItem>& af = W.h_arr_far;
-      std::vector<int32_t>& ts = W.h_tile_slots;
-      plan_arrival(s, mixed, R, RN, arrival_K(s->V, R, mixed), AP, an, af, ts, count);
-      B.arr_bounds = AP.bounds;
+      dd_scan::BatchArrPlan& C = s->barr;
+      const int K = arrival_K(s->V, R, mixed);
+      if (!(C.ok && C.mixed == mixed && C.R == R && C.RN == RN && C.K == K &&
+            (C.counted || !count))) {
+        ArrivalPlan AP;
+        C.ok = false;
+        plan_arrival(s, mixed, R, RN, K, AP, C.near, C.far, C.tile_slots, count);
+        C.mixed = mixed;
+        C.R = R;
+        C.RN = RN;
+        C.K = K;
+        C.S = AP.S;
+        C.bounds = AP.bounds;
+        C.pairs = AP.near_pairs + AP.far_pairs;
+        C.flops = AP.near_flops + AP.far_flops;
+        C.counted = count;
+        C.ok = true;
+      }
+      const std::vector<ArrItem>& an = C.near;
+      const std::vector<ArrItem>& af = C.far;
+      B.arr_bounds = C.bounds;
       arr_off[k] = partial_total;
-      partial_total += (int64_t)AP.S * s->V;
+      partial_total += (int64_t)C.S * s->V;
       slot_off[k] = (int64_t)all_slots.size();
-      all_slots.insert(all_slots.end(), ts.begin(), ts.end());
+      all_slots.insert(all_slots.end(), C.tile_slots.begin(), C.tile_slots.end());
       const double near_w = mixed ? 6.0 : 3.0;  // relative cost of a near pair
       auto add = [&](std::vector<BatchItem>& dst, const std::vector<ArrItem>& src, int kind,
                      double per_lag) {
@@ -689,32 +722,56 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       add(items, af, kBatchArrFar, 64.0 * R);
       reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref});
       out_total += s->V;
-      pairs += AP.near_pairs + AP.far_pairs;
-      flops += AP.near_flops + AP.far_flops;
+      pairs += C.pairs;
+      flops += C.flops;
     }
     if (want_map) {
       dd_grid g{0.0, B.map_row0 * s->desc.pitch_m, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx,
                 B.map_rows};
       const double t_end = (double)s->V * s->tau_v;
-      MapPlan MP;
-      plan_map(s, &g, &t_end, 1, mixed, RM, tune().map_K, true, MP, false, count);
-      B.map_time = MP.times[0];
+      const int64_t Kmap = tune().map_K;
+      dd_scan::BatchMapPlan* C = nullptr;
+      for (dd_scan::BatchMapPlan& c : s->bmap)
+        if (c.ok && c.mixed == mixed && c.R == RM && c.row0 == B.map_row0 &&
+            c.rows == B.map_rows && c.K == Kmap && (c.counted || !count))
+          C = &c;
+      if (!C) {  // plan, replacing the plan used least recently
+        C = s->bmap[0].used <= s->bmap[1].used ? &s->bmap[0] : &s->bmap[1];
+        MapPlan MP;
+        C->ok = false;
+        plan_map(s, &g, &t_end, 1, mixed, RM, Kmap, true, MP, false, count);
+        C->mixed = mixed;
+        C->R = RM;
+        C->row0 = B.map_row0;
+        C->rows = B.map_rows;
+        C->K = Kmap;
+        C->time = MP.times[0];
+        C->slots = MP.slots;
+        C->npix = MP.npix;
+        C->items.swap(MP.items);
+        C->pairs = MP.pairs;
+        C->flops = MP.flops;
+        C->counted = count;
+        C->ok = true;
+      }
+      C->used = ++g_plan_clock;
+      B.map_time = C->time;
       map_off[k] = partial_total;
-      partial_total += MP.slots * MP.npix;
+      partial_total += C->slots * C->npix;
       const double near_w = mixed ? 6.0 : 3.0;
-      for (const MapItem& m : MP.items) {
-        const int64_t tile_pix = std::min<int64_t>(64 * RM, MP.npix - (int64_t)m.tile * 64 * RM);
+      for (const MapItem& m : C->items) {
+        const int64_t tile_pix = std::min<int64_t>(64 * RM, C->npix - (int64_t)m.tile * 64 * RM);
         const double cost = (double)(m.n_hi - m.n_lo) * tile_pix * (m.near ? near_w : 1.0);
         const int64_t c = (int64_t)cost;
         (m.near ? map_near_items : map_items)
             .push_back(BatchItem{k, m.near ? kBatchMapNear : kBatchMapFar, m.tile, m.n_lo, m.n_hi,
                                  m.slot, (int32_t)(c >> 31), (int32_t)(c & 0x7fffffff)});
       }
-      reds.push_back(BatchReduce{nullptr, nullptr, MP.times[0].n_slots, 0, MP.npix, out_total,
+      reds.push_back(BatchReduce{nullptr, nullptr, C->time.n_slots, 0, C->npix, out_total,
                                  nullptr, s->pref});
-      out_total += MP.npix;
-      pairs += MP.pairs;
-      flops += MP.flops;
+      out_total += C->npix;
+      pairs += C->pairs;
+      flops += C->flops;
     }
   }
   if (W.pending) DD_HIP(hipStreamWaitEvent(st, W.done, 0), "stream wait");

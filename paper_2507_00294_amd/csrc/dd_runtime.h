@@ -105,6 +105,28 @@ struct dd_scan {
   // scan is outside what the surrogate accepts.
   dd::DevBuf sur;
   int sur_state = 0;
+  // Plans of the batched solve, kept on the handle: they depend only on the
+  // scan, the precision and the tile shape (and, for the map, its rows), so
+  // a scan solved again skips the host planning.  Two map plans are kept
+  // (the whole final map and one row subset, as the surrogate's judge uses).
+  struct BatchArrPlan {
+    bool ok = false, mixed = false, counted = false;
+    int R = 0, RN = 0, K = 0, S = 0;
+    dd::DegreeBounds bounds{};
+    std::vector<dd::ArrItem> near, far;
+    std::vector<int32_t> tile_slots;
+    double pairs = 0, flops = 0;
+  } barr;
+  struct BatchMapPlan {
+    bool ok = false, mixed = false, counted = false;
+    int R = 0;
+    int32_t row0 = 0, rows = 0;
+    int64_t K = 0, slots = 0, npix = 0;
+    uint64_t used = 0;
+    dd::MapTime time{};
+    std::vector<dd::MapItem> items;
+    double pairs = 0, flops = 0;
+  } bmap[2];
 
   void release_device() {
     for (dd::DevBuf* b : {&pos32, &pos64, &pos4, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,

@@ -51,7 +51,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int CBM = 256;    // output pixels per block
-constexpr int CLDK = 40;    // LDS row: 32 channels + 8 padding (BF16)
+constexpr int CLDK = 40;    // LDS row of the halo tile: 32 channels + 8 padding (BF16)
+constexpr int CLDB = 40;    // LDS row of the staged weights
 constexpr int HPMAX = 400;  // halo-tile pixels: 6 x 66, 10 x 34, 18 x 18 or 4 x 10 x 10
 
 enum { IN_PLAIN = 0, IN_UPCAT = 1 };
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
   // 64^2, which depend on occupancy) each wave reads them from L2, one tap ahead
   constexpr bool BLDS = BN >= 64;
   __shared__ __attribute__((aligned(16))) __bf16 As[HPMAX][CLDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BLDS ? 9 : 1][BLDS ? BN : 1][CLDK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[BLDS ? 9 : 1][BLDS ? BN : 1][CLDB];
   constexpr int NB = BN / 16;
   constexpr int BPIECES = 9 * BN * 4;  // 16-byte pieces of the chunk's weights
   constexpr int BSLOTS = (BPIECES + 255) / 256;

@@ -76,3 +76,39 @@ def test_batched_configuration_sampled(dd, ora, wl):
         t = np.full(pix.size, spec.n_visits * spec.tau_v)
         assert_close(o[spec.n_visits + pix], ora_s.psi_points(x, y, t), spec, "mixed",
                      f"scan {k} final")
+
+
+DEFAULT_TUNE = {"arch": "gfx950", "arrival_mixed": {"R": 4, "RN": 2, "K": 2048},
+                "arrival_fp64": {"R": 2, "RN": 2, "K": 1024}, "map_mixed": {"R": 4, "K": 4096},
+                "map_fp64": {"R": 1}}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_map_tile_width_leaves_results_unchanged(dd, wl, prec, tmp_path):
+    """A pixel's sum is the same whatever the number of pixels per lane of
+    the map tile (1, 2 or 4): maps of several sizes, by the per-scan call and
+    by the batched call, are equal bit for bit across tile widths."""
+    import json
+
+    specs = wl.batch_scans(5, seed=45, side_lo=30, side_hi=90)
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    key = "map_mixed" if prec == "mixed" else "map_fp64"
+    ref = None
+    try:
+        for R in (4, 2, 1):
+            cfg = json.loads(json.dumps(DEFAULT_TUNE))
+            cfg[key]["R"] = R
+            path = tmp_path / f"tune_{R}.json"
+            path.write_text(json.dumps(cfg))
+            dd.tune_load(str(path))
+            single = [s.final_at_probes(prec).cpu().numpy().ravel() for s in scans]
+            batch = [o.cpu().numpy() for o in dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, prec)]
+            if ref is None:
+                ref = single
+            for a, b, c in zip(ref, single, batch):
+                assert np.array_equal(a, b), R
+                assert np.array_equal(a, c), R
+    finally:
+        path = tmp_path / "tune_default.json"
+        path.write_text(json.dumps(DEFAULT_TUNE))
+        dd.tune_load(str(path))
