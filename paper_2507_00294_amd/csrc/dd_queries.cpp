@@ -419,9 +419,18 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
     const int64_t K = times[m].K;
     const int64_t kf = std::max<int64_t>(groups[tgroup[m]].kf, nlo[m]);
     const int64_t near_hi = std::max<int64_t>(nlo[m], std::min<int64_t>(kf, K + 1));
+    // The near band is one work item per tile; a small map splits it into up
+    // to 64 / units pieces of at least 32 lags (slots 0 .. np-1), by the same
+    // per-map rule as the far chunks.
+    const int64_t near_len = near_hi - nlo[m];
+    const int64_t np = std::max<int64_t>(
+        1, std::min<int64_t>((64 + units - 1) / units, near_len / 32));
+    for (int64_t j = 0; j < np; ++j) {
+      const int64_t a = nlo[m] + near_len * j / np, e = nlo[m] + near_len * (j + 1) / np;
+      for (int64_t t = 0; t < n_tiles; ++t)
+        near.push_back(MapItem{(int32_t)t, m, (int32_t)a, (int32_t)e, (int32_t)j, 1, 0, 0});
+    }
     int c = 0;
-    for (int64_t t = 0; t < n_tiles; ++t)
-      near.push_back(MapItem{(int32_t)t, m, (int32_t)nlo[m], (int32_t)near_hi, 0, 1, 0, 0});
     if (count) {
       P.pairs += (double)npix * (double)(near_hi - nlo[m]);
       P.flops += (double)npix * (double)(near_hi - nlo[m]) *
@@ -430,15 +439,15 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
     for (int64_t lo = std::max(kf, nlo[m]); lo <= K; lo += Kc, ++c) {
       const int64_t hi = std::min<int64_t>(lo + Kc, K + 1);
       for (int64_t t = 0; t < n_tiles; ++t)
-        far.push_back(MapItem{(int32_t)t, m, (int32_t)lo, (int32_t)hi, 1 + c, 0, 0, 0});
+        far.push_back(MapItem{(int32_t)t, m, (int32_t)lo, (int32_t)hi, (int32_t)np + c, 0, 0, 0});
       if (count)
         count_segments(times[m].bounds, lo, hi, mixed,
                        [&](int64_t a, int64_t e) { return (double)npix * (double)(e - a); },
                        P.pairs, P.flops);
     }
     times[m].slot_base = slot_base;
-    times[m].n_slots = 1 + c;
-    slot_base += 1 + c;
+    times[m].n_slots = (int32_t)np + c;
+    slot_base += np + c;
   }
   P.slots = slot_base;
   auto longer = [](const MapItem& a, const MapItem& b) {
