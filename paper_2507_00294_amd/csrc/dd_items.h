@@ -469,6 +469,80 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
   }
 }
 
+// One-pixel tiles, degrees <= 3.  A one-pixel tile has too little work per
+// lag to hide per-lag scalar loads of rows that are read once (as for a
+// single map row), so the rows and probe positions of 64 lags at a time are
+// brought into LDS by one vector load per lane, the next 64 in flight while
+// the current ones are evaluated, and read back by broadcast.  The arithmetic
+// and its order are those of map_far32: groups of four lags from lo, each an
+// explicit FMA chain, then single lags.
+__device__ __forceinline__ float4* map_r1_stage() {
+  __shared__ float4 stage[4 * 2 * 64 * 3];  // wave, buffer, lag, (row lo, row hi, position)
+  return stage;
+}
+
+template <int M, bool LAT>
+__device__ __forceinline__ void map_far32_r1(int lo, int hi, int64_t K, const float4* __restrict__ pos,
+                                             const float* __restrict__ rows, const float (&ex)[1],
+                                             const float (&ey)[1], const float (&ee)[1],
+                                             double (&acc)[1]) {
+  static_assert(M <= kMaxA, "row staging holds the 8 fields of degrees <= 3");
+  if (lo >= hi) return;
+  const int lane = threadIdx.x & 63;
+  float4* const st = map_r1_stage() + (threadIdx.x >> 6) * (2 * 64 * 3);
+  // lane i fetches lag base + i (clamped into [lo, hi))
+  auto fetch = [&](int base, float4& r0, float4& r1, float4& pp) {
+    const int n = min(base + lane, hi - 1);
+    const float4* row = reinterpret_cast<const float4*>(rows + (int64_t)n * kRow32);
+    r0 = row[0];
+    r1 = row[1];
+    pp = pos[K - n];
+  };
+  auto put = [&](int buf, const float4& r0, const float4& r1, const float4& pp) {
+    float4* d = st + (buf * 64 + lane) * 3;
+    d[0] = r0;
+    d[1] = r1;
+    d[2] = pp;
+  };
+  auto term = [&](int buf, int j, float& t) {
+    const float4* d = st + (buf * 64 + j) * 3;
+    const float4 u = d[0], v = d[1], p = d[2];
+    const RowA row{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+    return series_f32a_q<M>(map_a32<LAT, 1>(p, ex, ey, ee, 0), row, t);
+  };
+  float4 r0, r1, pp;
+  fetch(lo, r0, r1, pp);
+  put(0, r0, r1, pp);
+  __builtin_amdgcn_wave_barrier();
+  int buf = 0;
+  for (int base = lo; base < hi; base += 64, buf ^= 1) {
+    const int cnt = min(64, hi - base);
+    const bool more = base + 64 < hi;
+    if (more) fetch(base + 64, r0, r1, pp);
+    int j = 0;
+    for (; j + 4 <= cnt; j += 4) {
+      float t0, t1, t2, t3;
+      const float q0 = term(buf, j, t0), q1 = term(buf, j + 1, t1);
+      const float q2 = term(buf, j + 2, t2), q3 = term(buf, j + 3, t3);
+      float g = t0 * q0;
+      g = __builtin_fmaf(t1, q1, g);
+      g = __builtin_fmaf(t2, q2, g);
+      g = __builtin_fmaf(t3, q3, g);
+      acc[0] += (double)g;
+    }
+    for (; j < cnt; ++j) {
+      float t;
+      const float q = term(buf, j, t);
+      acc[0] += (double)(t * q);
+    }
+    if (more) {
+      __builtin_amdgcn_wave_barrier();
+      put(buf ^ 1, r0, r1, pp);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
 template <int M, int R>
 __device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const double2* __restrict__ pos,
                                           const double* __restrict__ rows, const double (&ex)[R],
@@ -509,10 +583,18 @@ __device__ __forceinline__ void map_far32_seg(int M, int lo, int hi, int64_t K,
                                               const float* __restrict__ rows, const float (&ex)[R],
                                               const float (&ey)[R], const float (&ee)[R],
                                               double (&acc)[R]) {
-  // One pixel per lane: eight lags per step for more loads in flight.  The sum
-  // still runs over groups of four in lag order, so the result does not
-  // depend on the tile width.
+  // One pixel per lane: degrees <= 3 from rows staged in LDS; higher degrees
+  // eight lags per step for more loads in flight.  The sum runs over groups
+  // of four in lag order either way, so the result does not depend on the
+  // tile width.
   if constexpr (R == 1) {
+    switch (M) {
+      case 0: map_far32_r1<0, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); return;
+      case 1: map_far32_r1<1, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); return;
+      case 2: map_far32_r1<2, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); return;
+      case 3: map_far32_r1<3, LAT>(lo, hi, K, pos, rows, ex, ey, ee, acc); return;
+      default: break;
+    }
     const int mid = lo + ((hi - lo) & ~7);
     map_far32_u<R, 8, LAT>(M, lo, mid, K, pos, rows, ex, ey, ee, acc);
     lo = mid;
