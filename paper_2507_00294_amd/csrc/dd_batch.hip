@@ -29,7 +29,7 @@ k_batch_arrival_far(const BatchScan* __restrict__ scans, const BatchItem* __rest
     const BatchScan& S = scans[bi.scan];
     const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
     if (MIXED)
-      do_arrival_far32<R>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
+      do_arrival_far32<R, true>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
     else
       do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds, S.arr_partial);
   }

@@ -17,6 +17,45 @@
 
 namespace dd {
 
+// Load of read-only data through the constant address space: where the
+// address is the same for the whole wave (a lag row, a visit position shared
+// by all pixels) it becomes a scalar load, also when the pointer itself was
+// read from memory (the batched kernels' per-scan descriptors).
+#define DD_CONST_AS __attribute__((address_space(4)))
+__device__ __forceinline__ float ldc(const float* p) {
+  return *reinterpret_cast<const DD_CONST_AS float*>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ double ldc(const double* p) {
+  return *reinterpret_cast<const DD_CONST_AS double*>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ float2 ldc(const float2* p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *reinterpret_cast<const DD_CONST_AS v2*>(reinterpret_cast<uintptr_t>(p));
+  return make_float2(v[0], v[1]);
+}
+__device__ __forceinline__ float4 ldc(const float4* p) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 v = *reinterpret_cast<const DD_CONST_AS v4*>(reinterpret_cast<uintptr_t>(p));
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ double2 ldc(const double2* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *reinterpret_cast<const DD_CONST_AS v2*>(reinterpret_cast<uintptr_t>(p));
+  return make_double2(v[0], v[1]);
+}
+#undef DD_CONST_AS
+
+// Per-lane load of the first three fields of a float4 known to be in global
+// memory (a plain vector load, not a flat one, also through a pointer read
+// from memory); the fourth field is returned as 0.
+__device__ __forceinline__ float4 ldg3(const float4* p) {
+  typedef float v3 __attribute__((ext_vector_type(3)));
+  const v3 v =
+      *reinterpret_cast<const __attribute__((address_space(1))) v3*>(reinterpret_cast<uintptr_t>(p));
+  return make_float4(v[0], v[1], v[2], 0.0f);
+}
+
+
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 constexpr double kEulerGamma = 0.5772156649015329;
@@ -185,9 +224,18 @@ __device__ __forceinline__ float series_f32a(float a, const RowA& w) {
   return t * q;
 }
 
+// The 8 bulk fields of an FP32 row; CAS: through the constant address space
+// (scalar loads also where the table pointer was read from memory).
+template <bool CAS>
 __device__ __forceinline__ RowA load_rowa(const float* __restrict__ row) {
-  const float4 u = *(const float4*)row;
-  const float4 v = *(const float4*)(row + 4);
+  float4 u, v;
+  if constexpr (CAS) {
+    u = ldc(reinterpret_cast<const float4*>(row));
+    v = ldc(reinterpret_cast<const float4*>(row + 4));
+  } else {
+    u = *(const float4*)row;
+    v = *(const float4*)(row + 4);
+  }
   return RowA{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 }
 

@@ -107,11 +107,11 @@ struct RowSel {
   using type = typename std::conditional<(M <= kMaxA), RowA, const float*>::type;
 };
 
-template <int M>
+template <int M, bool CAS = true>
 __device__ __forceinline__ typename RowSel<M>::type fetch_row(const float* __restrict__ rows,
                                                               int64_t n) {
   if constexpr (M <= kMaxA)
-    return load_rowa(rows + n * kRow32);
+    return load_rowa<CAS>(rows + n * kRow32);
   else
     return rows + n * kRow32;
 }
@@ -160,7 +160,17 @@ __device__ __forceinline__ void arr_chunk32(int n0, int64_t jl, const float4 (&W
   for (int r = 0; r < R; ++r) acc[r] += (double)part[r];
 }
 
-template <int M, int R, bool EDGE>
+// A visit position of the arrival window (per lane); CAS: through the global
+// address space, for pointers read from memory.
+template <bool CAS>
+__device__ __forceinline__ float4 ldpos(const float4* p) {
+  if constexpr (CAS)
+    return ldg3(p);
+  else
+    return *p;
+}
+
+template <int M, int R, bool EDGE, bool CAS>
 __device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restrict__ pos, int64_t jl,
                                           const float (&ex)[R], const float (&ey)[R],
                                           const float (&ee)[R], const float* __restrict__ rows,
@@ -170,28 +180,28 @@ __device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restri
   // moves: A covers the chunk at n0, B the chunk at n0 + R.
   float4 A[2 * R - 1], B[2 * R - 1];
 #pragma unroll
-  for (int q = 0; q < 2 * R - 1; ++q) A[q] = pos[jl - lo - (R - 1) + q];
+  for (int q = 0; q < 2 * R - 1; ++q) A[q] = ldpos<CAS>(pos + (jl - lo - (R - 1) + q));
   Row cur[R];
 #pragma unroll
-  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, lo + s);
+  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS>(rows, lo + s);
   int n0 = lo;
   for (; n0 + 2 * R <= hi; n0 += 2 * R) {
     Row nxt[R];
 #pragma unroll
-    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M>(rows, n0 + R + s);
+    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M, CAS>(rows, n0 + R + s);
 #pragma unroll
     for (int q = R; q < 2 * R - 1; ++q) B[q] = A[q - R];
     const int64_t b1 = jl - (n0 + R) - (R - 1);
 #pragma unroll
-    for (int q = 0; q < R; ++q) B[q] = pos[b1 + q];
+    for (int q = 0; q < R; ++q) B[q] = ldpos<CAS>(pos + (b1 + q));
     arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);
 #pragma unroll
-    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M>(rows, min(n0 + 2 * R + s, hi - 1));
+    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS>(rows, min(n0 + 2 * R + s, hi - 1));
 #pragma unroll
     for (int q = R; q < 2 * R - 1; ++q) A[q] = B[q - R];
     const int64_t b2 = jl - (n0 + 2 * R) - (R - 1);
 #pragma unroll
-    for (int q = 0; q < R; ++q) A[q] = pos[b2 + q];
+    for (int q = 0; q < R; ++q) A[q] = ldpos<CAS>(pos + (b2 + q));
     arr_chunk32<M, R, EDGE>(n0 + R, jl, B, ex, ey, ee, nxt, acc);
   }
   if (n0 < hi) arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);  // one chunk left
@@ -227,19 +237,19 @@ __device__ __forceinline__ void arr_far64(int lo, int hi, const double2* __restr
 }
 
 // Degree dispatch for one segment (uniform branch).
-template <int R, bool EDGE>
+template <int R, bool EDGE, bool CAS>
 __device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float4* __restrict__ pos,
                                               int64_t jl, const float (&ex)[R], const float (&ey)[R],
                                               const float (&ee)[R], const float* __restrict__ rows,
                                               double (&acc)[R]) {
   switch (M) {
-    case 0: arr_far32<0, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 1: arr_far32<1, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 2: arr_far32<2, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 3: arr_far32<3, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 4: arr_far32<4, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    case 5: arr_far32<5, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
-    default: arr_far32<6, R, EDGE>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 0: arr_far32<0, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 1: arr_far32<1, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 2: arr_far32<2, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 3: arr_far32<3, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 4: arr_far32<4, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    case 5: arr_far32<5, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    default: arr_far32<6, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
   }
 }
 
@@ -266,7 +276,7 @@ __device__ __forceinline__ void seg_range(const DegreeBounds& b, int M, int n_lo
 }
 
 // One wavefront processes one arrival work item (far region).
-template <int R>
+template <int R, bool CAS>
 __device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const float4* __restrict__ pos,
                                                  const float* __restrict__ rows, int64_t V,
                                                  const DegreeBounds& bnd,
@@ -289,9 +299,9 @@ __device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const floa
     seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
     if (lo >= hi) continue;
     if (edge)
-      arr_far32_seg<R, true>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
+      arr_far32_seg<R, true, CAS>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
     else
-      arr_far32_seg<R, false>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
+      arr_far32_seg<R, false, CAS>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
   }
   double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
 #pragma unroll
@@ -360,9 +370,9 @@ __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void*
           const float2 p = pos[i];
           const float dx = ex[r] - p.x, dy = ey[r] - p.y;
           const float a = __builtin_fmaf(dy, dy, dx * dx);
-          if (a * r32[kR32_C] <= kThr32)
+          if (a * ldc(r32 + kR32_C) <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else if (a * r32[kR32_RHI] <= kCull32Log2)
+          else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2)
             acc[r] += phi_general_f64((double)a, r64);
         }
       }
@@ -422,7 +432,7 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
 #pragma unroll
     for (int s = 0; s < U; ++s) {
       cur[s] = fetch_row<M>(rows, n + s);
-      pc[s] = pos[K - (n + s)];
+      pc[s] = ldc(pos + (K - (n + s)));
     }
     for (; n + U <= hi; n += U) {
       Row nxt[U];
@@ -431,7 +441,7 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
       for (int s = 0; s < U; ++s) {
         const int nn = min(n + U + s, hi - 1);
         nxt[s] = fetch_row<M>(rows, nn);
-        pn[s] = pos[K - nn];
+        pn[s] = ldc(pos + (K - nn));
       }
       float t[R][U], qv[R][U];
 #pragma unroll
@@ -461,7 +471,7 @@ __device__ __forceinline__ void map_far32(int lo, int hi, int64_t K, const float
     }
   }
   for (; n < hi; ++n) {
-    const float4 p = pos[K - n];
+    const float4 p = ldc(pos + (K - n));
     const Row row = fetch_row<M>(rows, n);
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -548,7 +558,7 @@ __device__ __forceinline__ void map_far64(int lo, int hi, int64_t K, const doubl
                                           const double* __restrict__ rows, const double (&ex)[R],
                                           const double (&ey)[R], double (&acc)[R]) {
   for (int n = lo; n < hi; ++n) {
-    const double2 p = pos[K - n];
+    const double2 p = ldc(pos + (K - n));
     const double* row = rows + (int64_t)n * kRow64;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -650,16 +660,16 @@ __device__ __forceinline__ void do_map(const MapItem& item, const MapTime& tm,
     }
     if (item.near) {
       for (int n = item.n_lo; n < item.n_hi; ++n) {
-        const float2 p = pos[tm.K - n];
+        const float2 p = ldc(pos + (tm.K - n));
         const float* r32 = r32b + (int64_t)n * kRow32;
         const double* r64 = r64b + (int64_t)n * kRow64;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const float dx = ex[r] - p.x, dy = ey[r] - p.y;
           const float a = __builtin_fmaf(dy, dy, dx * dx);
-          if (a * r32[kR32_C] <= kThr32)
+          if (a * ldc(r32 + kR32_C) <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else if (a * r32[kR32_RHI] <= kCull32Log2)
+          else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2)
             acc[r] += phi_general_f64((double)a, r64);
         }
       }
@@ -678,7 +688,7 @@ __device__ __forceinline__ void do_map(const MapItem& item, const MapTime& tm,
     const double2* pos = (const double2*)pos_v;
     if (item.near) {
       for (int n = item.n_lo; n < item.n_hi; ++n) {
-        const double2 p = pos[tm.K - n];
+        const double2 p = ldc(pos + (tm.K - n));
         const double* r64 = r64b + (int64_t)n * kRow64;
 #pragma unroll
         for (int r = 0; r < R; ++r) {

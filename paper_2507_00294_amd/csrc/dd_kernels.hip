@@ -46,7 +46,7 @@ k_arrival_far32(const float4* __restrict__ pos,
                                                        double* __restrict__ partial) {
   const int it = blockIdx.x * 4 + wave_id();
   if (it >= n_items) return;
-  do_arrival_far32<R>(items[it], pos, rows, V, bnd, partial);
+  do_arrival_far32<R, false>(items[it], pos, rows, V, bnd, partial);
 }
 
 template <int R>
