@@ -631,9 +631,11 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     }
     while (RM > 1 && 64LL * (RM / 2) >= most) RM /= 2;
     // A small call (the surrogate's fallback) yields too few far items to
-    // fill the chip with 4-pixel tiles; 2-pixel tiles double them.  The tile
-    // width does not change any pixel's sum.  The estimate takes every lag
-    // as far and the chunk length of plan_map.
+    // fill the chip with 4-pixel tiles: below ~24k items (about 100 maps of
+    // 64x64) 2-pixel tiles, below ~6k 1-pixel tiles (rows staged in LDS) are
+    // faster (measured on 64x64 final maps).  The tile width does not change
+    // any pixel's sum.  The estimate takes every lag as far and the chunk
+    // length of plan_map.
     if (RM == 4) {
       double est = 0;
       for (int32_t k = 0; k < n; ++k) {
@@ -646,7 +648,10 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
         while (Kc > 512 && units * ((V + Kc - 1) / Kc) < 64) Kc /= 2;
         est += (double)((npix + 255) / 256) * (double)((V + Kc - 1) / Kc);
       }
-      if (est < 6144) RM = 2;
+      if (est < 6144)
+        RM = 1;
+      else if (est < 24576)
+        RM = 2;
     }
   }
   // host tables, kept by the thread between calls (no reallocation per call)
