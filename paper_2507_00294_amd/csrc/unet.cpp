@@ -72,6 +72,9 @@ struct dd_unet {
   // exact judge while the network runs on the caller's stream
   hipStream_t judge_stream = nullptr;
   hipEvent_t judge_done = nullptr;
+  // predict's buffers (input chunk, own-visit term, per-scan pointers and
+  // prefactors, judge rows, spot errors), kept between calls
+  DevBuf px, pown, pfeat, pout, ppref, pspot, prel;
 };
 
 namespace {
@@ -457,7 +460,8 @@ void dd_unet_destroy(dd_unet* u) {
   for (DevBuf* b : {&u->w, &u->wf, &u->wd, &u->g, &u->m, &u->v, &u->col0, &u->p1, &u->p2, &u->p3,
                     &u->y, &u->col, &u->dA0, &u->dA1, &u->dZ, &u->dZb,
                     &u->ds1, &u->ds2, &u->ds3, &u->part, &u->loss_map, &u->norm_part,
-                    &u->scale_norm})
+                    &u->scale_norm, &u->px, &u->pown, &u->pfeat, &u->pout, &u->ppref, &u->pspot,
+                    &u->prel})
     b->release();
   for (Conv& c : u->L) {
     c.Z.release();
@@ -629,7 +633,8 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
     (ok ? ok_idx : fb_idx).push_back(k);
   }
   const size_t nok = ok_idx.size();
-  DevBuf x, own, d_feat, d_out, d_pref, spot, rel;
+  DevBuf &x = u->px, &own = u->pown, &d_feat = u->pfeat, &d_out = u->pout, &d_pref = u->ppref,
+         &spot = u->pspot, &rel = u->prel;
   if (nok) {
     std::vector<const float*> feat(nok);
     std::vector<double*> outs(nok);
