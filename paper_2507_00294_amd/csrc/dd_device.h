@@ -20,7 +20,11 @@ namespace dd {
 // Load of read-only data through the constant address space: where the
 // address is the same for the whole wave (a lag row, a visit position shared
 // by all pixels) it becomes a scalar load, also when the pointer itself was
-// read from memory (the batched kernels' per-scan descriptors).
+// read from memory (the batched kernels' per-scan descriptors).  Only for
+// device-memory tables that no kernel writes while the caller runs: a pointer
+// to a thread's private array or to LDS is not a valid constant address, so
+// helpers that may receive such rows (phi_general_f64, series_f64_q,
+// series_f32_q, as k_pair_terms calls them) read through plain pointers.
 #define DD_CONST_AS __attribute__((address_space(4)))
 __device__ __forceinline__ float ldc(const float* p) {
   return *reinterpret_cast<const DD_CONST_AS float*>(reinterpret_cast<uintptr_t>(p));
