@@ -181,7 +181,9 @@ struct In {
   const float* x0 = nullptr;
 };
 
-dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st) {
+// pool: where the 2x2 average of the activation goes (layers 1, 3, 5), or NULL
+dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st,
+                   __bf16* pool = nullptr) {
   Conv& c = u.L[l];
   const __bf16* wt = u.wf.as<__bf16>() + c.wf_off;
   const float* bias = u.w.as<float>() + c.b_off;
@@ -197,7 +199,8 @@ dd_status conv_fwd(dd_unet& u, size_t l, In in, bool train, hipStream_t st) {
                                train ? c.A.as<__bf16>() : nullptr, z, u.y.as<float>(), st),
            "conv");
   } else {
-    UN_HIP(nn::conv3_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<__bf16>(), z, c.co, st), "conv");
+    UN_HIP(nn::conv3_silu(in.x, u.B, c.lg, c.ci, wt, bias, c.A.as<__bf16>(), z, c.co, pool, st),
+           "conv");
   }
   return DD_OK;
 }
@@ -263,19 +266,16 @@ std::vector<In> layer_inputs(dd_unet& u, const float* x) {
 
 dd_status forward(dd_unet& u, const float* x, bool train, hipStream_t st) {
   auto& L = u.L;
-  const int B = u.B;
   dd_status rc;
   u.last_train = train;
   const std::vector<In> in = layer_inputs(u, x);
   STEP(conv_fwd(u, 0, in[0], train, st));
-  STEP(conv_fwd(u, 1, in[1], train, st));
-  UN_HIP(nn::pool_fwd(L[1].A.as<__bf16>(), B, 64, 64, 32, u.p1.as<__bf16>(), st), "pool");
+  // the 2x2 poolings run in the epilogues of layers 1, 3 and 5
+  STEP(conv_fwd(u, 1, in[1], train, st, u.p1.as<__bf16>()));
   STEP(conv_fwd(u, 2, in[2], train, st));
-  STEP(conv_fwd(u, 3, in[3], train, st));
-  UN_HIP(nn::pool_fwd(L[3].A.as<__bf16>(), B, 32, 32, 64, u.p2.as<__bf16>(), st), "pool");
+  STEP(conv_fwd(u, 3, in[3], train, st, u.p2.as<__bf16>()));
   STEP(conv_fwd(u, 4, in[4], train, st));
-  STEP(conv_fwd(u, 5, in[5], train, st));
-  UN_HIP(nn::pool_fwd(L[5].A.as<__bf16>(), B, 16, 16, 128, u.p3.as<__bf16>(), st), "pool");
+  STEP(conv_fwd(u, 5, in[5], train, st, u.p3.as<__bf16>()));
   for (size_t l = 6; l < L.size(); ++l) STEP(conv_fwd(u, l, in[l], train, st));
   return DD_OK;
 }

@@ -77,6 +77,7 @@ struct ConvArgs {
   const float* hw;   // EPI_HEAD: 32 weights, then the bias
   float* y;          // EPI_HEAD: [M]
   int N;
+  __bf16* pool;      // EPI_SILU: 2x2 average of the activation [M / 4][N], or NULL
 };
 
 // Epilogue of the block's accumulators.  The MFMAs take the weights as their
@@ -88,7 +89,16 @@ __device__ __forceinline__ float silu(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
-template <int NB, int EPI>
+// Tile pixel of fragment row group a of a wave: 64 consecutive pixels per
+// wave, or, with COLS (64-pixel-wide images), a 16-pixel column strip of each
+// of the tile's 4 rows (row a), so that the rows of a 2x2 pooling window sit
+// in the same lane.
+template <bool COLS>
+__device__ __forceinline__ int tile_pixel(int wave, int a, int lane) {
+  return COLS ? a * 64 + wave * 16 + (lane & 15) : wave * 64 + a * 16 + (lane & 15);
+}
+
+template <int NB, int EPI, bool COLS = false, int LG = 0>
 __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB], int m0, int n0,
                                          int wave, int lane) {
   const int c4 = 4 * (lane >> 4);
@@ -104,7 +114,7 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
     const float hb = p.hw[32];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int row = m0 + wave * 64 + a * 16 + (lane & 15);
+      const int row = m0 + tile_pixel<COLS>(wave, a, lane);
       float s = 0.f;
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -132,9 +142,52 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
   for (int b = 0; b < NB; ++b)
     bs[b] = EPI == EPI_SILU ? *reinterpret_cast<const f32x4*>(p.bias + n0 + 16 * b + c4)
                             : f32x4{0.f, 0.f, 0.f, 0.f};
+  if (EPI == EPI_SILU && LG >= 4 && p.pool) {
+    // Activation and its 2x2 average.  Vertical window partners are
+    // fragment groups a and a ^ VA of the same lane, horizontal ones lanes
+    // l and l ^ 1; the sum runs in the order of the separate pooling kernel
+    // (top-left, top-right, bottom-left, bottom-right) over the BF16 values.
+    // Every M here is a multiple of the 256-pixel tile.
+    static_assert(LG != 6 || COLS, "64-wide tiles pool from column strips");
+    constexpr int VA = LG == 5 ? 2 : 1;
+    constexpr int W = 1 << LG, Wo = W / 2;
+    bf16x4 act[4][NB];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int row = m0 + tile_pixel<COLS>(wave, a, lane);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int64_t o = (int64_t)row * p.N + n0 + 16 * b + c4;
+        const f32x4 z = acc[a][b] + bs[b];
+        if (p.z) *reinterpret_cast<f32x4*>(p.z + o) = z;
+        act[a][b] = to_bf16x4(f32x4{silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3])});
+        *reinterpret_cast<bf16x4*>(static_cast<__bf16*>(p.out) + o) = act[a][b];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a & VA) continue;
+      const int row = m0 + tile_pixel<COLS>(wave, a, lane);  // even image row and column
+      const int img = row >> (2 * LG), yy = (row >> LG) & (W - 1), xx = row & (W - 1);
+      const int64_t po = ((int64_t)img * Wo + (yy >> 1)) * Wo + (xx >> 1);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        f32x4 sum;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float tl = (float)act[a][b][v], bl = (float)act[a ^ VA][b][v];
+          const float tr = __shfl_xor(tl, 1), br = __shfl_xor(bl, 1);
+          sum[v] = 0.25f * (((tl + tr) + bl) + br);
+        }
+        if ((lane & 1) == 0)
+          *reinterpret_cast<bf16x4*>(p.pool + po * p.N + n0 + 16 * b + c4) = to_bf16x4(sum);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int row = m0 + wave * 64 + a * 16 + (lane & 15);
+    const int row = m0 + tile_pixel<COLS>(wave, a, lane);
     if (row >= p.M) continue;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -197,10 +250,11 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
     src[i] = s;
   }
   // halo-tile pixel of each of this lane's 4 A-fragment rows at tap (0, 0)
+  constexpr bool COLS = LG == 6;
   int hbase[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int o = wave * 64 + a * 16 + (lane & 15);
+    const int o = tile_pixel<COLS>(wave, a, lane);
     const int g = o >> lgRW, r = (o >> lg) & (R - 1), x = o & (W - 1);
     hbase[a] = g * slice + r * HW2 + x;
   }
@@ -316,7 +370,7 @@ __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
     }
     __syncthreads();
   }
-  epilogue<NB, EPI>(p, acc, m0, n0, wave, lane);
+  epilogue<NB, EPI, COLS, LG>(p, acc, m0, n0, wave, lane);
 }
 
 // First layer: CI (< 32) input channels, K = 9 CI <= 64 padded to 64; N = 32.
@@ -432,9 +486,9 @@ bool halo_ok(int M, int lg, int ci, int N) {
 }  // namespace
 
 hipError_t conv3_silu(const __bf16* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
-                      __bf16* act, float* z, int co, hipStream_t st) {
-  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, co};
-  if (!halo_ok(p.M, lg, ci, co) || !act) return hipErrorInvalidValue;
+                      __bf16* act, float* z, int co, __bf16* pool, hipStream_t st) {
+  ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, co, pool};
+  if (!halo_ok(p.M, lg, ci, co) || !act || (pool && lg < 4)) return hipErrorInvalidValue;
   return launch_halo<__bf16, IN_PLAIN, EPI_SILU>(p, st);
 }
 

@@ -22,7 +22,10 @@ constexpr int kNormBlocks = 256;  // partial sums of the gradient norm
 
 // 3x3 convolutions (unet_conv.hip) of x [B][side][side][ci], side = 2^lg in
 // 8..64, weights wt [co][9 ci] (k = tap ci + c):
-//   conv3_silu:        z = conv + bias, act = SiLU(z) (z stored when non-NULL);
+//   conv3_silu:        z = conv + bias, act = SiLU(z) (z stored when non-NULL;
+//                      with pool non-NULL, side >= 16, also the 2x2 average of
+//                      act, [B][side/2][side/2][co]: the four BF16 values in row order, x 0.25,
+//                      rounded to BF16);
 //   conv3_upcat_silu:  the same on the channel concatenation [nearest-2x
 //                      upsampling of coarse [B][side/2][side/2][c1], skip
 //                      [B][side][side][c2]];
@@ -32,7 +35,7 @@ constexpr int kNormBlocks = 256;  // partial sums of the gradient norm
 //   conv3_first_silu:  ci < 32 with 9 ci <= 64, co = 32, weights [32][64].
 // ci, c1 and co must be multiples of 32 except in conv3_first_silu.
 hipError_t conv3_silu(const __bf16* x, int B, int lg, int ci, const __bf16* wt, const float* bias,
-                      __bf16* act, float* z, int co, hipStream_t st);
+                      __bf16* act, float* z, int co, __bf16* pool, hipStream_t st);
 hipError_t conv3_upcat_silu(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B,
                             int lg, const __bf16* wt, const float* bias, __bf16* act, float* z,
                             int co, hipStream_t st);
@@ -60,7 +63,6 @@ hipError_t im2col_upcat(const __bf16* coarse, int c1, const __bf16* skip, int c2
 hipError_t silu_bwd(const float* dA, const float* Z, int64_t n, float* dZ, __bf16* dZb,
                     hipStream_t st);
 hipError_t colsum_add(const float* dZ, int M, int N, float* db, hipStream_t st);
-hipError_t pool_fwd(const __bf16* x, int B, int H, int W, int C, __bf16* y, hipStream_t st);
 hipError_t pool_bwd_add(const float* dy, int B, int H, int W, int C, float* dx, hipStream_t st);
 hipError_t up_concat_bwd(const float* dout, int B, int h, int w, int C1, int C2, float* dx,
                          float* dskip, hipStream_t st);

@@ -1,7 +1,7 @@
 // unet_kernels.hip -- kernels of the learned surrogate other than the
 // implicit-GEMM convolution (unet_conv.hip): the weight-gradient GEMM on BF16
 // MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulation) over im2col columns, the
-// first layer's im2col, SiLU backward, bias gradients, 2x2 average pooling,
+// first layer's im2col, SiLU backward, bias gradients, the adjoint of the 2x2 pooling,
 // nearest 2x upsampling with the skip concatenation, the FP32 1x1 head, the
 // relative-L2 loss, gradient-norm clipping, Adam with FP32 master weights and
 // the rearrangement of the weights into the convolution's BF16 layouts, the
@@ -208,23 +208,8 @@ __global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dZ, in
   if (threadIdx.x == 0) db[j] = red[0];
 }
 
-// 2x2 average pooling (NHWC, BF16 activations, summed in FP32) and its
-// adjoint on FP32 gradients (which accumulates).
-__global__ void __launch_bounds__(256) k_pool_fwd(const __bf16* __restrict__ x, int B, int H, int W,
-                                                  int C, __bf16* __restrict__ y) {
-  const int Ho = H / 2, Wo = W / 2;
-  const int64_t total = (int64_t)B * Ho * Wo * C;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % C);
-    const int64_t p = e / C;
-    const int xo = (int)(p % Wo), yo = (int)((p / Wo) % Ho), n = (int)(p / ((int64_t)Wo * Ho));
-    const int64_t base = (((int64_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
-    y[e] = (__bf16)(0.25f * ((float)x[base] + (float)x[base + C] + (float)x[base + (int64_t)W * C] +
-                             (float)x[base + (int64_t)W * C + C]));
-  }
-}
-
+// Adjoint of the 2x2 average pooling (which runs in the convolution
+// epilogue) on FP32 gradients (accumulates).
 __global__ void __launch_bounds__(256) k_pool_bwd(const float* __restrict__ dy, int B, int H, int W,
                                                   int C, float* __restrict__ dx) {
   const int64_t total = (int64_t)B * H * W * C;
@@ -610,12 +595,6 @@ hipError_t silu_bwd(const float* dA, const float* Z, int64_t n, float* dZ, __bf1
 
 hipError_t colsum_add(const float* dZ, int M, int N, float* db, hipStream_t st) {
   hipLaunchKernelGGL(k_colsum, dim3(N), dim3(256), 0, st, dZ, M, N, db);
-  return hipGetLastError();
-}
-
-hipError_t pool_fwd(const __bf16* x, int B, int H, int W, int C, __bf16* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((int64_t)B * H * W * C / 4)), dim3(256), 0, st, x,
-                     B, H, W, C, y);
   return hipGetLastError();
 }
 
