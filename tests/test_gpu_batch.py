@@ -112,3 +112,28 @@ def test_map_tile_width_leaves_results_unchanged(dd, wl, prec, tmp_path):
         path = tmp_path / "tune_default.json"
         path.write_text(json.dumps(DEFAULT_TUNE))
         dd.tune_load(str(path))
+
+
+def test_batch_output_buffers(dd, wl):
+    """The three ways of handing over outputs give the same values: one view
+    per scan of a call-allocated buffer, one tensor per scan, and a single
+    caller buffer holding every scan's result back to back."""
+    import torch
+
+    specs = wl.batch_scans(5, seed=47, side_lo=8, side_hi=30)
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    q = dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES
+    views = dd.batch_solve(scans, q, "mixed")
+    sizes = [s.num_visits + s.nx * s.ny for s in scans]
+    assert [v.numel() for v in views] == sizes
+    own = [torch.empty(n, dtype=torch.float64, device="cuda") for n in sizes]
+    assert dd.batch_solve(scans, q, "mixed", outs=own) is own
+    flat = torch.empty(sum(sizes), dtype=torch.float64, device="cuda")
+    assert dd.batch_solve(scans, q, "mixed", out=flat) is flat
+    off = 0
+    for v, o, n in zip(views, own, sizes):
+        assert torch.equal(v, o)
+        assert torch.equal(v, flat[off:off + n])
+        off += n
+    with pytest.raises(ValueError):
+        dd.batch_solve(scans, q, "mixed", out=flat[:-1])
