@@ -237,7 +237,7 @@ double row_dx_bound(double lam, double a_max, double cull, double kappa, double 
 
 int degree_needed(double dx, bool mixed) {
   // smallest M with e^{2 dx} dx^{M+1} / (M+1)! below the precision's target
-  const double tol = mixed ? 2e-8 : 5e-15;
+  const double tol = mixed ? 2e-8 : kTrunc64;
   const int mmax = mixed ? kM32 : kM64;
   if (dx <= 0) return 0;
   double term = std::exp(2 * dx);
@@ -291,7 +291,7 @@ static const double* dx_cover(bool mixed) {
       }
     }
   };
-  static const Table t32(2e-8), t64(5e-15);
+  static const Table t32(2e-8), t64(kTrunc64);
   return mixed ? t32.v : t64.v;
 }
 

@@ -45,6 +45,10 @@ struct RowA {
 // series above is used; the truncation bound after P_M is
 // e^{2 dx} dx^{M+1} / (M+1)!  relative to the term.
 constexpr double kThr64 = 1.0;    // FP64: M = 17 covers dx <= 1 to 5e-15
+// Truncation target per term of the FP64 far-region series (degree chosen
+// per lag segment): 1e-13, three orders below the FP64 path's 1e-10 bound on
+// a sum of positive terms.
+constexpr double kTrunc64 = 1e-13;
 constexpr float kThr32 = 0.25f;   // FP32: M = 6 covers dx <= 0.25 to 2e-8
 constexpr int kMNear32 = 6;
 // Mixed path: terms with x1 = a/b1 > 100 (below e^-100 each, fewer than
