@@ -29,7 +29,9 @@
  *  - Precision DD_FP64 evaluates every term in double precision;
  *    DD_MIXED evaluates the bulk of the E1 differences in single precision
  *    (with exact lattice distances, exact dwell increments and a split
- *    exponent) and accumulates in double precision.
+ *    exponent) and accumulates in double precision.  A map grid whose pixels
+ *    are not on a dyadic lattice shared with the probes (multiples of 2^-q
+ *    pitches, q <= 8) is evaluated in double precision under DD_MIXED too.
  *  - Lengths are metres, times seconds, D m^2/s, Q0 u/s.
  */
 #ifndef DD_H
@@ -109,6 +111,20 @@ dd_status dd_scan_visits(const dd_scan *s, int32_t *out_host);
  * is taken to be on it.                                                   */
 dd_status dd_damage_map(dd_scan *s, const dd_grid *g, const double *t_s, int32_t n_t,
                         dd_precision p, double *out, int32_t out_on_device, void *hip_stream);
+
+/* Time-sampled simulation, the paper's workload of maps every time step dt
+ * on a sampling grid (Sec. III, the cost model of Eq. 7; Fig. 1 shows maps
+ * of it): psi on grid g at t_k = t0_s + k dt_s, k = 0 .. n_t-1, out
+ * [n_t][h][w] row-major.  The same values as dd_damage_map with that list of
+ * times (up to the order of the per-pixel sums); the library evaluates the
+ * times in chunks so that its scratch stays bounded whatever n_t is.
+ * t0_s: finite, >= 0; dt_s: finite, > 0; n_t >= 1; the last time finite.
+ * Host outputs (out_on_device = 0) are copied chunk by chunk; the call then
+ * returns when all of them are in out.
+ * Errors: DD_EINVAL (bad times, grid, precision or NULL), DD_ENOMEM,
+ * DD_EDEVICE.                                                             */
+dd_status dd_damage_sweep(dd_scan *s, const dd_grid *g, double t0_s, double dt_s, int32_t n_t,
+                          dd_precision p, double *out, int32_t out_on_device, void *hip_stream);
 
 /* psi at every probe visit at the moment that visit starts: out[j] =
  * psi(r_j, t_j), summed over visits i < j (Eq. 6 with j the visit being

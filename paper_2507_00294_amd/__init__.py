@@ -28,7 +28,8 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 # Every symbol the header declares (checked by the tests).
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
-    "dd_damage_map", "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms",
+    "dd_damage_map", "dd_damage_sweep", "dd_damage_at_probe_arrival", "dd_batch_solve",
+    "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
     "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
@@ -82,6 +83,7 @@ def load_library():
     lib.dd_scan_num_visits.restype = i64
     lib.dd_scan_visits.argtypes = [vp, P(i32)]
     lib.dd_damage_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
+    lib.dd_damage_sweep.argtypes = [vp, P(Grid), dbl, dbl, i32, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_at_probe_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_batch_solve.argtypes = [P(vp), i32, ctypes.c_uint32, ctypes.c_int, P(vp), i32, vp]
     lib.dd_pair_terms.argtypes = [dbl, dbl, i64, vp, vp, ctypes.c_int, vp, vp]
@@ -106,7 +108,7 @@ def load_library():
     lib.dd_surrogate_targets.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_unet_predict.argtypes = [vp, P(vp), i32, dbl, ctypes.c_int, vp, P(i32), vp]
     lib.dd_last_error.restype = ctypes.c_char_p
-    for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map",
+    for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
@@ -223,6 +225,22 @@ class Scan:
         _check(load_library().dd_damage_map(
             self._h, ctypes.byref(g), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
             _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+
+    def damage_sweep(self, x0_m: float, y0_m: float, dx_m: float, dy_m: float, w: int, h: int,
+                     t0_s: float, dt_s: float, n_t: int, precision: str = "fp64", out=None,
+                     stream=None):
+        """Maps at t0 + k dt, k < n_t (``dd_damage_sweep``) as a float64 CUDA
+        tensor [n_t, h, w]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((n_t, h, w), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == n_t * w * h
+        g = Grid(x0_m, y0_m, dx_m, dy_m, w, h)
+        _check(load_library().dd_damage_sweep(self._h, ctypes.byref(g), t0_s, dt_s, n_t,
+                                              _prec(precision), ctypes.c_void_p(out.data_ptr()),
+                                              1, _stream(stream)))
         return out
 
     def final_at_probes(self, precision: str = "fp64", stream=None):

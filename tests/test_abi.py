@@ -103,6 +103,17 @@ def test_null_and_bad_arguments(dd):
                              None) == dd.DD_EINVAL
     assert lib.dd_pair_terms(-1.0, 0.5, 1, None, None, 0, None, None) == dd.DD_EINVAL
     assert b"kappa" in lib.dd_last_error()
+    # the time sweep rejects bad times before touching a device
+    o = ctypes.c_void_p(16)
+    for t0, dt, n_t in ((-1.0, 1e-6, 4), (0.0, 0.0, 4), (0.0, -1e-6, 4), (0.0, 1e-6, 0),
+                        (float("nan"), 1e-6, 4), (0.0, float("inf"), 4), (0.0, 1e308, 4)):
+        assert lib.dd_damage_sweep(s.handle, ctypes.byref(g), t0, dt, n_t, 0, o, 1,
+                                   None) == dd.DD_EINVAL, (t0, dt, n_t)
+    bad = dd.Grid(0, 0, 1e-9, 1e-9, 4, 0)
+    assert lib.dd_damage_sweep(s.handle, ctypes.byref(bad), 0.0, 1e-6, 4, 0, o, 1,
+                               None) == dd.DD_EINVAL
+    assert lib.dd_damage_sweep(s.handle, ctypes.byref(g), 0.0, 1e-6, 4, 9, o, 1,
+                               None) == dd.DD_EINVAL
 
 
 def test_queries_fail_loudly_without_device(dd):
@@ -116,6 +127,10 @@ def test_queries_fail_loudly_without_device(dd):
     st = lib.dd_damage_at_probe_arrival(s.handle, 0, ctypes.cast(out, ctypes.c_void_p), 0, None)
     assert st == dd.DD_EDEVICE
     assert lib.dd_last_error()
+    g = dd.Grid(0, 0, 1e-9, 1e-9, 2, 2)
+    st = lib.dd_damage_sweep(s.handle, ctypes.byref(g), 0.0, 1e-6, 1, 0,
+                             ctypes.cast(out, ctypes.c_void_p), 0, None)
+    assert st == dd.DD_EDEVICE
 
 
 def test_out_of_memory_path():
