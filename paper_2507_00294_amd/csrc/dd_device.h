@@ -64,26 +64,33 @@ constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 constexpr double kEulerGamma = 0.5772156649015329;
 
+// 1/k! for k = 0 .. 23, each the correctly rounded quotient of two exact
+// doubles (k! is exact in double up to 18!; beyond, the first rounding).
+struct InvFact {
+  double v[24];
+  constexpr InvFact() : v() {
+    double f = 1.0;
+    for (int k = 0; k < 24; ++k) {
+      if (k > 0) f *= k;
+      v[k] = 1.0 / f;
+    }
+  }
+};
+
 // 2^-y for y >= 0 in double precision, y -> 2^-n 2^-f with n = rint(y),
-// f in [-1/2, 1/2]; 2^-f = e^{-f ln 2} by its Taylor polynomial of degree 11
-// (relative remainder < 1.3e-14 on |f ln 2| <= 0.347, below the FP64 path's
-// per-term budget of 1e-13).  Returns 0 for y > 1100.
+// f in [-1/2, 1/2]; 2^-f = e^{-f ln 2} by its Taylor polynomial of degree
+// DEG: relative remainder < 1.3e-14 for DEG = 11 (the FP64 path's per-term
+// budget is 1e-13), < 7.4e-9 for DEG = 7 (the mixed path's general form).
+// Returns 0 for y > 1100.
+template <int DEG = 11>
 __device__ __forceinline__ double exp2_neg(double y) {
+  constexpr InvFact f{};
   y = fmin(y, 1100.0);
   const double n = __builtin_rint(y);
   const double g = (n - y) * kLn2;  // e^g with |g| <= 0.3466
-  double p = 1.0 / 39916800.0;       // 1/11!
-  p = fma(p, g, 1.0 / 3628800.0);
-  p = fma(p, g, 1.0 / 362880.0);
-  p = fma(p, g, 1.0 / 40320.0);
-  p = fma(p, g, 1.0 / 5040.0);
-  p = fma(p, g, 1.0 / 720.0);
-  p = fma(p, g, 1.0 / 120.0);
-  p = fma(p, g, 1.0 / 24.0);
-  p = fma(p, g, 1.0 / 6.0);
-  p = fma(p, g, 0.5);
-  p = fma(p, g, 1.0);
-  p = fma(p, g, 1.0);
+  double p = f.v[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) p = fma(p, g, f.v[k]);
   return __builtin_ldexp(p, -(int)n);
 }
 
@@ -99,21 +106,25 @@ struct E1SeriesCoef {
   }
 };
 
-// E1(x) for x > 0 in double precision (relative error < 3e-15 for
-// x <= 2.5, < 1e-14 above).  Power series about 0 (A&S 5.1.11) for
-// x <= 2.5; for x > 2.5 the even continued fraction
+// E1(x) for x > 0 in double precision.  Power series about 0 (A&S 5.1.11)
+// with NSER terms for x <= 2.5; for x > 2.5 the even continued fraction
 //   E1(x) = e^-x / (x+1 - 1/(x+3 - 4/(x+5 - ...)))   (A&S 5.1.22)
-// truncated after 5 + 90/x levels and evaluated by the forward three-term
-// recurrence of its convergents (no divisions inside the loop).
-__device__ __forceinline__ double e1_f64(double x) {
+// truncated after CFA + CFB/x levels and evaluated by the forward three-term
+// recurrence of its convergents (no divisions inside the loop).  The depths
+// come from a numerical study against the oracle's E1:
+//   e1_f64  (24 terms, 5 + 90/x, exp degree 11): relative error < 3e-15 for
+//           x <= 2.5, < 1e-14 above;
+//   e1_mixed (18 terms, 4 + 30/x, exp degree 7): < 1e-8, for the mixed path.
+template <int NSER, int CFA, int CFB, int EXPDEG>
+__device__ __forceinline__ double e1_eval(double x) {
   if (x <= 2.5) {
     constexpr E1SeriesCoef k{};
-    double s = k.c[23];
+    double s = k.c[NSER - 1];
 #pragma unroll
-    for (int n = 22; n >= 0; --n) s = fma(s, x, k.c[n]);
+    for (int n = NSER - 2; n >= 0; --n) s = fma(s, x, k.c[n]);
     return -kEulerGamma - ::log(x) - x * s;
   }
-  const int depth = 5 + (int)(90.0 / x);
+  const int depth = CFA + (int)((double)CFB / x);
   double am1 = 1.0, bm1 = 0.0, a0 = x + 1.0, b0 = 1.0;
   double bj = x + 1.0;
   for (int j = 1; j <= depth; ++j) {
@@ -123,8 +134,11 @@ __device__ __forceinline__ double e1_f64(double x) {
     const double b1 = fma(bj, b0, aj * bm1);
     am1 = a0; bm1 = b0; a0 = a1; b0 = b1;
   }
-  return exp2_neg(x * kLog2e) * (b0 / a0);
+  return exp2_neg<EXPDEG>(x * kLog2e) * (b0 / a0);
 }
+
+__device__ __forceinline__ double e1_f64(double x) { return e1_eval<24, 5, 90, 11>(x); }
+__device__ __forceinline__ double e1_mixed(double x) { return e1_eval<18, 4, 30, 7>(x); }
 
 // Series form in double precision with P_0..P_M read from an FP64 row.
 // The two factors of the term: returns q and sets t = exp(-x1) (term = t q).
@@ -155,6 +169,35 @@ __device__ __forceinline__ double phi_general_f64(double a, const double* __rest
   const double x0 = a * row[kR64_RB0];
   const double e0 = x0 > 745.0 ? 0.0 : e1_f64(x0);
   return e1_f64(x1) - e0;
+}
+
+// General pair term of the mixed path, for the pairs its FP32 series does not
+// cover (dx > 0.25), to ~1e-8 relative, a hundredth of the mixed bound:
+// dx <= 1: the series of degree 12 (truncation < 2e-9) in FP64 times
+// exp(-x1) in the split FP32 form of the bulk (a exact, x1 log2(e) = yh + yl);
+// dx > 1: E1(x1) - E1(x0) by e1_mixed (the two values differ by more than a
+// factor e, so the difference keeps ~2e-8).
+__device__ __forceinline__ double phi_general_mixed(float a, const double* __restrict__ r64,
+                                                    const float* __restrict__ r32) {
+  const double ad = (double)a;
+  const double z = ad * r64[kR64_C];
+  if (z <= kThr64) {
+    double q = r64[kR64_P + 12];
+#pragma unroll
+    for (int m = 11; m >= 0; --m) q = fma(q, z, r64[kR64_P + m]);
+    const float rhi = r32[kR32_RHI];
+    const float yh = a * rhi;
+    float yl = __builtin_fmaf(a, rhi, -yh);
+    yl = __builtin_fmaf(a, r32[kR32_RLO], yl);
+    float t = __builtin_amdgcn_exp2f(-yh);
+    t = __builtin_fmaf(t, yl * (float)(-kLn2), t);
+    return (double)t * q;
+  }
+  const double x1 = ad * r64[kR64_RB1];
+  if (x1 > 745.0) return 0.0;
+  const double x0 = ad * r64[kR64_RB0];
+  const double e0 = x0 > 745.0 ? 0.0 : e1_mixed(x0);
+  return e1_mixed(x1) - e0;
 }
 
 // Mixed-precision series with P_0..P_M from an FP32 row.  `a` is exact

@@ -373,7 +373,7 @@ __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void*
           if (a * ldc(r32 + kR32_C) <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
           else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2)
-            acc[r] += phi_general_f64((double)a, r64);
+            acc[r] += phi_general_mixed(a, r64, r32);
         }
       }
     }
@@ -670,7 +670,7 @@ __device__ __forceinline__ void do_map(const MapItem& item, const MapTime& tm,
           if (a * ldc(r32 + kR32_C) <= kThr32)
             acc[r] += (double)series_f32<kMNear32>(a, r32);
           else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2)
-            acc[r] += phi_general_f64((double)a, r64);
+            acc[r] += phi_general_mixed(a, r64, r32);
         }
       }
     } else {

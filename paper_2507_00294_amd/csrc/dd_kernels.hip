@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_pair_terms(double kappa, double s2, int
       if (af * r32[kR32_C] <= kThr32)
         v = (double)series_f32<kMNear32>(af, r32);
       else
-        v = phi_general_f64(ak, r64);
+        v = phi_general_mixed(af, r64, r32);
     } else {
       v = phi_general_f64(ak, r64);
     }
