@@ -16,7 +16,8 @@ the accuracy check of the GPU result.  The learned surrogate is measured
 against the exact batched kernel on 2000 held-out 64x64 scans (speedup at its
 relative L2 error, with its exact judge and fallback), the batched
 configuration (256 scans in one call) and the time-sampled simulation (maps
-every half dwell over a whole 64x64 scan) are reported beside it.
+every half dwell over a whole 64x64 scan) and the streaming query (the last
+1024 visits of the scan) are reported beside it.
 """
 import argparse
 import json
@@ -112,6 +113,8 @@ def main():
                     help="skip the batched-configuration measurement")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the time-sampled simulation measurement")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the streaming (visit range) measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM byte counters) and exit")
@@ -177,6 +180,29 @@ def main():
                                       "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
                                       "frac": round(rate / VALU_ISSUE_PEAK, 4)}
     result = out.cpu().numpy()
+    # Streaming: psi at the last 1024 visits of the scan (the visits just made,
+    # the most expensive 1024 of the scan), latency of one call.
+    stream = None
+    if not args.no_stream:
+        j0 = V - 1024
+        tail = torch.empty(V - j0, dtype=torch.float64, device="cuda")
+        scan.arrival_range(j0, V, prec, out=tail)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            scan.arrival_range(j0, V, prec, out=tail)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t_st = float(np.median(ts))
+        pairs_st = float(sum(range(j0, V)))
+        dev = float(np.max(np.abs(tail.cpu().numpy() - result[j0:]) / np.abs(result[j0:])))
+        stream = {"ms_per_call": t_st * 1e3, "visits": V - j0, "pairs_per_call": pairs_st,
+                  "value": pairs_st / t_st, "unit": "pair-terms/s",
+                  "max_rel_diff_vs_full_query": dev,
+                  "workload": "arrival at the last 1024 visits of the same scan, one call "
+                              "(host to host latency with the scan tables resident)"}
+        log(f"[bench] streaming: last {V - j0} visits in {t_st * 1e3:.3f} ms")
 
     # The other precision on the same workload, for context.
     other = "fp64" if prec == "mixed" else "mixed"
@@ -318,6 +344,7 @@ def main():
         "kernels_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in kern.items()},
         "batched": bat,
         "sweep": swp,
+        "streaming": stream,
         "surrogate": sur,
     }
     print(json.dumps(line), flush=True)

@@ -132,6 +132,16 @@ dd_status dd_damage_sweep(dd_scan *s, const dd_grid *g, double t0_s, double dt_s
 dd_status dd_damage_at_probe_arrival(dd_scan *s, dd_precision p, double *out,
                                      int32_t out_on_device, void *hip_stream);
 
+/* Streaming form of the arrival query (the real-time simulation the paper
+ * aims at, Sec. V): psi at the visits j0 <= j < j1 only, out[j - j0] =
+ * psi(r_j, t_j) summed over visits i < j (Eq. 6), e.g. for the visits the
+ * scan has just made.  The same values as dd_damage_at_probe_arrival (up to
+ * the order of the per-visit sums); the work is the pairs of those visits
+ * (about j per visit).  0 <= j0 <= j1 <= V; j0 == j1 does nothing.
+ * Errors: DD_EINVAL (range, precision, NULL), DD_ENOMEM, DD_EDEVICE.     */
+dd_status dd_damage_at_probe_arrival_range(dd_scan *s, int64_t j0, int64_t j1, dd_precision p,
+                                           double *out, int32_t out_on_device, void *hip_stream);
+
 /* Queries for dd_batch_solve (bit mask).                                  */
 typedef enum {
   DD_Q_ARRIVAL = 1,          /* [V] as dd_damage_at_probe_arrival              */

@@ -28,7 +28,8 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 # Every symbol the header declares (checked by the tests).
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
-    "dd_damage_map", "dd_damage_sweep", "dd_damage_at_probe_arrival", "dd_batch_solve",
+    "dd_damage_map", "dd_damage_sweep", "dd_damage_at_probe_arrival",
+    "dd_damage_at_probe_arrival_range", "dd_batch_solve",
     "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
@@ -84,6 +85,7 @@ def load_library():
     lib.dd_scan_visits.argtypes = [vp, P(i32)]
     lib.dd_damage_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_sweep.argtypes = [vp, P(Grid), dbl, dbl, i32, ctypes.c_int, vp, i32, vp]
+    lib.dd_damage_at_probe_arrival_range.argtypes = [vp, i64, i64, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_at_probe_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_batch_solve.argtypes = [P(vp), i32, ctypes.c_uint32, ctypes.c_int, P(vp), i32, vp]
     lib.dd_pair_terms.argtypes = [dbl, dbl, i64, vp, vp, ctypes.c_int, vp, vp]
@@ -109,7 +111,7 @@ def load_library():
     lib.dd_unet_predict.argtypes = [vp, P(vp), i32, dbl, ctypes.c_int, vp, P(i32), vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
-                 "dd_damage_at_probe_arrival", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
+                 "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
@@ -209,6 +211,19 @@ class Scan:
         assert out.numel() == self.num_visits
         _check(load_library().dd_damage_at_probe_arrival(
             self._h, _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
+
+    def arrival_range(self, j0: int, j1: int, precision: str = "fp64", out=None, stream=None):
+        """psi at visits j0 <= j < j1 at their start
+        (``dd_damage_at_probe_arrival_range``) as a float64 CUDA tensor [j1 - j0]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(max(j1 - j0, 0), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == max(j1 - j0, 0)
+        _check(load_library().dd_damage_at_probe_arrival_range(
+            self._h, j0, j1, _prec(precision), ctypes.c_void_p(out.data_ptr()), 1,
+            _stream(stream)))
         return out
 
     def damage_map(self, x0_m: float, y0_m: float, dx_m: float, dy_m: float, w: int, h: int,

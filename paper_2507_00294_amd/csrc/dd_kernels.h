@@ -50,7 +50,8 @@ struct MapLaunch {
 hipError_t launch_map(const MapLaunch& L, hipStream_t st);
 
 hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
-                                 int tile, double pref, double* out, hipStream_t st);
+                                 int tile, double pref, int64_t j0, int64_t n, double* out,
+                                 hipStream_t st);
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
                              int64_t npix, double pref, double* out, hipStream_t st);
 

@@ -89,16 +89,19 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
 
 // ---------------------------------------------------------------------------
 // Fixed-order reductions of the partial slots.
+// out[i] = pref * (sum of the slots of visit j0 + i), i < n.
 __global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict__ partial,
                                                         const int32_t* __restrict__ tile_slots,
                                                         int64_t V, int tile, double pref,
+                                                        int64_t j0, int64_t n,
                                                         double* __restrict__ out) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < V;
-       j += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = j0 + i;
     const int ns = tile_slots[j / tile];
     double s = 0.0;
     for (int k = 0; k < ns; ++k) s += partial[(int64_t)k * V + j];
-    out[j] = pref * s;
+    out[i] = pref * s;
   }
 }
 
@@ -225,9 +228,11 @@ hipError_t launch_map(const MapLaunch& L, hipStream_t st) {
 }
 
 hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
-                                 int tile, double pref, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_arrival, dim3(grid_for(V)), dim3(256), 0, st, partial, tile_slots,
-                     V, tile, pref, out);
+                                 int tile, double pref, int64_t j0, int64_t n, double* out,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_arrival, dim3(grid_for(n)), dim3(256), 0, st, partial, tile_slots,
+                     V, tile, pref, j0, n, out);
   return hipGetLastError();
 }
 

@@ -132,9 +132,12 @@ void count_segments(const DegreeBounds& b, int64_t lo, int64_t hi, bool mixed, P
 // far chunks of K lags from kf, aligned to R.
 // The near items go to `near` and the far items to `far`, both in planning
 // order.  Pair and flop counts (for the profiler) are formed only if `count`.
+// With j1 >= 0 only the tiles holding visits [j0, j1) get items (tile_slots
+// keeps one entry per tile of the scan).
 void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPlan& P,
                   std::vector<ArrItem>& near, std::vector<ArrItem>& far,
-                  std::vector<int32_t>& tile_slots, bool count) {
+                  std::vector<int32_t>& tile_slots, bool count, int64_t j0 = 0,
+                  int64_t j1 = -1) {
   const int T = 64 * R, TN = 64 * RN;
   const int64_t V = s->V;
   const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
@@ -150,8 +153,9 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
   near.clear();
   far.clear();
   tile_slots.assign(n_tiles, 1);
+  if (j1 < 0) j1 = V;
   int S = 1;
-  for (int64_t t = 0; t < n_tiles; ++t) {
+  for (int64_t t = j0 / T; t < n_tiles && t * T < j1; ++t) {
     const int64_t J0 = t * T;
     const int64_t maxlag = std::min<int64_t>(J0 + T - 1, V - 1);
     const int64_t jend = std::min<int64_t>(J0 + T, V);
@@ -172,7 +176,7 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
     S = std::max(S, 1 + c);
   }
   // near band: tiles of 64 RN visits, lags [1, kf), slot 0
-  for (int64_t t = 0; t < (V + TN - 1) / TN; ++t) {
+  for (int64_t t = j0 / TN; t < (V + TN - 1) / TN && t * TN < j1; ++t) {
     const int64_t J0 = t * TN;
     const int64_t maxlag = std::min<int64_t>(J0 + TN - 1, V - 1);
     const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
@@ -261,7 +265,69 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   prof_end(tf, st, P.far_pairs, P.far_flops);
   ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 64 * R,
-                               s->pref, out_dev, st),
+                               s->pref, 0, s->V, out_dev, st),
+         "arrival reduce launch");
+  prof_end(tq, st, 0, 0);
+  return DD_OK;
+}
+
+// Arrival at the visits [j0, j1) only (streaming: the visits just made).
+// Only the tiles holding them are planned, with lag chunks of 512 lags (at
+// least V/256, which bounds the partial rows at 257 V), so that a few tiles
+// still spread over many waves.
+dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, double* out_dev,
+                            hipStream_t st) {
+  dd_status rc = s->prepare(st);
+  if (rc != DD_OK) return rc;
+  rc = build_int_rows(s, st);
+  if (rc != DD_OK) return rc;
+  if (j1 <= j0) return DD_OK;
+  const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
+  const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
+  int K = (int)std::min<int64_t>(std::max<int64_t>(512, (s->V + 255) / 256), 1 << 28);
+  K = std::max(R, (K + R - 1) / R * R);
+  ArrivalPlan P;
+  std::vector<ArrItem> items, far;
+  std::vector<int32_t> tile_slots;
+  plan_arrival(s, mixed, R, RN, K, P, items, far, tile_slots, prof_on(), j0, j1);
+  auto longer = [](const ArrItem& a, const ArrItem& b) {
+    return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
+  };
+  std::stable_sort(items.begin(), items.end(), longer);
+  std::stable_sort(far.begin(), far.end(), longer);
+  items.insert(items.end(), far.begin(), far.end());  // near items first
+  rc = upload(s->aux2, items, st);
+  if (rc != DD_OK) return rc;
+  rc = upload(s->aux3, tile_slots, st);
+  if (rc != DD_OK) return rc;
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)s->V), "device allocation");
+  ArrivalLaunch L{};
+  L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
+                : (const void*)(s->pos64.as<double2>() + kPosPad);
+  L.pos4 = s->pos4.as<float4>() + kPosPad;
+  L.rows64 = s->rows64.as<double>();
+  L.rows32 = s->rows32.as<float>();
+  L.V = s->V;
+  L.bounds = P.bounds;
+  L.partial = s->partial.as<double>();
+  L.mixed = mixed;
+  L.items = s->aux2.as<ArrItem>();
+  L.n_items = P.n_near;
+  L.near = true;
+  L.R = RN;
+  ProfToken tn = prof_begin("arrival_near", st);
+  DD_HIP(launch_arrival(L, st), "arrival near-band launch");
+  prof_end(tn, st, P.near_pairs, P.near_flops);
+  L.items = s->aux2.as<ArrItem>() + P.n_near;
+  L.n_items = P.n_far;
+  L.near = false;
+  L.R = R;
+  ProfToken tf = prof_begin("arrival_far", st);
+  DD_HIP(launch_arrival(L, st), "arrival far-region launch");
+  prof_end(tf, st, P.far_pairs, P.far_flops);
+  ProfToken tq = prof_begin("reduce", st);
+  DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux3.as<int32_t>(), s->V, 64 * R,
+                               s->pref, j0, j1 - j0, out_dev, st),
          "arrival reduce launch");
   prof_end(tq, st, 0, 0);
   return DD_OK;
@@ -925,6 +991,20 @@ dd_status dd_damage_sweep(dd_scan* s, const dd_grid* g, double t0_s, double dt_s
     if (rc != DD_OK) return rc;
   }
   return DD_OK;
+}
+
+dd_status dd_damage_at_probe_arrival_range(dd_scan* s, int64_t j0, int64_t j1, dd_precision p,
+                                           double* out, int32_t out_on_device, void* hip_stream) {
+  if (!s || (!out && j1 > j0)) return fail(DD_EINVAL, "NULL argument");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  if (j0 < 0 || j1 < j0 || j1 > s->V)
+    return fail(DD_EINVAL, "visit range [%lld, %lld) outside [0, %lld]", (long long)j0,
+                (long long)j1, (long long)s->V);
+  if (j1 == j0) return DD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  return deliver(s, (size_t)(j1 - j0), out, out_on_device, st, [&](double* o) {
+    return run_arrival_range(s, p == DD_MIXED, j0, j1, o, st);
+  });
 }
 
 dd_status dd_damage_at_probe_arrival(dd_scan* s, dd_precision p, double* out,

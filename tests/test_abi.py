@@ -109,6 +109,11 @@ def test_null_and_bad_arguments(dd):
                         (float("nan"), 1e-6, 4), (0.0, float("inf"), 4), (0.0, 1e308, 4)):
         assert lib.dd_damage_sweep(s.handle, ctypes.byref(g), t0, dt, n_t, 0, o, 1,
                                    None) == dd.DD_EINVAL, (t0, dt, n_t)
+    # the streaming arrival query checks its visit range (V = 4 here)
+    for j0, j1 in ((-1, 2), (3, 2), (0, 5)):
+        assert lib.dd_damage_at_probe_arrival_range(s.handle, j0, j1, 1, o, 1,
+                                                    None) == dd.DD_EINVAL, (j0, j1)
+    assert lib.dd_damage_at_probe_arrival_range(s.handle, 2, 2, 1, None, 1, None) == dd.DD_OK
     bad = dd.Grid(0, 0, 1e-9, 1e-9, 4, 0)
     assert lib.dd_damage_sweep(s.handle, ctypes.byref(bad), 0.0, 1e-6, 4, 0, o, 1,
                                None) == dd.DD_EINVAL
