@@ -50,6 +50,15 @@ class _Scan(ctypes.Structure):
     ]
 
 
+class _Visits(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("x", ctypes.POINTER(ctypes.c_double)), ("y", ctypes.POINTER(ctypes.c_double)),
+        ("t0", ctypes.POINTER(ctypes.c_double)), ("dwell", ctypes.POINTER(ctypes.c_double)),
+        ("sigma", ctypes.c_double), ("D", ctypes.c_double), ("Q0", ctypes.c_double),
+    ]
+
+
 def _load():
     global _lib
     with _lock:
@@ -81,6 +90,9 @@ def _load():
             lib.ddo_psi_map.restype = ctypes.c_int
             lib.ddo_psi_map.argtypes = [P(_Scan), D, D, D, D, I32, I32, P(D), I32, P(D),
                                         ctypes.c_int]
+            lib.ddo_psi_points_general.restype = ctypes.c_int
+            lib.ddo_psi_points_general.argtypes = [P(_Visits), I64, P(D), P(D), P(D), P(D),
+                                                   ctypes.c_int]
             lib.ddo_default_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -184,3 +196,46 @@ class Scan:
                                _dptr(out), nthreads) != 0:
             raise ValueError("bad arguments")
         return out
+
+
+class Visits:
+    """A general visit list: visit v sits at (x[v], y[v]) (metres) with the beam
+    on from t0[v] for dwell[v] seconds.  Each visit carries its own dwell and
+    start time, so flyback and dead time, subsampled or repeated positions and
+    any visit order are all expressed directly.  psi sums Eqs. 1-4 over the
+    visits that started before the query time (Eq. 6)."""
+
+    def __init__(self, x, y, t0, dwell, sigma, D, Q0=1.0):
+        self.x, self.y, self.t0, self.dwell = (np.ascontiguousarray(v, dtype=np.float64)
+                                               for v in (x, y, t0, dwell))
+        n = self.x.size
+        if not (self.y.size == n and self.t0.size == n and self.dwell.size == n):
+            raise ValueError("x, y, t0 and dwell must have one entry per visit")
+        self.sigma, self.D, self.Q0 = float(sigma), float(D), float(Q0)
+        self._v = _Visits(n, _dptr(self.x), _dptr(self.y), _dptr(self.t0), _dptr(self.dwell),
+                          self.sigma, self.D, self.Q0)
+
+    @property
+    def n_visits(self):
+        return int(self.x.size)
+
+    def psi_points(self, x, y, t, nthreads=0):
+        x, y, t = (np.ascontiguousarray(v, dtype=np.float64) for v in (x, y, t))
+        out = np.empty(x.size, dtype=np.float64)
+        if _load().ddo_psi_points_general(ctypes.byref(self._v), x.size, _dptr(x), _dptr(y),
+                                          _dptr(t), _dptr(out), nthreads) != 0:
+            raise ValueError("bad arguments")
+        return out
+
+    def psi_arrival(self, nthreads=0):
+        """psi at each visit's own position at the instant its beam turns on."""
+        return self.psi_points(self.x, self.y, self.t0, nthreads)
+
+    def psi_map(self, x0, y0, dx, dy, w, h, t, nthreads=0):
+        t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+        xs = x0 + dx * np.arange(w, dtype=np.float64)
+        ys = y0 + dy * np.arange(h, dtype=np.float64)
+        X = np.broadcast_to(xs[None, None, :], (t.size, h, w))
+        Y = np.broadcast_to(ys[None, :, None], (t.size, h, w))
+        T = np.broadcast_to(t[:, None, None], (t.size, h, w))
+        return self.psi_points(X.ravel(), Y.ravel(), T.ravel(), nthreads).reshape(t.size, h, w)

@@ -13,10 +13,14 @@
  * with a = |r - r_i|^2, Ds = r_s^2 = sigma^2, b1 = 2Ds + 4D(t - t_i),
  * b0 = 2Ds while the beam is on (t <= t_i + tau) and
  * b0 = 2Ds + 4D(t - t_i - tau) once it is off.
+ * A uniform scan takes t_i = i tau on a probe lattice; a general visit list
+ * (ddo_psi_points_general) gives every visit its own position, start time
+ * and dwell, and the same sum runs over it.
  *
  * Parity status of every function is pinned by tests (series vs continued
  * fraction vs quadrature vs library E1, heat-kernel time quadrature, a -> 0
- * limit, Fick's law residual, mass balance, symmetry, scaling).
+ * limit, Fick's law residual, mass balance, symmetry, scaling; for general
+ * visit lists: heat-kernel quadrature, the uniform scan, dwell splitting).
  */
 #include "ddo.h"
 
@@ -267,9 +271,25 @@ static long double psi_point(const ddo_scan *s, long double x, long double y, lo
   return (long double)s->Q0 / (4.0L * PI_L * D) * sum;
 }
 
+/* psi at one point of a general visit list: every visit that started before t. */
+static long double psi_point_general(const ddo_vlist *g, long double x, long double y,
+                                     long double t) {
+  long double Ds = (long double)g->sigma * (long double)g->sigma;
+  long double D = g->D;
+  long double sum = 0.0L;
+  for (int64_t v = 0; v < g->n; ++v) {
+    long double tv = g->t0[v];
+    if (!(tv < t)) continue;
+    long double dx = x - (long double)g->x[v], dy = y - (long double)g->y[v];
+    sum += phi_bracket(dx * dx + dy * dy, t - tv, (long double)g->dwell[v], Ds, D);
+  }
+  return (long double)g->Q0 / (4.0L * PI_L * D) * sum;
+}
+
 typedef struct {
   const ddo_scan *s;
-  int kind; /* 0 points, 1 arrival, 2 map */
+  const ddo_vlist *g;
+  int kind; /* 0 points, 1 arrival, 2 map, 3 points of a general visit list */
   int64_t n;
   const double *x, *y, *t;
   const int64_t *idx;
@@ -284,6 +304,10 @@ static void *worker(void *arg) {
   const ddo_scan *s = j->s;
   for (int64_t k = j->tid; k < j->n; k += j->nth) {
     long double x, y, t;
+    if (j->kind == 3) {
+      j->out[k] = (double)psi_point_general(j->g, j->x[k], j->y[k], j->t[k]);
+      continue;
+    }
     if (j->kind == 0) {
       x = j->x[k];
       y = j->y[k];
@@ -370,5 +394,18 @@ int ddo_psi_map(const ddo_scan *s, double x0, double y0, double dx, double dy, i
   memset(&j, 0, sizeof j);
   j.s = s; j.kind = 2; j.n = (int64_t)w * h * nt; j.t = t; j.out = out;
   j.x0 = x0; j.y0 = y0; j.dx = dx; j.dy = dy; j.w = w; j.h = h;
+  return run_jobs(&j, nthreads);
+}
+
+int ddo_psi_points_general(const ddo_vlist *g, int64_t n, const double *px, const double *py,
+                           const double *pt, double *out, int nthreads) {
+  if (!g || g->n < 0 || (g->n > 0 && (!g->x || !g->y || !g->t0 || !g->dwell)) ||
+      !(g->sigma > 0) || !(g->D > 0) || n < 0 || (n > 0 && (!px || !py || !pt || !out)))
+    return -1;
+  for (int64_t v = 0; v < g->n; ++v)
+    if (!(g->dwell[v] > 0)) return -1;
+  job_t j;
+  memset(&j, 0, sizeof j);
+  j.g = g; j.kind = 3; j.n = n; j.x = px; j.y = py; j.t = pt; j.out = out;
   return run_jobs(&j, nthreads);
 }

@@ -78,6 +78,22 @@ int ddo_psi_arrival(const ddo_scan *s, int64_t n, const int64_t *visit_idx, doub
 int ddo_psi_map(const ddo_scan *s, double x0, double y0, double dx, double dy, int32_t w,
                 int32_t h, const double *t, int32_t nt, double *out, int nthreads);
 
+/* ---- general visit lists --------------------------------------------------
+ * Visit v at (x[v], y[v]) (metres), beam on from t0[v] for dwell[v]
+ * seconds; visits in any order, each on its own window.  psi(r, t) = sum
+ * over visits with t0[v] < t of phi_v(r, t) (Eqs. 1-4 with the visit's own
+ * dwell, Eq. 6).                                                           */
+typedef struct {
+  int64_t n;
+  const double *x, *y, *t0, *dwell; /* [n] */
+  double sigma, D, Q0;
+} ddo_vlist;
+
+/* psi at n points (px[k], py[k], pt[k]); nthreads <= 0 -> all cores.
+ * Returns 0, or -1 on bad arguments.                                       */
+int ddo_psi_points_general(const ddo_vlist *g, int64_t n, const double *px, const double *py,
+                           const double *pt, double *out, int nthreads);
+
 /* Number of hardware threads the oracle uses for nthreads <= 0.           */
 int ddo_default_threads(void);
 
