@@ -270,6 +270,41 @@ dd_status dd_surrogate_targets(dd_scan *const *scans, int32_t n, const double *p
 dd_status dd_unet_predict(dd_unet *u, dd_scan *const *scans, int32_t n, double spot_tol,
                           dd_precision p, double *psi, int32_t *used_fallback, void *hip_stream);
 
+/* ---- General visit lists ----------------------------------------------------
+ * Sec. II's single-visit field (Eqs. 1-4) holds for each visit with its own
+ * position r_i, start time t_i and dwell tau_i, and Eq. 6 sums it over the
+ * visits with t_i < t.  A general list states every visit this way, so
+ * per-visit dwells, flyback and dead time between lines or frames,
+ * subsampled (sparse) scans, revisits and any visit order are all lists.
+ * Evaluated in FP64 (the same bound as DD_FP64 above).                   */
+typedef struct dd_visits dd_visits; /* opaque */
+
+/* Copies n >= 1 visits: x_m, y_m (metres), t0_s (beam-on start, seconds)
+ * and dwell_s (seconds, > 0), host arrays in any order; visits may overlap
+ * in time.  sigma_m, D_m2s > 0, Q0_us >= 0 as in dd_scan_desc.  Host only.
+ * Errors: DD_EINVAL (NULL, n < 1 or n > 2^31, a non-finite value, a dwell
+ * <= 0), DD_ENOMEM.                                                       */
+dd_status dd_visits_create(int64_t n, const double *x_m, const double *y_m, const double *t0_s,
+                           const double *dwell_s, double sigma_m, double D_m2s, double Q0_us,
+                           dd_visits **out);
+/* Frees the handle and its device buffers; NULL is allowed.               */
+void dd_visits_destroy(dd_visits *v);
+/* Number of visits; -1 for NULL.                                          */
+int64_t dd_visits_count(const dd_visits *v);
+
+/* psi at each visit's position at the moment its beam turns on: out[i] =
+ * psi(r_i, t0_i), the sum over visits j with t0_j < t0_i (Eq. 6), in the
+ * caller's visit order.  out: [n].
+ * Errors: DD_EINVAL (NULL), DD_ENOMEM, DD_EDEVICE.                        */
+dd_status dd_visits_arrival(dd_visits *v, double *out, int32_t out_on_device, void *hip_stream);
+
+/* psi on grid g at n_t >= 1 finite times t_s (host array, seconds on the
+ * visits' clock), out [n_t][h][w] row-major; visits not started at a time
+ * give it nothing.
+ * Errors: DD_EINVAL (NULL, grid, times), DD_ENOMEM, DD_EDEVICE.           */
+dd_status dd_visits_map(dd_visits *v, const dd_grid *g, const double *t_s, int32_t n_t,
+                        double *out, int32_t out_on_device, void *hip_stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);
 

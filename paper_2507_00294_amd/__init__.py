@@ -34,7 +34,9 @@ EXPORTS = (
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
     "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
-    "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_last_error",
+    "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
+    "dd_visits_destroy", "dd_visits_count", "dd_visits_arrival", "dd_visits_map",
+    "dd_last_error",
 )
 
 
@@ -109,13 +111,21 @@ def load_library():
     lib.dd_surrogate_inputs.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_surrogate_targets.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_unet_predict.argtypes = [vp, P(vp), i32, dbl, ctypes.c_int, vp, P(i32), vp]
+    lib.dd_visits_create.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, P(vp)]
+    lib.dd_visits_destroy.argtypes = [vp]
+    lib.dd_visits_destroy.restype = None
+    lib.dd_visits_count.argtypes = [vp]
+    lib.dd_visits_count.restype = i64
+    lib.dd_visits_arrival.argtypes = [vp, vp, i32, vp]
+    lib.dd_visits_map.argtypes = [vp, P(Grid), P(dbl), i32, vp, i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
-                 "dd_surrogate_targets", "dd_unet_predict"):
+                 "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
+                 "dd_visits_arrival", "dd_visits_map"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -263,6 +273,68 @@ class Scan:
         t_end = self.num_visits * self.tau_v
         return self.damage_map(0.0, 0.0, self.pitch_m, self.pitch_m, self.nx, self.ny, [t_end],
                                precision, stream=stream)[0]
+
+
+class Visits:
+    """A general visit list (``dd_visits``): visit i at (x_m[i], y_m[i]) with
+    the beam on from t0_s[i] for dwell_s[i] seconds (any order, overlaps
+    allowed), evaluated in FP64.  SI units as in ``Scan``."""
+
+    def __init__(self, x_m, y_m, t0_s, dwell_s, *, sigma_m: float = 0.5e-9,
+                 D_m2s: float = 2.5e-13, Q0_us: float = 1.0):
+        lib = load_library()
+        cols = [np.ascontiguousarray(c, dtype=np.float64).ravel() for c in (x_m, y_m, t0_s, dwell_s)]
+        n = cols[0].size
+        if any(c.size != n for c in cols):
+            raise ValueError("x_m, y_m, t0_s and dwell_s need one entry per visit")
+        h = ctypes.c_void_p()
+        _check(lib.dd_visits_create(n, *(ctypes.c_void_p(c.ctypes.data) for c in cols), sigma_m,
+                                    D_m2s, Q0_us, ctypes.byref(h)))
+        self._h = h
+        self.sigma_m, self.D_m2s, self.Q0_us = sigma_m, D_m2s, Q0_us
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().dd_visits_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_visits(self) -> int:
+        return int(load_library().dd_visits_count(self._h))
+
+    def arrival(self, out=None, stream=None):
+        """psi at each visit's position when its beam turns on
+        (``dd_visits_arrival``), float64 CUDA tensor [n] in visit order."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.num_visits, dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == self.num_visits
+        _check(load_library().dd_visits_arrival(self._h, ctypes.c_void_p(out.data_ptr()), 1,
+                                                _stream(stream)))
+        return out
+
+    def damage_map(self, x0_m: float, y0_m: float, dx_m: float, dy_m: float, w: int, h: int,
+                   times_s: Iterable[float], out=None, stream=None):
+        """psi on a w-by-h pixel grid at each time (``dd_visits_map``),
+        float64 CUDA tensor [n_t, h, w]."""
+        torch = _torch()
+        t = np.ascontiguousarray(np.atleast_1d(np.asarray(times_s, dtype=np.float64)))
+        if out is None:
+            out = torch.empty((t.size, h, w), dtype=torch.float64, device="cuda")
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == t.size * w * h
+        g = Grid(x0_m, y0_m, dx_m, dy_m, w, h)
+        _check(load_library().dd_visits_map(
+            self._h, ctypes.byref(g), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
+            ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+        return out
 
 
 def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PROBES,

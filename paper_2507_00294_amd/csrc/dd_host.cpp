@@ -86,28 +86,32 @@ dd_status ensure_device() {
   return DD_OK;
 }
 
-// Gauss-Legendre nodes on [0, 1] by Newton iteration on P_n.
+// Gauss-Legendre rule on [0, 1] with n nodes by Newton iteration on P_n:
+// x[i] = (1 - z_i) / 2, w[i] = half the weight of z_i on [-1, 1].
+void gauss_legendre01(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 1; k < n; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
 const GLNodes& gl_nodes() {
   static GLNodes g = [] {
     GLNodes r;
-    const int n = kGL;
-    for (int i = 0; i < n; ++i) {
-      double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
-      for (int it = 0; it < 100; ++it) {
-        double p0 = 1.0, p1 = z;
-        for (int k = 1; k < n; ++k) {
-          const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
-          p0 = p1;
-          p1 = p2;
-        }
-        dp = n * (z * p1 - p0) / (z * z - 1.0);
-        const double dz = p1 / dp;
-        z -= dz;
-        if (std::fabs(dz) < 1e-16) break;
-      }
-      r.x[i] = 0.5 * (1.0 - z);
-      r.w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // half of the [-1,1] weight
-    }
+    gauss_legendre01(kGL, r.x, r.w);
     return r;
   }();
   return g;

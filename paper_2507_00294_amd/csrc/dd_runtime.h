@@ -17,6 +17,7 @@ bool host_alloc_ok(size_t bytes);
 hipError_t dev_alloc(void** p, size_t bytes);
 dd_status ensure_device();
 const GLNodes& gl_nodes();
+void gauss_legendre01(int n, double* x, double* w);
 double row_c(double lam, double kappa, double s2);
 int degree_needed(double dx, bool mixed);
 double row_dx_bound(double lam, double a_max, double cull, double kappa, double s2);

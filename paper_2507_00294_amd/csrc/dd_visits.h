@@ -1,0 +1,71 @@
+// dd_visits.h -- general visit lists: shared types of the host plan and the
+// kernels of dd_visits.hip.  Not part of the public ABI.
+//
+// A general list gives every visit its own position, start time and dwell;
+// the field is the sum of Eqs. 1-4 over the visits that started before the
+// query time (Eq. 6).  Positions are kept in metres and times in seconds, so
+// that the lag t - t_i and the distance r - r_i are formed from the caller's
+// own values before any scaling (a product taken first, e.g. D t / sigma^2,
+// would turn the rounding of t into an error of the short lags).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dd {
+
+constexpr int kVisGL = 12;        // Gauss-Legendre nodes of the near-pair integral
+constexpr int kVisTile = 256;     // evaluation points per tile (one per thread)
+constexpr int kVisStage = 256;    // visits staged in LDS at a time
+constexpr int kVisMaxSlots = 32;  // visit chunks (partial sums) per tile at most
+
+// Gauss-Legendre rule on [0, 1]: nodes x, weights w (summing to 1).
+struct VisGL {
+  double x[kVisGL];
+  double w[kVisGL];
+};
+
+// Scaling of a pair: a_hat = |r - r_i|^2 / sigma^2 with inv_sigma, and
+// b_hat = 2 + 4 (D / sigma^2) lag with th4 = 4 D / sigma^2.
+struct VisPhys {
+  double inv_sigma, th4;
+};
+
+// A tile of evaluation points.  Arrival: the visits p0 .. p0+n-1 in start
+// order, each at its own position and start time.  Map: pixels p0 .. p0+n-1
+// of the grid at time index m.  Its partial sums sit at pbase + slot * 256.
+struct VisTile {
+  int64_t p0;
+  int64_t pbase;
+  int64_t out0;  // map: output index of the first point
+  double tmax;   // latest point time of the tile
+  int32_t n, m, slots, pad;
+};
+
+// One work item: a tile against visits v0 .. v0+nv-1 (start order).
+struct VisItem {
+  int32_t tile, slot;
+  int64_t v0;
+  int64_t nv;
+};
+
+// Map grid (pixel (u, v) at (x0 + u dx, y0 + v dy), w columns).
+struct VisGrid {
+  double x0, y0, dx, dy;
+  int32_t w, pad;
+};
+
+// Partial sums of every item: arrival (map = false) or map points.  vis
+// holds (x, y, t0, dwell) per visit in start order; times the map's times.
+hipError_t launch_visit_pairs(bool map, const double4* vis, const VisTile* tiles,
+                              const VisItem* items, int64_t n_items, const double* times,
+                              VisGrid grid, VisPhys phys, VisGL rule, double* partial,
+                              hipStream_t st);
+
+// out[dst] = pref * (sum over the tile's slots, in slot order) for every
+// point of every tile; dst = perm[p0 + k] when perm is given (arrival: the
+// caller's visit order), else out0 + k (map).
+hipError_t launch_visit_reduce(const VisTile* tiles, int64_t n_tiles, const double* partial,
+                               const int64_t* perm, double pref, double* out, hipStream_t st);
+
+}  // namespace dd

@@ -1,0 +1,316 @@
+// dd_visits_host.cpp -- the general visit list handle (dd_visits_*): every visit
+// with its own position, start time and dwell (Sec. II, Eqs. 1-4 per visit,
+// Eq. 6 over the visits started before the query time), in FP64.
+//
+// Work planning.  Visits are kept in start order.  Evaluation points go in
+// tiles of 256 (one thread each); visits in chunks of K (a multiple of 256,
+// at most 32 chunks per list).  A work item is one tile against one chunk,
+// written to a partial-sum slot of its own, and the slots are summed in a
+// fixed order, so results do not depend on scheduling.  Items are dropped
+// on the host when no pair can contribute:
+//   * the chunk's first start is at or after the tile's latest time
+//     (nothing has started), and
+//   * the bounding boxes of tile and chunk are so far apart that
+//     a / b1 > 745 for every pair, with b1 taken at the largest lag
+//     (the kernel would cull each pair; a margin of 1e-9 keeps host and
+//     device roundings on the same side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/dd.h"
+#include "dd_runtime.h"
+#include "dd_visits.h"
+
+using namespace dd;
+
+namespace {
+
+struct Box {
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  void add(double x, double y) {
+    x0 = std::min(x0, x);
+    x1 = std::max(x1, x);
+    y0 = std::min(y0, y);
+    y1 = std::max(y1, y);
+  }
+};
+
+// Smallest squared distance between two boxes, in units of sigma^2.
+double box_a_min(const Box& p, const Box& q, double inv_sigma) {
+  const double gx = std::max({0.0, q.x0 - p.x1, p.x0 - q.x1}) * inv_sigma;
+  const double gy = std::max({0.0, q.y0 - p.y1, p.y0 - q.y1}) * inv_sigma;
+  return gx * gx + gy * gy;
+}
+
+constexpr int64_t kGroupTiles = 4096;  // tiles per launch (partial sums <= 256 MiB)
+
+#define VIS_HIP(call, what)                            \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, what);   \
+  } while (0)
+
+}  // namespace
+
+struct dd_visits {
+  int64_t n = 0;
+  std::vector<double4> vis;   // (x, y, t0, dwell) in start order
+  std::vector<int64_t> perm;  // start order -> caller's index
+  double sigma = 0, D = 0, Q0 = 0, inv_sigma = 0, th4 = 0, pref = 0;
+  int64_t K = 0;              // visits per chunk
+  std::vector<Box> chunk_box;
+  std::vector<double> chunk_t0;  // first start of each chunk
+  VisGL rule{};
+
+  int dev = -1;
+  DevBuf d_vis, d_perm, d_tiles, d_items, d_partial, d_times, tmp_out;
+  std::vector<VisTile> h_tiles;
+  std::vector<VisItem> h_items;
+
+  void release_device() {
+    for (DevBuf* b : {&d_vis, &d_perm, &d_tiles, &d_items, &d_partial, &d_times, &tmp_out})
+      b->release();
+    dev = -1;
+  }
+
+  dd_status prepare(hipStream_t st) {
+    dd_status rc = ensure_device();
+    if (rc != DD_OK) return rc;
+    int cur = 0;
+    VIS_HIP(hipGetDevice(&cur), "hipGetDevice");
+    if (dev >= 0 && dev != cur) release_device();
+    if (dev == cur) return DD_OK;
+    VIS_HIP(d_vis.ensure(sizeof(double4) * n), "device allocation");
+    VIS_HIP(d_perm.ensure(sizeof(int64_t) * n), "device allocation");
+    VIS_HIP(hipMemcpyAsync(d_vis.p, vis.data(), sizeof(double4) * n, hipMemcpyHostToDevice, st),
+            "host-to-device copy");
+    VIS_HIP(hipMemcpyAsync(d_perm.p, perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st),
+            "host-to-device copy");
+    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+    dev = cur;
+    return DD_OK;
+  }
+
+  // Items of one tile (box, latest time) against every chunk that can
+  // contribute; returns the number of slots used.
+  int32_t plan_tile(int32_t tile, const Box& box, double tmax) {
+    int32_t slot = 0;
+    const int64_t n_chunks = (int64_t)chunk_t0.size();
+    for (int64_t c = 0; c < n_chunks && chunk_t0[c] < tmax; ++c) {
+      const double b1_max = 2.0 + th4 * (tmax - chunk_t0[c]);
+      if (box_a_min(box, chunk_box[c], inv_sigma) > 745.0 * (1.0 + 1e-9) * b1_max) continue;
+      const int64_t v0 = c * K;
+      h_items.push_back(VisItem{tile, slot++, v0, std::min(K, n - v0)});
+    }
+    return slot;
+  }
+
+  // Uploads the current tiles and items, launches the pair and reduce
+  // kernels for them.
+  dd_status launch(bool map, const VisGrid& grid, double* out, hipStream_t st) {
+    int64_t pbase = 0;
+    for (VisTile& t : h_tiles) {
+      t.pbase = pbase;
+      pbase += (int64_t)t.slots * kVisTile;
+    }
+    VIS_HIP(d_tiles.ensure(sizeof(VisTile) * std::max<size_t>(h_tiles.size(), 1)),
+            "device allocation");
+    VIS_HIP(d_items.ensure(sizeof(VisItem) * std::max<size_t>(h_items.size(), 1)),
+            "device allocation");
+    VIS_HIP(d_partial.ensure(sizeof(double) * std::max<int64_t>(pbase, 1)), "device allocation");
+    VIS_HIP(hipMemcpyAsync(d_tiles.p, h_tiles.data(), sizeof(VisTile) * h_tiles.size(),
+                           hipMemcpyHostToDevice, st),
+            "host-to-device copy");
+    if (!h_items.empty())
+      VIS_HIP(hipMemcpyAsync(d_items.p, h_items.data(), sizeof(VisItem) * h_items.size(),
+                             hipMemcpyHostToDevice, st),
+              "host-to-device copy");
+    const ProfToken tok = prof_begin("k_visit_pairs", st);
+    VIS_HIP(launch_visit_pairs(map, d_vis.as<double4>(), d_tiles.as<VisTile>(),
+                               d_items.as<VisItem>(), (int64_t)h_items.size(),
+                               d_times.as<double>(), grid, VisPhys{inv_sigma, th4}, rule,
+                               d_partial.as<double>(), st),
+            "k_visit_pairs launch");
+    prof_end(tok, st, pairs_of_items(map), 0.0);
+    VIS_HIP(launch_visit_reduce(d_tiles.as<VisTile>(), (int64_t)h_tiles.size(),
+                                d_partial.as<double>(), map ? nullptr : d_perm.as<int64_t>(), pref,
+                                out, st),
+            "k_visit_reduce launch");
+    // the host tables are rewritten by the next group: wait for the copies
+    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+    return DD_OK;
+  }
+
+  // Candidate pairs of the current items (tile points times chunk visits).
+  double pairs_of_items(bool) const {
+    double p = 0;
+    for (const VisItem& it : h_items) p += (double)h_tiles[it.tile].n * (double)it.nv;
+    return p;
+  }
+
+  dd_status arrival(double* out, hipStream_t st) {
+    const int64_t n_tiles = (n + kVisTile - 1) / kVisTile;
+    for (int64_t g0 = 0; g0 < n_tiles; g0 += kGroupTiles) {
+      const int64_t g1 = std::min(n_tiles, g0 + kGroupTiles);
+      h_tiles.clear();
+      h_items.clear();
+      for (int64_t t = g0; t < g1; ++t) {
+        const int64_t p0 = t * kVisTile, p1 = std::min(n, p0 + kVisTile);
+        Box b;
+        for (int64_t p = p0; p < p1; ++p) b.add(vis[p].x, vis[p].y);
+        const double tmax = vis[p1 - 1].z;  // start order
+        VisTile tile{p0, 0, 0, tmax, (int32_t)(p1 - p0), 0, 0, 0};
+        tile.slots = plan_tile((int32_t)(t - g0), b, tmax);
+        h_tiles.push_back(tile);
+      }
+      dd_status rc = launch(false, VisGrid{}, out, st);
+      if (rc != DD_OK) return rc;
+    }
+    return DD_OK;
+  }
+
+  dd_status map(const dd_grid* g, const double* t_s, int32_t n_t, double* out, hipStream_t st) {
+    const int64_t npix = (int64_t)g->w * g->h;
+    const int64_t per = (npix + kVisTile - 1) / kVisTile;  // tiles per time
+    VIS_HIP(d_times.ensure(sizeof(double) * n_t), "device allocation");
+    VIS_HIP(hipMemcpyAsync(d_times.p, t_s, sizeof(double) * n_t, hipMemcpyHostToDevice, st),
+            "host-to-device copy");
+    // pixel boxes of the tiles (the same at every time)
+    std::vector<Box> boxes(per);
+    for (int64_t b = 0; b < per; ++b) {
+      const int64_t q0 = b * kVisTile, q1 = std::min(npix, q0 + kVisTile) - 1;
+      const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
+      const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
+      boxes[b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
+      boxes[b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
+    }
+    const int64_t total = per * n_t;
+    const VisGrid grid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0};
+    for (int64_t g0 = 0; g0 < total; g0 += kGroupTiles) {
+      const int64_t g1 = std::min(total, g0 + kGroupTiles);
+      h_tiles.clear();
+      h_items.clear();
+      for (int64_t t = g0; t < g1; ++t) {
+        const int64_t m = t / per, b = t % per;
+        const int64_t p0 = b * kVisTile, p1 = std::min(npix, p0 + kVisTile);
+        VisTile tile{p0, 0, m * npix + p0, t_s[m], (int32_t)(p1 - p0), (int32_t)m, 0, 0};
+        tile.slots = plan_tile((int32_t)(t - g0), boxes[b], t_s[m]);
+        h_tiles.push_back(tile);
+      }
+      dd_status rc = launch(true, grid, out, st);
+      if (rc != DD_OK) return rc;
+    }
+    return DD_OK;
+  }
+};
+
+extern "C" {
+
+dd_status dd_visits_create(int64_t n, const double* x_m, const double* y_m, const double* t0_s,
+                           const double* dwell_s, double sigma_m, double D_m2s, double Q0_us,
+                           dd_visits** out) {
+  if (!out) return fail(DD_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 1) return fail(DD_EINVAL, "a visit list needs at least one visit");
+  if (!x_m || !y_m || !t0_s || !dwell_s) return fail(DD_EINVAL, "NULL argument");
+  if (n > (int64_t)1 << 31) return fail(DD_EINVAL, "at most 2^31 visits");
+  if (!(std::isfinite(sigma_m) && sigma_m > 0)) return fail(DD_EINVAL, "sigma must be > 0");
+  if (!(std::isfinite(D_m2s) && D_m2s > 0)) return fail(DD_EINVAL, "D must be > 0");
+  if (!(std::isfinite(Q0_us) && Q0_us >= 0)) return fail(DD_EINVAL, "Q0 must be >= 0");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(x_m[i]) || !std::isfinite(y_m[i]))
+      return fail(DD_EINVAL, "visit %lld: position not finite", (long long)i);
+    if (!std::isfinite(t0_s[i])) return fail(DD_EINVAL, "visit %lld: start not finite", (long long)i);
+    if (!(std::isfinite(dwell_s[i]) && dwell_s[i] > 0))
+      return fail(DD_EINVAL, "visit %lld: dwell must be finite and > 0", (long long)i);
+  }
+  if (!host_alloc_ok(sizeof(double4) * (size_t)n)) return fail(DD_ENOMEM, "host allocation");
+  dd_visits* v = new (std::nothrow) dd_visits;
+  if (!v) return fail(DD_ENOMEM, "host allocation");
+  try {
+    v->n = n;
+    v->perm.resize(n);
+    std::iota(v->perm.begin(), v->perm.end(), (int64_t)0);
+    std::stable_sort(v->perm.begin(), v->perm.end(),
+                     [&](int64_t a, int64_t b) { return t0_s[a] < t0_s[b]; });
+    v->vis.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t k = v->perm[i];
+      v->vis[i] = make_double4(x_m[k], y_m[k], t0_s[k], dwell_s[k]);
+    }
+    v->K = std::max<int64_t>(512, ((n + kVisMaxSlots - 1) / kVisMaxSlots + kVisStage - 1) /
+                                      kVisStage * kVisStage);
+    for (int64_t c0 = 0; c0 < n; c0 += v->K) {
+      Box b;
+      for (int64_t i = c0; i < std::min(n, c0 + v->K); ++i) b.add(v->vis[i].x, v->vis[i].y);
+      v->chunk_box.push_back(b);
+      v->chunk_t0.push_back(v->vis[c0].z);
+    }
+  } catch (const std::bad_alloc&) {
+    delete v;
+    return fail(DD_ENOMEM, "host allocation");
+  }
+  v->sigma = sigma_m;
+  v->D = D_m2s;
+  v->Q0 = Q0_us;
+  v->inv_sigma = 1.0 / sigma_m;
+  v->th4 = 4.0 * D_m2s / (sigma_m * sigma_m);
+  v->pref = Q0_us / (4.0 * M_PI * D_m2s);
+  gauss_legendre01(kVisGL, v->rule.x, v->rule.w);
+  *out = v;
+  return DD_OK;
+}
+
+void dd_visits_destroy(dd_visits* v) {
+  if (!v) return;
+  v->release_device();
+  delete v;
+}
+
+int64_t dd_visits_count(const dd_visits* v) { return v ? v->n : -1; }
+
+dd_status dd_visits_arrival(dd_visits* v, double* out, int32_t out_on_device, void* hip_stream) {
+  if (!v || !out) return fail(DD_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  dd_status rc = v->prepare(st);
+  if (rc != DD_OK) return rc;
+  if (out_on_device) return v->arrival(out, st);
+  VIS_HIP(v->tmp_out.ensure(sizeof(double) * v->n), "device allocation");
+  rc = v->arrival(v->tmp_out.as<double>(), st);
+  if (rc != DD_OK) return rc;
+  VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * v->n, hipMemcpyDeviceToHost, st),
+          "device-to-host copy");
+  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return DD_OK;
+}
+
+dd_status dd_visits_map(dd_visits* v, const dd_grid* g, const double* t_s, int32_t n_t,
+                        double* out, int32_t out_on_device, void* hip_stream) {
+  if (!v || !g || !out || (n_t > 0 && !t_s)) return fail(DD_EINVAL, "NULL argument");
+  if (n_t < 1) return fail(DD_EINVAL, "n_t must be >= 1");
+  if (g->w < 1 || g->h < 1) return fail(DD_EINVAL, "grid w and h must be >= 1");
+  if ((int64_t)g->w * g->h > (1LL << 30)) return fail(DD_EINVAL, "grid too large");
+  for (double x : {g->x0_m, g->y0_m, g->dx_m, g->dy_m})
+    if (!std::isfinite(x)) return fail(DD_EINVAL, "grid values must be finite");
+  for (int32_t m = 0; m < n_t; ++m)
+    if (!std::isfinite(t_s[m])) return fail(DD_EINVAL, "time %d not finite", m);
+  hipStream_t st = (hipStream_t)hip_stream;
+  dd_status rc = v->prepare(st);
+  if (rc != DD_OK) return rc;
+  if (out_on_device) return v->map(g, t_s, n_t, out, st);
+  const size_t nout = (size_t)n_t * g->w * g->h;
+  VIS_HIP(v->tmp_out.ensure(sizeof(double) * nout), "device allocation");
+  rc = v->map(g, t_s, n_t, v->tmp_out.as<double>(), st);
+  if (rc != DD_OK) return rc;
+  VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * nout, hipMemcpyDeviceToHost, st),
+          "device-to-host copy");
+  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return DD_OK;
+}
+
+}  // extern "C"

@@ -133,3 +133,75 @@ def sampled_visits(n_visits: int, k: int, seed: int) -> np.ndarray:
     idx = set(rng.choice(n_visits, size=k, replace=False).tolist())
     idx.update({0, n_visits - 1})
     return np.array(sorted(idx), dtype=np.int64)
+
+
+# ---- general visit lists: per-visit position, start time and dwell -----------
+@dataclass
+class VisitList:
+    """Visits with their own position (m), start time and dwell (s)."""
+    x_m: np.ndarray
+    y_m: np.ndarray
+    t0_s: np.ndarray
+    dwell_s: np.ndarray
+    sigma_m: float
+    D_m2s: float
+    Q0_us: float = 1.0
+    name: str = ""
+
+    @property
+    def n_visits(self) -> int:
+        return int(self.x_m.size)
+
+    @property
+    def t_end(self) -> float:
+        return float(np.max(self.t0_s + self.dwell_s))
+
+    def kwargs(self) -> dict:
+        return dict(sigma_m=self.sigma_m, D_m2s=self.D_m2s, Q0_us=self.Q0_us)
+
+
+def visit_list(kind: str, nx: int, ny: int, seed: int = 0, pitch_m: float = 1 * NM,
+               dwell_s: float = 1 * US, sigma_m: float = 0.5 * NM, D_m2s: float = 2.5e-13,
+               Q0_us: float = 1.0) -> VisitList:
+    """Seeded general visit lists on an nx-by-ny probe lattice:
+    * "flyback": raster lines, dwell x U(0.5, 1.5) per visit, a dead time of
+      nx/4 dwells at the end of each line (beam blanked while it returns);
+    * "sparse": a random quarter of the probes in random order, dwell x
+      U(0.5, 1.5), dead time U(0, 2) dwells before each visit;
+    * "frames": 3 raster frames with dwells 1/2, 1/3, 1/6 of the dwell and a
+      dead time of 10 dwells between frames (revisits at the same positions);
+    * "drift": raster with each position displaced by a slow drift plus
+      U(-0.1, 0.1) pitch noise (off the lattice), dwell x U(0.5, 1.5).
+    Visits never overlap in time except where stated; visit order is the
+    list order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ids = np.arange(nx * ny)
+    if kind == "flyback":
+        col, row = ids % nx, ids // nx
+        dw = dwell_s * rng.uniform(0.5, 1.5, ids.size)
+        gap = np.where(col == 0, (nx / 4) * dwell_s, 0.0)
+        gap[0] = 0.0
+        x, y = col * pitch_m, row * pitch_m
+    elif kind == "sparse":
+        pick = rng.permutation(ids)[: max(1, ids.size // 4)]
+        x, y = (pick % nx) * pitch_m, (pick // nx) * pitch_m
+        dw = dwell_s * rng.uniform(0.5, 1.5, pick.size)
+        gap = dwell_s * rng.uniform(0.0, 2.0, pick.size)
+    elif kind == "frames":
+        fr = np.repeat(np.arange(3), ids.size)
+        base = np.tile(ids, 3)
+        x, y = (base % nx) * pitch_m, (base // nx) * pitch_m
+        dw = dwell_s * np.array([1 / 2, 1 / 3, 1 / 6])[fr]
+        gap = np.where((np.arange(base.size) % ids.size == 0) & (fr > 0), 10 * dwell_s, 0.0)
+    elif kind == "drift":
+        col, row = ids % nx, ids // nx
+        s = np.arange(ids.size) / ids.size
+        x = (col + 0.3 * s + rng.uniform(-0.1, 0.1, ids.size)) * pitch_m
+        y = (row + 0.2 * s * s + rng.uniform(-0.1, 0.1, ids.size)) * pitch_m
+        dw = dwell_s * rng.uniform(0.5, 1.5, ids.size)
+        gap = np.zeros(ids.size)
+    else:
+        raise ValueError(f"unknown visit list kind {kind!r}")
+    t0 = np.cumsum(gap + np.concatenate([[0.0], dw[:-1]]))
+    return VisitList(np.asarray(x, np.float64), np.asarray(y, np.float64), t0, dw, sigma_m,
+                     D_m2s, Q0_us, kind)

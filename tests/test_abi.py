@@ -168,3 +168,51 @@ def test_tune_cache_load(dd, tmp_path):
     with pytest.raises(dd.DDError):
         dd.tune_load(str(other))
     dd.tune_load(str(good))  # leave the defaults in place
+
+
+def test_visit_list_validation(dd):
+    lib = dd.load_library()
+    D = ctypes.c_double
+    x = (D * 3)(0.0, 1e-9, 2e-9)
+    t0 = (D * 3)(0.0, 1e-6, 2e-6)
+    dw = (D * 3)(1e-6, 1e-6, 1e-6)
+    bad_dw = (D * 3)(1e-6, 0.0, 1e-6)
+    nan_t = (D * 3)(0.0, float("nan"), 2e-6)
+    h = ctypes.c_void_p()
+    vp = lambda a: ctypes.cast(a, ctypes.c_void_p)  # noqa: E731
+    for args in [(0, x, x, t0, dw, 0.5e-9, 1e-13, 1.0),      # no visits
+                 (3, x, x, t0, bad_dw, 0.5e-9, 1e-13, 1.0),  # dwell 0
+                 (3, x, x, nan_t, dw, 0.5e-9, 1e-13, 1.0),   # start not finite
+                 (3, x, x, t0, dw, 0.0, 1e-13, 1.0),         # sigma 0
+                 (3, x, x, t0, dw, 0.5e-9, -1.0, 1.0),       # D < 0
+                 (3, x, x, t0, dw, 0.5e-9, 1e-13, -1.0)]:    # Q0 < 0
+        n, *arrs, sig, Dm, q = args
+        assert lib.dd_visits_create(n, *map(vp, arrs), sig, Dm, q, ctypes.byref(h)) == dd.DD_EINVAL
+        assert not h.value
+    assert lib.dd_visits_create(3, vp(x), None, vp(t0), vp(dw), 0.5e-9, 1e-13, 1.0,
+                                ctypes.byref(h)) == dd.DD_EINVAL
+    v = dd.Visits([0.0, 1e-9, 2e-9], [0.0] * 3, [2e-6, 0.0, 1e-6], [1e-6] * 3)
+    assert v.num_visits == 3
+    assert lib.dd_visits_count(None) == -1
+    out = (D * 3)()
+    g = dd.Grid(0, 0, 1e-9, 1e-9, 2, 2)
+    t = (D * 1)(1e-6)
+    assert lib.dd_visits_arrival(None, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_map(v._h, ctypes.byref(g), t, 0, vp(out), 0, None) == dd.DD_EINVAL
+    g_bad = dd.Grid(0, 0, 1e-9, 1e-9, 0, 2)
+    assert lib.dd_visits_map(v._h, ctypes.byref(g_bad), t, 1, vp(out), 0, None) == dd.DD_EINVAL
+    t_bad = (D * 1)(float("inf"))
+    assert lib.dd_visits_map(v._h, ctypes.byref(g), t_bad, 1, vp(out), 0, None) == dd.DD_EINVAL
+    lib.dd_visits_destroy(None)
+
+
+def test_visit_list_fails_loudly_without_device(dd):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = dd.load_library()
+    v = dd.Visits([0.0, 1e-9], [0.0, 0.0], [0.0, 1e-6], [1e-6, 1e-6])
+    out = (ctypes.c_double * 2)()
+    assert lib.dd_visits_arrival(v._h, ctypes.cast(out, ctypes.c_void_p), 0, None) == dd.DD_EDEVICE
+    assert lib.dd_last_error()

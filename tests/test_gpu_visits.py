@@ -1,0 +1,131 @@
+"""General visit lists (``dd_visits_*``): per-visit dwell, flyback and dead
+time, sparse random subsets, revisits with unequal dwells and off-lattice
+positions, against the oracle's general list element by element (FP64
+bound); a uniform scan written as a list against the scan kernels; input
+order, host output and several tiles and visit chunks with ragged tails."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_close
+
+pytestmark = pytest.mark.gpu
+KINDS = ["flyback", "sparse", "frames", "drift"]
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_00294_amd as dd
+
+    dd.load_library()
+    return dd
+
+
+@pytest.fixture(scope="module")
+def wl():
+    from paper_2507_00294_amd import workloads
+
+    return workloads
+
+
+def both(dd, ora, vl):
+    g = dd.Visits(vl.x_m, vl.y_m, vl.t0_s, vl.dwell_s, **vl.kwargs())
+    o = ora.Visits(vl.x_m, vl.y_m, vl.t0_s, vl.dwell_s, vl.sigma_m, vl.D_m2s, vl.Q0_us)
+    return g, o
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("D", [2.5e-13, 3e-11])
+def test_arrival_vs_oracle(dd, ora, wl, kind, D):
+    # 9x7 lattice; D spans a diffusion length well below and well above the pitch
+    vl = wl.visit_list(kind, 9, 7, seed=11, D_m2s=D)
+    g, o = both(dd, ora, vl)
+    got = g.arrival().cpu().numpy()
+    ref = o.psi_arrival()
+    assert_close(got, ref, vl, "fp64", f"{kind} arrival")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_maps_vs_oracle(dd, ora, wl, kind):
+    # off-lattice grid; times before the first start, mid-dwell, in a dead
+    # time, at a dwell boundary and after the end
+    vl = wl.visit_list(kind, 8, 6, seed=12, D_m2s=1e-12, sigma_m=0.4e-9)
+    g, o = both(dd, ora, vl)
+    i = vl.n_visits // 2
+    times = [float(vl.t0_s[0]) * 0.5, float(vl.t0_s[1] + 0.3 * vl.dwell_s[1]),
+             float(vl.t0_s[i]), float(vl.t0_s[i] + vl.dwell_s[i]), vl.t_end, 3 * vl.t_end]
+    args = (-1.1e-9, -0.7e-9, 0.37e-9, 0.41e-9, 29, 21)
+    got = g.damage_map(*args, times).cpu().numpy()
+    ref = o.psi_map(*args, times)
+    assert_close(got, ref, vl, "fp64", f"{kind} maps")
+    if vl.t0_s.min() > times[0]:
+        assert np.all(got[0] == 0.0)
+
+
+def test_many_tiles_and_chunks_vs_oracle(dd, ora, wl):
+    # 1480 visits: 6 tiles (the last ragged) against 3 visit chunks of 512
+    # (the last ragged); maps of 3 x 2400 pixels (10 tiles per time)
+    vl = wl.visit_list("flyback", 40, 37, seed=13, D_m2s=1e-12)
+    g, o = both(dd, ora, vl)
+    assert_close(g.arrival().cpu().numpy(), o.psi_arrival(), vl, "fp64", "arrival")
+    times = [0.37 * vl.t_end, 0.81 * vl.t_end, vl.t_end]
+    args = (-2e-9, -1e-9, 0.9e-9, 0.8e-9, 60, 40)
+    assert_close(g.damage_map(*args, times).cpu().numpy(), o.psi_map(*args, times), vl, "fp64",
+                 "maps")
+
+
+def test_uniform_scan_as_list_matches_scan_kernels(dd, wl):
+    # a random-order scan written as a general list: the same field as the
+    # scan's own FP64 kernels (arrival and a final map)
+    spec = wl.ScanSpec(24, 20, "random", 1e-9, 1e-6, 0.5e-9, 4e-13, 1.0, seed=5)
+    scan = dd.Scan(**spec.kwargs())
+    ids = scan.visits()
+    k = np.arange(ids.size)
+    g = dd.Visits((ids % spec.nx) * spec.pitch_m, (ids // spec.nx) * spec.pitch_m, k * spec.tau_v,
+                  np.full(ids.size, spec.tau_v), sigma_m=spec.sigma_m, D_m2s=spec.D_m2s,
+                  Q0_us=spec.Q0_us)
+    a = scan.arrival("fp64").cpu().numpy()
+    b = g.arrival().cpu().numpy()
+    assert_close(b, a, spec, "fp64", "arrival")
+    t = [ids.size * spec.tau_v]
+    args = (0.0, 0.0, 0.5e-9, 0.5e-9, 48, 40)
+    assert_close(g.damage_map(*args, t).cpu().numpy(), scan.damage_map(*args, t, "fp64").cpu().numpy(),
+                 spec, "fp64", "map")
+
+
+def test_input_order_and_host_output(dd, wl):
+    vl = wl.visit_list("sparse", 30, 30, seed=14, D_m2s=2e-12)
+    g = dd.Visits(vl.x_m, vl.y_m, vl.t0_s, vl.dwell_s, **vl.kwargs())
+    a = g.arrival().cpu().numpy()
+    p = np.random.default_rng(15).permutation(vl.n_visits)
+    h = dd.Visits(vl.x_m[p], vl.y_m[p], vl.t0_s[p], vl.dwell_s[p], **vl.kwargs())
+    b = h.arrival().cpu().numpy()
+    assert np.array_equal(b, a[p])  # same start order inside, the same sums
+    lib = dd.load_library()
+    out = np.empty(vl.n_visits)
+    assert lib.dd_visits_arrival(g._h, ctypes.c_void_p(out.ctypes.data), 0, None) == 0
+    assert np.array_equal(out, a)
+    gr = dd.Grid(0.0, 0.0, 1e-9, 1e-9, 30, 30)
+    t = np.array([0.5 * vl.t_end, vl.t_end])
+    mo = np.empty((2, 30, 30))
+    assert lib.dd_visits_map(g._h, ctypes.byref(gr), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             2, ctypes.c_void_p(mo.ctypes.data), 0, None) == 0
+    assert np.array_equal(mo, g.damage_map(0.0, 0.0, 1e-9, 1e-9, 30, 30, t).cpu().numpy())
+
+
+def test_single_visit_and_coincident_revisit(dd, ora):
+    # one visit, then the same position visited again: the a = 0 (log) form
+    g = dd.Visits([1e-9, 1e-9], [2e-9, 2e-9], [0.0, 3e-6], [1e-6, 2e-6], sigma_m=0.5e-9,
+                  D_m2s=1e-12)
+    o = ora.Visits([1e-9, 1e-9], [2e-9, 2e-9], [0.0, 3e-6], [1e-6, 2e-6], 0.5e-9, 1e-12)
+    got = g.arrival().cpu().numpy()
+    assert got[0] == 0.0
+    ref = o.psi_arrival()
+    assert abs(got[1] - ref[1]) <= 1e-10 * ref[1]
+    one = dd.Visits([0.0], [0.0], [1e-6], [1e-6], sigma_m=0.5e-9, D_m2s=1e-12)
+    assert one.arrival().cpu().numpy()[0] == 0.0
