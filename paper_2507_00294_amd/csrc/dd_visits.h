@@ -14,16 +14,9 @@
 
 namespace dd {
 
-constexpr int kVisGL = 12;        // Gauss-Legendre nodes of the near-pair integral
 constexpr int kVisTile = 256;     // evaluation points per tile (one per thread)
 constexpr int kVisStage = 256;    // visits staged in LDS at a time
 constexpr int kVisMaxSlots = 32;  // visit chunks (partial sums) per tile at most
-
-// Gauss-Legendre rule on [0, 1]: nodes x, weights w (summing to 1).
-struct VisGL {
-  double x[kVisGL];
-  double w[kVisGL];
-};
 
 // Scaling of a pair: a_hat = |r - r_i|^2 / sigma^2 with inv_sigma, and
 // b_hat = 2 + 4 (D / sigma^2) lag with th4 = 4 D / sigma^2.
@@ -59,7 +52,7 @@ struct VisGrid {
 // holds (x, y, t0, dwell) per visit in start order; times the map's times.
 hipError_t launch_visit_pairs(bool map, const double4* vis, const VisTile* tiles,
                               const VisItem* items, int64_t n_items, const double* times,
-                              VisGrid grid, VisPhys phys, VisGL rule, double* partial,
+                              VisGrid grid, VisPhys phys, double* partial,
                               hipStream_t st);
 
 // out[dst] = pref * (sum over the tile's slots, in slot order) for every

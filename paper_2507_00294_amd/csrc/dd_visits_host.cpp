@@ -65,7 +65,6 @@ struct dd_visits {
   int64_t K = 0;              // visits per chunk
   std::vector<Box> chunk_box;
   std::vector<double> chunk_t0;  // first start of each chunk
-  VisGL rule{};
 
   int dev = -1;
   DevBuf d_vis, d_perm, d_tiles, d_items, d_partial, d_times, tmp_out;
@@ -133,7 +132,7 @@ struct dd_visits {
     const ProfToken tok = prof_begin("k_visit_pairs", st);
     VIS_HIP(launch_visit_pairs(map, d_vis.as<double4>(), d_tiles.as<VisTile>(),
                                d_items.as<VisItem>(), (int64_t)h_items.size(),
-                               d_times.as<double>(), grid, VisPhys{inv_sigma, th4}, rule,
+                               d_times.as<double>(), grid, VisPhys{inv_sigma, th4},
                                d_partial.as<double>(), st),
             "k_visit_pairs launch");
     prof_end(tok, st, pairs_of_items(map), 0.0);
@@ -261,7 +260,6 @@ dd_status dd_visits_create(int64_t n, const double* x_m, const double* y_m, cons
   v->inv_sigma = 1.0 / sigma_m;
   v->th4 = 4.0 * D_m2s / (sigma_m * sigma_m);
   v->pref = Q0_us / (4.0 * M_PI * D_m2s);
-  gauss_legendre01(kVisGL, v->rule.x, v->rule.w);
   *out = v;
   return DD_OK;
 }

@@ -129,3 +129,20 @@ def test_single_visit_and_coincident_revisit(dd, ora):
     assert abs(got[1] - ref[1]) <= 1e-10 * ref[1]
     one = dd.Visits([0.0], [0.0], [1e-6], [1e-6], sigma_m=0.5e-9, D_m2s=1e-12)
     assert one.arrival().cpu().numpy()[0] == 0.0
+
+
+def test_bench_workload_sampled_vs_oracle(dd, ora, wl):
+    # the benchmark's list (256x256 raster, dwell jitter, flyback; 65536
+    # visits) in the same calls the benchmark times: arrival at 48 sampled
+    # visits and the final map at 48 sampled probes against the oracle
+    vl = wl.visit_list("flyback", 256, 256, seed=21)
+    g, o = both(dd, ora, vl)
+    arr = g.arrival().cpu().numpy()
+    idx = wl.sampled_visits(vl.n_visits, 48, seed=22)
+    ref = o.psi_points(vl.x_m[idx], vl.y_m[idx], vl.t0_s[idx])
+    assert_close(arr[idx], ref, vl, "fp64", "arrival (sampled)")
+    fin = g.damage_map(0.0, 0.0, 1e-9, 1e-9, 256, 256, [vl.t_end]).cpu().numpy()[0]
+    pix = wl.sampled_visits(256 * 256, 48, seed=23)
+    u, v = pix % 256, pix // 256
+    ref = o.psi_points(u * 1e-9, v * 1e-9, np.full(pix.size, vl.t_end))
+    assert_close(fin[v, u], ref, vl, "fp64", "final map (sampled)")
