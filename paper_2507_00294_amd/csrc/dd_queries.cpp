@@ -206,6 +206,54 @@ int arrival_K(int64_t V, int R, bool mixed) {
   return std::max(R, (K + R - 1) / R * R);
 }
 
+// Order of the far items for the per-scan arrival kernel, where wave w of
+// block b takes item 4b + w and blocks are dealt to the 8 XCDs round robin
+// (block b on XCD b mod 8, each XCD with its own L2).  Items of one lag
+// chunk read the same lag rows, and items of adjacent tiles in one chunk
+// read overlapping position windows; so the chunks are dealt to the XCDs by
+// work (largest first onto the least loaded XCD), each XCD's items are kept
+// chunk by chunk in tile order, and the item list interleaves the XCDs'
+// queues four items at a time.  Every item writes its own partial slot, so
+// the order changes no result.
+void order_far_for_xcds(std::vector<ArrItem>& far) {
+  constexpr int kX = 8, kW = 4;
+  std::map<int32_t, std::vector<ArrItem>> chunks;  // n_lo -> items
+  for (const ArrItem& it : far) chunks[it.n_lo].push_back(it);
+  std::vector<std::pair<double, int32_t>> work;  // (work, n_lo)
+  for (auto& kv : chunks) {
+    double w = 0;
+    for (const ArrItem& it : kv.second) w += (double)(it.n_hi - it.n_lo);
+    std::stable_sort(kv.second.begin(), kv.second.end(),
+                     [](const ArrItem& a, const ArrItem& b) { return a.tile < b.tile; });
+    work.push_back({w, kv.first});
+  }
+  std::stable_sort(work.begin(), work.end(),
+                   [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+                     return a.first > b.first;
+                   });
+  std::vector<std::vector<ArrItem>> q(kX);
+  std::vector<double> load(kX, 0.0);
+  for (const auto& w : work) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += w.first;
+    const auto& v = chunks[w.second];
+    q[x].insert(q[x].end(), v.begin(), v.end());
+  }
+  std::vector<size_t> pos(kX, 0);
+  std::vector<ArrItem> out;
+  out.reserve(far.size());
+  for (size_t b = 0; out.size() < far.size(); ++b) {
+    int x = (int)(b % kX);
+    if (pos[x] >= q[x].size()) {  // this XCD's queue is done: lend it the fullest one's items
+      size_t best = 0;
+      for (int y = 0; y < kX; ++y)
+        if (q[y].size() - pos[y] > best) best = q[y].size() - pos[y], x = y;
+    }
+    for (int k = 0; k < kW && pos[x] < q[x].size(); ++k) out.push_back(q[x][pos[x]++]);
+  }
+  far.swap(out);
+}
+
 struct PlanCache {
   ArrivalPlan arr;
 };
@@ -230,7 +278,7 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
       return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
     };
     std::stable_sort(items.begin(), items.end(), longer);
-    std::stable_sort(far.begin(), far.end(), longer);
+    order_far_for_xcds(far);
     items.insert(items.end(), far.begin(), far.end());  // near items first
     rc = upload(s->items, items, st);
     if (rc != DD_OK) return rc;

@@ -146,3 +146,22 @@ def test_bench_workload_sampled_vs_oracle(dd, ora, wl):
     u, v = pix % 256, pix // 256
     ref = o.psi_points(u * 1e-9, v * 1e-9, np.full(pix.size, vl.t_end))
     assert_close(fin[v, u], ref, vl, "fp64", "final map (sampled)")
+
+
+def test_map_launch_groups(dd, ora, wl):
+    # 70 maps of 128x128 = 4480 point tiles: more than one launch group of
+    # 4096 tiles; every map equals the same map asked for alone, bit for
+    # bit, and sampled pixels match the oracle
+    vl = wl.visit_list("drift", 20, 15, seed=24, D_m2s=5e-13)
+    g, o = both(dd, ora, vl)
+    times = np.linspace(0.02, 1.3, 70) * vl.t_end
+    args = (-3e-9, -3e-9, 0.2e-9, 0.2e-9, 128, 128)
+    many = g.damage_map(*args, times).cpu().numpy()
+    for m in (0, 35, 63, 64, 69):
+        one = g.damage_map(*args, [times[m]]).cpu().numpy()[0]
+        assert np.array_equal(many[m], one), m
+    rng = np.random.default_rng(25)
+    m = rng.integers(0, 70, 64)
+    u, v = rng.integers(0, 128, 64), rng.integers(0, 128, 64)
+    ref = o.psi_points(-3e-9 + u * 0.2e-9, -3e-9 + v * 0.2e-9, times[m])
+    assert_close(many[m, v, u], ref, vl, "fp64", "maps (sampled)")
