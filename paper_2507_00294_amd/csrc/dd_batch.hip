@@ -29,9 +29,10 @@ k_batch_arrival_far(const BatchScan* __restrict__ scans, const BatchItem* __rest
     const BatchScan& S = scans[bi.scan];
     const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
     if (MIXED)
-      do_arrival_far32<R, true>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial);
+      do_arrival_far32<R, true>(ai, S.pos4, S.rows32, S.V, S.arr_bounds, S.arr_partial, S.V, 0);
     else
-      do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds, S.arr_partial);
+      do_arrival_far64<R>(ai, (const double2*)S.pos, S.rows64, S.V, S.arr_bounds, S.arr_partial,
+                          S.V, 0);
   }
 }
 
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(256) k_batch_arrival_near(const BatchScan* __r
     const BatchItem bi = items[it];
     const BatchScan& S = scans[bi.scan];
     const ArrItem ai{bi.tile, bi.n_lo, bi.n_hi, bi.slot_flags};
-    do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial);
+    do_arrival_near<RN, MIXED>(ai, S.pos, S.rows64, S.rows32, S.V, S.arr_partial, S.V, 0);
   }
 }
 

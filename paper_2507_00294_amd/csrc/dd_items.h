@@ -275,12 +275,15 @@ __device__ __forceinline__ void seg_range(const DegreeBounds& b, int M, int n_lo
   hi = (M == 0) ? n_hi : min(n_hi, b.b[M - 1]);
 }
 
-// One wavefront processes one arrival work item (far region).
+// One wavefront processes one arrival work item (far region).  The sums of
+// visit j go to partial[slot * pstride + j - pj0]: pstride = V and pj0 = 0
+// for a whole-scan query; a visit range keeps only the columns of its tiles.
 template <int R, bool CAS>
 __device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const float4* __restrict__ pos,
                                                  const float* __restrict__ rows, int64_t V,
                                                  const DegreeBounds& bnd,
-                                                 double* __restrict__ partial) {
+                                                 double* __restrict__ partial, int64_t pstride,
+                                                 int64_t pj0) {
   const int lane = threadIdx.x & 63;
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   float ex[R], ey[R], ee[R];
@@ -303,17 +306,18 @@ __device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const floa
     else
       arr_far32_seg<R, false, CAS>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
   }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+  const int64_t base = (int64_t)(item.slot_flags & kSlotMask) * pstride - pj0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
+    if (jl + r < V) partial[base + jl + r] = acc[r];
 }
 
 template <int R>
 __device__ __forceinline__ void do_arrival_far64(const ArrItem& item, const double2* __restrict__ pos,
                                                  const double* __restrict__ rows, int64_t V,
                                                  const DegreeBounds& bnd,
-                                                 double* __restrict__ partial) {
+                                                 double* __restrict__ partial, int64_t pstride,
+                                                 int64_t pj0) {
   const int lane = threadIdx.x & 63;
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   double ex[R], ey[R], acc[R];
@@ -334,10 +338,10 @@ __device__ __forceinline__ void do_arrival_far64(const ArrItem& item, const doub
     else
       arr_far64_seg<R, false>(M, lo, hi, pos, jl, ex, ey, rows, acc);
   }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+  const int64_t base = (int64_t)(item.slot_flags & kSlotMask) * pstride - pj0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
+    if (jl + r < V) partial[base + jl + r] = acc[r];
 }
 
 // Near band: per-pair regime choice, every pair masked by causality.
@@ -345,7 +349,8 @@ template <int R, bool MIXED>
 __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void* __restrict__ pos_v,
                                                 const double* __restrict__ rows64,
                                                 const float* __restrict__ rows32, int64_t V,
-                                                double* __restrict__ partial) {
+                                                double* __restrict__ partial, int64_t pstride,
+                                                int64_t pj0) {
   const int lane = threadIdx.x & 63;
   const int64_t jl = (int64_t)item.tile * (64 * R) + (int64_t)R * lane;
   double acc[R];
@@ -399,10 +404,10 @@ __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void*
       }
     }
   }
-  double* out = partial + (int64_t)(item.slot_flags & kSlotMask) * V;
+  const int64_t base = (int64_t)(item.slot_flags & kSlotMask) * pstride - pj0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (jl + r < V) out[jl + r] = acc[r];
+    if (jl + r < V) partial[base + jl + r] = acc[r];
 }
 
 // ---------------------------------------------------------------------------

@@ -25,7 +25,8 @@ struct ArrivalLaunch {
   int32_t n_items;
   int64_t V;
   DegreeBounds bounds;
-  double* partial;          // [slots][V]
+  double* partial;          // [slots][pstride], column j - pj0 for visit j
+  int64_t pstride, pj0;     // V and 0 for a whole-scan query
   int R;                    // eval visits per lane (tile = 64 R)
   bool mixed;
   bool near;                // items are near-band items (per-pair regime)
@@ -49,9 +50,13 @@ struct MapLaunch {
 };
 hipError_t launch_map(const MapLaunch& L, hipStream_t st);
 
-hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
-                                 int tile, double pref, int64_t j0, int64_t n, double* out,
-                                 hipStream_t st);
+hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots,
+                                 int64_t pstride, int64_t pj0, int tile, double pref, int64_t j0,
+                                 int64_t n, double* out, hipStream_t st);
+// One wave per visit (for visits with many slots).
+hipError_t launch_reduce_arrival_wide(const double* partial, const int32_t* tile_slots,
+                                      int64_t pstride, int64_t pj0, int tile, double pref,
+                                      int64_t j0, int64_t n, double* out, hipStream_t st);
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
                              int64_t npix, double pref, double* out, hipStream_t st);
 

@@ -43,10 +43,11 @@ k_arrival_far32(const float4* __restrict__ pos,
                                                        const float* __restrict__ rows,
                                                        const ArrItem* __restrict__ items, int n_items,
                                                        int64_t V, DegreeBounds bnd,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, int64_t pstride,
+                                                       int64_t pj0) {
   const int it = blockIdx.x * 4 + wave_id();
   if (it >= n_items) return;
-  do_arrival_far32<R, false>(items[it], pos, rows, V, bnd, partial);
+  do_arrival_far32<R, false>(items[it], pos, rows, V, bnd, partial, pstride, pj0);
 }
 
 template <int R>
@@ -54,10 +55,11 @@ __global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict
                                                        const double* __restrict__ rows,
                                                        const ArrItem* __restrict__ items, int n_items,
                                                        int64_t V, DegreeBounds bnd,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, int64_t pstride,
+                                                       int64_t pj0) {
   const int it = blockIdx.x * 4 + wave_id();
   if (it >= n_items) return;
-  do_arrival_far64<R>(items[it], pos, rows, V, bnd, partial);
+  do_arrival_far64<R>(items[it], pos, rows, V, bnd, partial, pstride, pj0);
 }
 
 template <int R, bool MIXED>
@@ -65,10 +67,11 @@ __global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ p
                                                       const double* __restrict__ rows64,
                                                       const float* __restrict__ rows32,
                                                       const ArrItem* __restrict__ items, int n_items,
-                                                      int64_t V, double* __restrict__ partial) {
+                                                      int64_t V, double* __restrict__ partial,
+                                                      int64_t pstride, int64_t pj0) {
   const int it = blockIdx.x * 4 + wave_id();
   if (it >= n_items) return;
-  do_arrival_near<R, MIXED>(items[it], pos_v, rows64, rows32, V, partial);
+  do_arrival_near<R, MIXED>(items[it], pos_v, rows64, rows32, V, partial, pstride, pj0);
 }
 
 template <int R, bool MIXED>
@@ -92,16 +95,36 @@ __global__ void __launch_bounds__(256) k_map(const void* __restrict__ pos_v,
 // out[i] = pref * (sum of the slots of visit j0 + i), i < n.
 __global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict__ partial,
                                                         const int32_t* __restrict__ tile_slots,
-                                                        int64_t V, int tile, double pref,
-                                                        int64_t j0, int64_t n,
+                                                        int64_t pstride, int64_t pj0, int tile,
+                                                        double pref, int64_t j0, int64_t n,
                                                         double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = j0 + i;
     const int ns = tile_slots[j / tile];
     double s = 0.0;
-    for (int k = 0; k < ns; ++k) s += partial[(int64_t)k * V + j];
+    for (int k = 0; k < ns; ++k) s += partial[(int64_t)k * pstride + (j - pj0)];
     out[i] = pref * s;
+  }
+}
+
+// The same sums when a visit has many slots (a visit range with short lag
+// chunks): one wave per visit, lane l adding slots l, l + 64, ... in order,
+// then a butterfly over the lanes in a fixed pattern (deterministic).
+__global__ void __launch_bounds__(256) k_reduce_arrival_wide(const double* __restrict__ partial,
+                                                             const int32_t* __restrict__ tile_slots,
+                                                             int64_t pstride, int64_t pj0, int tile,
+                                                             double pref, int64_t j0, int64_t n,
+                                                             double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = blockIdx.x * 4 + wave_id(); i < n; i += (int64_t)gridDim.x * 4) {
+    const int64_t j = j0 + i;
+    const int ns = tile_slots[j / tile];
+    double s = 0.0;
+    for (int k = lane; k < ns; k += 64) s += partial[(int64_t)k * pstride + (j - pj0)];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) out[i] = pref * s;
   }
 }
 
@@ -169,11 +192,11 @@ template <int R>
 static void launch_arrival_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
   if (L.mixed) {
     hipLaunchKernelGGL((k_arrival_far32<R>), dim3(blocks), dim3(256), 0, st, L.pos4,
-                       L.rows32, L.items, L.n_items, L.V, L.bounds, L.partial);
+                       L.rows32, L.items, L.n_items, L.V, L.bounds, L.partial, L.pstride, L.pj0);
   } else {
     hipLaunchKernelGGL((k_arrival_far64<R>), dim3(blocks), dim3(256), 0, st,
                        (const double2*)L.pos, L.rows64, L.items, L.n_items, L.V, L.bounds,
-                       L.partial);
+                       L.partial, L.pstride, L.pj0);
   }
 }
 
@@ -181,10 +204,10 @@ template <int R>
 static void launch_arrival_near_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
   if (L.mixed)
     hipLaunchKernelGGL((k_arrival_near<R, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,
-                       L.rows32, L.items, L.n_items, L.V, L.partial);
+                       L.rows32, L.items, L.n_items, L.V, L.partial, L.pstride, L.pj0);
   else
     hipLaunchKernelGGL((k_arrival_near<R, false>), dim3(blocks), dim3(256), 0, st, L.pos,
-                       L.rows64, L.rows32, L.items, L.n_items, L.V, L.partial);
+                       L.rows64, L.rows32, L.items, L.n_items, L.V, L.partial, L.pstride, L.pj0);
 }
 
 // Near-band and far-region items are launched separately (L.near).
@@ -227,12 +250,22 @@ hipError_t launch_map(const MapLaunch& L, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots, int64_t V,
-                                 int tile, double pref, int64_t j0, int64_t n, double* out,
-                                 hipStream_t st) {
+hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots,
+                                 int64_t pstride, int64_t pj0, int tile, double pref, int64_t j0,
+                                 int64_t n, double* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_arrival, dim3(grid_for(n)), dim3(256), 0, st, partial, tile_slots,
-                     V, tile, pref, j0, n, out);
+                     pstride, pj0, tile, pref, j0, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_arrival_wide(const double* partial, const int32_t* tile_slots,
+                                      int64_t pstride, int64_t pj0, int tile, double pref,
+                                      int64_t j0, int64_t n, double* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_reduce_arrival_wide, dim3(blocks), dim3(256), 0, st, partial, tile_slots,
+                     pstride, pj0, tile, pref, j0, n, out);
   return hipGetLastError();
 }
 

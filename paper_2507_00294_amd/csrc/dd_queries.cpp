@@ -133,11 +133,15 @@ void count_segments(const DegreeBounds& b, int64_t lo, int64_t hi, bool mixed, P
 // The near items go to `near` and the far items to `far`, both in planning
 // order.  Pair and flop counts (for the profiler) are formed only if `count`.
 // With j1 >= 0 only the tiles holding visits [j0, j1) get items (tile_slots
-// keeps one entry per tile of the scan).
+// keeps one entry per tile of the scan).  near_piece > 0 cuts the near band
+// into pieces of that many lags, each a work item with its own slot (slots
+// 0 .. np-1; the far chunks follow), so that a short range still has
+// enough items; every piece is planned for every near tile, empty ones
+// included, so that each slot a visit sums is written.
 void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPlan& P,
                   std::vector<ArrItem>& near, std::vector<ArrItem>& far,
                   std::vector<int32_t>& tile_slots, bool count, int64_t j0 = 0,
-                  int64_t j1 = -1) {
+                  int64_t j1 = -1, int64_t near_piece = 0) {
   const int T = 64 * R, TN = 64 * RN;
   const int64_t V = s->V;
   const double a_max = (double)(s->desc.nx - 1) * (s->desc.nx - 1) +
@@ -150,11 +154,13 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
   P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
   P.near_pairs = P.near_flops = P.far_pairs = P.far_flops = 0;
   const int64_t n_tiles = (V + T - 1) / T;
+  const int64_t piece = near_piece > 0 ? near_piece : std::max<int64_t>(1, kf - 1);
+  const int np = (int)std::max<int64_t>(1, (kf - 1 + piece - 1) / piece);
   near.clear();
   far.clear();
-  tile_slots.assign(n_tiles, 1);
+  tile_slots.assign(n_tiles, np);
   if (j1 < 0) j1 = V;
-  int S = 1;
+  int S = np;
   for (int64_t t = j0 / T; t < n_tiles && t * T < j1; ++t) {
     const int64_t J0 = t * T;
     const int64_t maxlag = std::min<int64_t>(J0 + T - 1, V - 1);
@@ -165,26 +171,30 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
       for (int64_t lo = kf; lo < span_end; lo += K, ++c) {
         const int64_t hi = std::min<int64_t>(lo + K, span_end);
         const int edge = (hi - 1 > J0) ? kItemEdge : 0;
-        far.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)hi, (1 + c) | edge});
+        far.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)hi, (np + c) | edge});
         if (count)
           count_segments(P.bounds, lo, hi, mixed,
                          [&](int64_t a, int64_t e) { return arrival_pairs(J0, jend, a, e); },
                          P.far_pairs, P.far_flops);
       }
     }
-    tile_slots[t] = 1 + c;
-    S = std::max(S, 1 + c);
+    tile_slots[t] = np + c;
+    S = std::max(S, np + c);
   }
-  // near band: tiles of 64 RN visits, lags [1, kf), slot 0
+  // near band: tiles of 64 RN visits, lags [1, kf) in np pieces, slots 0 .. np-1
   for (int64_t t = j0 / TN; t < (V + TN - 1) / TN && t * TN < j1; ++t) {
     const int64_t J0 = t * TN;
     const int64_t maxlag = std::min<int64_t>(J0 + TN - 1, V - 1);
-    const int64_t nhi = std::max<int64_t>(1, std::min<int64_t>(kf, maxlag + 1));
-    near.push_back(ArrItem{(int32_t)t, 1, (int32_t)nhi, 0 | kItemNear});
-    if (count) {
-      const double np_ = arrival_pairs(J0, std::min<int64_t>(J0 + TN, V), 1, nhi);
-      P.near_pairs += np_;
-      P.near_flops += np_ * series_flops(mixed ? kMNear32 : kM64, mixed);
+    for (int p = 0; p < np; ++p) {
+      const int64_t lo = 1 + (int64_t)p * piece;
+      const int64_t hi = std::min<int64_t>(kf, lo + piece);
+      const int64_t nhi = std::max<int64_t>(lo, std::min<int64_t>(hi, maxlag + 1));
+      near.push_back(ArrItem{(int32_t)t, (int32_t)lo, (int32_t)nhi, p | kItemNear});
+      if (count) {
+        const double np_ = arrival_pairs(J0, std::min<int64_t>(J0 + TN, V), lo, nhi);
+        P.near_pairs += np_;
+        P.near_flops += np_ * series_flops(mixed ? kMNear32 : kM64, mixed);
+      }
     }
   }
   P.R = R;
@@ -295,6 +305,8 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   L.V = s->V;
   L.bounds = P.bounds;
   L.partial = s->partial.as<double>();
+  L.pstride = s->V;
+  L.pj0 = 0;
   L.R = R;
   L.mixed = mixed;
   L.items = s->items.as<ArrItem>();
@@ -312,7 +324,7 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   DD_HIP(launch_arrival(L, st), "arrival far-region launch");
   prof_end(tf, st, P.far_pairs, P.far_flops);
   ProfToken tq = prof_begin("reduce", st);
-  DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 64 * R,
+  DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 0, 64 * R,
                                s->pref, 0, s->V, out_dev, st),
          "arrival reduce launch");
   prof_end(tq, st, 0, 0);
@@ -332,12 +344,20 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   if (j1 <= j0) return DD_OK;
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
-  int K = (int)std::min<int64_t>(std::max<int64_t>(512, (s->V + 255) / 256), 1 << 28);
-  K = std::max(R, (K + R - 1) / R * R);
+  // Partial sums keep only the columns of the range's tiles, so the lag
+  // chunks can be short: about 8192 far items over the range's tiles, and
+  // the near band in pieces of 16 lags.
+  const int64_t T = 64 * R, TN = 64 * RN;
+  const int64_t pj0 = std::min(j0 / T * T, j0 / TN * TN);
+  const int64_t pend = std::max((j1 + T - 1) / T * T, (j1 + TN - 1) / TN * TN);
+  const int64_t pstride = pend - pj0;
+  const int64_t tiles = (j1 - 1) / T - j0 / T + 1;
+  int64_t K64 = std::max<int64_t>(64, (tiles * j1 + 8191) / 8192);
+  const int K = (int)std::min<int64_t>((K64 + R - 1) / R * R, 1 << 28);
   ArrivalPlan P;
   std::vector<ArrItem> items, far;
   std::vector<int32_t> tile_slots;
-  plan_arrival(s, mixed, R, RN, K, P, items, far, tile_slots, prof_on(), j0, j1);
+  plan_arrival(s, mixed, R, RN, K, P, items, far, tile_slots, prof_on(), j0, j1, 16);
   auto longer = [](const ArrItem& a, const ArrItem& b) {
     return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
   };
@@ -348,7 +368,7 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   if (rc != DD_OK) return rc;
   rc = upload(s->aux3, tile_slots, st);
   if (rc != DD_OK) return rc;
-  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)s->V), "device allocation");
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)pstride), "device allocation");
   ArrivalLaunch L{};
   L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
                 : (const void*)(s->pos64.as<double2>() + kPosPad);
@@ -358,6 +378,8 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   L.V = s->V;
   L.bounds = P.bounds;
   L.partial = s->partial.as<double>();
+  L.pstride = pstride;
+  L.pj0 = pj0;
   L.mixed = mixed;
   L.items = s->aux2.as<ArrItem>();
   L.n_items = P.n_near;
@@ -374,8 +396,9 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   DD_HIP(launch_arrival(L, st), "arrival far-region launch");
   prof_end(tf, st, P.far_pairs, P.far_flops);
   ProfToken tq = prof_begin("reduce", st);
-  DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux3.as<int32_t>(), s->V, 64 * R,
-                               s->pref, j0, j1 - j0, out_dev, st),
+  DD_HIP((P.S > 64 ? launch_reduce_arrival_wide : launch_reduce_arrival)(
+             s->partial.as<double>(), s->aux3.as<int32_t>(), pstride, pj0, 64 * R, s->pref, j0,
+             j1 - j0, out_dev, st),
          "arrival reduce launch");
   prof_end(tq, st, 0, 0);
   return DD_OK;
