@@ -275,9 +275,9 @@ def main():
         del out
         sc.close()
 
-    # General visit list (FP64): a 256x256 raster with per-visit dwell
-    # jitter and a flyback dead time after every line; psi at every visit
-    # when it starts and the final map at the probes, one call each.
+    # General visit list: a 256x256 raster with per-visit dwell jitter and a
+    # flyback dead time after every line; psi at every visit when it starts
+    # and the final map at the probes, one call each, in FP64 and mixed.
     gvl = None
     if not args.no_visits:
         vl = wl.visit_list("flyback", 256, 256, seed=21)
@@ -285,31 +285,34 @@ def main():
         arr = torch.empty(vl.n_visits, dtype=torch.float64, device="cuda")
         fin = torch.empty((1, 256, 256), dtype=torch.float64, device="cuda")
         margs = (0.0, 0.0, 1e-9, 1e-9, 256, 256, [vl.t_end])
-        gv.arrival(out=arr)
-        gv.damage_map(*margs, out=fin)
-        torch.cuda.synchronize()
-        ta, tm = [], []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            gv.arrival(out=arr)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            gv.damage_map(*margs, out=fin)
-            torch.cuda.synchronize()
-            ta.append(t1 - t0)
-            tm.append(time.perf_counter() - t1)
-        t_a, t_m = float(np.median(ta)), float(np.median(tm))
         pa = float(wl.causal_arrival_pairs(vl.n_visits))
         pm = float(vl.n_visits) * 256 * 256
-        gvl = {"value": (pa + pm) / (t_a + t_m), "unit": "pair-terms/s",
-               "ms_per_call": (t_a + t_m) * 1e3, "arrival_ms": t_a * 1e3, "map_ms": t_m * 1e3,
-               "pairs_per_call": pa + pm, "precision": "fp64",
-               "workload": "general visit list: 256x256 raster (pitch 1 nm, sigma 0.5 nm, "
-                           "D 2.5e-13 m^2/s), dwell 1 us x U(0.5, 1.5) per visit, 64 us "
-                           "flyback after every line (seed 21); arrival at every visit + "
-                           "final map at the probes"}
-        log(f"[bench] visit list: arrival {t_a * 1e3:.1f} ms, final map {t_m * 1e3:.1f} ms, "
-            f"{gvl['value']:.4e} pairs/s")
+        res = {}
+        for pr in ("fp64", "mixed"):
+            gv.arrival(pr, out=arr)
+            gv.damage_map(*margs, pr, out=fin)
+            torch.cuda.synchronize()
+            ta, tm = [], []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                gv.arrival(pr, out=arr)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                gv.damage_map(*margs, pr, out=fin)
+                torch.cuda.synchronize()
+                ta.append(t1 - t0)
+                tm.append(time.perf_counter() - t1)
+            t_a, t_m = float(np.median(ta)), float(np.median(tm))
+            res[pr] = {"value": (pa + pm) / (t_a + t_m), "ms_per_call": (t_a + t_m) * 1e3,
+                       "arrival_ms": t_a * 1e3, "map_ms": t_m * 1e3}
+            log(f"[bench] visit list {pr}: arrival {t_a * 1e3:.1f} ms, final map "
+                f"{t_m * 1e3:.1f} ms, {res[pr]['value']:.4e} pairs/s")
+        gvl = dict(res["fp64"], unit="pair-terms/s", pairs_per_call=pa + pm, precision="fp64",
+                   mixed=res["mixed"],
+                   workload="general visit list: 256x256 raster (pitch 1 nm, sigma 0.5 nm, "
+                            "D 2.5e-13 m^2/s), dwell 1 us x U(0.5, 1.5) per visit, 64 us "
+                            "flyback after every line (seed 21); arrival at every visit + "
+                            "final map at the probes")
         gv.close()
 
     # Learned surrogate against the exact batched kernel on the held-out 64x64

@@ -276,7 +276,8 @@ dd_status dd_unet_predict(dd_unet *u, dd_scan *const *scans, int32_t n, double s
  * visits with t_i < t.  A general list states every visit this way, so
  * per-visit dwells, flyback and dead time between lines or frames,
  * subsampled (sparse) scans, revisits and any visit order are all lists.
- * Evaluated in FP64 (the same bound as DD_FP64 above).                   */
+ * DD_FP64 meets the FP64 bound; DD_MIXED evaluates the near-pair integral
+ * (almost every pair of a long list) in FP32 and meets the mixed bound.   */
 typedef struct dd_visits dd_visits; /* opaque */
 
 /* Copies n >= 1 visits: x_m, y_m (metres), t0_s (beam-on start, seconds)
@@ -295,15 +296,16 @@ int64_t dd_visits_count(const dd_visits *v);
 /* psi at each visit's position at the moment its beam turns on: out[i] =
  * psi(r_i, t0_i), the sum over visits j with t0_j < t0_i (Eq. 6), in the
  * caller's visit order.  out: [n].
- * Errors: DD_EINVAL (NULL), DD_ENOMEM, DD_EDEVICE.                        */
-dd_status dd_visits_arrival(dd_visits *v, double *out, int32_t out_on_device, void *hip_stream);
+ * Errors: DD_EINVAL (NULL, precision), DD_ENOMEM, DD_EDEVICE.             */
+dd_status dd_visits_arrival(dd_visits *v, dd_precision p, double *out, int32_t out_on_device,
+                            void *hip_stream);
 
 /* psi on grid g at n_t >= 1 finite times t_s (host array, seconds on the
  * visits' clock), out [n_t][h][w] row-major; visits not started at a time
  * give it nothing.
- * Errors: DD_EINVAL (NULL, grid, times), DD_ENOMEM, DD_EDEVICE.           */
+ * Errors: DD_EINVAL (NULL, grid, times, precision), DD_ENOMEM, DD_EDEVICE. */
 dd_status dd_visits_map(dd_visits *v, const dd_grid *g, const double *t_s, int32_t n_t,
-                        double *out, int32_t out_on_device, void *hip_stream);
+                        dd_precision p, double *out, int32_t out_on_device, void *hip_stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);

@@ -116,8 +116,8 @@ def load_library():
     lib.dd_visits_destroy.restype = None
     lib.dd_visits_count.argtypes = [vp]
     lib.dd_visits_count.restype = i64
-    lib.dd_visits_arrival.argtypes = [vp, vp, i32, vp]
-    lib.dd_visits_map.argtypes = [vp, P(Grid), P(dbl), i32, vp, i32, vp]
+    lib.dd_visits_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
+    lib.dd_visits_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
@@ -278,7 +278,8 @@ class Scan:
 class Visits:
     """A general visit list (``dd_visits``): visit i at (x_m[i], y_m[i]) with
     the beam on from t0_s[i] for dwell_s[i] seconds (any order, overlaps
-    allowed), evaluated in FP64.  SI units as in ``Scan``."""
+    allowed), evaluated in FP64 or "mixed" (the near-pair integral in FP32).
+    SI units as in ``Scan``."""
 
     def __init__(self, x_m, y_m, t0_s, dwell_s, *, sigma_m: float = 0.5e-9,
                  D_m2s: float = 2.5e-13, Q0_us: float = 1.0):
@@ -308,7 +309,7 @@ class Visits:
     def num_visits(self) -> int:
         return int(load_library().dd_visits_count(self._h))
 
-    def arrival(self, out=None, stream=None):
+    def arrival(self, precision: str = "fp64", out=None, stream=None):
         """psi at each visit's position when its beam turns on
         (``dd_visits_arrival``), float64 CUDA tensor [n] in visit order."""
         torch = _torch()
@@ -316,12 +317,13 @@ class Visits:
             out = torch.empty(self.num_visits, dtype=torch.float64, device="cuda")
         assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
         assert out.numel() == self.num_visits
-        _check(load_library().dd_visits_arrival(self._h, ctypes.c_void_p(out.data_ptr()), 1,
+        _check(load_library().dd_visits_arrival(self._h, _prec(precision),
+                                                ctypes.c_void_p(out.data_ptr()), 1,
                                                 _stream(stream)))
         return out
 
     def damage_map(self, x0_m: float, y0_m: float, dx_m: float, dy_m: float, w: int, h: int,
-                   times_s: Iterable[float], out=None, stream=None):
+                   times_s: Iterable[float], precision: str = "fp64", out=None, stream=None):
         """psi on a w-by-h pixel grid at each time (``dd_visits_map``),
         float64 CUDA tensor [n_t, h, w]."""
         torch = _torch()
@@ -333,7 +335,7 @@ class Visits:
         g = Grid(x0_m, y0_m, dx_m, dy_m, w, h)
         _check(load_library().dd_visits_map(
             self._h, ctypes.byref(g), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
-            ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
+            _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
         return out
 
 

@@ -48,9 +48,10 @@ struct VisGrid {
   int32_t w, pad;
 };
 
-// Partial sums of every item: arrival (map = false) or map points.  vis
+// Partial sums of every item: arrival (map = false) or map points, in FP64
+// or with the FP32 near form (mixed).  vis
 // holds (x, y, t0, dwell) per visit in start order; times the map's times.
-hipError_t launch_visit_pairs(bool map, const double4* vis, const VisTile* tiles,
+hipError_t launch_visit_pairs(bool map, bool mixed, const double4* vis, const VisTile* tiles,
                               const VisItem* items, int64_t n_items, const double* times,
                               VisGrid grid, VisPhys phys, double* partial,
                               hipStream_t st);

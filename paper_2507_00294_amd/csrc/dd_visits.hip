@@ -113,6 +113,37 @@ __device__ __forceinline__ int near_rule(double q, double dx) {
   return q <= 0.3 ? 3 : 4;
 }
 
+// The linear near form in FP32 for the mixed precision: e^-w and 1/(x1 + w)
+// per node by the hardware exp2 and reciprocal (about 1 ulp each); e^-x1
+// with its integer power of two split off in FP64 (x1 reaches 745, beyond
+// the FP32 range, and x1 rounded to FP32 would cost x1 * 6e-8 relative).
+template <int N>
+__device__ __forceinline__ double near_linear_f32(double x1, double dx) {
+  constexpr GLRule<N> g{};
+  const float x1f = (float)x1, dxf = (float)dx;
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const float w = dxf * (float)g.x[k];
+    const float e = __builtin_amdgcn_exp2f(-w * 1.44269504f);
+    s = __builtin_fmaf((float)g.w[k], e * __builtin_amdgcn_rcpf(x1f + w), s);
+  }
+  const double y = x1 * kLog2e;
+  const double n = __builtin_rint(y);
+  const float f = (float)(n - y);  // |f| <= 1/2
+  return __builtin_ldexp((double)(__builtin_amdgcn_exp2f(f) * dxf * s), -(int)n);
+}
+
+// Node counts of the FP32 form: rule errors below 4e-8 relative (same study
+// as near_rule): 2 nodes for q <= 0.01 and dx <= 0.1, 3 for q <= 0.03 and
+// dx <= 0.3, 4 for q <= 0.1, 6 for q <= 0.3, 8 up to q = 1.
+__device__ __forceinline__ int near_rule_mixed(double q, double dx) {
+  if (q <= 0.01 && dx <= 0.1) return 0;
+  if (q <= 0.03 && dx <= 0.3) return 1;
+  if (q <= 0.1) return 2;
+  return q <= 0.3 ? 3 : 4;
+}
+
 // sum_{n>=1} (-1)^n x^n / (n n!) for x <= 1.16 (18 terms, remainder < 2e-17).
 __device__ __forceinline__ double e1_series_tail(double x) {
   constexpr E1SeriesCoef k{};
@@ -147,23 +178,38 @@ __device__ __noinline__ double far_or_log_term(double x1, double dx, double q) {
 // contributes at all.  The linear near form, almost every pair of a long
 // scan, runs with the node count the wave's lanes need at most, so that
 // the branch is the same for the whole wave.
+template <bool MIXED>
 __device__ __forceinline__ double pair_term(bool active, double x1, double dx, double q) {
   const bool lin = active && dx <= 1.0 && q <= 1.0 && x1 > 0.0;
   double t = 0.0;
   if (__ballot(lin)) {
-    const int need = lin ? near_rule(q, dx) : -1;
     const double u = lin ? x1 : 1.0, v = lin ? dx : 0.0;
     double r;
-    if (__ballot(need == 4))
-      r = near_linear<12, 0>(u, v);
-    else if (__ballot(need == 3))
-      r = near_linear<8, 0>(u, v);
-    else if (__ballot(need == 2))
-      r = near_linear<6, 0>(u, v);
-    else if (__ballot(need == 1))
-      r = near_linear<4, 9>(u, v);
-    else
-      r = near_linear<3, 7>(u, v);
+    if (MIXED) {
+      const int need = lin ? near_rule_mixed(q, dx) : -1;
+      if (__ballot(need == 4))
+        r = near_linear_f32<8>(u, v);
+      else if (__ballot(need == 3))
+        r = near_linear_f32<6>(u, v);
+      else if (__ballot(need == 2))
+        r = near_linear_f32<4>(u, v);
+      else if (__ballot(need == 1))
+        r = near_linear_f32<3>(u, v);
+      else
+        r = near_linear_f32<2>(u, v);
+    } else {
+      const int need = lin ? near_rule(q, dx) : -1;
+      if (__ballot(need == 4))
+        r = near_linear<12, 0>(u, v);
+      else if (__ballot(need == 3))
+        r = near_linear<8, 0>(u, v);
+      else if (__ballot(need == 2))
+        r = near_linear<6, 0>(u, v);
+      else if (__ballot(need == 1))
+        r = near_linear<4, 9>(u, v);
+      else
+        r = near_linear<3, 7>(u, v);
+    }
     t = lin ? r : 0.0;
   }
   if (active && !lin) t = far_or_log_term(x1, dx, q);
@@ -175,7 +221,7 @@ __device__ __forceinline__ double pair_term(bool active, double x1, double dx, d
 // that starts at or after the tile's latest time ends the item for the
 // whole block.  Map tiles share one time: the per-visit factors (1/b1,
 // db/(b0 b1), db/b0) are then formed once per staged visit.
-template <bool MAP>
+template <bool MAP, bool MIXED>
 __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
     const double4* __restrict__ vis, const VisTile* __restrict__ tiles,
     const VisItem* __restrict__ items, int64_t n_items, const double* __restrict__ times,
@@ -236,7 +282,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
         if (MAP) {
           const double4 f = s_f[j];
           const double x1 = a * f.x;
-          sum += pair_term(live && f.x > 0.0 && x1 <= 745.0, x1, a * f.y, f.z);
+          sum += pair_term<MIXED>(live && f.x > 0.0 && x1 <= 745.0, x1, a * f.y, f.z);
         } else {
           const double dt = pt - v.z;
           const bool started = live && dt > 0.0;
@@ -245,7 +291,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
           const double b1 = b0 + db;
           const double rr = rcp64(started ? b0 * b1 : 4.0);  // 1 / (b0 b1)
           const double x1 = a * (b0 * rr), q = db * (b1 * rr);
-          sum += pair_term(started && x1 <= 745.0, x1, x1 * q, q);
+          sum += pair_term<MIXED>(started && x1 <= 745.0, x1, x1 * q, q);
         }
       }
     }
@@ -268,18 +314,24 @@ __global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisTile* __rest
 
 }  // namespace
 
-hipError_t launch_visit_pairs(bool map, const double4* vis, const VisTile* tiles,
+hipError_t launch_visit_pairs(bool map, bool mixed, const double4* vis, const VisTile* tiles,
                               const VisItem* items, int64_t n_items, const double* times,
                               VisGrid grid, VisPhys phys, double* partial,
                               hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(n_items, 1 << 20);
-  if (map)
-    k_visit_pairs<true><<<blocks, kVisTile, 0, st>>>(vis, tiles, items, n_items, times, grid,
-                                                     phys, partial);
+#define DD_VISIT_LAUNCH(M, X)                                                                 \
+  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(vis, tiles, items, n_items, times, grid, phys, \
+                                                   partial)
+  if (map && mixed)
+    DD_VISIT_LAUNCH(true, true);
+  else if (map)
+    DD_VISIT_LAUNCH(true, false);
+  else if (mixed)
+    DD_VISIT_LAUNCH(false, true);
   else
-    k_visit_pairs<false><<<blocks, kVisTile, 0, st>>>(vis, tiles, items, n_items, times, grid,
-                                                      phys, partial);
+    DD_VISIT_LAUNCH(false, false);
+#undef DD_VISIT_LAUNCH
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // dd_visits_host.cpp -- the general visit list handle (dd_visits_*): every visit
 // with its own position, start time and dwell (Sec. II, Eqs. 1-4 per visit,
-// Eq. 6 over the visits started before the query time), in FP64.
+// Eq. 6 over the visits started before the query time), in FP64 or with
+// the near form in FP32 (mixed).
 //
 // Work planning.  Visits are kept in start order.  Evaluation points go in
 // tiles of 256 (one thread each); visits in chunks of K (a multiple of 256,
@@ -111,7 +112,7 @@ struct dd_visits {
 
   // Uploads the current tiles and items, launches the pair and reduce
   // kernels for them.
-  dd_status launch(bool map, const VisGrid& grid, double* out, hipStream_t st) {
+  dd_status launch(bool map, bool mixed, const VisGrid& grid, double* out, hipStream_t st) {
     int64_t pbase = 0;
     for (VisTile& t : h_tiles) {
       t.pbase = pbase;
@@ -130,7 +131,7 @@ struct dd_visits {
                              hipMemcpyHostToDevice, st),
               "host-to-device copy");
     const ProfToken tok = prof_begin("k_visit_pairs", st);
-    VIS_HIP(launch_visit_pairs(map, d_vis.as<double4>(), d_tiles.as<VisTile>(),
+    VIS_HIP(launch_visit_pairs(map, mixed, d_vis.as<double4>(), d_tiles.as<VisTile>(),
                                d_items.as<VisItem>(), (int64_t)h_items.size(),
                                d_times.as<double>(), grid, VisPhys{inv_sigma, th4},
                                d_partial.as<double>(), st),
@@ -152,7 +153,7 @@ struct dd_visits {
     return p;
   }
 
-  dd_status arrival(double* out, hipStream_t st) {
+  dd_status arrival(bool mixed, double* out, hipStream_t st) {
     const int64_t n_tiles = (n + kVisTile - 1) / kVisTile;
     for (int64_t g0 = 0; g0 < n_tiles; g0 += kGroupTiles) {
       const int64_t g1 = std::min(n_tiles, g0 + kGroupTiles);
@@ -167,13 +168,14 @@ struct dd_visits {
         tile.slots = plan_tile((int32_t)(t - g0), b, tmax);
         h_tiles.push_back(tile);
       }
-      dd_status rc = launch(false, VisGrid{}, out, st);
+      dd_status rc = launch(false, mixed, VisGrid{}, out, st);
       if (rc != DD_OK) return rc;
     }
     return DD_OK;
   }
 
-  dd_status map(const dd_grid* g, const double* t_s, int32_t n_t, double* out, hipStream_t st) {
+  dd_status map(const dd_grid* g, const double* t_s, int32_t n_t, bool mixed, double* out,
+                hipStream_t st) {
     const int64_t npix = (int64_t)g->w * g->h;
     const int64_t per = (npix + kVisTile - 1) / kVisTile;  // tiles per time
     VIS_HIP(d_times.ensure(sizeof(double) * n_t), "device allocation");
@@ -201,7 +203,7 @@ struct dd_visits {
         tile.slots = plan_tile((int32_t)(t - g0), boxes[b], t_s[m]);
         h_tiles.push_back(tile);
       }
-      dd_status rc = launch(true, grid, out, st);
+      dd_status rc = launch(true, mixed, grid, out, st);
       if (rc != DD_OK) return rc;
     }
     return DD_OK;
@@ -272,14 +274,17 @@ void dd_visits_destroy(dd_visits* v) {
 
 int64_t dd_visits_count(const dd_visits* v) { return v ? v->n : -1; }
 
-dd_status dd_visits_arrival(dd_visits* v, double* out, int32_t out_on_device, void* hip_stream) {
+dd_status dd_visits_arrival(dd_visits* v, dd_precision p, double* out, int32_t out_on_device,
+                            void* hip_stream) {
   if (!v || !out) return fail(DD_EINVAL, "NULL argument");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  const bool mixed = p == DD_MIXED;
   hipStream_t st = (hipStream_t)hip_stream;
   dd_status rc = v->prepare(st);
   if (rc != DD_OK) return rc;
-  if (out_on_device) return v->arrival(out, st);
+  if (out_on_device) return v->arrival(mixed, out, st);
   VIS_HIP(v->tmp_out.ensure(sizeof(double) * v->n), "device allocation");
-  rc = v->arrival(v->tmp_out.as<double>(), st);
+  rc = v->arrival(mixed, v->tmp_out.as<double>(), st);
   if (rc != DD_OK) return rc;
   VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * v->n, hipMemcpyDeviceToHost, st),
           "device-to-host copy");
@@ -288,8 +293,10 @@ dd_status dd_visits_arrival(dd_visits* v, double* out, int32_t out_on_device, vo
 }
 
 dd_status dd_visits_map(dd_visits* v, const dd_grid* g, const double* t_s, int32_t n_t,
-                        double* out, int32_t out_on_device, void* hip_stream) {
+                        dd_precision p, double* out, int32_t out_on_device, void* hip_stream) {
   if (!v || !g || !out || (n_t > 0 && !t_s)) return fail(DD_EINVAL, "NULL argument");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  const bool mixed = p == DD_MIXED;
   if (n_t < 1) return fail(DD_EINVAL, "n_t must be >= 1");
   if (g->w < 1 || g->h < 1) return fail(DD_EINVAL, "grid w and h must be >= 1");
   if ((int64_t)g->w * g->h > (1LL << 30)) return fail(DD_EINVAL, "grid too large");
@@ -300,10 +307,10 @@ dd_status dd_visits_map(dd_visits* v, const dd_grid* g, const double* t_s, int32
   hipStream_t st = (hipStream_t)hip_stream;
   dd_status rc = v->prepare(st);
   if (rc != DD_OK) return rc;
-  if (out_on_device) return v->map(g, t_s, n_t, out, st);
+  if (out_on_device) return v->map(g, t_s, n_t, mixed, out, st);
   const size_t nout = (size_t)n_t * g->w * g->h;
   VIS_HIP(v->tmp_out.ensure(sizeof(double) * nout), "device allocation");
-  rc = v->map(g, t_s, n_t, v->tmp_out.as<double>(), st);
+  rc = v->map(g, t_s, n_t, mixed, v->tmp_out.as<double>(), st);
   if (rc != DD_OK) return rc;
   VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * nout, hipMemcpyDeviceToHost, st),
           "device-to-host copy");

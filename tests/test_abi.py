@@ -197,12 +197,14 @@ def test_visit_list_validation(dd):
     out = (D * 3)()
     g = dd.Grid(0, 0, 1e-9, 1e-9, 2, 2)
     t = (D * 1)(1e-6)
-    assert lib.dd_visits_arrival(None, vp(out), 0, None) == dd.DD_EINVAL
-    assert lib.dd_visits_map(v._h, ctypes.byref(g), t, 0, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_arrival(None, 0, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_arrival(v._h, 7, vp(out), 0, None) == dd.DD_EINVAL  # precision
+    assert lib.dd_visits_map(v._h, ctypes.byref(g), t, 0, 0, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_map(v._h, ctypes.byref(g), t, 1, 5, vp(out), 0, None) == dd.DD_EINVAL
     g_bad = dd.Grid(0, 0, 1e-9, 1e-9, 0, 2)
-    assert lib.dd_visits_map(v._h, ctypes.byref(g_bad), t, 1, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_map(v._h, ctypes.byref(g_bad), t, 1, 0, vp(out), 0, None) == dd.DD_EINVAL
     t_bad = (D * 1)(float("inf"))
-    assert lib.dd_visits_map(v._h, ctypes.byref(g), t_bad, 1, vp(out), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_map(v._h, ctypes.byref(g), t_bad, 1, 0, vp(out), 0, None) == dd.DD_EINVAL
     lib.dd_visits_destroy(None)
 
 
@@ -214,5 +216,6 @@ def test_visit_list_fails_loudly_without_device(dd):
     lib = dd.load_library()
     v = dd.Visits([0.0, 1e-9], [0.0, 0.0], [0.0, 1e-6], [1e-6, 1e-6])
     out = (ctypes.c_double * 2)()
-    assert lib.dd_visits_arrival(v._h, ctypes.cast(out, ctypes.c_void_p), 0, None) == dd.DD_EDEVICE
+    assert lib.dd_visits_arrival(v._h, 0, ctypes.cast(out, ctypes.c_void_p), 0,
+                                 None) == dd.DD_EDEVICE
     assert lib.dd_last_error()

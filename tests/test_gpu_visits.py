@@ -1,8 +1,9 @@
 """General visit lists (``dd_visits_*``): per-visit dwell, flyback and dead
 time, sparse random subsets, revisits with unequal dwells and off-lattice
-positions, against the oracle's general list element by element (FP64
-bound); a uniform scan written as a list against the scan kernels; input
-order, host output and several tiles and visit chunks with ragged tails."""
+positions, against the oracle's general list element by element (the FP64
+and the mixed bound); a uniform scan written as a list against the scan
+kernels; input order, host output, several tiles, visit chunks and launch
+groups with ragged tails, and the benchmark's list sampled at full size."""
 import ctypes
 
 import numpy as np
@@ -12,6 +13,7 @@ from gpu_util import assert_close
 
 pytestmark = pytest.mark.gpu
 KINDS = ["flyback", "sparse", "frames", "drift"]
+PRECS = ["fp64", "mixed"]
 
 
 @pytest.fixture(scope="module")
@@ -39,19 +41,21 @@ def both(dd, ora, vl):
     return g, o
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("D", [2.5e-13, 3e-11])
-def test_arrival_vs_oracle(dd, ora, wl, kind, D):
+def test_arrival_vs_oracle(dd, ora, wl, kind, D, prec):
     # 9x7 lattice; D spans a diffusion length well below and well above the pitch
     vl = wl.visit_list(kind, 9, 7, seed=11, D_m2s=D)
     g, o = both(dd, ora, vl)
-    got = g.arrival().cpu().numpy()
+    got = g.arrival(prec).cpu().numpy()
     ref = o.psi_arrival()
-    assert_close(got, ref, vl, "fp64", f"{kind} arrival")
+    assert_close(got, ref, vl, prec, f"{kind} arrival")
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("kind", KINDS)
-def test_maps_vs_oracle(dd, ora, wl, kind):
+def test_maps_vs_oracle(dd, ora, wl, kind, prec):
     # off-lattice grid; times before the first start, mid-dwell, in a dead
     # time, at a dwell boundary and after the end
     vl = wl.visit_list(kind, 8, 6, seed=12, D_m2s=1e-12, sigma_m=0.4e-9)
@@ -60,23 +64,24 @@ def test_maps_vs_oracle(dd, ora, wl, kind):
     times = [float(vl.t0_s[0]) * 0.5, float(vl.t0_s[1] + 0.3 * vl.dwell_s[1]),
              float(vl.t0_s[i]), float(vl.t0_s[i] + vl.dwell_s[i]), vl.t_end, 3 * vl.t_end]
     args = (-1.1e-9, -0.7e-9, 0.37e-9, 0.41e-9, 29, 21)
-    got = g.damage_map(*args, times).cpu().numpy()
+    got = g.damage_map(*args, times, prec).cpu().numpy()
     ref = o.psi_map(*args, times)
-    assert_close(got, ref, vl, "fp64", f"{kind} maps")
+    assert_close(got, ref, vl, prec, f"{kind} maps")
     if vl.t0_s.min() > times[0]:
         assert np.all(got[0] == 0.0)
 
 
-def test_many_tiles_and_chunks_vs_oracle(dd, ora, wl):
+@pytest.mark.parametrize("prec", PRECS)
+def test_many_tiles_and_chunks_vs_oracle(dd, ora, wl, prec):
     # 1480 visits: 6 tiles (the last ragged) against 3 visit chunks of 512
     # (the last ragged); maps of 3 x 2400 pixels (10 tiles per time)
     vl = wl.visit_list("flyback", 40, 37, seed=13, D_m2s=1e-12)
     g, o = both(dd, ora, vl)
-    assert_close(g.arrival().cpu().numpy(), o.psi_arrival(), vl, "fp64", "arrival")
+    assert_close(g.arrival(prec).cpu().numpy(), o.psi_arrival(), vl, prec, "arrival")
     times = [0.37 * vl.t_end, 0.81 * vl.t_end, vl.t_end]
     args = (-2e-9, -1e-9, 0.9e-9, 0.8e-9, 60, 40)
-    assert_close(g.damage_map(*args, times).cpu().numpy(), o.psi_map(*args, times), vl, "fp64",
-                 "maps")
+    assert_close(g.damage_map(*args, times, prec).cpu().numpy(), o.psi_map(*args, times), vl,
+                 prec, "maps")
 
 
 def test_uniform_scan_as_list_matches_scan_kernels(dd, wl):
@@ -108,13 +113,13 @@ def test_input_order_and_host_output(dd, wl):
     assert np.array_equal(b, a[p])  # same start order inside, the same sums
     lib = dd.load_library()
     out = np.empty(vl.n_visits)
-    assert lib.dd_visits_arrival(g._h, ctypes.c_void_p(out.ctypes.data), 0, None) == 0
+    assert lib.dd_visits_arrival(g._h, 0, ctypes.c_void_p(out.ctypes.data), 0, None) == 0
     assert np.array_equal(out, a)
     gr = dd.Grid(0.0, 0.0, 1e-9, 1e-9, 30, 30)
     t = np.array([0.5 * vl.t_end, vl.t_end])
     mo = np.empty((2, 30, 30))
     assert lib.dd_visits_map(g._h, ctypes.byref(gr), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                             2, ctypes.c_void_p(mo.ctypes.data), 0, None) == 0
+                             2, 0, ctypes.c_void_p(mo.ctypes.data), 0, None) == 0
     assert np.array_equal(mo, g.damage_map(0.0, 0.0, 1e-9, 1e-9, 30, 30, t).cpu().numpy())
 
 
@@ -131,21 +136,22 @@ def test_single_visit_and_coincident_revisit(dd, ora):
     assert one.arrival().cpu().numpy()[0] == 0.0
 
 
-def test_bench_workload_sampled_vs_oracle(dd, ora, wl):
+@pytest.mark.parametrize("prec", PRECS)
+def test_bench_workload_sampled_vs_oracle(dd, ora, wl, prec):
     # the benchmark's list (256x256 raster, dwell jitter, flyback; 65536
     # visits) in the same calls the benchmark times: arrival at 48 sampled
     # visits and the final map at 48 sampled probes against the oracle
     vl = wl.visit_list("flyback", 256, 256, seed=21)
     g, o = both(dd, ora, vl)
-    arr = g.arrival().cpu().numpy()
+    arr = g.arrival(prec).cpu().numpy()
     idx = wl.sampled_visits(vl.n_visits, 48, seed=22)
     ref = o.psi_points(vl.x_m[idx], vl.y_m[idx], vl.t0_s[idx])
-    assert_close(arr[idx], ref, vl, "fp64", "arrival (sampled)")
-    fin = g.damage_map(0.0, 0.0, 1e-9, 1e-9, 256, 256, [vl.t_end]).cpu().numpy()[0]
+    assert_close(arr[idx], ref, vl, prec, "arrival (sampled)")
+    fin = g.damage_map(0.0, 0.0, 1e-9, 1e-9, 256, 256, [vl.t_end], prec).cpu().numpy()[0]
     pix = wl.sampled_visits(256 * 256, 48, seed=23)
     u, v = pix % 256, pix // 256
     ref = o.psi_points(u * 1e-9, v * 1e-9, np.full(pix.size, vl.t_end))
-    assert_close(fin[v, u], ref, vl, "fp64", "final map (sampled)")
+    assert_close(fin[v, u], ref, vl, prec, "final map (sampled)")
 
 
 def test_map_launch_groups(dd, ora, wl):
