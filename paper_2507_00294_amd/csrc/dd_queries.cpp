@@ -331,6 +331,31 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   return DD_OK;
 }
 
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    const size_t want = std::max(need, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+};
+
+// Staging of a visit range's plan: one pinned buffer per thread, copied to
+// the device asynchronously; the next range query on the thread waits for
+// that copy (`copied`) before it rewrites the buffer.
+struct RangeStage {
+  PinnedBuf host;
+  hipEvent_t copied = nullptr;  // kept until the process ends
+  bool pending = false;
+};
+static thread_local RangeStage g_range;
+
 // Arrival at the visits [j0, j1) only (streaming: the visits just made).
 // Only the tiles holding them are planned, with lag chunks of 512 lags (at
 // least V/256, which bounds the partial rows at 257 V), so that a few tiles
@@ -364,10 +389,22 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   std::stable_sort(items.begin(), items.end(), longer);
   std::stable_sort(far.begin(), far.end(), longer);
   items.insert(items.end(), far.begin(), far.end());  // near items first
-  rc = upload(s->aux2, items, st);
-  if (rc != DD_OK) return rc;
-  rc = upload(s->aux3, tile_slots, st);
-  if (rc != DD_OK) return rc;
+  const size_t bi = sizeof(ArrItem) * items.size(), bt = sizeof(int32_t) * tile_slots.size();
+  DD_HIP(s->aux2.ensure(std::max<size_t>(bi, 16)), "device allocation");
+  DD_HIP(s->aux3.ensure(std::max<size_t>(bt, 16)), "device allocation");
+  RangeStage& G = g_range;
+  if (G.pending) DD_HIP(hipEventSynchronize(G.copied), "event synchronize");
+  G.pending = false;
+  DD_HIP(G.host.ensure(bi + bt), "pinned host allocation");
+  if (bi) std::memcpy(G.host.p, items.data(), bi);
+  if (bt) std::memcpy((char*)G.host.p + bi, tile_slots.data(), bt);
+  if (!G.copied) DD_HIP(hipEventCreateWithFlags(&G.copied, hipEventDisableTiming), "event creation");
+  if (bi) DD_HIP(hipMemcpyAsync(s->aux2.p, G.host.p, bi, hipMemcpyHostToDevice, st),
+                 "host-to-device copy");
+  if (bt) DD_HIP(hipMemcpyAsync(s->aux3.p, (char*)G.host.p + bi, bt, hipMemcpyHostToDevice, st),
+                 "host-to-device copy");
+  DD_HIP(hipEventRecord(G.copied, st), "event record");
+  G.pending = true;
   DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)pstride), "device allocation");
   ArrivalLaunch L{};
   L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
@@ -684,20 +721,6 @@ dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStrea
 // The call's tables (scans, four item lists, reductions, tile slots) travel
 // in one pinned host block and one copy; the next call waits for that copy
 // (`copied`) before it rewrites the block.
-struct PinnedBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipError_t ensure(size_t need) {
-    if (need <= bytes && p) return hipSuccess;
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    bytes = 0;
-    const size_t want = std::max(need, (size_t)1 << 20);
-    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
-    if (e == hipSuccess) bytes = want;
-    return e;
-  }
-};
 
 struct BatchScratch {
   DevBuf block, partial, counter, staging;
