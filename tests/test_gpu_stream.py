@@ -52,3 +52,36 @@ def test_ranges_equal_full_arrival_and_oracle(dd, ora, wl, prec):
             assert_close(got, ref[j0:j1], spec, prec, f"range {j0}:{j1}")
         empty = scan.arrival_range(7, 7, prec)
         assert empty.numel() == 0
+
+
+@pytest.mark.parametrize("R,RN", [(2, 4), (4, 4), (2, 2)])
+def test_ranges_with_other_tile_shapes(dd, ora, wl, R, RN, tmp_path):
+    # tuned tile shapes (R, RN in {2, 4}) where the near tile (64 RN
+    # visits) is wider than or as wide as the far tile (64 R): the range's
+    # partial columns start at the earlier of the two tile origins
+    import json
+
+    default = {"arch": "gfx950", "arrival_mixed": {"R": 4, "RN": 2, "K": 2048},
+               "arrival_fp64": {"R": 2, "RN": 2, "K": 1024}, "map_mixed": {"R": 4, "K": 4096},
+               "map_fp64": {"R": 1}}
+    spec = wl.ScanSpec(23, 29, "random", 1e-9, 1e-6, 0.5e-9, 5e-13, 1.0, seed=13)
+    scan = dd.Scan(**spec.kwargs())
+    V = scan.num_visits
+    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+    try:
+        for prec, key in (("fp64", "arrival_fp64"), ("mixed", "arrival_mixed")):
+            cfg = json.loads(json.dumps(default))
+            cfg[key]["R"], cfg[key]["RN"] = R, RN
+            path = tmp_path / f"tune_{prec}.json"
+            path.write_text(json.dumps(cfg))
+            dd.tune_load(str(path))
+            full = scan.arrival(prec).cpu().numpy()
+            for j0, j1 in ((70, 200), (129, 130), (250, 520), (V - 300, V)):
+                got = scan.arrival_range(j0, j1, prec).cpu().numpy()
+                np.testing.assert_allclose(got, full[j0:j1],
+                                           rtol=1e-13 if prec == "fp64" else 2e-7, atol=0)
+                assert_close(got, ref[j0:j1], spec, prec, f"R={R} RN={RN} range {j0}:{j1}")
+    finally:
+        path = tmp_path / "tune_default.json"
+        path.write_text(json.dumps(default))
+        dd.tune_load(str(path))
