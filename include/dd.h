@@ -307,6 +307,15 @@ dd_status dd_visits_arrival(dd_visits *v, dd_precision p, double *out, int32_t o
 dd_status dd_visits_map(dd_visits *v, const dd_grid *g, const double *t_s, int32_t n_t,
                         dd_precision p, double *out, int32_t out_on_device, void *hip_stream);
 
+/* Arrival queries of n >= 1 lists in one launch, for many small lists:
+ * outs[k] gets [count(lists[k])] values, the same as dd_visits_arrival on
+ * lists[k] alone, bit for bit.  outs: n pointers, all on the device or all
+ * on the host (out_on_device).
+ * Errors: DD_EINVAL (NULL list or output, n < 1, precision), DD_ENOMEM,
+ * DD_EDEVICE.                                                             */
+dd_status dd_visits_batch_arrival(dd_visits *const *lists, int32_t n, dd_precision p,
+                                  double *const *outs, int32_t out_on_device, void *hip_stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);
 

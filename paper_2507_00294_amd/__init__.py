@@ -36,7 +36,7 @@ EXPORTS = (
     "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
     "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
     "dd_visits_destroy", "dd_visits_count", "dd_visits_arrival", "dd_visits_map",
-    "dd_last_error",
+    "dd_visits_batch_arrival", "dd_last_error",
 )
 
 
@@ -118,6 +118,7 @@ def load_library():
     lib.dd_visits_count.restype = i64
     lib.dd_visits_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_visits_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
+    lib.dd_visits_batch_arrival.argtypes = [P(vp), i32, ctypes.c_int, P(vp), i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
@@ -125,7 +126,7 @@ def load_library():
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
                  "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
-                 "dd_visits_arrival", "dd_visits_map"):
+                 "dd_visits_arrival", "dd_visits_map", "dd_visits_batch_arrival"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -337,6 +338,26 @@ class Visits:
             self._h, ctypes.byref(g), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t.size,
             _prec(precision), ctypes.c_void_p(out.data_ptr()), 1, _stream(stream)))
         return out
+
+
+def visits_batch_arrival(lists: Sequence[Visits], precision: str = "fp64", out=None,
+                         stream=None):
+    """Arrival queries of many visit lists in one launch
+    (``dd_visits_batch_arrival``): a list of float64 CUDA tensors, views of
+    one flat buffer (``out``, if given, of sum(num_visits) elements)."""
+    torch = _torch()
+    counts = [v.num_visits for v in lists]
+    if out is None:
+        out = torch.empty(sum(counts), dtype=torch.float64, device="cuda")
+    assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+    assert out.numel() == sum(counts)
+    views = list(torch.split(out, counts))
+    n = len(lists)
+    hs = (ctypes.c_void_p * n)(*[v._h.value for v in lists])
+    os_ = (ctypes.c_void_p * n)(*[t.data_ptr() for t in views])
+    _check(load_library().dd_visits_batch_arrival(hs, n, _prec(precision), os_, 1,
+                                                  _stream(stream)))
+    return views
 
 
 def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PROBES,

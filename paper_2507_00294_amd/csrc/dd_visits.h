@@ -18,21 +18,27 @@ constexpr int kVisTile = 256;     // evaluation points per tile (one per thread)
 constexpr int kVisStage = 256;    // visits staged in LDS at a time
 constexpr int kVisMaxSlots = 32;  // visit chunks (partial sums) per tile at most
 
-// Scaling of a pair: a_hat = |r - r_i|^2 / sigma^2 with inv_sigma, and
-// b_hat = 2 + 4 (D / sigma^2) lag with th4 = 4 D / sigma^2.
-struct VisPhys {
-  double inv_sigma, th4;
+// One visit list of a launch: its visits (x, y, t0, dwell) in start order,
+// the start order's caller indices (arrival), the output, and the scaling
+// of a pair: a_hat = |r - r_i|^2 / sigma^2 with inv_sigma, b_hat = 2 +
+// 4 (D / sigma^2) lag with th4 = 4 D / sigma^2, psi = pref * sum.
+struct VisList {
+  const double4* vis;
+  const int64_t* perm;
+  double* out;
+  double inv_sigma, th4, pref;
 };
 
-// A tile of evaluation points.  Arrival: the visits p0 .. p0+n-1 in start
-// order, each at its own position and start time.  Map: pixels p0 .. p0+n-1
-// of the grid at time index m.  Its partial sums sit at pbase + slot * 256.
+// A tile of evaluation points of list `list`.  Arrival: the visits p0 ..
+// p0+n-1 in start order, each at its own position and start time.  Map:
+// pixels p0 .. p0+n-1 of the grid at time index m.  Its partial sums sit at
+// pbase + slot * 256.
 struct VisTile {
   int64_t p0;
   int64_t pbase;
   int64_t out0;  // map: output index of the first point
   double tmax;   // latest point time of the tile
-  int32_t n, m, slots, pad;
+  int32_t n, m, slots, list;
 };
 
 // One work item: a tile against visits v0 .. v0+nv-1 (start order).
@@ -49,17 +55,15 @@ struct VisGrid {
 };
 
 // Partial sums of every item: arrival (map = false) or map points, in FP64
-// or with the FP32 near form (mixed).  vis
-// holds (x, y, t0, dwell) per visit in start order; times the map's times.
-hipError_t launch_visit_pairs(bool map, bool mixed, const double4* vis, const VisTile* tiles,
+// or with the FP32 near form (mixed); times are the map's times.
+hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const VisTile* tiles,
                               const VisItem* items, int64_t n_items, const double* times,
-                              VisGrid grid, VisPhys phys, double* partial,
-                              hipStream_t st);
+                              VisGrid grid, double* partial, hipStream_t st);
 
-// out[dst] = pref * (sum over the tile's slots, in slot order) for every
-// point of every tile; dst = perm[p0 + k] when perm is given (arrival: the
-// caller's visit order), else out0 + k (map).
-hipError_t launch_visit_reduce(const VisTile* tiles, int64_t n_tiles, const double* partial,
-                               const int64_t* perm, double pref, double* out, hipStream_t st);
+// For every point of every tile: out[dst] = pref * (sum over the tile's
+// slots, in slot order), with the tile's list's out and pref; dst = perm[p0
+// + k] for an arrival (the caller's visit order), out0 + k for a map.
+hipError_t launch_visit_reduce(bool map, const VisList* lists, const VisTile* tiles,
+                               int64_t n_tiles, const double* partial, hipStream_t st);
 
 }  // namespace dd

@@ -223,15 +223,18 @@ __device__ __forceinline__ double pair_term(bool active, double x1, double dx, d
 // db/(b0 b1), db/b0) are then formed once per staged visit.
 template <bool MAP, bool MIXED>
 __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
-    const double4* __restrict__ vis, const VisTile* __restrict__ tiles,
+    const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
     const VisItem* __restrict__ items, int64_t n_items, const double* __restrict__ times,
-    VisGrid grid, VisPhys ph, double* __restrict__ partial) {
+    VisGrid grid, double* __restrict__ partial) {
   __shared__ double4 s_v[kVisStage];
   __shared__ double4 s_f[MAP ? kVisStage : 1];
   const int lane = threadIdx.x;
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const VisItem item = items[it];
     const VisTile tile = tiles[item.tile];
+    const VisList& L = lists[tile.list];
+    const double4* __restrict__ vis = L.vis;
+    const double inv_sigma = L.inv_sigma, th4 = L.th4;
     const bool live = lane < tile.n;
     double px = 0.0, py = 0.0, pt = tile.tmax;
     if (MAP) {
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
           double4 f = make_double4(-1.0, 0.0, 0.0, 0.0);  // rb1 < 0: not started
           if (dt > 0.0) {
             const double on = fmin(dt, v.w), off = dt - on;
-            const double b0 = fma(ph.th4, off, 2.0), db = ph.th4 * on, b1 = b0 + db;
+            const double b0 = fma(th4, off, 2.0), db = th4 * on, b1 = b0 + db;
             const double r0 = rcp64(b0), r1 = rcp64(b1);
             f = make_double4(r1, db * r0 * r1, db * r0, 0.0);
           }
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
           done = true;  // uniform: no later visit starts before any point
           break;
         }
-        const double ex = (px - v.x) * ph.inv_sigma, ey = (py - v.y) * ph.inv_sigma;
+        const double ex = (px - v.x) * inv_sigma, ey = (py - v.y) * inv_sigma;
         const double a = fma(ex, ex, ey * ey);
         if (MAP) {
           const double4 f = s_f[j];
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
           const double dt = pt - v.z;
           const bool started = live && dt > 0.0;
           const double on = fmin(dt, v.w), off = dt - on;
-          const double b0 = fma(ph.th4, off, 2.0), db = ph.th4 * on;
+          const double b0 = fma(th4, off, 2.0), db = th4 * on;
           const double b1 = b0 + db;
           const double rr = rcp64(started ? b0 * b1 : 4.0);  // 1 / (b0 b1)
           const double x1 = a * (b0 * rr), q = db * (b1 * rr);
@@ -299,29 +302,29 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
   }
 }
 
-__global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisTile* __restrict__ tiles,
-                                                           const double* __restrict__ partial,
-                                                           const int64_t* __restrict__ perm,
-                                                           double pref, double* __restrict__ out) {
+template <bool MAP>
+__global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisList* __restrict__ lists,
+                                                           const VisTile* __restrict__ tiles,
+                                                           const double* __restrict__ partial) {
   const VisTile tile = tiles[blockIdx.x];
+  const VisList& L = lists[tile.list];
   const int lane = threadIdx.x;
   if (lane >= tile.n) return;
   double s = 0.0;
   for (int k = 0; k < tile.slots; ++k) s += partial[tile.pbase + (int64_t)k * kVisTile + lane];
-  const int64_t dst = perm ? perm[tile.p0 + lane] : tile.out0 + lane;
-  out[dst] = pref * s;
+  const int64_t dst = MAP ? tile.out0 + lane : L.perm[tile.p0 + lane];
+  L.out[dst] = L.pref * s;
 }
 
 }  // namespace
 
-hipError_t launch_visit_pairs(bool map, bool mixed, const double4* vis, const VisTile* tiles,
+hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const VisTile* tiles,
                               const VisItem* items, int64_t n_items, const double* times,
-                              VisGrid grid, VisPhys phys, double* partial,
-                              hipStream_t st) {
+                              VisGrid grid, double* partial, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(n_items, 1 << 20);
-#define DD_VISIT_LAUNCH(M, X)                                                                 \
-  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(vis, tiles, items, n_items, times, grid, phys, \
+#define DD_VISIT_LAUNCH(M, X)                                                                  \
+  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, times, grid, \
                                                    partial)
   if (map && mixed)
     DD_VISIT_LAUNCH(true, true);
@@ -335,10 +338,13 @@ hipError_t launch_visit_pairs(bool map, bool mixed, const double4* vis, const Vi
   return hipGetLastError();
 }
 
-hipError_t launch_visit_reduce(const VisTile* tiles, int64_t n_tiles, const double* partial,
-                               const int64_t* perm, double pref, double* out, hipStream_t st) {
+hipError_t launch_visit_reduce(bool map, const VisList* lists, const VisTile* tiles,
+                               int64_t n_tiles, const double* partial, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  k_visit_reduce<<<(unsigned)n_tiles, kVisTile, 0, st>>>(tiles, partial, perm, pref, out);
+  if (map)
+    k_visit_reduce<true><<<(unsigned)n_tiles, kVisTile, 0, st>>>(lists, tiles, partial);
+  else
+    k_visit_reduce<false><<<(unsigned)n_tiles, kVisTile, 0, st>>>(lists, tiles, partial);
   return hipGetLastError();
 }
 

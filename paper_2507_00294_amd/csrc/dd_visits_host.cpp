@@ -3,7 +3,9 @@
 // Eq. 6 over the visits started before the query time), in FP64 or with
 // the near form in FP32 (mixed).
 //
-// Work planning.  Visits are kept in start order.  Evaluation points go in
+// Work planning.  Visits are kept in start order.  A launch serves one list
+// or, for dd_visits_batch_arrival, many: every tile names its list, whose
+// descriptor (visits, order, output, scaling) the kernels read.  Evaluation points go in
 // tiles of 256 (one thread each); visits in chunks of K (a multiple of 256,
 // at most 32 chunks per list).  A work item is one tile against one chunk,
 // written to a partial-sum slot of its own, and the slots are summed in a
@@ -68,12 +70,10 @@ struct dd_visits {
   std::vector<double> chunk_t0;  // first start of each chunk
 
   int dev = -1;
-  DevBuf d_vis, d_perm, d_tiles, d_items, d_partial, d_times, tmp_out;
-  std::vector<VisTile> h_tiles;
-  std::vector<VisItem> h_items;
+  DevBuf d_vis, d_perm, d_times, tmp_out;
 
   void release_device() {
-    for (DevBuf* b : {&d_vis, &d_perm, &d_tiles, &d_items, &d_partial, &d_times, &tmp_out})
+    for (DevBuf* b : {&d_vis, &d_perm, &d_times, &tmp_out})
       b->release();
     dev = -1;
   }
@@ -97,118 +97,164 @@ struct dd_visits {
   }
 
   // Items of one tile (box, latest time) against every chunk that can
-  // contribute; returns the number of slots used.
-  int32_t plan_tile(int32_t tile, const Box& box, double tmax) {
+  // contribute, appended to `items`; returns the number of slots used.
+  int32_t plan_tile(int32_t tile, const Box& box, double tmax, std::vector<VisItem>& items) const {
     int32_t slot = 0;
     const int64_t n_chunks = (int64_t)chunk_t0.size();
     for (int64_t c = 0; c < n_chunks && chunk_t0[c] < tmax; ++c) {
       const double b1_max = 2.0 + th4 * (tmax - chunk_t0[c]);
       if (box_a_min(box, chunk_box[c], inv_sigma) > 745.0 * (1.0 + 1e-9) * b1_max) continue;
       const int64_t v0 = c * K;
-      h_items.push_back(VisItem{tile, slot++, v0, std::min(K, n - v0)});
+      items.push_back(VisItem{tile, slot++, v0, std::min(K, n - v0)});
     }
     return slot;
   }
 
-  // Uploads the current tiles and items, launches the pair and reduce
-  // kernels for them.
-  dd_status launch(bool map, bool mixed, const VisGrid& grid, double* out, hipStream_t st) {
-    int64_t pbase = 0;
-    for (VisTile& t : h_tiles) {
-      t.pbase = pbase;
-      pbase += (int64_t)t.slots * kVisTile;
+  VisList desc(double* out) const {
+    return VisList{d_vis.as<double4>(), d_perm.as<int64_t>(), out, inv_sigma, th4, pref};
+  }
+
+  // Tiles of the arrival query (visits in start order), appended for list `list`.
+  void arrival_tiles(int32_t list, std::vector<VisTile>& tiles) const {
+    for (int64_t p0 = 0; p0 < n; p0 += kVisTile) {
+      const int64_t p1 = std::min(n, p0 + kVisTile);
+      tiles.push_back(VisTile{p0, 0, 0, vis[p1 - 1].z, (int32_t)(p1 - p0), 0, 0, list});
     }
-    VIS_HIP(d_tiles.ensure(sizeof(VisTile) * std::max<size_t>(h_tiles.size(), 1)),
-            "device allocation");
-    VIS_HIP(d_items.ensure(sizeof(VisItem) * std::max<size_t>(h_items.size(), 1)),
-            "device allocation");
-    VIS_HIP(d_partial.ensure(sizeof(double) * std::max<int64_t>(pbase, 1)), "device allocation");
-    VIS_HIP(hipMemcpyAsync(d_tiles.p, h_tiles.data(), sizeof(VisTile) * h_tiles.size(),
+  }
+  Box tile_box(const VisTile& t) const {
+    Box b;
+    for (int64_t p = t.p0; p < t.p0 + t.n; ++p) b.add(vis[p].x, vis[p].y);
+    return b;
+  }
+
+};
+
+namespace {
+
+// Per-thread launch tables of the visit-list queries (host vectors reused
+// between calls, device buffers grown as needed).
+struct VisScratch {
+  std::vector<VisTile> h_tiles;
+  std::vector<VisItem> h_items;
+  std::vector<VisList> h_lists;
+  DevBuf d_tiles, d_items, d_partial, d_lists;
+};
+thread_local VisScratch g_vis;
+
+// Partial sums and reduce of the current tiles and items (one launch group);
+// the descriptors are already on the device.
+dd_status launch_group(bool map, bool mixed, const VisGrid& grid, const double* times,
+                       hipStream_t st) {
+  VisScratch& W = g_vis;
+  int64_t pbase = 0;
+  double pairs = 0;
+  for (VisTile& t : W.h_tiles) {
+    t.pbase = pbase;
+    pbase += (int64_t)t.slots * kVisTile;
+  }
+  for (const VisItem& it : W.h_items) pairs += (double)W.h_tiles[it.tile].n * (double)it.nv;
+  VIS_HIP(W.d_tiles.ensure(sizeof(VisTile) * std::max<size_t>(W.h_tiles.size(), 1)),
+          "device allocation");
+  VIS_HIP(W.d_items.ensure(sizeof(VisItem) * std::max<size_t>(W.h_items.size(), 1)),
+          "device allocation");
+  VIS_HIP(W.d_partial.ensure(sizeof(double) * std::max<int64_t>(pbase, 1)), "device allocation");
+  VIS_HIP(hipMemcpyAsync(W.d_tiles.p, W.h_tiles.data(), sizeof(VisTile) * W.h_tiles.size(),
+                         hipMemcpyHostToDevice, st),
+          "host-to-device copy");
+  if (!W.h_items.empty())
+    VIS_HIP(hipMemcpyAsync(W.d_items.p, W.h_items.data(), sizeof(VisItem) * W.h_items.size(),
                            hipMemcpyHostToDevice, st),
             "host-to-device copy");
-    if (!h_items.empty())
-      VIS_HIP(hipMemcpyAsync(d_items.p, h_items.data(), sizeof(VisItem) * h_items.size(),
-                             hipMemcpyHostToDevice, st),
-              "host-to-device copy");
-    const ProfToken tok = prof_begin("k_visit_pairs", st);
-    VIS_HIP(launch_visit_pairs(map, mixed, d_vis.as<double4>(), d_tiles.as<VisTile>(),
-                               d_items.as<VisItem>(), (int64_t)h_items.size(),
-                               d_times.as<double>(), grid, VisPhys{inv_sigma, th4},
-                               d_partial.as<double>(), st),
-            "k_visit_pairs launch");
-    prof_end(tok, st, pairs_of_items(map), 0.0);
-    VIS_HIP(launch_visit_reduce(d_tiles.as<VisTile>(), (int64_t)h_tiles.size(),
-                                d_partial.as<double>(), map ? nullptr : d_perm.as<int64_t>(), pref,
-                                out, st),
-            "k_visit_reduce launch");
-    // the host tables are rewritten by the next group: wait for the copies
-    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
-    return DD_OK;
-  }
+  const ProfToken tok = prof_begin("k_visit_pairs", st);
+  VIS_HIP(launch_visit_pairs(map, mixed, W.d_lists.as<VisList>(), W.d_tiles.as<VisTile>(),
+                             W.d_items.as<VisItem>(), (int64_t)W.h_items.size(), times, grid,
+                             W.d_partial.as<double>(), st),
+          "k_visit_pairs launch");
+  prof_end(tok, st, pairs, 0.0);
+  VIS_HIP(launch_visit_reduce(map, W.d_lists.as<VisList>(), W.d_tiles.as<VisTile>(),
+                              (int64_t)W.h_tiles.size(), W.d_partial.as<double>(), st),
+          "k_visit_reduce launch");
+  // the host tables are rewritten by the next group: wait for the copies
+  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+  return DD_OK;
+}
 
-  // Candidate pairs of the current items (tile points times chunk visits).
-  double pairs_of_items(bool) const {
-    double p = 0;
-    for (const VisItem& it : h_items) p += (double)h_tiles[it.tile].n * (double)it.nv;
-    return p;
-  }
+dd_status upload_lists(hipStream_t st) {
+  VisScratch& W = g_vis;
+  VIS_HIP(W.d_lists.ensure(sizeof(VisList) * W.h_lists.size()), "device allocation");
+  VIS_HIP(hipMemcpyAsync(W.d_lists.p, W.h_lists.data(), sizeof(VisList) * W.h_lists.size(),
+                         hipMemcpyHostToDevice, st),
+          "host-to-device copy");
+  return DD_OK;
+}
 
-  dd_status arrival(bool mixed, double* out, hipStream_t st) {
-    const int64_t n_tiles = (n + kVisTile - 1) / kVisTile;
-    for (int64_t g0 = 0; g0 < n_tiles; g0 += kGroupTiles) {
-      const int64_t g1 = std::min(n_tiles, g0 + kGroupTiles);
-      h_tiles.clear();
-      h_items.clear();
-      for (int64_t t = g0; t < g1; ++t) {
-        const int64_t p0 = t * kVisTile, p1 = std::min(n, p0 + kVisTile);
-        Box b;
-        for (int64_t p = p0; p < p1; ++p) b.add(vis[p].x, vis[p].y);
-        const double tmax = vis[p1 - 1].z;  // start order
-        VisTile tile{p0, 0, 0, tmax, (int32_t)(p1 - p0), 0, 0, 0};
-        tile.slots = plan_tile((int32_t)(t - g0), b, tmax);
-        h_tiles.push_back(tile);
-      }
-      dd_status rc = launch(false, mixed, VisGrid{}, out, st);
-      if (rc != DD_OK) return rc;
+// Arrival queries of lists[k] into outs[k] (device), all in the same launch
+// groups: each list's tiles and items are planned exactly as for a call of
+// its own, so the results do not depend on the batch.
+dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* const* outs,
+                       hipStream_t st) {
+  VisScratch& W = g_vis;
+  W.h_lists.resize(n);
+  for (int32_t k = 0; k < n; ++k) W.h_lists[k] = lists[k]->desc(outs[k]);
+  dd_status rc = upload_lists(st);
+  if (rc != DD_OK) return rc;
+  std::vector<VisTile> all;
+  for (int32_t k = 0; k < n; ++k) lists[k]->arrival_tiles(k, all);
+  for (size_t g0 = 0; g0 < all.size(); g0 += kGroupTiles) {
+    const size_t g1 = std::min(all.size(), g0 + (size_t)kGroupTiles);
+    W.h_tiles.assign(all.begin() + g0, all.begin() + g1);
+    W.h_items.clear();
+    for (size_t t = 0; t < W.h_tiles.size(); ++t) {
+      VisTile& tile = W.h_tiles[t];
+      const dd_visits* v = lists[tile.list];
+      tile.slots = v->plan_tile((int32_t)t, v->tile_box(tile), tile.tmax, W.h_items);
     }
-    return DD_OK;
+    rc = launch_group(false, mixed, VisGrid{}, nullptr, st);
+    if (rc != DD_OK) return rc;
   }
+  return DD_OK;
+}
 
-  dd_status map(const dd_grid* g, const double* t_s, int32_t n_t, bool mixed, double* out,
-                hipStream_t st) {
-    const int64_t npix = (int64_t)g->w * g->h;
-    const int64_t per = (npix + kVisTile - 1) / kVisTile;  // tiles per time
-    VIS_HIP(d_times.ensure(sizeof(double) * n_t), "device allocation");
-    VIS_HIP(hipMemcpyAsync(d_times.p, t_s, sizeof(double) * n_t, hipMemcpyHostToDevice, st),
-            "host-to-device copy");
-    // pixel boxes of the tiles (the same at every time)
-    std::vector<Box> boxes(per);
-    for (int64_t b = 0; b < per; ++b) {
-      const int64_t q0 = b * kVisTile, q1 = std::min(npix, q0 + kVisTile) - 1;
-      const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
-      const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
-      boxes[b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
-      boxes[b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
-    }
-    const int64_t total = per * n_t;
-    const VisGrid grid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0};
-    for (int64_t g0 = 0; g0 < total; g0 += kGroupTiles) {
-      const int64_t g1 = std::min(total, g0 + kGroupTiles);
-      h_tiles.clear();
-      h_items.clear();
-      for (int64_t t = g0; t < g1; ++t) {
-        const int64_t m = t / per, b = t % per;
-        const int64_t p0 = b * kVisTile, p1 = std::min(npix, p0 + kVisTile);
-        VisTile tile{p0, 0, m * npix + p0, t_s[m], (int32_t)(p1 - p0), (int32_t)m, 0, 0};
-        tile.slots = plan_tile((int32_t)(t - g0), boxes[b], t_s[m]);
-        h_tiles.push_back(tile);
-      }
-      dd_status rc = launch(true, mixed, grid, out, st);
-      if (rc != DD_OK) return rc;
-    }
-    return DD_OK;
+dd_status run_map(dd_visits* v, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
+                  double* out, hipStream_t st) {
+  VisScratch& W = g_vis;
+  W.h_lists.assign(1, v->desc(out));
+  dd_status rc = upload_lists(st);
+  if (rc != DD_OK) return rc;
+  const int64_t npix = (int64_t)g->w * g->h;
+  const int64_t per = (npix + kVisTile - 1) / kVisTile;  // tiles per time
+  VIS_HIP(v->d_times.ensure(sizeof(double) * n_t), "device allocation");
+  VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s, sizeof(double) * n_t, hipMemcpyHostToDevice, st),
+          "host-to-device copy");
+  // pixel boxes of the tiles (the same at every time)
+  std::vector<Box> boxes(per);
+  for (int64_t b = 0; b < per; ++b) {
+    const int64_t q0 = b * kVisTile, q1 = std::min(npix, q0 + kVisTile) - 1;
+    const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
+    const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
+    boxes[b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
+    boxes[b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
   }
-};
+  const int64_t total = per * n_t;
+  const VisGrid grid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0};
+  for (int64_t g0 = 0; g0 < total; g0 += kGroupTiles) {
+    const int64_t g1 = std::min(total, g0 + kGroupTiles);
+    W.h_tiles.clear();
+    W.h_items.clear();
+    for (int64_t t = g0; t < g1; ++t) {
+      const int64_t m = t / per, b = t % per;
+      const int64_t p0 = b * kVisTile, p1 = std::min(npix, p0 + kVisTile);
+      VisTile tile{p0, 0, m * npix + p0, t_s[m], (int32_t)(p1 - p0), (int32_t)m, 0, 0};
+      tile.slots = v->plan_tile((int32_t)(t - g0), boxes[b], t_s[m], W.h_items);
+      W.h_tiles.push_back(tile);
+    }
+    rc = launch_group(true, mixed, grid, v->d_times.as<double>(), st);
+    if (rc != DD_OK) return rc;
+  }
+  return DD_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -282,9 +328,10 @@ dd_status dd_visits_arrival(dd_visits* v, dd_precision p, double* out, int32_t o
   hipStream_t st = (hipStream_t)hip_stream;
   dd_status rc = v->prepare(st);
   if (rc != DD_OK) return rc;
-  if (out_on_device) return v->arrival(mixed, out, st);
+  if (out_on_device) return run_arrivals(&v, 1, mixed, &out, st);
   VIS_HIP(v->tmp_out.ensure(sizeof(double) * v->n), "device allocation");
-  rc = v->arrival(mixed, v->tmp_out.as<double>(), st);
+  double* tmp = v->tmp_out.as<double>();
+  rc = run_arrivals(&v, 1, mixed, &tmp, st);
   if (rc != DD_OK) return rc;
   VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * v->n, hipMemcpyDeviceToHost, st),
           "device-to-host copy");
@@ -307,15 +354,49 @@ dd_status dd_visits_map(dd_visits* v, const dd_grid* g, const double* t_s, int32
   hipStream_t st = (hipStream_t)hip_stream;
   dd_status rc = v->prepare(st);
   if (rc != DD_OK) return rc;
-  if (out_on_device) return v->map(g, t_s, n_t, mixed, out, st);
+  if (out_on_device) return run_map(v, g, t_s, n_t, mixed, out, st);
   const size_t nout = (size_t)n_t * g->w * g->h;
   VIS_HIP(v->tmp_out.ensure(sizeof(double) * nout), "device allocation");
-  rc = v->map(g, t_s, n_t, mixed, v->tmp_out.as<double>(), st);
+  rc = run_map(v, g, t_s, n_t, mixed, v->tmp_out.as<double>(), st);
   if (rc != DD_OK) return rc;
   VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * nout, hipMemcpyDeviceToHost, st),
           "device-to-host copy");
   VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
   return DD_OK;
+}
+
+dd_status dd_visits_batch_arrival(dd_visits* const* lists, int32_t n, dd_precision p,
+                                  double* const* outs, int32_t out_on_device, void* hip_stream) {
+  if (!lists || !outs || n < 1) return fail(DD_EINVAL, "NULL argument or n < 1");
+  if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  for (int32_t k = 0; k < n; ++k)
+    if (!lists[k] || !outs[k]) return fail(DD_EINVAL, "list or output %d is NULL", k);
+  const bool mixed = p == DD_MIXED;
+  hipStream_t st = (hipStream_t)hip_stream;
+  for (int32_t k = 0; k < n; ++k) {
+    dd_status rc = lists[k]->prepare(st);
+    if (rc != DD_OK) return rc;
+  }
+  if (out_on_device) return run_arrivals(lists, n, mixed, outs, st);
+  // host outputs: one device buffer for all lists, then a copy per list
+  std::vector<int64_t> off(n + 1, 0);
+  for (int32_t k = 0; k < n; ++k) off[k + 1] = off[k] + lists[k]->n;
+  DevBuf tmp;
+  VIS_HIP(tmp.ensure(sizeof(double) * off[n]), "device allocation");
+  std::vector<double*> douts(n);
+  for (int32_t k = 0; k < n; ++k) douts[k] = tmp.as<double>() + off[k];
+  dd_status rc = run_arrivals(lists, n, mixed, douts.data(), st);
+  if (rc == DD_OK) {
+    for (int32_t k = 0; k < n && rc == DD_OK; ++k) {
+      hipError_t e = hipMemcpyAsync(outs[k], douts[k], sizeof(double) * lists[k]->n,
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) rc = hip_fail(e, "device-to-host copy");
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (rc == DD_OK && e != hipSuccess) rc = hip_fail(e, "stream synchronize");
+  }
+  tmp.release();
+  return rc;
 }
 
 }  // extern "C"

@@ -219,3 +219,21 @@ def test_visit_list_fails_loudly_without_device(dd):
     assert lib.dd_visits_arrival(v._h, 0, ctypes.cast(out, ctypes.c_void_p), 0,
                                  None) == dd.DD_EDEVICE
     assert lib.dd_last_error()
+
+
+def test_visit_batch_validation(dd):
+    lib = dd.load_library()
+    v = dd.Visits([0.0, 1e-9], [0.0, 0.0], [0.0, 1e-6], [1e-6, 1e-6])
+    out = (ctypes.c_double * 2)()
+    hs = (ctypes.c_void_p * 1)(v._h.value)
+    os_ = (ctypes.c_void_p * 1)(ctypes.cast(out, ctypes.c_void_p).value)
+    assert lib.dd_visits_batch_arrival(None, 1, 0, os_, 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_batch_arrival(hs, 0, 0, os_, 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_batch_arrival(hs, 1, 9, os_, 0, None) == dd.DD_EINVAL
+    nul = (ctypes.c_void_p * 1)(None)
+    assert lib.dd_visits_batch_arrival(nul, 1, 0, os_, 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_batch_arrival(hs, 1, 0, nul, 0, None) == dd.DD_EINVAL
+    import torch
+
+    if not torch.cuda.is_available():
+        assert lib.dd_visits_batch_arrival(hs, 1, 0, os_, 0, None) == dd.DD_EDEVICE

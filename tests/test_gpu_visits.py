@@ -171,3 +171,44 @@ def test_map_launch_groups(dd, ora, wl):
     u, v = rng.integers(0, 128, 64), rng.integers(0, 128, 64)
     ref = o.psi_points(-3e-9 + u * 0.2e-9, -3e-9 + v * 0.2e-9, times[m])
     assert_close(many[m, v, u], ref, vl, "fp64", "maps (sampled)")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_superposition_of_single_visits(dd, wl, prec):
+    # the field of a list is the sum of the fields of its visits taken one
+    # at a time: a check of the tiling, chunking and slot sums that does not
+    # go through the oracle
+    vl = wl.visit_list("sparse", 16, 16, seed=26, D_m2s=8e-13)
+    args = (-1e-9, -1e-9, 0.6e-9, 0.6e-9, 31, 29)
+    times = [0.5 * vl.t_end, vl.t_end]
+    whole = dd.Visits(vl.x_m, vl.y_m, vl.t0_s, vl.dwell_s, **vl.kwargs()).damage_map(
+        *args, times, prec).cpu().numpy()
+    parts = np.zeros_like(whole)
+    for i in range(vl.n_visits):
+        one = dd.Visits(vl.x_m[i:i + 1], vl.y_m[i:i + 1], vl.t0_s[i:i + 1], vl.dwell_s[i:i + 1],
+                        **vl.kwargs())
+        parts += one.damage_map(*args, times, prec).cpu().numpy()
+    np.testing.assert_allclose(whole, parts, rtol=1e-12 if prec == "fp64" else 1e-6,
+                               atol=1e-250 * vl.Q0_us / (4 * np.pi * vl.D_m2s))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_arrival_equals_single_lists(dd, wl, prec):
+    # lists of every shape, size and physics in one launch: each list's
+    # values equal its own call bit for bit (device and host outputs)
+    vls = [wl.visit_list(kind, nx, ny, seed=30 + k, D_m2s=D)
+           for k, (kind, nx, ny, D) in enumerate([
+               ("flyback", 9, 7, 2.5e-13), ("sparse", 40, 30, 3e-11), ("frames", 12, 11, 1e-12),
+               ("drift", 33, 17, 5e-13), ("flyback", 1, 1, 1e-12), ("sparse", 70, 70, 2e-13)])]
+    lists = [dd.Visits(v.x_m, v.y_m, v.t0_s, v.dwell_s, **v.kwargs()) for v in vls]
+    single = [g.arrival(prec).cpu().numpy() for g in lists]
+    batch = [t.cpu().numpy() for t in dd.visits_batch_arrival(lists, prec)]
+    for a, b in zip(single, batch):
+        assert np.array_equal(a, b)
+    lib = dd.load_library()
+    outs = [np.empty(g.num_visits) for g in lists]
+    hs = (ctypes.c_void_p * len(lists))(*[g._h.value for g in lists])
+    os_ = (ctypes.c_void_p * len(lists))(*[o.ctypes.data for o in outs])
+    assert lib.dd_visits_batch_arrival(hs, len(lists), dd.PRECISIONS[prec], os_, 0, None) == 0
+    for a, o in zip(single, outs):
+        assert np.array_equal(a, o)
