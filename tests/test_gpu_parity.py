@@ -194,6 +194,8 @@ def test_fractional_and_late_times(dd, ora, wl):
                                                         times)
     for prec in PRECS:
         got = scan.damage_map(0.3e-9, -0.7e-9, 0.37e-9, 0.29e-9, 11, 9, times, prec).cpu().numpy()
-        tol = TOL[prec] if prec == "fp64" else 5e-6  # non-lattice pixels: see the design doc
+        # pixels off the probes' lattice: mixed maps of such grids run on the
+        # FP64 kernels, so both precisions meet their own bound
+        tol = TOL[prec]
         err = rel_err(got, ref, spec, prec)
         assert err.max() <= tol, (prec, float(err.max()))
