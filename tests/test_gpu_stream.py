@@ -85,3 +85,20 @@ def test_ranges_with_other_tile_shapes(dd, ora, wl, R, RN, tmp_path):
         path = tmp_path / "tune_default.json"
         path.write_text(json.dumps(default))
         dd.tune_load(str(path))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_range_sampled_vs_oracle(dd, ora, wl, prec):
+    # the benchmark's streaming call: the last 1024 visits of the 512x512
+    # random scan, against the full arrival query and, at 24 sampled visits,
+    # the oracle
+    spec = wl.large_random()
+    scan = dd.Scan(**spec.kwargs())
+    V = scan.num_visits
+    got = scan.arrival_range(V - 1024, V, prec).cpu().numpy()
+    full = scan.arrival(prec).cpu().numpy()
+    np.testing.assert_allclose(got, full[V - 1024:], rtol=1e-13 if prec == "fp64" else 2e-7,
+                               atol=0)
+    idx = np.sort(np.random.default_rng(42).choice(1024, 24, replace=False)) + (V - 1024)
+    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival(idx)
+    assert_close(got[idx - (V - 1024)], ref, spec, prec, "bench range (sampled)")

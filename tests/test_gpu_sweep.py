@@ -89,3 +89,25 @@ def test_sweep_chunks_and_host_output(dd, wl):
                              host.ctypes.data_as(ctypes.c_void_p), 0, None)
     assert st == dd.DD_OK
     assert np.array_equal(host, got.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_bench_sweep_sampled_vs_oracle(dd, ora, wl, prec):
+    # the benchmark's sweep in the call it times: 64x64 raster, 128x128 maps
+    # at half the pitch every half dwell over the whole scan (8192 maps);
+    # 64 sampled (map, pixel) values against the oracle
+    import torch
+
+    spec = wl.ScanSpec(64, 64, "raster", 1e-9, 1e-6, 0.5e-9, 2.5e-13, 1.0)
+    scan = dd.Scan(**spec.kwargs())
+    n_t, w, dt = 2 * spec.n_visits, 128, spec.tau_v / 2
+    out = scan.damage_sweep(0.0, 0.0, 0.5e-9, 0.5e-9, w, w, 0.0, dt, n_t, prec)
+    rng = np.random.default_rng(41)
+    m = rng.integers(0, n_t, 64)
+    m[:2] = (n_t - 1, 1)
+    u, v = rng.integers(0, w, 64), rng.integers(0, w, 64)
+    got = out[torch.as_tensor(m, device="cuda"), torch.as_tensor(v, device="cuda"),
+              torch.as_tensor(u, device="cuda")].cpu().numpy()
+    del out
+    ref = oracle_scan(ora, spec, scan.visits()).psi_points(u * 0.5e-9, v * 0.5e-9, m * dt)
+    assert_close(got, ref, spec, prec, "bench sweep (sampled)")
