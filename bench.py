@@ -54,11 +54,12 @@ def device_source_hash():
     return h.hexdigest()
 
 
-def counter_record(precision, side):
-    """The committed counter record of the dominant kernel (HBM bytes and VALU
-    lane-instructions per pair), or None when the kernel sources changed since
-    the counters were taken or the workload is not the recorded one."""
-    if precision != "mixed" or side != 512 or not os.path.exists(TRAFFIC_RECORD):
+def counter_record(side):
+    """The committed counter record of the far kernels on the 512x512 arrival
+    query (HBM bytes of the mixed kernel, VALU lane-instructions per pair of
+    both), or None when the kernel sources changed since the counters were
+    taken or the workload is not the recorded one."""
+    if side != 512 or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = {}
     with open(TRAFFIC_RECORD) as f:
@@ -72,9 +73,42 @@ def counter_record(precision, side):
 
 
 def recorded_traffic(precision, side):
-    """Bytes per launch from the committed counter record, or None."""
-    rec = counter_record(precision, side)
+    """Bytes per launch of the mixed far kernel from the committed counter
+    record, or None."""
+    rec = counter_record(side) if precision == "mixed" else None
     return None if rec is None else float(rec["fetch_bytes"]) + float(rec["write_bytes"])
+
+
+def far_roofline(prec, kern, side):
+    """Roofline of the far-region kernel from its live HIP-event time and the
+    plan's algorithmic flops; the VALU issue rate from the recorded
+    instructions per pair (rocprofv3 SQ_INSTS_VALU) times the live pair rate."""
+    far = kern["arrival_far"]
+    far_ms = far["ms"] / max(far["launches"], 1)
+    far_flops = far["flops"] / max(far["launches"], 1)
+    achieved = far_flops / (far_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu", "kernel": "k_arrival_far32" if prec == "mixed" else "k_arrival_far64",
+        "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+        "traffic": recorded_traffic(prec, side),
+        "avg_launch_ms": round(far_ms, 4),
+        "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
+        "flops_per_launch": far_flops,
+    }
+    if prec == "mixed":
+        # this build does not emit packed FP32, so 78.6 TFLOP/s is the FLOP ceiling
+        roofline["frac_of_fp32_nonpacked"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
+    rec = counter_record(side)
+    key = "valu_lane_instructions_per_pair" if prec == "mixed" else \
+        "fp64_valu_lane_instructions_per_pair"
+    if rec is not None and key in rec:
+        ipp = float(rec[key])
+        rate = roofline["pairs_per_launch"] / (far_ms * 1e-3) * ipp
+        roofline["valu_issue"] = {"lane_instructions_per_pair": ipp, "achieved": rate,
+                                  "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
+                                  "frac": round(rate / VALU_ISSUE_PEAK, 4)}
+    return roofline
 
 
 def time_query(scan, prec, out, steps, warmup, dd, torch):
@@ -156,31 +190,7 @@ def main():
     sec, kern = time_query(scan, prec, out, args.steps, args.warmup, dd, torch)
     value = pairs / sec
     log(f"[bench] {prec}: {sec * 1e3:.3f} ms/step, {value:.4e} pairs/s")
-    far = kern["arrival_far"]
-    far_ms = far["ms"] / max(far["launches"], 1)
-    far_flops = far["flops"] / max(far["launches"], 1)
-    achieved = far_flops / (far_ms * 1e-3) / 1e12
-    roofline = {
-        "bound": "alu", "kernel": "k_arrival_far32" if prec == "mixed" else "k_arrival_far64",
-        "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_TFLOPS[prec], 4),
-        "traffic": recorded_traffic(prec, args.side),
-        "avg_launch_ms": round(far_ms, 4),
-        "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
-        "flops_per_launch": far_flops,
-    }
-    if prec == "mixed":
-        # this build does not emit packed FP32, so 78.6 TFLOP/s is the FLOP
-        # ceiling; the VALU issue rate comes from the recorded instructions
-        # per pair (rocprofv3 SQ_INSTS_VALU) times the live pair rate
-        roofline["frac_of_fp32_nonpacked"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
-        rec = counter_record(prec, args.side)
-        if rec is not None and "valu_lane_instructions_per_pair" in rec:
-            ipp = float(rec["valu_lane_instructions_per_pair"])
-            rate = roofline["pairs_per_launch"] / (far_ms * 1e-3) * ipp
-            roofline["valu_issue"] = {"lane_instructions_per_pair": ipp, "achieved": rate,
-                                      "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
-                                      "frac": round(rate / VALU_ISSUE_PEAK, 4)}
+    roofline = far_roofline(prec, kern, args.side)
     result = out.cpu().numpy()
     # Streaming: psi at the last 1024 visits of the scan (the visits just made,
     # the most expensive 1024 of the scan), latency of one call.
@@ -208,7 +218,7 @@ def main():
 
     # The other precision on the same workload, for context.
     other = "fp64" if prec == "mixed" else "mixed"
-    sec_o, _ = time_query(scan, other, out, max(2, args.steps // 4), 1, dd, torch)
+    sec_o, kern_o = time_query(scan, other, out, max(2, args.steps // 4), 1, dd, torch)
     other_res = out.cpu().numpy()
     floor = 1e-30 * spec.Q0_us / (4 * math.pi * spec.D_m2s)
     diff = np.abs(result - other_res) / np.maximum(np.abs(other_res if other == "fp64" else result),
@@ -417,7 +427,8 @@ def main():
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": max_err,
         "other_precision": {"precision": other, "ms_per_step": sec_o * 1e3,
-                            "value": pairs / sec_o, "max_rel_diff_mixed_vs_fp64": float(diff.max())},
+                            "value": pairs / sec_o, "max_rel_diff_mixed_vs_fp64": float(diff.max()),
+                            "roofline": far_roofline(other, kern_o, args.side)},
         "kernels_ms_per_step": {k: v["ms"] / max(v["launches"], 1) for k, v in kern.items()},
         "batched": bat,
         "sweep": swp,
