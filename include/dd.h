@@ -316,6 +316,16 @@ dd_status dd_visits_map(dd_visits *v, const dd_grid *g, const double *t_s, int32
 dd_status dd_visits_batch_arrival(dd_visits *const *lists, int32_t n, dd_precision p,
                                   double *const *outs, int32_t out_on_device, void *hip_stream);
 
+/* Maps of n >= 1 distinct lists in one launch: list k on grids[k] at the
+ * n_t[k] host times t_s[k], into outs[k] [n_t[k]][h][w], the same as
+ * dd_visits_map on list k alone, bit for bit.  outs: all on the device or
+ * all on the host (out_on_device).
+ * Errors: DD_EINVAL (NULL, n < 1, a list given twice, a grid, times or
+ * precision as for dd_visits_map), DD_ENOMEM, DD_EDEVICE.                 */
+dd_status dd_visits_batch_map(dd_visits *const *lists, int32_t n, const dd_grid *grids,
+                              const double *const *t_s, const int32_t *n_t, dd_precision p,
+                              double *const *outs, int32_t out_on_device, void *hip_stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);
 

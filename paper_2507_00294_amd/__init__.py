@@ -36,7 +36,7 @@ EXPORTS = (
     "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
     "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
     "dd_visits_destroy", "dd_visits_count", "dd_visits_arrival", "dd_visits_map",
-    "dd_visits_batch_arrival", "dd_last_error",
+    "dd_visits_batch_arrival", "dd_visits_batch_map", "dd_last_error",
 )
 
 
@@ -119,6 +119,8 @@ def load_library():
     lib.dd_visits_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_visits_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
     lib.dd_visits_batch_arrival.argtypes = [P(vp), i32, ctypes.c_int, P(vp), i32, vp]
+    lib.dd_visits_batch_map.argtypes = [P(vp), i32, P(Grid), P(P(dbl)), P(i32), ctypes.c_int,
+                                        P(vp), i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
@@ -126,7 +128,8 @@ def load_library():
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
                  "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
-                 "dd_visits_arrival", "dd_visits_map", "dd_visits_batch_arrival"):
+                 "dd_visits_arrival", "dd_visits_map", "dd_visits_batch_arrival",
+                 "dd_visits_batch_map"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -358,6 +361,27 @@ def visits_batch_arrival(lists: Sequence[Visits], precision: str = "fp64", out=N
     _check(load_library().dd_visits_batch_arrival(hs, n, _prec(precision), os_, 1,
                                                   _stream(stream)))
     return views
+
+
+def visits_batch_map(lists: Sequence[Visits], grids, times, precision: str = "fp64",
+                     stream=None):
+    """Maps of many visit lists in one launch (``dd_visits_batch_map``):
+    list k on grids[k] = (x0_m, y0_m, dx_m, dy_m, w, h) at times[k]; a list of
+    float64 CUDA tensors [n_t, h, w]."""
+    torch = _torch()
+    n = len(lists)
+    ts = [np.ascontiguousarray(np.atleast_1d(np.asarray(t, dtype=np.float64))) for t in times]
+    gs = (Grid * n)(*[Grid(*g) for g in grids])
+    outs = [torch.empty((t.size, g[5], g[4]), dtype=torch.float64, device="cuda")
+            for t, g in zip(ts, grids)]
+    D = ctypes.POINTER(ctypes.c_double)
+    tp = (D * n)(*[t.ctypes.data_as(D) for t in ts])
+    nt = (ctypes.c_int32 * n)(*[t.size for t in ts])
+    hs = (ctypes.c_void_p * n)(*[v._h.value for v in lists])
+    os_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(load_library().dd_visits_batch_map(hs, n, gs, tp, nt, _prec(precision), os_, 1,
+                                              _stream(stream)))
+    return outs
 
 
 def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PROBES,

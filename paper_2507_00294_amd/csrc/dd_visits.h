@@ -18,21 +18,30 @@ constexpr int kVisTile = 256;     // evaluation points per tile (one per thread)
 constexpr int kVisStage = 256;    // visits staged in LDS at a time
 constexpr int kVisMaxSlots = 32;  // visit chunks (partial sums) per tile at most
 
+// Map grid (pixel (u, v) at (x0 + u dx, y0 + v dy), w columns).
+struct VisGrid {
+  double x0, y0, dx, dy;
+  int32_t w, pad;
+};
+
 // One visit list of a launch: its visits (x, y, t0, dwell) in start order,
-// the start order's caller indices (arrival), the output, and the scaling
-// of a pair: a_hat = |r - r_i|^2 / sigma^2 with inv_sigma, b_hat = 2 +
-// 4 (D / sigma^2) lag with th4 = 4 D / sigma^2, psi = pref * sum.
+// the start order's caller indices (arrival), the output, the map's grid
+// and times (maps), and the scaling of a pair: a_hat = |r - r_i|^2 /
+// sigma^2 with inv_sigma, b_hat = 2 + 4 (D / sigma^2) lag with th4 =
+// 4 D / sigma^2, psi = pref * sum.
 struct VisList {
   const double4* vis;
   const int64_t* perm;
   double* out;
+  const double* times;
+  VisGrid grid;
   double inv_sigma, th4, pref;
 };
 
 // A tile of evaluation points of list `list`.  Arrival: the visits p0 ..
 // p0+n-1 in start order, each at its own position and start time.  Map:
-// pixels p0 .. p0+n-1 of the grid at time index m.  Its partial sums sit at
-// pbase + slot * 256.
+// pixels p0 .. p0+n-1 of the list's grid at its time index m.  Its partial
+// sums sit at pbase + slot * 256.
 struct VisTile {
   int64_t p0;
   int64_t pbase;
@@ -48,17 +57,11 @@ struct VisItem {
   int64_t nv;
 };
 
-// Map grid (pixel (u, v) at (x0 + u dx, y0 + v dy), w columns).
-struct VisGrid {
-  double x0, y0, dx, dy;
-  int32_t w, pad;
-};
-
 // Partial sums of every item: arrival (map = false) or map points, in FP64
-// or with the FP32 near form (mixed); times are the map's times.
+// or with the FP32 near form (mixed).
 hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const VisTile* tiles,
-                              const VisItem* items, int64_t n_items, const double* times,
-                              VisGrid grid, double* partial, hipStream_t st);
+                              const VisItem* items, int64_t n_items, double* partial,
+                              hipStream_t st);
 
 // For every point of every tile: out[dst] = pref * (sum over the tile's
 // slots, in slot order), with the tile's list's out and pref; dst = perm[p0

@@ -224,8 +224,7 @@ __device__ __forceinline__ double pair_term(bool active, double x1, double dx, d
 template <bool MAP, bool MIXED>
 __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
     const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
-    const VisItem* __restrict__ items, int64_t n_items, const double* __restrict__ times,
-    VisGrid grid, double* __restrict__ partial) {
+    const VisItem* __restrict__ items, int64_t n_items, double* __restrict__ partial) {
   __shared__ double4 s_v[kVisStage];
   __shared__ double4 s_f[MAP ? kVisStage : 1];
   const int lane = threadIdx.x;
@@ -238,10 +237,11 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
     const bool live = lane < tile.n;
     double px = 0.0, py = 0.0, pt = tile.tmax;
     if (MAP) {
+      const VisGrid grid = L.grid;
       const int64_t pix = tile.p0 + (live ? lane : 0);
       px = grid.x0 + (double)(pix % grid.w) * grid.dx;
       py = grid.y0 + (double)(pix / grid.w) * grid.dy;
-      pt = times[tile.m];
+      pt = L.times[tile.m];
     } else if (live) {
       const double4 me = vis[tile.p0 + lane];
       px = me.x;
@@ -319,13 +319,12 @@ __global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisList* __rest
 }  // namespace
 
 hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const VisTile* tiles,
-                              const VisItem* items, int64_t n_items, const double* times,
-                              VisGrid grid, double* partial, hipStream_t st) {
+                              const VisItem* items, int64_t n_items, double* partial,
+                              hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>(n_items, 1 << 20);
 #define DD_VISIT_LAUNCH(M, X)                                                                  \
-  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, times, grid, \
-                                                   partial)
+  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial)
   if (map && mixed)
     DD_VISIT_LAUNCH(true, true);
   else if (map)

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <new>
 #include <numeric>
+#include <set>
 #include <vector>
 
 #include "../../include/dd.h"
@@ -110,8 +111,9 @@ struct dd_visits {
     return slot;
   }
 
-  VisList desc(double* out) const {
-    return VisList{d_vis.as<double4>(), d_perm.as<int64_t>(), out, inv_sigma, th4, pref};
+  VisList desc(double* out, const double* times = nullptr, VisGrid grid = VisGrid{}) const {
+    return VisList{d_vis.as<double4>(), d_perm.as<int64_t>(), out, times, grid,
+                   inv_sigma, th4, pref};
   }
 
   // Tiles of the arrival query (visits in start order), appended for list `list`.
@@ -143,8 +145,7 @@ thread_local VisScratch g_vis;
 
 // Partial sums and reduce of the current tiles and items (one launch group);
 // the descriptors are already on the device.
-dd_status launch_group(bool map, bool mixed, const VisGrid& grid, const double* times,
-                       hipStream_t st) {
+dd_status launch_group(bool map, bool mixed, hipStream_t st) {
   VisScratch& W = g_vis;
   int64_t pbase = 0;
   double pairs = 0;
@@ -167,7 +168,7 @@ dd_status launch_group(bool map, bool mixed, const VisGrid& grid, const double* 
             "host-to-device copy");
   const ProfToken tok = prof_begin("k_visit_pairs", st);
   VIS_HIP(launch_visit_pairs(map, mixed, W.d_lists.as<VisList>(), W.d_tiles.as<VisTile>(),
-                             W.d_items.as<VisItem>(), (int64_t)W.h_items.size(), times, grid,
+                             W.d_items.as<VisItem>(), (int64_t)W.h_items.size(),
                              W.d_partial.as<double>(), st),
           "k_visit_pairs launch");
   prof_end(tok, st, pairs, 0.0);
@@ -209,48 +210,78 @@ dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* c
       const dd_visits* v = lists[tile.list];
       tile.slots = v->plan_tile((int32_t)t, v->tile_box(tile), tile.tmax, W.h_items);
     }
-    rc = launch_group(false, mixed, VisGrid{}, nullptr, st);
+    rc = launch_group(false, mixed, st);
     if (rc != DD_OK) return rc;
   }
   return DD_OK;
 }
 
-dd_status run_map(dd_visits* v, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
-                  double* out, hipStream_t st) {
+// Maps of lists[k] on grids[k] at times t_s[k][0 .. n_t[k]) into outs[k]
+// (device), all in the same launch groups; each list's tiles and items are
+// planned exactly as for a call of its own (tiles time by time, pixel
+// blocks in order), so the results do not depend on the batch.
+dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
+                   const double* const* t_s, const int32_t* n_t, bool mixed, double* const* outs,
+                   hipStream_t st) {
   VisScratch& W = g_vis;
-  W.h_lists.assign(1, v->desc(out));
+  std::vector<int64_t> npix(n), per(n);
+  std::vector<std::vector<Box>> boxes(n);
+  W.h_lists.resize(n);
+  for (int32_t k = 0; k < n; ++k) {
+    const dd_grid* g = &grids[k];
+    dd_visits* v = lists[k];
+    npix[k] = (int64_t)g->w * g->h;
+    per[k] = (npix[k] + kVisTile - 1) / kVisTile;  // tiles per time
+    VIS_HIP(v->d_times.ensure(sizeof(double) * n_t[k]), "device allocation");
+    VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s[k], sizeof(double) * n_t[k], hipMemcpyHostToDevice,
+                           st),
+            "host-to-device copy");
+    W.h_lists[k] = v->desc(outs[k], v->d_times.as<double>(),
+                           VisGrid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0});
+    // pixel boxes of the tiles (the same at every time)
+    boxes[k].resize(per[k]);
+    for (int64_t b = 0; b < per[k]; ++b) {
+      const int64_t q0 = b * kVisTile, q1 = std::min(npix[k], q0 + kVisTile) - 1;
+      const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
+      const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
+      boxes[k][b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
+      boxes[k][b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
+    }
+  }
   dd_status rc = upload_lists(st);
   if (rc != DD_OK) return rc;
-  const int64_t npix = (int64_t)g->w * g->h;
-  const int64_t per = (npix + kVisTile - 1) / kVisTile;  // tiles per time
-  VIS_HIP(v->d_times.ensure(sizeof(double) * n_t), "device allocation");
-  VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s, sizeof(double) * n_t, hipMemcpyHostToDevice, st),
-          "host-to-device copy");
-  // pixel boxes of the tiles (the same at every time)
-  std::vector<Box> boxes(per);
-  for (int64_t b = 0; b < per; ++b) {
-    const int64_t q0 = b * kVisTile, q1 = std::min(npix, q0 + kVisTile) - 1;
-    const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
-    const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
-    boxes[b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
-    boxes[b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
-  }
-  const int64_t total = per * n_t;
-  const VisGrid grid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0};
-  for (int64_t g0 = 0; g0 < total; g0 += kGroupTiles) {
-    const int64_t g1 = std::min(total, g0 + kGroupTiles);
+  int32_t k = 0;
+  int64_t local = 0;  // next tile of list k
+  while (k < n) {
     W.h_tiles.clear();
     W.h_items.clear();
-    for (int64_t t = g0; t < g1; ++t) {
-      const int64_t m = t / per, b = t % per;
-      const int64_t p0 = b * kVisTile, p1 = std::min(npix, p0 + kVisTile);
-      VisTile tile{p0, 0, m * npix + p0, t_s[m], (int32_t)(p1 - p0), (int32_t)m, 0, 0};
-      tile.slots = v->plan_tile((int32_t)(t - g0), boxes[b], t_s[m], W.h_items);
+    while ((int64_t)W.h_tiles.size() < kGroupTiles && k < n) {
+      const int64_t m = local / per[k], b = local % per[k];
+      const int64_t p0 = b * kVisTile, p1 = std::min(npix[k], p0 + kVisTile);
+      const double t = t_s[k][m];
+      VisTile tile{p0, 0, m * npix[k] + p0, t, (int32_t)(p1 - p0), (int32_t)m, 0, k};
+      tile.slots = lists[k]->plan_tile((int32_t)W.h_tiles.size(), boxes[k][b], t, W.h_items);
       W.h_tiles.push_back(tile);
+      if (++local == per[k] * n_t[k]) {
+        ++k;
+        local = 0;
+      }
     }
-    rc = launch_group(true, mixed, grid, v->d_times.as<double>(), st);
+    rc = launch_group(true, mixed, st);
     if (rc != DD_OK) return rc;
   }
+  return DD_OK;
+}
+
+dd_status check_map_args(const dd_grid* g, const double* t_s, int32_t n_t) {
+  if (!g || !t_s) return fail(DD_EINVAL, "NULL argument");
+  if (n_t < 1) return fail(DD_EINVAL, "n_t must be >= 1");
+  if (g->w < 1 || g->h < 1) return fail(DD_EINVAL, "grid w and h must be >= 1");
+  if ((int64_t)g->w * g->h > (1LL << 30)) return fail(DD_EINVAL, "grid too large");
+  for (double x : {g->x0_m, g->y0_m, g->dx_m, g->dy_m})
+    if (!std::isfinite(x)) return fail(DD_EINVAL, "grid values must be finite");
+  for (int32_t m = 0; m < n_t; ++m)
+    if (!std::isfinite(t_s[m])) return fail(DD_EINVAL, "time %d not finite", m);
   return DD_OK;
 }
 
@@ -341,28 +372,51 @@ dd_status dd_visits_arrival(dd_visits* v, dd_precision p, double* out, int32_t o
 
 dd_status dd_visits_map(dd_visits* v, const dd_grid* g, const double* t_s, int32_t n_t,
                         dd_precision p, double* out, int32_t out_on_device, void* hip_stream) {
-  if (!v || !g || !out || (n_t > 0 && !t_s)) return fail(DD_EINVAL, "NULL argument");
+  if (!v || !out) return fail(DD_EINVAL, "NULL argument");
+  return dd_visits_batch_map(&v, 1, g, &t_s, &n_t, p, &out, out_on_device, hip_stream);
+}
+
+dd_status dd_visits_batch_map(dd_visits* const* lists, int32_t n, const dd_grid* grids,
+                              const double* const* t_s, const int32_t* n_t, dd_precision p,
+                              double* const* outs, int32_t out_on_device, void* hip_stream) {
+  if (!lists || !grids || !t_s || !n_t || !outs || n < 1)
+    return fail(DD_EINVAL, "NULL argument or n < 1");
   if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
+  std::set<const dd_visits*> seen;
+  for (int32_t k = 0; k < n; ++k) {
+    if (!lists[k] || !outs[k]) return fail(DD_EINVAL, "list or output %d is NULL", k);
+    if (!seen.insert(lists[k]).second)
+      return fail(DD_EINVAL, "list %d appears twice (a list holds one set of map times)", k);
+    dd_status rc = check_map_args(&grids[k], t_s[k], n_t[k]);
+    if (rc != DD_OK) return rc;
+  }
   const bool mixed = p == DD_MIXED;
-  if (n_t < 1) return fail(DD_EINVAL, "n_t must be >= 1");
-  if (g->w < 1 || g->h < 1) return fail(DD_EINVAL, "grid w and h must be >= 1");
-  if ((int64_t)g->w * g->h > (1LL << 30)) return fail(DD_EINVAL, "grid too large");
-  for (double x : {g->x0_m, g->y0_m, g->dx_m, g->dy_m})
-    if (!std::isfinite(x)) return fail(DD_EINVAL, "grid values must be finite");
-  for (int32_t m = 0; m < n_t; ++m)
-    if (!std::isfinite(t_s[m])) return fail(DD_EINVAL, "time %d not finite", m);
   hipStream_t st = (hipStream_t)hip_stream;
-  dd_status rc = v->prepare(st);
-  if (rc != DD_OK) return rc;
-  if (out_on_device) return run_map(v, g, t_s, n_t, mixed, out, st);
-  const size_t nout = (size_t)n_t * g->w * g->h;
-  VIS_HIP(v->tmp_out.ensure(sizeof(double) * nout), "device allocation");
-  rc = run_map(v, g, t_s, n_t, mixed, v->tmp_out.as<double>(), st);
-  if (rc != DD_OK) return rc;
-  VIS_HIP(hipMemcpyAsync(out, v->tmp_out.p, sizeof(double) * nout, hipMemcpyDeviceToHost, st),
-          "device-to-host copy");
-  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
-  return DD_OK;
+  for (int32_t k = 0; k < n; ++k) {
+    dd_status rc = lists[k]->prepare(st);
+    if (rc != DD_OK) return rc;
+  }
+  if (out_on_device) return run_maps(lists, n, grids, t_s, n_t, mixed, outs, st);
+  // host outputs: one device buffer for all maps, then a copy per list
+  std::vector<int64_t> off(n + 1, 0);
+  for (int32_t k = 0; k < n; ++k)
+    off[k + 1] = off[k] + (int64_t)n_t[k] * grids[k].w * grids[k].h;
+  DevBuf tmp;
+  VIS_HIP(tmp.ensure(sizeof(double) * off[n]), "device allocation");
+  std::vector<double*> douts(n);
+  for (int32_t k = 0; k < n; ++k) douts[k] = tmp.as<double>() + off[k];
+  dd_status rc = run_maps(lists, n, grids, t_s, n_t, mixed, douts.data(), st);
+  if (rc == DD_OK) {
+    for (int32_t k = 0; k < n && rc == DD_OK; ++k) {
+      hipError_t e = hipMemcpyAsync(outs[k], douts[k], sizeof(double) * (off[k + 1] - off[k]),
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) rc = hip_fail(e, "device-to-host copy");
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (rc == DD_OK && e != hipSuccess) rc = hip_fail(e, "stream synchronize");
+  }
+  tmp.release();
+  return rc;
 }
 
 dd_status dd_visits_batch_arrival(dd_visits* const* lists, int32_t n, dd_precision p,

@@ -237,3 +237,27 @@ def test_visit_batch_validation(dd):
 
     if not torch.cuda.is_available():
         assert lib.dd_visits_batch_arrival(hs, 1, 0, os_, 0, None) == dd.DD_EDEVICE
+
+
+def test_visit_batch_map_validation(dd):
+    lib = dd.load_library()
+    D, I32 = ctypes.c_double, ctypes.c_int32
+    v = dd.Visits([0.0, 1e-9], [0.0, 0.0], [0.0, 1e-6], [1e-6, 1e-6])
+    w = dd.Visits([0.0], [0.0], [0.0], [1e-6])
+    out = (D * 8)()
+    t = (D * 2)(1e-6, 2e-6)
+    P = ctypes.POINTER(D)
+    one = lambda *xs: (ctypes.c_void_p * len(xs))(*xs)  # noqa: E731
+    grids = (dd.Grid * 2)(dd.Grid(0, 0, 1e-9, 1e-9, 2, 2), dd.Grid(0, 0, 1e-9, 1e-9, 2, 2))
+    tp = (P * 2)(ctypes.cast(t, P), ctypes.cast(t, P))
+    nt = (I32 * 2)(2, 2)
+    o = ctypes.cast(out, ctypes.c_void_p).value
+    ok = lambda hs, g=grids, n=nt: lib.dd_visits_batch_map(hs, 2, g, tp, n, 0, one(o, o), 0,  # noqa
+                                                          None)
+    assert ok(one(v._h.value, v._h.value)) == dd.DD_EINVAL  # the same list twice
+    bad = (dd.Grid * 2)(dd.Grid(0, 0, 1e-9, 1e-9, 2, 2), dd.Grid(0, 0, 1e-9, 1e-9, 0, 2))
+    assert ok(one(v._h.value, w._h.value), g=bad) == dd.DD_EINVAL
+    assert ok(one(v._h.value, w._h.value), n=(I32 * 2)(2, 0)) == dd.DD_EINVAL
+    assert lib.dd_visits_batch_map(None, 2, grids, tp, nt, 0, one(o, o), 0, None) == dd.DD_EINVAL
+    assert lib.dd_visits_batch_map(one(v._h.value, w._h.value), 2, grids, tp, nt, 4, one(o, o), 0,
+                                   None) == dd.DD_EINVAL

@@ -212,3 +212,20 @@ def test_batch_arrival_equals_single_lists(dd, wl, prec):
     assert lib.dd_visits_batch_arrival(hs, len(lists), dd.PRECISIONS[prec], os_, 0, None) == 0
     for a, o in zip(single, outs):
         assert np.array_equal(a, o)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batch_map_equals_single_lists(dd, wl, prec):
+    # maps of several lists on their own grids and times in one launch,
+    # more than one launch group in all: each equals its own call bit for bit
+    vls = [wl.visit_list(kind, nx, ny, seed=50 + k, D_m2s=D)
+           for k, (kind, nx, ny, D) in enumerate([
+               ("flyback", 9, 7, 2.5e-13), ("sparse", 30, 20, 3e-11), ("drift", 12, 11, 1e-12)])]
+    lists = [dd.Visits(v.x_m, v.y_m, v.t0_s, v.dwell_s, **v.kwargs()) for v in vls]
+    grids = [(-1e-9, -1e-9, 0.4e-9, 0.5e-9, 37, 23), (0.0, 0.0, 1e-9, 1e-9, 128, 128),
+             (0.3e-9, -0.2e-9, 0.7e-9, 0.3e-9, 17, 45)]
+    times = [np.linspace(0.1, 1.2, 5) * v.t_end for v in vls]
+    times[1] = np.linspace(0.05, 1.0, 70) * vls[1].t_end  # 70 x 64 tiles
+    batch = dd.visits_batch_map(lists, grids, times, prec)
+    for g, gr, t, b in zip(lists, grids, times, batch):
+        assert np.array_equal(g.damage_map(*gr, t, prec).cpu().numpy(), b.cpu().numpy())
