@@ -229,3 +229,28 @@ def test_batch_map_equals_single_lists(dd, wl, prec):
     batch = dd.visits_batch_map(lists, grids, times, prec)
     for g, gr, t, b in zip(lists, grids, times, batch):
         assert np.array_equal(g.damage_map(*gr, t, prec).cpu().numpy(), b.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_overlaps_equal_starts_negative_times(dd, ora, prec):
+    # visits that overlap in time, share a start time, start before t = 0,
+    # and a far-away visit: against the oracle; Q0 = 0 gives zeros
+    rng = np.random.default_rng(60)
+    n = 300
+    x = rng.uniform(-5e-9, 5e-9, n)
+    y = rng.uniform(-5e-9, 5e-9, n)
+    t0 = np.sort(rng.uniform(-20e-6, 40e-6, n))
+    t0[10:14] = t0[10]                     # four visits starting together
+    dw = rng.uniform(0.2e-6, 8e-6, n)      # long dwells: neighbours overlap
+    x[-1], y[-1] = 1e-6, -1e-6             # far from everything
+    kw = dict(sigma_m=0.4e-9, D_m2s=6e-13)
+    g = dd.Visits(x, y, t0, dw, **kw)
+    o = ora.Visits(x, y, t0, dw, 0.4e-9, 6e-13, 1.0)
+    spec = type("S", (), {"Q0_us": 1.0, "D_m2s": 6e-13})
+    assert_close(g.arrival(prec).cpu().numpy(), o.psi_arrival(), spec, prec, "arrival")
+    times = [-10e-6, 0.0, 13.3e-6, 45e-6, 200e-6]
+    args = (-6e-9, -6e-9, 0.5e-9, 0.5e-9, 25, 25)
+    assert_close(g.damage_map(*args, times, prec).cpu().numpy(), o.psi_map(*args, times), spec,
+                 prec, "maps")
+    z = dd.Visits(x, y, t0, dw, sigma_m=0.4e-9, D_m2s=6e-13, Q0_us=0.0)
+    assert np.all(z.arrival(prec).cpu().numpy() == 0.0)
