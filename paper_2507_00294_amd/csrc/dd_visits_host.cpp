@@ -4,15 +4,16 @@
 // the near form in FP32 (mixed).
 //
 // Work planning.  Visits are kept in start order.  A launch serves one list
-// or, for dd_visits_batch_arrival, many: every tile names its list, whose
-// descriptor (visits, order, output, scaling) the kernels read.  Evaluation points go in
-// tiles of 256 (one thread each); visits in chunks of K (a multiple of 256,
-// at most 32 chunks per list).  A work item is one tile against one chunk,
-// written to a partial-sum slot of its own, and the slots are summed in a
-// fixed order, so results do not depend on scheduling.  Items are dropped
-// on the host when no pair can contribute:
+// or, for the batch calls, many: every tile names its list, whose
+// descriptor (visits, order, output, grid and times, scaling) the kernels
+// read.  Evaluation points go in tiles of 256 (one thread each); visits in
+// chunks of K (a multiple of 256, at most 32 chunks per list).  A work item
+// is one tile against one chunk, written to a partial-sum slot of its own,
+// and the slots are summed in a fixed order, so results depend neither on
+// scheduling nor on the other lists of a batch.  Items are dropped on the
+// host when no pair can contribute, that is when
 //   * the chunk's first start is at or after the tile's latest time
-//     (nothing has started), and
+//     (nothing has started), or
 //   * the bounding boxes of tile and chunk are so far apart that
 //     a / b1 > 745 for every pair, with b1 taken at the largest lag
 //     (the kernel would cull each pair; a margin of 1e-9 keeps host and
