@@ -194,9 +194,9 @@ def load_weights(net, path=DEFAULT_WEIGHTS):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="train and evaluate the surrogate")
-    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--train", type=int, default=30000)
     ap.add_argument("--test", type=int, default=2000)
-    ap.add_argument("--steps", type=int, default=40000)
+    ap.add_argument("--steps", type=int, default=80000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--clip", type=float, default=1.0)
