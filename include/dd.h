@@ -69,7 +69,9 @@ typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
  * (0-based) starts at v * tau_v and lasts tau_v, back to back, where
  * tau_v = dwell_s / frames for DD_MULTIFRAME and dwell_s otherwise.       */
 typedef struct {
-  int32_t nx, ny;          /* probe grid, >= 1 each                            */
+  int32_t nx, ny;          /* probe grid, 1 .. 2048 each (DD_EINVAL beyond:   *
+                            * squared lattice distances, below 2^23, then    *
+                            * stay exact in single precision)                */
   int32_t order;           /* dd_order                                         */
   int32_t stride;          /* DD_INTERLEAVED: >= 1                             */
   int32_t frames;          /* DD_MULTIFRAME: >= 1                              */

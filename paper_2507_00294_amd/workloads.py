@@ -135,6 +135,20 @@ def sampled_visits(n_visits: int, k: int, seed: int) -> np.ndarray:
     return np.array(sorted(idx), dtype=np.int64)
 
 
+def stratified_visits(n_visits: int, k: int, seed: int) -> np.ndarray:
+    """k visit indices, one drawn uniformly (seeded) from each of k equal
+    strata of [0, n_visits); the first stratum gives visit 0 and the last
+    gives the last visit, so both ends of the scan are always included."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = min(k, n_visits)
+    edges = (np.arange(k + 1, dtype=np.int64) * n_visits) // k
+    lo, hi = edges[:-1], edges[1:]
+    idx = lo + (rng.random(k) * (hi - lo)).astype(np.int64)
+    idx = np.minimum(idx, hi - 1)
+    idx[0], idx[-1] = 0, n_visits - 1
+    return idx
+
+
 # ---- general visit lists: per-visit position, start time and dwell -----------
 @dataclass
 class VisitList:

@@ -58,6 +58,38 @@ def test_visit_orders_match_oracle(dd, ora):
         assert s.num_visits == o.size
 
 
+def _specs_match_oracle(dd, ora, specs, what):
+    from gpu_util import oracle_visits
+
+    for k, spec in enumerate(specs):
+        s = dd.Scan(**spec.kwargs())
+        o = oracle_visits(ora, spec)
+        assert s.num_visits == o.size == spec.n_visits, (what, k)
+        assert np.array_equal(s.visits(), o), (what, k, spec.order, spec.nx, spec.seed)
+
+
+def test_visit_orders_of_every_workload_match_oracle(dd, ora):
+    """Every scan the parity tests, the benchmark and the surrogate data use:
+    the 32x32 raster and interleaved (stride 2) scans, the 512x512 random
+    scan, all 256 scans of the batched configuration (seed 4) and the
+    surrogate's training, test and validation sets (seeds 5, 6, 7)."""
+    from paper_2507_00294_amd import workloads as wl
+
+    _specs_match_oracle(dd, ora, wl.medium_scans(), "medium")
+    _specs_match_oracle(dd, ora, [wl.small_raster(), wl.large_random()], "small/large")
+    batch = wl.batch_scans()
+    assert {s.order for s in batch} == {"raster", "interleaved", "random", "multiframe"}
+    _specs_match_oracle(dd, ora, batch, "batched seed 4")
+    for seed, n in ((5, 30000), (6, 2000), (7, 2000)):
+        _specs_match_oracle(dd, ora, wl.surrogate_scans(n, seed), f"surrogate seed {seed}")
+
+
+def test_largest_grid_side_accepted(dd):
+    # 2048 probes per side is the largest grid (exact FP32 lattice distances)
+    for nx, ny in ((2048, 1), (1, 2048), (2048, 2048)):
+        assert dd.Scan(nx, ny).num_visits == nx * ny
+
+
 def test_explicit_order_copied(dd):
     v = [3, 1, 1, 0, 2]
     s = dd.Scan(2, 2, "explicit", visits=v)
@@ -74,7 +106,7 @@ def test_explicit_order_copied(dd):
     dict(nx=4, ny=4, order="multiframe", frames=0),
     dict(nx=2, ny=2, order="explicit", visits=[0, 4]),
     dict(nx=2, ny=2, order="explicit", visits=[0, -1]),
-    dict(nx=3000, ny=2),
+    dict(nx=3000, ny=2), dict(nx=2049, ny=1), dict(nx=1, ny=2049),
 ])
 def test_invalid_descriptions(dd, kw):
     nx, ny = kw.pop("nx"), kw.pop("ny")

@@ -52,7 +52,7 @@ def test_batch_small_vs_oracle(dd, ora, wl, prec):
     outs = dd.batch_solve(scans, dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES, prec)
     for spec, s, o in zip(specs, scans, outs):
         o = o.cpu().numpy()
-        ora_s = oracle_scan(ora, spec, s.visits())
+        ora_s = oracle_scan(ora, spec, s)
         assert_close(o[:s.num_visits], ora_s.psi_arrival(), spec, prec, f"batch arrival {spec.order}")
         fin = ora_s.psi_map(0.0, 0.0, spec.pitch_m, spec.pitch_m, spec.nx, spec.ny,
                             [spec.n_visits * spec.tau_v])[0].ravel()
@@ -67,7 +67,7 @@ def test_batched_configuration_sampled(dd, ora, wl):
     rng = np.random.default_rng(17)
     for k in rng.choice(len(specs), size=16, replace=False):
         spec, s, o = specs[k], scans[k], outs[k].cpu().numpy()
-        ora_s = oracle_scan(ora, spec, s.visits())
+        ora_s = oracle_scan(ora, spec, s)
         idx = wl.sampled_visits(spec.n_visits, 6, seed=int(k))
         assert_close(o[idx], ora_s.psi_arrival(idx), spec, "mixed", f"scan {k} arrival")
         pix = rng.choice(spec.nx * spec.ny, size=6, replace=False)

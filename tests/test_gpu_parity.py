@@ -67,7 +67,7 @@ def test_small_raster_maps(dd, ora, wl, prec):
     scan = dd.Scan(**spec.kwargs())
     m = wl.small_raster_maps(spec)
     got = scan.damage_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w, m.h, m.times_s, prec).cpu().numpy()
-    ref = oracle_scan(ora, spec, scan.visits()).psi_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w, m.h,
+    ref = oracle_scan(ora, spec, scan).psi_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w, m.h,
                                                         m.times_s)
     assert_close(got, ref, spec, prec, "small raster maps")
 
@@ -77,7 +77,7 @@ def test_small_raster_arrival(dd, ora, wl, prec):
     spec = wl.small_raster()
     scan = dd.Scan(**spec.kwargs())
     got = scan.arrival(prec).cpu().numpy()
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+    ref = oracle_scan(ora, spec, scan).psi_arrival()
     assert got[0] == 0.0
     assert_close(got, ref, spec, prec, "small raster arrival")
 
@@ -90,7 +90,7 @@ def test_medium_arrival(dd, ora, wl, prec):
     for spec in wl.medium_scans():
         scan = dd.Scan(**spec.kwargs())
         got = scan.arrival(prec).cpu().numpy()
-        ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+        ref = oracle_scan(ora, spec, scan).psi_arrival()
         assert_close(got, ref, spec, prec, f"medium arrival D={spec.D_m2s:.3e} {spec.order}")
 
 
@@ -102,7 +102,7 @@ def test_medium_final_map(dd, ora, wl, prec):
         m = wl.medium_final_map(spec)
         got = scan.damage_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w, m.h, m.times_s,
                               prec).cpu().numpy()
-        ref = oracle_scan(ora, spec, scan.visits()).psi_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w,
+        ref = oracle_scan(ora, spec, scan).psi_map(m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w,
                                                             m.h, m.times_s)
         assert_close(got, ref, spec, prec, "medium final map")
 
@@ -110,14 +110,22 @@ def test_medium_final_map(dd, ora, wl, prec):
 # ---------------------------------------------------------------------------
 # 512x512 random scan at full size, sampled against the oracle, in the launch
 # configuration the benchmark times
-@pytest.mark.parametrize("prec", PRECS)
-def test_large_random_sampled(dd, ora, wl, prec):
+@pytest.fixture(scope="module")
+def large_random_oracle(dd, ora, wl):
+    """The oracle at 2048 stratified visits of the 512x512 random scan (one
+    per 128-visit stratum, first and last included): about 2.7e8 pairs."""
     spec = wl.large_random()
     scan = dd.Scan(**spec.kwargs())
+    idx = wl.stratified_visits(spec.n_visits, 2048, seed=31)
+    assert idx.size == 2048
+    return spec, scan, idx, oracle_scan(ora, spec, scan).psi_arrival(idx)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_large_random_sampled(large_random_oracle, prec):
+    spec, scan, idx, ref = large_random_oracle
     got = scan.arrival(prec).cpu().numpy()
-    idx = wl.sampled_visits(spec.n_visits, 48, seed=31)
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival(idx)
-    assert_close(got[idx], ref, spec, prec, "large random arrival (sampled)")
+    assert_close(got[idx], ref, spec, prec, "large random arrival (2048 stratified visits)")
     assert np.all(got >= 0) and np.all(np.isfinite(got))
 
 
@@ -143,7 +151,7 @@ def test_bitwise_reproducible(dd, wl):
 # edge cases
 def _both(dd, ora, spec, what):
     scan = dd.Scan(**spec.kwargs())
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+    ref = oracle_scan(ora, spec, scan).psi_arrival()
     for prec in PRECS:
         got = scan.arrival(prec).cpu().numpy()
         assert_close(got, ref, spec, prec, what)
@@ -156,7 +164,7 @@ def test_single_probe(dd, ora, wl):
     t = [0.0, 0.25e-6, 1e-6, 3e-6]
     for prec in PRECS:
         got = scan.damage_map(-1e-9, -1e-9, 0.5e-9, 0.5e-9, 5, 5, t, prec).cpu().numpy()
-        ref = oracle_scan(ora, spec, scan.visits()).psi_map(-1e-9, -1e-9, 0.5e-9, 0.5e-9, 5, 5, t)
+        ref = oracle_scan(ora, spec, scan).psi_map(-1e-9, -1e-9, 0.5e-9, 0.5e-9, 5, 5, t)
         assert_close(got, ref, spec, prec, "single probe map")
         assert np.all(got[0] == 0)
 
@@ -190,7 +198,7 @@ def test_fractional_and_late_times(dd, ora, wl):
     scan = dd.Scan(**spec.kwargs())
     tau = spec.tau_v
     times = [0.0, 0.5 * tau, 1.0 * tau, 2.37 * tau, 17.999 * tau, 30 * tau, 31.5 * tau, 500 * tau]
-    ref = oracle_scan(ora, spec, scan.visits()).psi_map(0.3e-9, -0.7e-9, 0.37e-9, 0.29e-9, 11, 9,
+    ref = oracle_scan(ora, spec, scan).psi_map(0.3e-9, -0.7e-9, 0.37e-9, 0.29e-9, 11, 9,
                                                         times)
     for prec in PRECS:
         got = scan.damage_map(0.3e-9, -0.7e-9, 0.37e-9, 0.29e-9, 11, 9, times, prec).cpu().numpy()

@@ -38,7 +38,7 @@ def test_ranges_equal_full_arrival_and_oracle(dd, ora, wl, prec):
         scan = dd.Scan(**spec.kwargs())
         V = scan.num_visits
         full = scan.arrival(prec).cpu().numpy()
-        ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+        ref = oracle_scan(ora, spec, scan).psi_arrival()
         for j0, j1 in ((0, 1), (0, 300), (5, 6), (255, 257), (300, V - 100), (V - 256, V),
                        (V - 1, V), (0, V)):
             got = scan.arrival_range(j0, j1, prec).cpu().numpy()
@@ -67,7 +67,7 @@ def test_ranges_with_other_tile_shapes(dd, ora, wl, R, RN, tmp_path):
     spec = wl.ScanSpec(23, 29, "random", 1e-9, 1e-6, 0.5e-9, 5e-13, 1.0, seed=13)
     scan = dd.Scan(**spec.kwargs())
     V = scan.num_visits
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+    ref = oracle_scan(ora, spec, scan).psi_arrival()
     try:
         for prec, key in (("fp64", "arrival_fp64"), ("mixed", "arrival_mixed")):
             cfg = json.loads(json.dumps(default))
@@ -100,5 +100,5 @@ def test_bench_range_sampled_vs_oracle(dd, ora, wl, prec):
     np.testing.assert_allclose(got, full[V - 1024:], rtol=1e-13 if prec == "fp64" else 2e-7,
                                atol=0)
     idx = np.sort(np.random.default_rng(42).choice(1024, 24, replace=False)) + (V - 1024)
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival(idx)
+    ref = oracle_scan(ora, spec, scan).psi_arrival(idx)
     assert_close(got[idx - (V - 1024)], ref, spec, prec, "bench range (sampled)")

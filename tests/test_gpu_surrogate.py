@@ -93,8 +93,9 @@ def _expected_table(spec, ids):
     return x, own.reshape(64, 64)
 
 
-def test_inputs_and_targets(dd):
+def test_inputs_and_targets(dd, ora):
     import torch
+    from gpu_util import oracle_visits
 
     from paper_2507_00294_amd import workloads as wl
 
@@ -104,7 +105,8 @@ def test_inputs_and_targets(dd):
     x, own = dd.surrogate_inputs(scans)
     x, own = x.cpu().numpy(), own.cpu().numpy()
     for k, (spec, s) in enumerate(zip(specs, scans)):
-        ex, eo = _expected_table(spec, s.visits())
+        ex, eo = _expected_table(spec, oracle_visits(ora, spec))
+        assert np.array_equal(s.visits(), oracle_visits(ora, spec))
         np.testing.assert_allclose(x[k], ex, rtol=2e-6, atol=2e-7)
         np.testing.assert_allclose(own[k], eo, rtol=2e-6, atol=0)
     outs = dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, "fp64")

@@ -42,7 +42,7 @@ def test_sweep_whole_scan_vs_oracle(dd, ora, wl, prec):
     n_t = 4 * spec.n_visits + 8
     got = scan.damage_sweep(0.0, 0.0, 0.25e-9, 0.25e-9, 32, 32, 0.0, dt, n_t, prec).cpu().numpy()
     times = [k * dt for k in range(n_t)]
-    ref = oracle_scan(ora, spec, scan.visits()).psi_map(0.0, 0.0, 0.25e-9, 0.25e-9, 32, 32, times)
+    ref = oracle_scan(ora, spec, scan).psi_map(0.0, 0.0, 0.25e-9, 0.25e-9, 32, 32, times)
     assert np.all(got[0] == 0.0)  # nothing has started at t = 0
     assert_close(got, ref, spec, prec, "sweep")
 
@@ -58,7 +58,7 @@ def test_sweep_off_lattice_vs_oracle(dd, ora, wl, prec):
     args = (0.3e-9, -0.2e-9, 0.45e-9, 0.45e-9, 13, 11)
     got = scan.damage_sweep(*args, 0.05 * spec.tau_v, dt, n_t, prec).cpu().numpy()
     times = [0.05 * spec.tau_v + k * dt for k in range(n_t)]
-    ref = oracle_scan(ora, spec, scan.visits()).psi_map(*args, times)
+    ref = oracle_scan(ora, spec, scan).psi_map(*args, times)
     assert_close(got, ref, spec, prec, "off-lattice sweep")
     same = scan.damage_map(*args, times, prec).cpu().numpy()
     assert np.array_equal(got, same)
@@ -109,5 +109,5 @@ def test_bench_sweep_sampled_vs_oracle(dd, ora, wl, prec):
     got = out[torch.as_tensor(m, device="cuda"), torch.as_tensor(v, device="cuda"),
               torch.as_tensor(u, device="cuda")].cpu().numpy()
     del out
-    ref = oracle_scan(ora, spec, scan.visits()).psi_points(u * 0.5e-9, v * 0.5e-9, m * dt)
+    ref = oracle_scan(ora, spec, scan).psi_points(u * 0.5e-9, v * 0.5e-9, m * dt)
     assert_close(got, ref, spec, prec, "bench sweep (sampled)")

@@ -29,7 +29,7 @@ def test_autotune_roundtrip(ora, tmp_path):
     dd.tune_load(str(path))
     spec = wl.medium_scans(1)[0]
     scan = dd.Scan(**spec.kwargs())
-    ref = oracle_scan(ora, spec, scan.visits()).psi_arrival()
+    ref = oracle_scan(ora, spec, scan).psi_arrival()
     for prec in ("fp64", "mixed"):
         assert_close(scan.arrival(prec).cpu().numpy(), ref, spec, prec, "tuned arrival")
     specs = wl.batch_scans(6, seed=77, side_lo=8, side_hi=40)
