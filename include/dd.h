@@ -160,6 +160,20 @@ dd_status dd_batch_solve(dd_scan *const *scans, int32_t n, uint32_t query_mask,
                          dd_precision p, double *const *outs, int32_t out_on_device,
                          void *hip_stream);
 
+/* Non-finite output check of the handle's last query (its own call, or its
+ * part of the last dd_batch_solve that included it).  Waits for that call
+ * to finish on the device.  Returns DD_EDEVICE if a value it wrote for this
+ * scan was not finite, with *first_bad (may be NULL) set to the smallest
+ * such index of the scan's output of that call (for a batched call: [V]
+ * arrival first, then the final map), else DD_OK with *first_bad = -1
+ * (also for a handle that has run no query).  Calls with host outputs make
+ * this check themselves and return DD_EDEVICE before they return; a batched
+ * call then names the scan.  Every value of Eq. 6 is finite for a valid
+ * scan; a non-finite one means that Q0/(4 pi D) times the dimensionless
+ * sum overflowed, or a device fault.  The current device must be the one
+ * the handle ran on.  Errors: DD_EINVAL (NULL, another device), DD_EDEVICE. */
+dd_status dd_scan_check(dd_scan *s, int64_t *first_bad);
+
 /* Dimensionless pair term phi_hat = phi * 4 pi D / Q0 (Eqs. 1-4) for n
  * (a, lag) pairs: a[k] = squared distance / pitch^2 (>= 0), lag[k] = time
  * since the visit started / tau_v (> 0), with kappa = D tau_v / pitch^2 and
@@ -279,7 +293,10 @@ dd_status dd_unet_predict(dd_unet *u, dd_scan *const *scans, int32_t n, double s
  * per-visit dwells, flyback and dead time between lines or frames,
  * subsampled (sparse) scans, revisits and any visit order are all lists.
  * DD_FP64 meets the FP64 bound; DD_MIXED evaluates the near-pair integral
- * (almost every pair of a long list) in FP32 and meets the mixed bound.   */
+ * (almost every pair of a long list) in FP32 and meets the mixed bound.
+ * These calls synchronize the stream before they return (also with device
+ * outputs), and return DD_EDEVICE naming the list and the index of the
+ * first output value that is not finite.                                  */
 typedef struct dd_visits dd_visits; /* opaque */
 
 /* Copies n >= 1 visits: x_m, y_m (metres), t0_s (beam-on start, seconds)

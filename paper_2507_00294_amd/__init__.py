@@ -29,7 +29,7 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
     "dd_damage_map", "dd_damage_sweep", "dd_damage_at_probe_arrival",
-    "dd_damage_at_probe_arrival_range", "dd_batch_solve",
+    "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_scan_check",
     "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
@@ -90,6 +90,7 @@ def load_library():
     lib.dd_damage_at_probe_arrival_range.argtypes = [vp, i64, i64, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_at_probe_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_batch_solve.argtypes = [P(vp), i32, ctypes.c_uint32, ctypes.c_int, P(vp), i32, vp]
+    lib.dd_scan_check.argtypes = [vp, P(i64)]
     lib.dd_pair_terms.argtypes = [dbl, dbl, i64, vp, vp, ctypes.c_int, vp, vp]
     lib.dd_autotune.argtypes = [ctypes.c_char_p]
     lib.dd_tune_load.argtypes = [ctypes.c_char_p]
@@ -123,7 +124,7 @@ def load_library():
                                         P(vp), i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
-                 "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_pair_terms", "dd_autotune",
+                 "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_scan_check", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
@@ -214,6 +215,16 @@ class Scan:
         _check(load_library().dd_scan_visits(
             self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
+
+    def check(self) -> int:
+        """Waits for the handle's last query (``dd_scan_check``) and returns the
+        first index of its output that is not finite, or -1."""
+        bad = ctypes.c_int64(-1)
+        st = load_library().dd_scan_check(self._h, ctypes.byref(bad))
+        if st == DD_EDEVICE and bad.value >= 0:
+            return int(bad.value)
+        _check(st)
+        return -1
 
     def arrival(self, precision: str = "fp64", out=None, stream=None):
         """psi at each visit at its start (``dd_damage_at_probe_arrival``) as a

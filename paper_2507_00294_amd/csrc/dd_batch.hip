@@ -79,7 +79,7 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 // on the output offsets; slots added in the same order as the per-scan
 // reductions.
 __global__ void __launch_bounds__(256) k_reduce_batch(const BatchReduce* __restrict__ reds,
-                                                      int n_red, int64_t total) {
+                                                      int n_red, int64_t total, OutFlag fl) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = n_red - 1;
@@ -95,7 +95,10 @@ __global__ void __launch_bounds__(256) k_reduce_batch(const BatchReduce* __restr
     const int ns = Rd.tile_slots ? Rd.tile_slots[j / Rd.tile] : Rd.n_slots;
     double s = 0.0;
     for (int k = 0; k < ns; ++k) s += Rd.partial[(int64_t)k * Rd.n + j];
-    Rd.out[j] = Rd.pref * s;
+    const double v = Rd.pref * s;
+    Rd.out[j] = v;
+    flag_nonfinite(Rd.scan_flag, v, j);
+    flag_nonfinite(fl, v, e);
   }
 }
 
@@ -183,10 +186,10 @@ hipError_t launch_batch_map(const BatchScan* scans, const BatchItem* items, int3
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
+hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total, OutFlag fl,
                                hipStream_t st) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_batch, dim3(batch_grid_for(total)), dim3(256), 0, st, reds, n_red, total);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(batch_grid_for(total)), dim3(256), 0, st, reds, n_red, total, fl);
   return hipGetLastError();
 }
 

@@ -270,6 +270,15 @@ __device__ __forceinline__ float series_f32a(float a, const RowA& w) {
   return t * q;
 }
 
+// Marks a non-finite output value in the word of `f` (see OutFlag).
+__device__ __forceinline__ void flag_nonfinite(const OutFlag& f, double v, int64_t idx) {
+  if (__builtin_isfinite(v) || f.word == nullptr) return;
+  constexpr unsigned long long lim = (1ull << kFlagIndexBits) - 1;
+  unsigned long long i = (unsigned long long)(f.base + idx);
+  if (i >= lim) i = lim - 1;
+  atomicMax(f.word, (f.seq << kFlagIndexBits) | (lim - i));
+}
+
 // The 8 bulk fields of an FP32 row; CAS: through the constant address space
 // (scalar loads also where the table pointer was read from memory).
 template <bool CAS>

@@ -365,11 +365,8 @@ dd_status dd_scan_create(const dd_scan_desc* desc, dd_scan** out) {
   return DD_OK;
 }
 
-void dd_forget_plans(const dd_scan* s);
-
 void dd_scan_destroy(dd_scan* s) {
   if (!s) return;
-  dd_forget_plans(s);
   s->release_device();
   delete s;
 }

@@ -123,6 +123,20 @@ struct BatchScan {
 struct BatchItem {
   int32_t scan, kind, tile, n_lo, n_hi, slot_flags, cost_hi, cost_lo;
 };
+// Check of non-finite outputs.  A reduction that writes a value that is not
+// finite raises *word to (seq << kFlagIndexBits) | (2^kFlagIndexBits - 1 -
+// (base + index)) by an atomic max, so the word names the latest flagged
+// call (seq, 24 bits) and the smallest bad output index of that call.  No
+// word is cleared per call: a call owns a fresh seq.  word == nullptr: no
+// check.
+constexpr int kFlagIndexBits = 40;
+constexpr uint64_t kFlagSeqMax = (1ull << 24) - 1;
+struct OutFlag {
+  unsigned long long* word;
+  unsigned long long seq;
+  int64_t base;
+};
+
 // Reduction work of a batch: one entry per (scan, query).
 struct BatchReduce {
   const double* partial;
@@ -133,6 +147,7 @@ struct BatchReduce {
   int64_t out_off;            // first output in the flat index space
   double* out;
   double pref;
+  OutFlag scan_flag;          // the scan's own word (index: its output index)
 };
 
 }  // namespace dd

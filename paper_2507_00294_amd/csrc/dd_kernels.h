@@ -50,15 +50,18 @@ struct MapLaunch {
 };
 hipError_t launch_map(const MapLaunch& L, hipStream_t st);
 
+// Fixed-order sums of the partial slots times pref; non-finite results are
+// marked in the word of `fl` (fl.word may be null).
 hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots,
                                  int64_t pstride, int64_t pj0, int tile, double pref, int64_t j0,
-                                 int64_t n, double* out, hipStream_t st);
+                                 int64_t n, double* out, OutFlag fl, hipStream_t st);
 // One wave per visit (for visits with many slots).
 hipError_t launch_reduce_arrival_wide(const double* partial, const int32_t* tile_slots,
                                       int64_t pstride, int64_t pj0, int tile, double pref,
-                                      int64_t j0, int64_t n, double* out, hipStream_t st);
+                                      int64_t j0, int64_t n, double* out, OutFlag fl,
+                                      hipStream_t st);
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
-                             int64_t npix, double pref, double* out, hipStream_t st);
+                             int64_t npix, double pref, double* out, OutFlag fl, hipStream_t st);
 
 // Persistent batched launches (arrival far-region items; arrival near-band
 // items; map far-region or near-band items); `counter` is zeroed on the
@@ -69,7 +72,9 @@ hipError_t launch_batch_near(const BatchScan* scans, const BatchItem* items, int
                              int* counter, int RN, bool mixed, hipStream_t st);
 hipError_t launch_batch_map(const BatchScan* scans, const BatchItem* items, int32_t n_items,
                             int* counter, int RM, bool mixed, bool near, hipStream_t st);
-hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total,
+// Also marks each non-finite result in its scan's word and in `fl` (index:
+// the flat output index of the call).
+hipError_t launch_reduce_batch(const BatchReduce* reds, int32_t n_red, int64_t total, OutFlag fl,
                                hipStream_t st);
 
 hipError_t launch_pair_terms(double kappa, double s2, int64_t n, const double* a,

@@ -97,14 +97,16 @@ __global__ void __launch_bounds__(256) k_reduce_arrival(const double* __restrict
                                                         const int32_t* __restrict__ tile_slots,
                                                         int64_t pstride, int64_t pj0, int tile,
                                                         double pref, int64_t j0, int64_t n,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, OutFlag fl) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t j = j0 + i;
     const int ns = tile_slots[j / tile];
     double s = 0.0;
     for (int k = 0; k < ns; ++k) s += partial[(int64_t)k * pstride + (j - pj0)];
-    out[i] = pref * s;
+    const double v = pref * s;
+    out[i] = v;
+    flag_nonfinite(fl, v, i);
   }
 }
 
@@ -115,7 +117,7 @@ __global__ void __launch_bounds__(256) k_reduce_arrival_wide(const double* __res
                                                              const int32_t* __restrict__ tile_slots,
                                                              int64_t pstride, int64_t pj0, int tile,
                                                              double pref, int64_t j0, int64_t n,
-                                                             double* __restrict__ out) {
+                                                             double* __restrict__ out, OutFlag fl) {
   const int lane = threadIdx.x & 63;
   for (int64_t i = blockIdx.x * 4 + wave_id(); i < n; i += (int64_t)gridDim.x * 4) {
     const int64_t j = j0 + i;
@@ -124,14 +126,18 @@ __global__ void __launch_bounds__(256) k_reduce_arrival_wide(const double* __res
     for (int k = lane; k < ns; k += 64) s += partial[(int64_t)k * pstride + (j - pj0)];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) out[i] = pref * s;
+    if (lane == 0) {
+      const double v = pref * s;
+      out[i] = v;
+      flag_nonfinite(fl, v, i);
+    }
   }
 }
 
 __global__ void __launch_bounds__(256) k_reduce_map(const double* __restrict__ partial,
                                                     const MapTime* __restrict__ times, int n_t,
                                                     int64_t npix, double pref,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, OutFlag fl) {
   const int64_t total = npix * n_t;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -139,7 +145,9 @@ __global__ void __launch_bounds__(256) k_reduce_map(const double* __restrict__ p
     const MapTime tm = times[m];
     double s = 0.0;
     for (int k = 0; k < tm.n_slots; ++k) s += partial[(tm.slot_base + k) * npix + pix];
-    out[e] = pref * s;
+    const double v = pref * s;
+    out[e] = v;
+    flag_nonfinite(fl, v, e);
   }
 }
 
@@ -252,27 +260,28 @@ hipError_t launch_map(const MapLaunch& L, hipStream_t st) {
 
 hipError_t launch_reduce_arrival(const double* partial, const int32_t* tile_slots,
                                  int64_t pstride, int64_t pj0, int tile, double pref, int64_t j0,
-                                 int64_t n, double* out, hipStream_t st) {
+                                 int64_t n, double* out, OutFlag fl, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_arrival, dim3(grid_for(n)), dim3(256), 0, st, partial, tile_slots,
-                     pstride, pj0, tile, pref, j0, n, out);
+                     pstride, pj0, tile, pref, j0, n, out, fl);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_arrival_wide(const double* partial, const int32_t* tile_slots,
                                       int64_t pstride, int64_t pj0, int tile, double pref,
-                                      int64_t j0, int64_t n, double* out, hipStream_t st) {
+                                      int64_t j0, int64_t n, double* out, OutFlag fl,
+                                      hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<int64_t>((n + 3) / 4, 65536);
   hipLaunchKernelGGL(k_reduce_arrival_wide, dim3(blocks), dim3(256), 0, st, partial, tile_slots,
-                     pstride, pj0, tile, pref, j0, n, out);
+                     pstride, pj0, tile, pref, j0, n, out, fl);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_map(const double* partial, const MapTime* times, int32_t n_t,
-                             int64_t npix, double pref, double* out, hipStream_t st) {
+                             int64_t npix, double pref, double* out, OutFlag fl, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_map, dim3(grid_for(npix * n_t)), dim3(256), 0, st, partial, times,
-                     n_t, npix, pref, out);
+                     n_t, npix, pref, out, fl);
   return hipGetLastError();
 }
 

@@ -70,7 +70,71 @@ dd_status dd_scan::prepare(hipStream_t st) {
   if (rc != DD_OK) return rc;
   rc = upload(pos4, p4, st);
   if (rc != DD_OK) return rc;
+  rc = upload(flag, std::vector<unsigned long long>(1, 0ull), st);
+  if (rc != DD_OK) return rc;
+  seq = 0;
   dev = cur;
+  return DD_OK;
+}
+
+dd_status dd_scan::wait_last(hipStream_t st) {
+  if (last && last->stream != st) DD_HIP(hipStreamWaitEvent(st, last->ev, 0), "stream wait");
+  return DD_OK;
+}
+
+dd_status dd_scan::record_last(hipStream_t st) {
+  if (!own) {
+    auto e = std::make_shared<StreamEvent>();
+    DD_HIP(hipEventCreateWithFlags(&e->ev, hipEventDisableTiming), "event creation");
+    own = e;
+  }
+  DD_HIP(hipEventRecord(own->ev, st), "event record");
+  own->stream = st;
+  last = own;
+  return DD_OK;
+}
+
+dd_status dd_scan::next_flag(hipStream_t st, OutFlag& fl) {
+  if (seq >= kFlagSeqMax) {  // the seq wraps: clear the word first
+    dd_status rc = upload(flag, std::vector<unsigned long long>(1, 0ull), st);
+    if (rc != DD_OK) return rc;
+    seq = 0;
+  }
+  ++seq;
+  fl = OutFlag{flag.as<unsigned long long>(), (unsigned long long)seq, 0};
+  return DD_OK;
+}
+
+namespace dd {
+
+// Host word that receives a flag word (pinned, one per thread).
+static thread_local unsigned long long* g_flag_host = nullptr;
+
+// Copies a flag word to the host on st, synchronizes st and decodes it:
+// the first non-finite output index of call `call_seq`, or -1.
+static dd_status read_flag(const unsigned long long* word, hipStream_t st, uint64_t call_seq,
+                           int64_t& first_bad) {
+  first_bad = -1;
+  if (!g_flag_host)
+    DD_HIP(hipHostMalloc((void**)&g_flag_host, 256, hipHostMallocDefault), "pinned host allocation");
+  DD_HIP(hipMemcpyAsync(g_flag_host, word, sizeof(unsigned long long), hipMemcpyDeviceToHost, st),
+         "device-to-host copy");
+  DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  const unsigned long long w = *g_flag_host;
+  constexpr unsigned long long lim = (1ull << kFlagIndexBits) - 1;
+  if ((w >> kFlagIndexBits) == call_seq) first_bad = (int64_t)(lim - (w & lim));
+  return DD_OK;
+}
+
+}  // namespace dd
+
+dd_status dd_scan::check_flag(hipStream_t st, uint64_t call_seq) {
+  int64_t bad = -1;
+  dd_status rc = read_flag(flag.as<unsigned long long>(), st, call_seq, bad);
+  if (rc != DD_OK) return rc;
+  if (bad >= 0)
+    return fail(DD_EDEVICE, "non-finite output value at index %lld of the call's output",
+                (long long)bad);
   return DD_OK;
 }
 
@@ -90,15 +154,6 @@ dd_status build_int_rows(dd_scan* s, hipStream_t st) {
   s->n_rows = n_rows;
   return DD_OK;
 }
-
-struct ArrivalPlan {
-  int R = 0, RN = 0, K = 0;
-  bool mixed = false;
-  int64_t V = -1;
-  int n_near = 0, n_far = 0, S = 0;
-  DegreeBounds bounds{};
-  double near_pairs = 0, near_flops = 0, far_pairs = 0, far_flops = 0;
-};
 
 // Causal pairs of an arrival item: sum over visits j in [A, B) of the lags
 // n in [lo, hi) with n <= j.
@@ -264,12 +319,7 @@ void order_far_for_xcds(std::vector<ArrItem>& far) {
   far.swap(out);
 }
 
-struct PlanCache {
-  ArrivalPlan arr;
-};
-std::map<const dd_scan*, PlanCache> g_plans;  // per handle (handles are not thread safe)
-
-dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
+dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, const OutFlag& fl, hipStream_t st) {
   dd_status rc = s->prepare(st);
   if (rc != DD_OK) return rc;
   ProfToken tr = prof_begin("lag_rows", st);
@@ -279,7 +329,7 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
   const int K = arrival_K(s->V, R, mixed);
-  ArrivalPlan& P = g_plans[s].arr;
+  ArrivalPlan& P = s->arr_plan;
   if (P.V != s->V || P.R != R || P.RN != RN || P.K != K || P.mixed != mixed) {
     std::vector<ArrItem> items, far;
     std::vector<int32_t> tile_slots;
@@ -325,7 +375,7 @@ dd_status run_arrival(dd_scan* s, bool mixed, double* out_dev, hipStream_t st) {
   prof_end(tf, st, P.far_pairs, P.far_flops);
   ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_arrival(s->partial.as<double>(), s->aux.as<int32_t>(), s->V, 0, 64 * R,
-                               s->pref, 0, s->V, out_dev, st),
+                               s->pref, 0, s->V, out_dev, fl, st),
          "arrival reduce launch");
   prof_end(tq, st, 0, 0);
   return DD_OK;
@@ -356,56 +406,41 @@ struct RangeStage {
 };
 static thread_local RangeStage g_range;
 
+}  // namespace
+
 // Arrival at the visits [j0, j1) only (streaming: the visits just made).
-// Only the tiles holding them are planned, with lag chunks of 512 lags (at
-// least V/256, which bounds the partial rows at 257 V), so that a few tiles
-// still spread over many waves.
-dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, double* out_dev,
-                            hipStream_t st) {
-  dd_status rc = s->prepare(st);
-  if (rc != DD_OK) return rc;
-  rc = build_int_rows(s, st);
-  if (rc != DD_OK) return rc;
-  if (j1 <= j0) return DD_OK;
+// Only the tiles holding them are planned.  The partial sums keep only the
+// columns of the range's tiles, so the lag chunks can be short: about 8192
+// far items over the range's tiles, and the near band in pieces of 16 lags.
+// The plan is a pure function of the scan, the range, the precision and the
+// tuned tile shapes, so every entry point that runs it gives the same
+// results bit for bit.
+void dd::plan_range(const dd_scan* s, bool mixed, int64_t j0, int64_t j1, bool count,
+                    RangePlan& rp) {
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
-  // Partial sums keep only the columns of the range's tiles, so the lag
-  // chunks can be short: about 8192 far items over the range's tiles, and
-  // the near band in pieces of 16 lags.
   const int64_t T = 64 * R, TN = 64 * RN;
-  const int64_t pj0 = std::min(j0 / T * T, j0 / TN * TN);
+  rp.pj0 = std::min(j0 / T * T, j0 / TN * TN);
   const int64_t pend = std::max((j1 + T - 1) / T * T, (j1 + TN - 1) / TN * TN);
-  const int64_t pstride = pend - pj0;
+  rp.pstride = pend - rp.pj0;
   const int64_t tiles = (j1 - 1) / T - j0 / T + 1;
   int64_t K64 = std::max<int64_t>(64, (tiles * j1 + 8191) / 8192);
   const int K = (int)std::min<int64_t>((K64 + R - 1) / R * R, 1 << 28);
-  ArrivalPlan P;
-  std::vector<ArrItem> items, far;
-  std::vector<int32_t> tile_slots;
-  plan_arrival(s, mixed, R, RN, K, P, items, far, tile_slots, prof_on(), j0, j1, 16);
+  plan_arrival(s, mixed, R, RN, K, rp.P, rp.items, rp.far, rp.tile_slots, count, j0, j1, 16);
   auto longer = [](const ArrItem& a, const ArrItem& b) {
     return (a.n_hi - a.n_lo) > (b.n_hi - b.n_lo);
   };
-  std::stable_sort(items.begin(), items.end(), longer);
-  std::stable_sort(far.begin(), far.end(), longer);
-  items.insert(items.end(), far.begin(), far.end());  // near items first
-  const size_t bi = sizeof(ArrItem) * items.size(), bt = sizeof(int32_t) * tile_slots.size();
-  DD_HIP(s->aux2.ensure(std::max<size_t>(bi, 16)), "device allocation");
-  DD_HIP(s->aux3.ensure(std::max<size_t>(bt, 16)), "device allocation");
-  RangeStage& G = g_range;
-  if (G.pending) DD_HIP(hipEventSynchronize(G.copied), "event synchronize");
-  G.pending = false;
-  DD_HIP(G.host.ensure(bi + bt), "pinned host allocation");
-  if (bi) std::memcpy(G.host.p, items.data(), bi);
-  if (bt) std::memcpy((char*)G.host.p + bi, tile_slots.data(), bt);
-  if (!G.copied) DD_HIP(hipEventCreateWithFlags(&G.copied, hipEventDisableTiming), "event creation");
-  if (bi) DD_HIP(hipMemcpyAsync(s->aux2.p, G.host.p, bi, hipMemcpyHostToDevice, st),
-                 "host-to-device copy");
-  if (bt) DD_HIP(hipMemcpyAsync(s->aux3.p, (char*)G.host.p + bi, bt, hipMemcpyHostToDevice, st),
-                 "host-to-device copy");
-  DD_HIP(hipEventRecord(G.copied, st), "event record");
-  G.pending = true;
-  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)pstride), "device allocation");
+  std::stable_sort(rp.items.begin(), rp.items.end(), longer);
+  std::stable_sort(rp.far.begin(), rp.far.end(), longer);
+  rp.items.insert(rp.items.end(), rp.far.begin(), rp.far.end());  // near items first
+}
+
+// Launches of a planned range whose items, tile slots and partial sums are
+// at the given device addresses (rows and positions resident).
+dd_status dd::launch_range(dd_scan* s, bool mixed, const RangePlan& rp, int64_t j0, int64_t j1,
+                           const ArrItem* d_items, const int32_t* d_slots, double* d_partial,
+                           double* out_dev, const OutFlag& fl, hipStream_t st, bool profile) {
+  const ArrivalPlan& P = rp.P;
   ArrivalLaunch L{};
   L.pos = mixed ? (const void*)(s->pos32.as<float2>() + kPosPad)
                 : (const void*)(s->pos64.as<double2>() + kPosPad);
@@ -414,31 +449,64 @@ dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, doub
   L.rows32 = s->rows32.as<float>();
   L.V = s->V;
   L.bounds = P.bounds;
-  L.partial = s->partial.as<double>();
-  L.pstride = pstride;
-  L.pj0 = pj0;
+  L.partial = d_partial;
+  L.pstride = rp.pstride;
+  L.pj0 = rp.pj0;
   L.mixed = mixed;
-  L.items = s->aux2.as<ArrItem>();
+  L.items = d_items;
   L.n_items = P.n_near;
   L.near = true;
-  L.R = RN;
-  ProfToken tn = prof_begin("arrival_near", st);
+  L.R = P.RN;
+  ProfToken tn = profile ? prof_begin("arrival_near", st) : ProfToken{};
   DD_HIP(launch_arrival(L, st), "arrival near-band launch");
-  prof_end(tn, st, P.near_pairs, P.near_flops);
-  L.items = s->aux2.as<ArrItem>() + P.n_near;
+  if (profile) prof_end(tn, st, P.near_pairs, P.near_flops);
+  L.items = d_items + P.n_near;
   L.n_items = P.n_far;
   L.near = false;
-  L.R = R;
-  ProfToken tf = prof_begin("arrival_far", st);
+  L.R = P.R;
+  ProfToken tf = profile ? prof_begin("arrival_far", st) : ProfToken{};
   DD_HIP(launch_arrival(L, st), "arrival far-region launch");
-  prof_end(tf, st, P.far_pairs, P.far_flops);
-  ProfToken tq = prof_begin("reduce", st);
+  if (profile) prof_end(tf, st, P.far_pairs, P.far_flops);
+  ProfToken tq = profile ? prof_begin("reduce", st) : ProfToken{};
   DD_HIP((P.S > 64 ? launch_reduce_arrival_wide : launch_reduce_arrival)(
-             s->partial.as<double>(), s->aux3.as<int32_t>(), pstride, pj0, 64 * R, s->pref, j0,
-             j1 - j0, out_dev, st),
+             d_partial, d_slots, rp.pstride, rp.pj0, 64 * P.R, s->pref, j0, j1 - j0, out_dev, fl,
+             st),
          "arrival reduce launch");
-  prof_end(tq, st, 0, 0);
+  if (profile) prof_end(tq, st, 0, 0);
   return DD_OK;
+}
+
+namespace {
+
+dd_status run_arrival_range(dd_scan* s, bool mixed, int64_t j0, int64_t j1, double* out_dev,
+                            const OutFlag& fl, hipStream_t st) {
+  dd_status rc = s->prepare(st);
+  if (rc != DD_OK) return rc;
+  rc = build_int_rows(s, st);
+  if (rc != DD_OK) return rc;
+  if (j1 <= j0) return DD_OK;
+  static thread_local RangePlan rp;  // host vectors reused between calls
+  plan_range(s, mixed, j0, j1, prof_on(), rp);
+  const ArrivalPlan& P = rp.P;
+  const size_t bi = sizeof(ArrItem) * rp.items.size(), bt = sizeof(int32_t) * rp.tile_slots.size();
+  DD_HIP(s->aux2.ensure(std::max<size_t>(bi, 16)), "device allocation");
+  DD_HIP(s->aux3.ensure(std::max<size_t>(bt, 16)), "device allocation");
+  RangeStage& G = g_range;
+  if (G.pending) DD_HIP(hipEventSynchronize(G.copied), "event synchronize");
+  G.pending = false;
+  DD_HIP(G.host.ensure(bi + bt), "pinned host allocation");
+  if (bi) std::memcpy(G.host.p, rp.items.data(), bi);
+  if (bt) std::memcpy((char*)G.host.p + bi, rp.tile_slots.data(), bt);
+  if (!G.copied) DD_HIP(hipEventCreateWithFlags(&G.copied, hipEventDisableTiming), "event creation");
+  if (bi) DD_HIP(hipMemcpyAsync(s->aux2.p, G.host.p, bi, hipMemcpyHostToDevice, st),
+                 "host-to-device copy");
+  if (bt) DD_HIP(hipMemcpyAsync(s->aux3.p, (char*)G.host.p + bi, bt, hipMemcpyHostToDevice, st),
+                 "host-to-device copy");
+  DD_HIP(hipEventRecord(G.copied, st), "event record");
+  G.pending = true;
+  DD_HIP(s->partial.ensure(sizeof(double) * (size_t)P.S * (size_t)rp.pstride), "device allocation");
+  return launch_range(s, mixed, rp, j0, j1, s->aux2.as<ArrItem>(), s->aux3.as<int32_t>(),
+                      s->partial.as<double>(), out_dev, fl, st, true);
 }
 
 // Map query.  Times are snapped to a dwell boundary when within 8 ulp.
@@ -636,7 +704,7 @@ void plan_map(const dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t
 }
 
 dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, bool mixed,
-                  double* out_dev, hipStream_t st) {
+                  double* out_dev, const OutFlag& fl, hipStream_t st) {
   dd_status rc = s->prepare(st);
   if (rc != DD_OK) return rc;
   // The FP32 bulk takes the squared distance a exactly only when pixels and
@@ -689,23 +757,48 @@ dd_status run_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t, 
   prof_end(tm, st, P.pairs, P.flops);
   ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_map(s->partial.as<double>(), s->aux3.as<MapTime>(), n_t, P.npix, s->pref,
-                           out_dev, st),
+                           out_dev, fl, st),
          "map reduce launch");
   prof_end(tq, st, 0, 0);
   return DD_OK;
 }
 
-// Result delivery: device output directly, or a device scratch then a copy.
+// A query call on one scan.  It waits for the handle's last call if that ran
+// on another stream, takes a fresh non-finite flag, runs into `out` (device)
+// or into the handle's staging buffer and then host memory, and records its
+// event.  With host outputs it synchronizes and returns DD_EDEVICE if an
+// output value was not finite; with device outputs dd_scan_check reports
+// that later.
+}  // namespace
+
+dd_status dd::begin_call(dd_scan* s, hipStream_t st, OutFlag& fl) {
+  dd_status rc = s->prepare(st);
+  if (rc != DD_OK) return rc;
+  rc = s->wait_last(st);
+  if (rc != DD_OK) return rc;
+  return s->next_flag(st, fl);
+}
+
+namespace {
+
 template <typename F>
 dd_status deliver(dd_scan* s, size_t n, double* out, int32_t on_device, hipStream_t st, F&& run) {
-  if (on_device) return run(out);
+  OutFlag fl;
+  dd_status rc = begin_call(s, st, fl);
+  if (rc != DD_OK) return rc;
+  if (on_device) {
+    rc = run(out, fl);
+    if (rc != DD_OK) return rc;
+    return s->record_last(st);
+  }
   DD_HIP(s->tmp_out.ensure(sizeof(double) * std::max<size_t>(n, 1)), "device allocation");
-  dd_status rc = run(s->tmp_out.as<double>());
+  rc = run(s->tmp_out.as<double>(), fl);
   if (rc != DD_OK) return rc;
   if (n) DD_HIP(hipMemcpyAsync(out, s->tmp_out.p, sizeof(double) * n, hipMemcpyDeviceToHost, st),
                 "device-to-host copy");
-  DD_HIP(hipStreamSynchronize(st), "stream synchronize");
-  return DD_OK;
+  rc = s->record_last(st);
+  if (rc != DD_OK) return rc;
+  return s->check_flag(st, fl.seq);
 }
 
 
@@ -732,6 +825,11 @@ struct BatchScratch {
   std::vector<uint64_t> h_ka, h_kb;
   hipEvent_t done = nullptr, copied = nullptr;  // kept until the process ends
   bool pending = false, copy_pending = false;
+  // the call's non-finite flag (index: flat output index of the call) and
+  // the event each scan of the last call holds as its last call
+  DevBuf flag;
+  uint64_t seq = 0;
+  std::shared_ptr<StreamEvent> ev;
 };
 static thread_local BatchScratch g_batch;
 static thread_local uint64_t g_plan_clock = 0;  // recency of the handles' cached map plans
@@ -845,14 +943,29 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   int64_t partial_total = 0, out_total = 0;
   double pairs = 0, flops = 0;
   ProfToken trw = prof_begin("lag_rows", st);
+  std::vector<OutFlag> scan_flag(n);
+  const StreamEvent* waited = nullptr;
   for (int32_t k = 0; k < n; ++k) {
     dd_scan* s = scans[k];
     dd_status rc = s->prepare(st);
+    if (rc != DD_OK) return rc;
+    // rows (or a pending call) of a scan last used on another stream
+    if (s->last && s->last->stream != st && s->last.get() != waited) {
+      DD_HIP(hipStreamWaitEvent(st, s->last->ev, 0), "stream wait");
+      waited = s->last.get();
+    }
+    rc = s->next_flag(st, scan_flag[k]);
     if (rc != DD_OK) return rc;
     rc = build_int_rows(s, st);
     if (rc != DD_OK) return rc;
   }
   prof_end(trw, st, 0, 0);
+  if (!W.flag.p || W.seq >= kFlagSeqMax) {
+    dd_status rc = upload(W.flag, std::vector<unsigned long long>(1, 0ull), st);
+    if (rc != DD_OK) return rc;
+    W.seq = 0;
+  }
+  const OutFlag call_flag{W.flag.as<unsigned long long>(), (unsigned long long)++W.seq, 0};
   for (int32_t k = 0; k < n; ++k) {
     dd_scan* s = scans[k];
     BatchScan& B = bs[k];
@@ -904,7 +1017,8 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       };
       add(near_items, an, kBatchArrNear, 64.0 * RN * near_w);
       add(items, af, kBatchArrFar, 64.0 * R);
-      reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref});
+      reds.push_back(BatchReduce{nullptr, nullptr, 0, 64 * R, s->V, out_total, nullptr, s->pref,
+                                 scan_flag[k]});
       out_total += s->V;
       pairs += C.pairs;
       flops += C.flops;
@@ -951,8 +1065,10 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
             .push_back(BatchItem{k, m.near ? kBatchMapNear : kBatchMapFar, m.tile, m.n_lo, m.n_hi,
                                  m.slot, (int32_t)(c >> 31), (int32_t)(c & 0x7fffffff)});
       }
+      OutFlag mf = scan_flag[k];
+      mf.base = want_arr ? s->V : 0;  // index into the scan's output
       reds.push_back(BatchReduce{nullptr, nullptr, C->time.n_slots, 0, C->npix, out_total,
-                                 nullptr, s->pref});
+                                 nullptr, s->pref, mf});
       out_total += C->npix;
       pairs += C->pairs;
       flops += C->flops;
@@ -1036,12 +1152,21 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   prof_end(tb, st, pairs, flops);
   ProfToken tq = prof_begin("reduce", st);
   DD_HIP(launch_reduce_batch((const BatchReduce*)(blk + tab[5].off), (int32_t)reds.size(),
-                             out_total, st),
+                             out_total, call_flag, st),
          "batched reduce launch");
   prof_end(tq, st, 0, 0);
   if (!W.done) DD_HIP(hipEventCreateWithFlags(&W.done, hipEventDisableTiming), "event creation");
   DD_HIP(hipEventRecord(W.done, st), "event record");
   W.pending = true;
+  // each scan's last call is this one (its flag word is written here)
+  if (!W.ev || W.ev.use_count() > 1) {
+    auto e = std::make_shared<StreamEvent>();
+    DD_HIP(hipEventCreateWithFlags(&e->ev, hipEventDisableTiming), "event creation");
+    W.ev = e;
+  }
+  DD_HIP(hipEventRecord(W.ev->ev, st), "event record");
+  W.ev->stream = st;
+  for (int32_t k = 0; k < n; ++k) scans[k]->last = W.ev;
   if (!on_device) {
     for (int32_t k = 0; k < n; ++k) {
       const int64_t len = (k + 1 < n ? out_off[k + 1] : out_total) - out_off[k];
@@ -1050,15 +1175,18 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
                               hipMemcpyDeviceToHost, st),
                "device-to-host copy");
     }
-    DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+    int64_t bad = -1;
+    dd_status rc = read_flag(W.flag.as<unsigned long long>(), st, call_flag.seq, bad);
+    if (rc != DD_OK) return rc;
+    if (bad >= 0) {
+      const int32_t k = (int32_t)(std::upper_bound(out_off.begin(), out_off.end(), bad) -
+                                  out_off.begin()) - 1;
+      return fail(DD_EDEVICE, "scan %d: non-finite output value at index %lld of its output", k,
+                  (long long)(bad - out_off[k]));
+    }
   }
   return DD_OK;
 }
-
-namespace {
-}  // namespace
-
-void dd_forget_plans(const dd_scan* s) { g_plans.erase(s); }
 
 dd_status dd_damage_sweep(dd_scan* s, const dd_grid* g, double t0_s, double dt_s, int32_t n_t,
                           dd_precision p, double* out, int32_t out_on_device, void* hip_stream) {
@@ -1077,14 +1205,30 @@ dd_status dd_damage_sweep(dd_scan* s, const dd_grid* g, double t0_s, double dt_s
   // times per map call: at most 4096 and at most 2^25 output values (256 MiB)
   const int32_t chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(4096, (1LL << 25) / npix));
   std::vector<double> t(chunk);
+  // one call: one flag for all chunks, each chunk's indices offset by its
+  // first output
+  OutFlag fl;
+  dd_status rc = begin_call(s, st, fl);
+  if (rc != DD_OK) return rc;
+  if (!out_on_device)
+    DD_HIP(s->tmp_out.ensure(sizeof(double) * (size_t)chunk * npix), "device allocation");
   for (int32_t k0 = 0; k0 < n_t; k0 += chunk) {
     const int32_t c = std::min(chunk, n_t - k0);
     for (int32_t j = 0; j < c; ++j) t[j] = t0_s + (double)(k0 + j) * dt_s;
-    dd_status rc = deliver(s, (size_t)c * npix, out + (size_t)k0 * npix, out_on_device, st,
-                           [&](double* o) { return run_map(s, g, t.data(), c, p == DD_MIXED, o, st); });
+    double* o = out_on_device ? out + (size_t)k0 * npix : s->tmp_out.as<double>();
+    fl.base = (int64_t)k0 * npix;
+    rc = run_map(s, g, t.data(), c, p == DD_MIXED, o, fl, st);
     if (rc != DD_OK) return rc;
+    if (!out_on_device) {  // the staging buffer is reused by the next chunk
+      DD_HIP(hipMemcpyAsync(out + (size_t)k0 * npix, o, sizeof(double) * (size_t)c * npix,
+                            hipMemcpyDeviceToHost, st),
+             "device-to-host copy");
+      DD_HIP(hipStreamSynchronize(st), "stream synchronize");
+    }
   }
-  return DD_OK;
+  rc = s->record_last(st);
+  if (rc != DD_OK) return rc;
+  return out_on_device ? DD_OK : s->check_flag(st, fl.seq);
 }
 
 dd_status dd_damage_at_probe_arrival_range(dd_scan* s, int64_t j0, int64_t j1, dd_precision p,
@@ -1096,8 +1240,8 @@ dd_status dd_damage_at_probe_arrival_range(dd_scan* s, int64_t j0, int64_t j1, d
                 (long long)j1, (long long)s->V);
   if (j1 == j0) return DD_OK;
   hipStream_t st = (hipStream_t)hip_stream;
-  return deliver(s, (size_t)(j1 - j0), out, out_on_device, st, [&](double* o) {
-    return run_arrival_range(s, p == DD_MIXED, j0, j1, o, st);
+  return deliver(s, (size_t)(j1 - j0), out, out_on_device, st, [&](double* o, const OutFlag& fl) {
+    return run_arrival_range(s, p == DD_MIXED, j0, j1, o, fl, st);
   });
 }
 
@@ -1107,7 +1251,7 @@ dd_status dd_damage_at_probe_arrival(dd_scan* s, dd_precision p, double* out,
   if (p != DD_FP64 && p != DD_MIXED) return fail(DD_EINVAL, "unknown precision %d", (int)p);
   hipStream_t st = (hipStream_t)hip_stream;
   return deliver(s, (size_t)s->V, out, out_on_device, st,
-                 [&](double* o) { return run_arrival(s, p == DD_MIXED, o, st); });
+                 [&](double* o, const OutFlag& fl) { return run_arrival(s, p == DD_MIXED, o, fl, st); });
 }
 
 dd_status dd_damage_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t n_t,
@@ -1124,7 +1268,9 @@ dd_status dd_damage_map(dd_scan* s, const dd_grid* g, const double* t_s, int32_t
   hipStream_t st = (hipStream_t)hip_stream;
   const size_t n = (size_t)n_t * g->w * g->h;
   return deliver(s, n, out, out_on_device, st,
-                 [&](double* o) { return run_map(s, g, t_s, n_t, p == DD_MIXED, o, st); });
+                 [&](double* o, const OutFlag& fl) {
+                   return run_map(s, g, t_s, n_t, p == DD_MIXED, o, fl, st);
+                 });
 }
 
 dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, dd_precision p,
@@ -1136,6 +1282,24 @@ dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, 
     if (!scans[k] || !outs[k]) return fail(DD_EINVAL, "scan %d or its output is NULL", k);
   return dd::run_batch(scans, n, query_mask, p == DD_MIXED, outs, out_on_device,
                        (hipStream_t)hip_stream, 0, -1);
+}
+
+dd_status dd_scan_check(dd_scan* s, int64_t* first_bad) {
+  if (first_bad) *first_bad = -1;
+  if (!s) return fail(DD_EINVAL, "NULL argument");
+  if (s->dev < 0 || s->seq == 0) return DD_OK;
+  int cur = 0;
+  DD_HIP(hipGetDevice(&cur), "hipGetDevice");
+  if (cur != s->dev) return fail(DD_EINVAL, "the scan ran on device %d, not %d", s->dev, cur);
+  if (s->last) DD_HIP(hipEventSynchronize(s->last->ev), "event synchronize");
+  unsigned long long w = 0;
+  DD_HIP(hipMemcpy(&w, s->flag.p, sizeof(w), hipMemcpyDeviceToHost), "device-to-host copy");
+  constexpr unsigned long long lim = (1ull << kFlagIndexBits) - 1;
+  if ((w >> kFlagIndexBits) != s->seq) return DD_OK;
+  const int64_t bad = (int64_t)(lim - (w & lim));
+  if (first_bad) *first_bad = bad;
+  return fail(DD_EDEVICE, "non-finite output value at index %lld of the scan's last call",
+              (long long)bad);
 }
 
 dd_status dd_pair_terms(double kappa, double sigma_hat, int64_t n, const double* a,

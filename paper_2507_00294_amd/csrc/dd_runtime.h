@@ -4,10 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 #include "../../include/dd.h"
 #include "dd_internal.h"
+
+struct dd_scan;
 
 namespace dd {
 
@@ -81,11 +84,57 @@ struct TuneParams {
 };
 TuneParams& tune();
 
+// Plan of a scan's arrival query (tile shapes, items, slots), kept on the
+// handle; V = -1 until planned.  Its items and tile slots live in the
+// handle's device buffers `items` and `aux`.
+struct ArrivalPlan {
+  int R = 0, RN = 0, K = 0;
+  bool mixed = false;
+  int64_t V = -1;
+  int n_near = 0, n_far = 0, S = 0;
+  DegreeBounds bounds{};
+  double near_pairs = 0, near_flops = 0, far_pairs = 0, far_flops = 0;
+};
+
+// Plan of an arrival query over the visits [j0, j1) (the streaming range):
+// work items (near items first), partial-sum slots per tile, and the
+// partial columns [pj0, pj0 + pstride) of the range's tiles.
+struct RangePlan {
+  ArrivalPlan P;
+  std::vector<ArrItem> items, far;
+  std::vector<int32_t> tile_slots;
+  int64_t pj0 = 0, pstride = 0;
+};
+
+// An event recorded once, after a call's last launch, on the stream the call
+// ran on.  Shared by the handles the call used (a batched call records one).
+struct StreamEvent {
+  hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;
+  StreamEvent() = default;
+  StreamEvent(const StreamEvent&) = delete;
+  StreamEvent& operator=(const StreamEvent&) = delete;
+  ~StreamEvent() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 // Batched solve of many scans (arrival and/or final map, the final map
 // restricted to rows [row0, row0 + rows) of each grid; rows < 0 = all).
 dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
                     double* const* outs, int32_t on_device, hipStream_t st, int32_t row0,
                     int32_t rows);
+
+struct OutFlag;
+// Plans the range query (plan_range) and launches it with its items, tile
+// slots and partial sums at the given device addresses (launch_range): the
+// allocating and the no-allocation entry points share both steps.
+void plan_range(const dd_scan* s, bool mixed, int64_t j0, int64_t j1, bool count, RangePlan& rp);
+dd_status launch_range(dd_scan* s, bool mixed, const RangePlan& rp, int64_t j0, int64_t j1,
+                       const ArrItem* d_items, const int32_t* d_slots, double* d_partial,
+                       double* out_dev, const OutFlag& fl, hipStream_t st, bool profile);
+// Cross-stream order and non-finite flag of a query call on one scan.
+dd_status begin_call(dd_scan* s, hipStream_t st, OutFlag& fl);
 
 }  // namespace dd
 
@@ -129,14 +178,43 @@ struct dd_scan {
     double pairs = 0, flops = 0;
   } bmap[2];
 
+  // Plan of the per-scan arrival query (items in `items`, tile slots in `aux`).
+  dd::ArrivalPlan arr_plan;
+
+  // Non-finite output check: the handle's device word (dd::OutFlag) and the
+  // seq of its last call.
+  dd::DevBuf flag;
+  uint64_t seq = 0;
+
+  // Order of the handle's device state across streams: the event after the
+  // handle's last call that wrote it, and the handle's own reusable event.
+  // A call on another stream first makes its stream wait for `last`, so
+  // calls on different streams never overwrite each other's partial sums,
+  // items or lag rows.
+  std::shared_ptr<dd::StreamEvent> last, own;
+
   void release_device() {
     for (dd::DevBuf* b : {&pos32, &pos64, &pos4, &rows64, &rows32, &partial, &items, &aux, &aux2, &aux3,
-                          &tmp_out, &maprows64, &maprows32, &sur})
+                          &tmp_out, &maprows64, &maprows32, &sur, &flag})
       b->release();
     sur_state = 0;
     n_rows = 0;
+    arr_plan = dd::ArrivalPlan{};
+    seq = 0;
+    last.reset();
+    own.reset();
     dev = -1;
   }
-  // Uploads positions and integer-lag rows (rows 0 .. V + margin).
+  // Uploads positions (and clears the flag word) on the current device.
   dd_status prepare(hipStream_t st);
+  // Makes `st` wait for the handle's last call when that ran on another stream.
+  dd_status wait_last(hipStream_t st);
+  // Records the handle's own event on `st` as its last call.
+  dd_status record_last(hipStream_t st);
+  // A fresh seq for a call (the flag word is cleared, synchronously, when
+  // the 24-bit seq wraps) and the call's flag.
+  dd_status next_flag(hipStream_t st, dd::OutFlag& fl);
+  // Reads the flag word (st is synchronized first): DD_EDEVICE naming the
+  // first non-finite output of call `seq`, else DD_OK.
+  dd_status check_flag(hipStream_t st, uint64_t call_seq);
 };

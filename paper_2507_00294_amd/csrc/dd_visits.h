@@ -12,6 +12,8 @@
 
 #include <cstdint>
 
+#include "dd_internal.h"
+
 namespace dd {
 
 constexpr int kVisTile = 256;     // evaluation points per tile (one per thread)
@@ -28,7 +30,8 @@ struct VisGrid {
 // the start order's caller indices (arrival), the output, the map's grid
 // and times (maps), and the scaling of a pair: a_hat = |r - r_i|^2 /
 // sigma^2 with inv_sigma, b_hat = 2 + 4 (D / sigma^2) lag with th4 =
-// 4 D / sigma^2, psi = pref * sum.
+// 4 D / sigma^2, psi = pref * sum.  Non-finite results are marked in
+// fl's word, indexed by their output index plus fl.base.
 struct VisList {
   const double4* vis;
   const int64_t* perm;
@@ -36,6 +39,7 @@ struct VisList {
   const double* times;
   VisGrid grid;
   double inv_sigma, th4, pref;
+  OutFlag fl;
 };
 
 // A tile of evaluation points of list `list`.  Arrival: the visits p0 ..

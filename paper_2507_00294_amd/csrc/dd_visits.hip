@@ -313,7 +313,9 @@ __global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisList* __rest
   double s = 0.0;
   for (int k = 0; k < tile.slots; ++k) s += partial[tile.pbase + (int64_t)k * kVisTile + lane];
   const int64_t dst = MAP ? tile.out0 + lane : L.perm[tile.p0 + lane];
-  L.out[dst] = L.pref * s;
+  const double v = L.pref * s;
+  L.out[dst] = v;
+  flag_nonfinite(L.fl, v, dst);
 }
 
 }  // namespace

@@ -112,9 +112,10 @@ struct dd_visits {
     return slot;
   }
 
-  VisList desc(double* out, const double* times = nullptr, VisGrid grid = VisGrid{}) const {
+  VisList desc(double* out, OutFlag fl, const double* times = nullptr,
+               VisGrid grid = VisGrid{}) const {
     return VisList{d_vis.as<double4>(), d_perm.as<int64_t>(), out, times, grid,
-                   inv_sigma, th4, pref};
+                   inv_sigma, th4, pref, fl};
   }
 
   // Tiles of the arrival query (visits in start order), appended for list `list`.
@@ -141,8 +142,50 @@ struct VisScratch {
   std::vector<VisItem> h_items;
   std::vector<VisList> h_lists;
   DevBuf d_tiles, d_items, d_partial, d_lists;
+  // non-finite flag of the thread's calls (see OutFlag), read at the end
+  // of each call
+  DevBuf flag;
+  uint64_t seq = 0;
+  unsigned long long* flag_host = nullptr;  // pinned, kept until the process ends
 };
 thread_local VisScratch g_vis;
+
+// A fresh flag for a call; the word is cleared when first used and when
+// the seq wraps.
+dd_status call_flag(hipStream_t st, OutFlag& fl) {
+  VisScratch& W = g_vis;
+  if (!W.flag_host)
+    VIS_HIP(hipHostMalloc((void**)&W.flag_host, 256, hipHostMallocDefault),
+            "pinned host allocation");
+  if (!W.flag.p || W.seq >= kFlagSeqMax) {
+    VIS_HIP(W.flag.ensure(sizeof(unsigned long long)), "device allocation");
+    *W.flag_host = 0;
+    VIS_HIP(hipMemcpyAsync(W.flag.p, W.flag_host, sizeof(unsigned long long),
+                           hipMemcpyHostToDevice, st),
+            "host-to-device copy");
+    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+    W.seq = 0;
+  }
+  fl = OutFlag{W.flag.as<unsigned long long>(), (unsigned long long)++W.seq, 0};
+  return DD_OK;
+}
+
+// After a call's last launch: DD_EDEVICE naming the list and index of its
+// first non-finite output (off[k]: flat offset of list k's output).
+dd_status check_call_flag(const OutFlag& fl, const std::vector<int64_t>& off, hipStream_t st) {
+  VisScratch& W = g_vis;
+  VIS_HIP(hipMemcpyAsync(W.flag_host, fl.word, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         st),
+          "device-to-host copy");
+  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+  const unsigned long long w = *W.flag_host;
+  constexpr unsigned long long lim = (1ull << kFlagIndexBits) - 1;
+  if ((w >> kFlagIndexBits) != fl.seq) return DD_OK;
+  const int64_t bad = (int64_t)(lim - (w & lim));
+  const int32_t k = (int32_t)(std::upper_bound(off.begin(), off.end(), bad) - off.begin()) - 1;
+  return fail(DD_EDEVICE, "list %d: non-finite output value at index %lld", k,
+              (long long)(bad - off[k]));
+}
 
 // Partial sums and reduce of the current tiles and items (one launch group);
 // the descriptors are already on the device.
@@ -196,9 +239,17 @@ dd_status upload_lists(hipStream_t st) {
 dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* const* outs,
                        hipStream_t st) {
   VisScratch& W = g_vis;
+  OutFlag fl;
+  dd_status rc = call_flag(st, fl);
+  if (rc != DD_OK) return rc;
+  std::vector<int64_t> off(n, 0);
   W.h_lists.resize(n);
-  for (int32_t k = 0; k < n; ++k) W.h_lists[k] = lists[k]->desc(outs[k]);
-  dd_status rc = upload_lists(st);
+  for (int32_t k = 0; k < n; ++k) {
+    if (k > 0) off[k] = off[k - 1] + lists[k - 1]->n;
+    fl.base = off[k];
+    W.h_lists[k] = lists[k]->desc(outs[k], fl);
+  }
+  rc = upload_lists(st);
   if (rc != DD_OK) return rc;
   std::vector<VisTile> all;
   for (int32_t k = 0; k < n; ++k) lists[k]->arrival_tiles(k, all);
@@ -214,7 +265,7 @@ dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* c
     rc = launch_group(false, mixed, st);
     if (rc != DD_OK) return rc;
   }
-  return DD_OK;
+  return check_call_flag(fl, off, st);
 }
 
 // Maps of lists[k] on grids[k] at times t_s[k][0 .. n_t[k]) into outs[k]
@@ -225,8 +276,11 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
                    const double* const* t_s, const int32_t* n_t, bool mixed, double* const* outs,
                    hipStream_t st) {
   VisScratch& W = g_vis;
-  std::vector<int64_t> npix(n), per(n);
+  std::vector<int64_t> npix(n), per(n), off(n, 0);
   std::vector<std::vector<Box>> boxes(n);
+  OutFlag fl;
+  dd_status rc0 = call_flag(st, fl);
+  if (rc0 != DD_OK) return rc0;
   W.h_lists.resize(n);
   for (int32_t k = 0; k < n; ++k) {
     const dd_grid* g = &grids[k];
@@ -237,7 +291,9 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
     VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s[k], sizeof(double) * n_t[k], hipMemcpyHostToDevice,
                            st),
             "host-to-device copy");
-    W.h_lists[k] = v->desc(outs[k], v->d_times.as<double>(),
+    if (k > 0) off[k] = off[k - 1] + (int64_t)n_t[k - 1] * npix[k - 1];
+    fl.base = off[k];
+    W.h_lists[k] = v->desc(outs[k], fl, v->d_times.as<double>(),
                            VisGrid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0});
     // pixel boxes of the tiles (the same at every time)
     boxes[k].resize(per[k]);
@@ -271,7 +327,7 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
     rc = launch_group(true, mixed, st);
     if (rc != DD_OK) return rc;
   }
-  return DD_OK;
+  return check_call_flag(fl, off, st);
 }
 
 dd_status check_map_args(const dd_grid* g, const double* t_s, int32_t n_t) {

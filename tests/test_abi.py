@@ -293,3 +293,38 @@ def test_visit_batch_map_validation(dd):
     assert lib.dd_visits_batch_map(None, 2, grids, tp, nt, 0, one(o, o), 0, None) == dd.DD_EINVAL
     assert lib.dd_visits_batch_map(one(v._h.value, w._h.value), 2, grids, tp, nt, 4, one(o, o), 0,
                                    None) == dd.DD_EINVAL
+
+
+def test_handles_created_and_destroyed_in_threads(dd):
+    """Distinct handles are independent: threads create, read and destroy
+    scans and visit lists of their own concurrently (each handle keeps its
+    plans and device state itself; no table is shared between handles)."""
+    import threading
+
+    errors = []
+
+    def worker(seed):
+        try:
+            for k in range(40):
+                s = dd.Scan(8 + k % 5, 7, "random", seed=seed + k)
+                ids = s.visits()
+                assert np.array_equal(np.sort(ids), np.arange(ids.size))
+                if k % 3 == 0:
+                    lib = dd.load_library()
+                    bad = ctypes.c_int64(0)
+                    assert lib.dd_scan_check(s.handle, ctypes.byref(bad)) == dd.DD_OK
+                    assert bad.value == -1
+                s.close()
+                v = dd.Visits(np.arange(4.0) * 1e-9, np.zeros(4), np.arange(4.0) * 1e-6,
+                              np.full(4, 1e-6))
+                assert v.num_visits == 4
+                v.close()
+        except Exception as e:  # reported on the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(100 * i,)) for i in range(8)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
