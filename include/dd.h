@@ -144,6 +144,29 @@ dd_status dd_damage_at_probe_arrival(dd_scan *s, dd_precision p, double *out,
 dd_status dd_damage_at_probe_arrival_range(dd_scan *s, int64_t j0, int64_t j1, dd_precision p,
                                            double *out, int32_t out_on_device, void *hip_stream);
 
+/* The streaming arrival query for callers that cannot allocate device
+ * memory (code under stream capture, serving loops that must not allocate,
+ * harnesses that forbid allocation): the same values as
+ * dd_damage_at_probe_arrival_range(s, j0, j1, p, out_dev, 1, hip_stream),
+ * bit for bit, with no device or pinned allocation.  Its scratch (work
+ * items, slots per tile, partial sums) is one static device array of 32 MiB
+ * per GPU, held until the process ends; a range whose plan needs more
+ * returns DD_EINVAL (for a 512 x 512 scan, ranges up to about 60000 visits
+ * fit).  Every call on a GPU shares that array: calls that overlap on one
+ * GPU (other streams, other threads) race on it and must not be issued;
+ * calls on one stream are ordered by it.  The scan's device tables must be
+ * resident on the current device: any earlier query of this scan there by
+ * dd_damage_at_probe_arrival, dd_damage_at_probe_arrival_range,
+ * dd_damage_map or dd_damage_sweep builds them (else DD_EINVAL).  out_dev
+ * is a device array of j1 - j0 doubles; the work is enqueued on hip_stream
+ * and the call returns once it is (dd_scan_check reports non-finite
+ * values).  The plan is copied from host memory in stream order.
+ * Errors: DD_EINVAL (range, precision, NULL, tables not resident, scratch
+ * too small), DD_EDEVICE.                                                 */
+dd_status dd_damage_at_probe_arrival_range_noalloc(dd_scan *s, int64_t j0, int64_t j1,
+                                                   dd_precision p, double *out_dev,
+                                                   void *hip_stream);
+
 /* Queries for dd_batch_solve (bit mask).                                  */
 typedef enum {
   DD_Q_ARRIVAL = 1,          /* [V] as dd_damage_at_probe_arrival              */

@@ -29,7 +29,8 @@ Q_ARRIVAL, Q_FINAL_AT_PROBES = 1, 2
 EXPORTS = (
     "dd_scan_create", "dd_scan_destroy", "dd_scan_num_visits", "dd_scan_visits",
     "dd_damage_map", "dd_damage_sweep", "dd_damage_at_probe_arrival",
-    "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_scan_check",
+    "dd_damage_at_probe_arrival_range", "dd_damage_at_probe_arrival_range_noalloc",
+    "dd_batch_solve", "dd_scan_check",
     "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
@@ -88,6 +89,7 @@ def load_library():
     lib.dd_damage_map.argtypes = [vp, P(Grid), P(dbl), i32, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_sweep.argtypes = [vp, P(Grid), dbl, dbl, i32, ctypes.c_int, vp, i32, vp]
     lib.dd_damage_at_probe_arrival_range.argtypes = [vp, i64, i64, ctypes.c_int, vp, i32, vp]
+    lib.dd_damage_at_probe_arrival_range_noalloc.argtypes = [vp, i64, i64, ctypes.c_int, vp, vp]
     lib.dd_damage_at_probe_arrival.argtypes = [vp, ctypes.c_int, vp, i32, vp]
     lib.dd_batch_solve.argtypes = [P(vp), i32, ctypes.c_uint32, ctypes.c_int, P(vp), i32, vp]
     lib.dd_scan_check.argtypes = [vp, P(i64)]
@@ -124,7 +126,8 @@ def load_library():
                                         P(vp), i32, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
-                 "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range", "dd_batch_solve", "dd_scan_check", "dd_pair_terms", "dd_autotune",
+                 "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range",
+                 "dd_damage_at_probe_arrival_range_noalloc", "dd_batch_solve", "dd_scan_check", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
@@ -248,6 +251,20 @@ class Scan:
         assert out.numel() == max(j1 - j0, 0)
         _check(load_library().dd_damage_at_probe_arrival_range(
             self._h, j0, j1, _prec(precision), ctypes.c_void_p(out.data_ptr()), 1,
+            _stream(stream)))
+        return out
+
+    def arrival_range_noalloc(self, j0: int, j1: int, out, precision: str = "fp64",
+                              stream=None):
+        """The same values as ``arrival_range`` into the caller's float64 CUDA
+        tensor ``out`` [j1 - j0], with no allocation
+        (``dd_damage_at_probe_arrival_range_noalloc``); the scan's tables
+        must be resident (any earlier query of the scan builds them)."""
+        torch = _torch()
+        assert out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+        assert out.numel() == max(j1 - j0, 0)
+        _check(load_library().dd_damage_at_probe_arrival_range_noalloc(
+            self._h, j0, j1, _prec(precision), ctypes.c_void_p(out.data_ptr()),
             _stream(stream)))
         return out
 
