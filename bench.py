@@ -10,9 +10,12 @@ and lag-row tables resident in HBM (the first query builds them).  Prints
 one JSON line.
 
 The dominant kernel (far region) is timed with HIP events on the stream it
-runs on; its algorithmic FLOPs per launch come from the library's plan.  The
-CPU oracle is timed on a seeded sample of the same visits and its values are
-the accuracy check of the GPU result.  The learned surrogate is measured
+runs on; its FLOPs per launch are the causal pairs of the launch times the
+FLOPs per pair of the committed counter record (rocprofv3 instruction
+counters), or the library's plan while no record matches the sources.  The
+CPU oracle, on its own visit list, is timed on a seeded sample of the same
+visits on one core and on every core of the host, and its values are the
+accuracy check of the GPU result.  The learned surrogate is measured
 against the exact batched kernel on 2000 held-out 64x64 scans (speedup at its
 relative L2 error, with its exact judge and fallback), the batched
 configuration (256 scans in one call) and the time-sampled simulation (maps
@@ -33,7 +36,7 @@ if ROOT not in sys.path:
 METRIC = "pair E1-terms/s at oracle-matched accuracy; surrogate speedup @≤1% L2 err"
 # HBM bytes of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # valid only while the device sources hash to the recorded value.
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_arrival_far32_traffic.txt")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_arrival_far_512x512_random_record.txt")
 DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip", "dd_queries.cpp")
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X FP32 / FP64 vector peaks
 FP32_NONPACKED_TFLOPS = 78.6  # FP32 vector peak without packed instructions
@@ -80,12 +83,21 @@ def recorded_traffic(precision, side):
 
 
 def far_roofline(prec, kern, side):
-    """Roofline of the far-region kernel from its live HIP-event time and the
-    plan's algorithmic flops; the VALU issue rate from the recorded
-    instructions per pair (rocprofv3 SQ_INSTS_VALU) times the live pair rate."""
+    """Roofline of the far-region kernel: FLOPs per launch = its causal pairs
+    times the FLOPs per pair of the counter record (or of the plan while no
+    record matches the sources), over its live HIP-event time; the VALU
+    issue rate from the recorded instructions per pair (rocprofv3
+    SQ_INSTS_VALU) times the live pair rate."""
     far = kern["arrival_far"]
     far_ms = far["ms"] / max(far["launches"], 1)
-    far_flops = far["flops"] / max(far["launches"], 1)
+    pairs_l = far["pairs"] / max(far["launches"], 1)
+    plan_flops = far["flops"] / max(far["launches"], 1)
+    rec = counter_record(side)
+    tag = "" if prec == "mixed" else "fp64_"
+    if rec is not None and tag + "flops_per_pair" in rec:
+        far_flops, source = pairs_l * float(rec[tag + "flops_per_pair"]), "counters"
+    else:
+        far_flops, source = plan_flops, "plan"
     achieved = far_flops / (far_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu", "kernel": "k_arrival_far32" if prec == "mixed" else "k_arrival_far64",
@@ -93,8 +105,13 @@ def far_roofline(prec, kern, side):
         "frac": round(achieved / PEAK_TFLOPS[prec], 4),
         "traffic": recorded_traffic(prec, side),
         "avg_launch_ms": round(far_ms, 4),
-        "pairs_per_launch": far["pairs"] / max(far["launches"], 1),
+        "rocprof_avg_launch_ms": float(rec[tag + "rocprof_avg_launch_ms"])
+        if rec is not None and tag + "rocprof_avg_launch_ms" in rec else None,
+        "pairs_per_launch": pairs_l,
         "flops_per_launch": far_flops,
+        "flops_per_pair": far_flops / max(pairs_l, 1.0),
+        "flops_source": source,
+        "plan_flops_per_pair": plan_flops / max(pairs_l, 1.0),
     }
     if prec == "mixed":
         # this build does not emit packed FP32, so 78.6 TFLOP/s is the FLOP ceiling
@@ -130,6 +147,194 @@ def time_query(scan, prec, out, steps, warmup, dd, torch):
     return (t1 - t0) / steps, kern
 
 
+def host_cpu():
+    """(logical CPUs of the host, CPUs this process may run on, CPU model)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return os.cpu_count() or 1, usable, model
+
+
+def cpu_baseline(spec, result, floor, seconds, wl):
+    """The oracle on its own visit list of the benchmark scan, timed on a
+    seeded sample of visits: on one thread (about seconds / 5) and on every
+    CPU this process may use (about `seconds`).  Returns the record and the
+    largest relative error of the GPU result on the sampled visits."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build()
+    nproc, usable, model = host_cpu()
+    ids = oracle.visits(oracle.RANDOM, spec.nx, spec.ny, seed=spec.seed)
+    ora = oracle.Scan(spec.nx, spec.ny, ids, spec.pitch_m, spec.tau_v, spec.sigma_m, spec.D_m2s,
+                      spec.Q0_us)
+    V = ids.size
+
+    def timed(n_vis, seed, threads):
+        idx = wl.sampled_visits(V, n_vis, seed=seed)
+        t0 = time.perf_counter()
+        ref = ora.psi_arrival(idx, nthreads=threads)
+        return idx, ref, time.perf_counter() - t0
+
+    # calibrate on one thread, then size both samples to their targets
+    idx, _, dt = timed(8, 101, 1)
+    rate1 = max(float(idx.sum()), 1.0) / max(dt, 1e-6)
+    n1 = int(max(8, min(V, seconds / 5 * rate1 / (V / 2))))
+    idx1, _, dt1 = timed(n1, 5, 1)
+    per_core = float(idx1.sum()) / dt1
+    n_all = int(max(32, min(V, seconds * per_core * usable / (V / 2))))
+    idx, ref, dt = timed(n_all, 7, usable)
+    s_pairs = float(idx.sum())
+    err = np.abs(result[idx] - ref) / np.maximum(np.abs(ref), floor)
+    cpu = {"value": s_pairs / dt, "unit": "pair-terms/s", "cores": usable, "kind": "oracle",
+           "per_core": per_core, "nproc": nproc, "cpu_model": model,
+           "sample": f"arrival at {idx.size} seeded visits of the same scan ({s_pairs:.3e} pairs, "
+                     f"{dt:.1f} s on {usable} threads; one thread: {idx1.size} visits, "
+                     f"{float(idx1.sum()):.3e} pairs, {dt1:.1f} s), long double, the oracle's "
+                     f"own visit list"}
+    return cpu, float(err.max())
+
+
+def _gpu_time(fn, torch, reps=10):
+    import numpy as np
+
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def run_configs():
+    """The plain FP64 configurations in full and the batched one on sampled
+    scans, each against the oracle (own visit lists, every host CPU): GPU
+    time, largest relative error, oracle time."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2507_00294_amd as dd
+    from paper_2507_00294_amd import workloads as wl
+
+    oracle.build()
+    torch.cuda.set_device(0)
+    dd.load_library()
+    nproc, usable, model = host_cpu()
+    codes = {"raster": oracle.RASTER, "interleaved": oracle.INTERLEAVED,
+             "random": oracle.RANDOM, "multiframe": oracle.MULTIFRAME}
+
+    def ora_scan(sp):
+        ids = oracle.visits(codes[sp.order], sp.nx, sp.ny, stride=sp.stride, frames=sp.frames,
+                            seed=sp.seed)
+        return oracle.Scan(sp.nx, sp.ny, ids, sp.pitch_m, sp.tau_v, sp.sigma_m, sp.D_m2s,
+                           sp.Q0_us)
+
+    def rel(g, r, sp, fl):
+        return float(np.max(np.abs(g - r) / np.maximum(np.abs(r), fl * sp.Q0_us /
+                                                       (4 * math.pi * sp.D_m2s))))
+
+    out = {"host": {"nproc": nproc, "threads": usable, "cpu_model": model}}
+    # small: 8x8 raster, 64 maps of 32x32 at the end of every dwell
+    sp = wl.small_raster()
+    sc = dd.Scan(**sp.kwargs())
+    m = wl.small_raster_maps(sp)
+    args = (m.x0_m, m.y0_m, m.dx_m, m.dy_m, m.w, m.h, m.times_s)
+    res = {}
+    for pr in ("fp64", "mixed"):
+        g = sc.damage_map(*args, pr).cpu().numpy()
+        res[pr] = (g, _gpu_time(lambda: sc.damage_map(*args, pr), torch))
+    t0 = time.perf_counter()
+    ref = ora_scan(sp).psi_map(*args, nthreads=usable)
+    t_o = time.perf_counter() - t0
+    pairs = float(sum(m.w * m.h * min(k, sp.n_visits) for k in range(1, sp.n_visits + 1)))
+    out["small"] = {"pairs": pairs, "oracle_s": t_o,
+                    **{pr: {"gpu_ms": t * 1e3, "max_rel_err": rel(g, ref, sp, 1e-250 if pr == "fp64"
+                                                                   else 1e-30)}
+                       for pr, (g, t) in res.items()}}
+    log(f"[configs] small: {out['small']}")
+    # medium: 16 scans of 32x32 (raster, interleaved s = 2), arrival + 128x128 final map
+    specs = wl.medium_scans()
+    tg = {"fp64": 0.0, "mixed": 0.0}
+    err = {"fp64": 0.0, "mixed": 0.0}
+    t_o, pairs = 0.0, 0.0
+    for sp in specs:
+        sc = dd.Scan(**sp.kwargs())
+        fm = wl.medium_final_map(sp)
+        margs = (fm.x0_m, fm.y0_m, fm.dx_m, fm.dy_m, fm.w, fm.h, fm.times_s)
+        o = ora_scan(sp)
+        t0 = time.perf_counter()
+        ra = o.psi_arrival(nthreads=usable)
+        rm = o.psi_map(*margs, nthreads=usable)
+        t_o += time.perf_counter() - t0
+        pairs += wl.causal_arrival_pairs(sp.n_visits) + fm.w * fm.h * sp.n_visits
+        for pr in ("fp64", "mixed"):
+            def both():
+                sc.arrival(pr)
+                sc.damage_map(*margs, pr)
+            tg[pr] += _gpu_time(both, torch, 5)
+            fl = 1e-250 if pr == "fp64" else 1e-30
+            err[pr] = max(err[pr], rel(sc.arrival(pr).cpu().numpy(), ra, sp, fl),
+                          rel(sc.damage_map(*margs, pr).cpu().numpy(), rm, sp, fl))
+        sc.close()
+    out["medium"] = {"scans": len(specs), "pairs": pairs, "oracle_s": t_o,
+                     **{pr: {"gpu_ms": tg[pr] * 1e3, "max_rel_err": err[pr]} for pr in tg}}
+    log(f"[configs] medium: {out['medium']}")
+    # batched: 256 scans in one call; 16 of them against the oracle on sampled
+    # visits (64) and final-map pixels (64)
+    specs = wl.batch_scans()
+    scans = [dd.Scan(**sp.kwargs()) for sp in specs]
+    mask = dd.Q_ARRIVAL | dd.Q_FINAL_AT_PROBES
+    rng = np.random.default_rng(17)
+    pick = rng.choice(len(specs), size=16, replace=False)
+    bres = {}
+    t_o, s_pairs = 0.0, 0.0
+    refs = {}
+    for k in pick:
+        sp = specs[k]
+        o = ora_scan(sp)
+        idx = wl.sampled_visits(sp.n_visits, 64, seed=int(k))
+        pix = rng.choice(sp.nx * sp.ny, size=64, replace=False)
+        x, y = (pix % sp.nx) * sp.pitch_m, (pix // sp.nx) * sp.pitch_m
+        t = np.full(pix.size, sp.n_visits * sp.tau_v)
+        t0 = time.perf_counter()
+        refs[k] = (idx, o.psi_arrival(idx, nthreads=usable), pix,
+                   o.psi_points(x, y, t, nthreads=usable))
+        t_o += time.perf_counter() - t0
+        s_pairs += float(idx.sum()) + 64.0 * sp.n_visits
+    for pr in ("mixed", "fp64"):
+        outs = dd.batch_solve(scans, mask, pr)
+        e = 0.0
+        for k in pick:
+            idx, ra, pix, rf = refs[k]
+            o_ = outs[k].cpu().numpy()
+            fl = 1e-250 if pr == "fp64" else 1e-30
+            e = max(e, rel(o_[idx], ra, specs[k], fl),
+                    rel(o_[specs[k].n_visits + pix], rf, specs[k], fl))
+        t = _gpu_time(lambda: dd.batch_solve(scans, mask, pr), torch, 3)
+        bres[pr] = {"gpu_ms": t * 1e3, "max_rel_err_sampled": e}
+    pairs = float(sum(wl.causal_arrival_pairs(s.num_visits) + sp.nx * sp.ny * s.num_visits
+                      for s, sp in zip(scans, specs)))
+    out["batched"] = {"scans": len(specs), "pairs": pairs, "oracle_sample_pairs": s_pairs,
+                      "oracle_sample_s": t_o, **bres}
+    log(f"[configs] batched: {out['batched']}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +359,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes three times "
                          "(reference for the HBM byte counters) and exit")
+    ap.add_argument("--configs", action="store_true",
+                    help="only measure the small, medium and batched configurations against "
+                         "the oracle (GPU time, error, oracle time) and print one JSON line")
     args = ap.parse_args()
+    if args.configs:
+        run_configs()
+        return
     if args.copy_calibration:
         import torch
 
@@ -282,6 +493,27 @@ def main():
                            "dwell 1 us, D 2.5e-13 m^2/s), 128x128 maps at 0.5 nm every half "
                            "dwell from t = 0 to the end of the scan, one call"}
         log(f"[bench] sweep: {n_t} maps in {t_s * 1e3:.1f} ms, {swp['value']:.4e} pairs/s")
+        # Visualisation of the sweep: every frame to an RGB image (automatic
+        # log range per frame, iso-lines per decade), one call.
+        rgb = torch.empty((n_t, w, w, 3), dtype=torch.uint8, device="cuda")
+        dd.render_maps(out, decades=6.0, levels=6, out=rgb)
+        torch.cuda.synchronize()
+        tr = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            dd.render_maps(out, decades=6.0, levels=6, out=rgb)
+            torch.cuda.synchronize()
+            tr.append(time.perf_counter() - t0)
+        t_r = float(np.median(tr))
+        px = float(n_t * w * w)
+        swp["render"] = {"ms_per_call": t_r * 1e3, "frames": n_t, "pixels": px,
+                         "bytes_per_call": px * 11.0, "achieved_GBs": px * 11.0 / t_r / 1e9,
+                         "peak_GBs": 8000.0, "frac": px * 11.0 / t_r / 8e12,
+                         "workload": "the sweep's 8192 frames of 128x128 to 8-bit RGB: per pixel "
+                                     "8 bytes of psi read, 3 written (automatic log range over 6 "
+                                     "decades per frame, iso-line per decade)"}
+        log(f"[bench] render: {n_t} frames in {t_r * 1e3:.2f} ms")
+        del rgb
         del out
         sc.close()
 
@@ -390,30 +622,9 @@ def main():
     cpu = None
     max_err = None
     if not args.no_cpu_baseline:
-        import oracle
-
-        oracle.build()
-        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
-        ora = oracle.Scan(spec.nx, spec.ny, scan.visits(), spec.pitch_m, spec.tau_v,
-                          spec.sigma_m, spec.D_m2s, spec.Q0_us)
-        # calibrate on a small sample, then size the timed sample to the target
-        cal = wl.sampled_visits(V, 16, seed=101)
-        t0 = time.perf_counter()
-        ora.psi_arrival(cal, nthreads=threads)
-        rate = max(float(cal.sum()), 1.0) / max(time.perf_counter() - t0, 1e-6)
-        n_s = int(max(32, min(V, args.cpu_seconds * rate / (V / 2))))
-        idx = wl.sampled_visits(V, n_s, seed=7)
-        t0 = time.perf_counter()
-        ref = ora.psi_arrival(idx, nthreads=threads)
-        dt = time.perf_counter() - t0
-        s_pairs = float(idx.sum())
-        err = np.abs(result[idx] - ref) / np.maximum(np.abs(ref), floor)
-        max_err = float(err.max())
-        cpu = {"value": s_pairs / dt, "unit": "pair-terms/s", "cores": threads, "kind": "oracle",
-               "sample": f"arrival at {idx.size} seeded visits of the same scan "
-                         f"({s_pairs:.3e} pairs, {dt:.1f} s, long double)"}
-        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {threads} threads; "
-            f"max rel err GPU vs oracle {max_err:.3e}")
+        cpu, max_err = cpu_baseline(spec, result, floor, args.cpu_seconds, wl)
+        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {cpu['cores']} threads "
+            f"({cpu['per_core']:.3e} on one); max rel err GPU vs oracle {max_err:.3e}")
 
     line = {
         "metric": METRIC, "value": value, "unit": "pair-terms/s", "n_gpus": 1,

@@ -216,10 +216,11 @@ dd_status dd_tune_load(const char *cache_path);
  * launch of its main kernels with HIP events on the stream it launches on
  * and records the algorithmic work of the launch: pairs is the number of
  * causal (evaluation point, visit) pairs it evaluates, flops the FP32/FP64
- * operations of the evaluation form used for them (FMA counted as 2; per
- * pair 15 + 2M or 17 + 2M in mixed precision and 40 + 2M in FP64 for a
- * series of degree M).  Kernel names: "arrival_far", "arrival_near", "map",
- * "batch", "lag_rows", "reduce".                                          */
+ * operations of the evaluation form used for them, counted as the hardware
+ * FLOP counters count them (FMA 2; add, multiply, exp 1; per pair of a
+ * series of degree M: 13 + 2 max(M, 1) for M <= 3 and 17 + 2M above in
+ * mixed precision, 33 + 2M in FP64).  Kernel names: "arrival_far",
+ * "arrival_near", "map", "batch", "lag_rows", "reduce".                   */
 typedef struct {
   double ms;         /* summed event time of the launches                   */
   int64_t launches;
@@ -367,6 +368,41 @@ dd_status dd_visits_batch_arrival(dd_visits *const *lists, int32_t n, dd_precisi
 dd_status dd_visits_batch_map(dd_visits *const *lists, int32_t n, const dd_grid *grids,
                               const double *const *t_s, const int32_t *n_t, dd_precision p,
                               double *const *outs, int32_t out_on_device, void *hip_stream);
+
+/* ---- Visualisation -----------------------------------------------------------
+ * The paper's integrated 2-D views of the damage diffusion distribution
+ * (Sec. IV), on the device: n maps psi [n][h][w] (device doubles, e.g. the
+ * output of dd_damage_map, dd_damage_sweep or the final maps of
+ * dd_batch_solve) rendered to 8-bit RGB images rgb [n][h][w][3] (device),
+ * row-major, in the order of the maps.  Per pixel with value v and the
+ * range [lo, hi] of its map:
+ *   t = 0 if not (v > lo) (NaN, and v <= 0 on a log scale), 1 if v >= hi,
+ *       ln(v / lo) / ln(hi / lo) on a log scale, (v - lo) / (hi - lo) on a
+ *       linear one (a t that is not a number counts as 0);
+ *   colour = table[min(255, floor(256 t))], where table[i] interpolates the
+ *       anchors (bin; r, g, b) = (0; 0,0,0) (38; 32,12,96) (90; 118,24,132)
+ *       (141; 200,52,84) (192; 244,128,32) (230; 250,208,64)
+ *       (255; 255,255,232) linearly in the bin, each channel
+ *       c0 + (c1 - c0) (i - b0) / (b1 - b0) in double precision rounded to
+ *       the nearest integer (black through violet, red and orange to white).
+ * With levels L > 0, a pixel whose level min(L - 1, floor(L t)) differs
+ * from that of its right or lower neighbour in the same map is white
+ * (iso-lines, e.g. one per decade on a log scale).  lo = hi = 0 asks for an
+ * automatic range per map: hi = the map's largest finite value, lo =
+ * max(hi 10^-decades, 2^-1022) on a log scale and 0 on a linear one; a map
+ * with hi <= lo (no positive value) is black.  Work is enqueued on
+ * hip_stream.  n = 0 does nothing.
+ * Errors: DD_EINVAL (NULL, n < 0, w or h < 1, levels outside [0, 256],
+ * log_scale not 0/1, explicit range not finite with lo < hi, log scale with
+ * lo <= 0, automatic log range with decades outside (0, 300]), DD_EDEVICE. */
+typedef struct {
+  double lo, hi;       /* range shown; lo = hi = 0: automatic per map          */
+  double decades;      /* automatic log range: decades below the map's maximum */
+  int32_t log_scale;   /* 1: logarithmic, 0: linear                            */
+  int32_t levels;      /* iso-lines between `levels` equal steps of t; 0: none */
+} dd_render_opts;
+dd_status dd_render_maps(const double *psi, int64_t n, int32_t w, int32_t h,
+                         const dd_render_opts *opt, uint8_t *rgb, void *hip_stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *dd_last_error(void);

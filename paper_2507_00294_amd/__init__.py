@@ -37,7 +37,7 @@ EXPORTS = (
     "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
     "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
     "dd_visits_destroy", "dd_visits_count", "dd_visits_arrival", "dd_visits_map",
-    "dd_visits_batch_arrival", "dd_visits_batch_map", "dd_last_error",
+    "dd_visits_batch_arrival", "dd_visits_batch_map", "dd_render_maps", "dd_last_error",
 )
 
 
@@ -60,6 +60,11 @@ class ScanDesc(ctypes.Structure):
 class KernelStats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("pairs", ctypes.c_double),
                 ("flops", ctypes.c_double)]
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double), ("decades", ctypes.c_double),
+                ("log_scale", ctypes.c_int32), ("levels", ctypes.c_int32)]
 
 
 class Grid(ctypes.Structure):
@@ -124,6 +129,7 @@ def load_library():
     lib.dd_visits_batch_arrival.argtypes = [P(vp), i32, ctypes.c_int, P(vp), i32, vp]
     lib.dd_visits_batch_map.argtypes = [P(vp), i32, P(Grid), P(P(dbl)), P(i32), ctypes.c_int,
                                         P(vp), i32, vp]
+    lib.dd_render_maps.argtypes = [vp, i64, i32, i32, P(RenderOpts), vp, vp]
     lib.dd_last_error.restype = ctypes.c_char_p
     for name in ("dd_scan_create", "dd_scan_visits", "dd_damage_map", "dd_damage_sweep",
                  "dd_damage_at_probe_arrival", "dd_damage_at_probe_arrival_range",
@@ -133,7 +139,7 @@ def load_library():
                  "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
                  "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
                  "dd_visits_arrival", "dd_visits_map", "dd_visits_batch_arrival",
-                 "dd_visits_batch_map"):
+                 "dd_visits_batch_map", "dd_render_maps"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -490,6 +496,53 @@ def profile_read(kernel: str, reset: bool = True) -> dict:
 # Learned surrogate (dd_unet_*): U-Net on 64x64 scans, BF16 MFMA kernels.
 SIDE = 64
 CHANNELS = 5  # DD_SURROGATE_CHANNELS
+
+
+def render_maps(psi, lo: float = 0.0, hi: float = 0.0, decades: float = 6.0,
+                log_scale: bool = True, levels: int = 0, out=None, stream=None):
+    """8-bit RGB images [n, h, w, 3] (uint8 CUDA tensor) of psi maps [n, h, w]
+    or [h, w] (float64 CUDA tensor), rendered on the device
+    (``dd_render_maps``): log or linear scale over [lo, hi] (lo = hi = 0:
+    per map, its maximum and `decades` below), fixed colour map, optional
+    iso-lines between `levels` steps."""
+    torch = _torch()
+    assert psi.dtype == torch.float64 and psi.is_cuda and psi.is_contiguous()
+    shp = tuple(psi.shape)
+    if len(shp) == 2:
+        shp = (1,) + shp
+    n, h, w = shp
+    if out is None:
+        out = torch.empty((n, h, w, 3), dtype=torch.uint8, device="cuda")
+    assert out.dtype == torch.uint8 and out.is_cuda and out.is_contiguous()
+    assert out.numel() == n * h * w * 3
+    opt = RenderOpts(lo, hi, decades, 1 if log_scale else 0, levels)
+    _check(load_library().dd_render_maps(ctypes.c_void_p(psi.data_ptr()), n, w, h,
+                                         ctypes.byref(opt), ctypes.c_void_p(out.data_ptr()),
+                                         _stream(stream)))
+    return out
+
+
+def save_png(path: str, rgb) -> None:
+    """Writes one RGB image (uint8 array [h, w, 3], host or device) to `path` as
+    a PNG file (8-bit truecolour, no interlace)."""
+    import struct
+    import zlib
+
+    a = np.ascontiguousarray(rgb.cpu().numpy() if hasattr(rgb, "cpu") else rgb, dtype=np.uint8)
+    if a.ndim != 3 or a.shape[2] != 3:
+        raise ValueError("rgb must be [h, w, 3]")
+    h, w = a.shape[:2]
+    raw = b"".join(b"\x00" + a[y].tobytes() for y in range(h))  # filter 0 per row
+
+    def chunk(tag, data):
+        return (struct.pack(">I", len(data)) + tag + data +
+                struct.pack(">I", zlib.crc32(tag + data) & 0xFFFFFFFF))
+
+    with open(path, "wb") as f:
+        f.write(b"\x89PNG\r\n\x1a\n")
+        f.write(chunk(b"IHDR", struct.pack(">IIBBBBB", w, h, 8, 2, 0, 0, 0)))
+        f.write(chunk(b"IDAT", zlib.compress(raw, 6)))
+        f.write(chunk(b"IEND", b""))
 
 
 def _handles(scans):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdd.so")
 SOURCES = ["dd_kernels.hip", "dd_batch.hip", "unet_kernels.hip", "unet_conv.hip", "dd_host.cpp",
-           "dd_queries.cpp", "dd_tune.cpp", "unet.cpp", "dd_visits.hip", "dd_visits_host.cpp", "dd_noalloc.hip"]
+           "dd_queries.cpp", "dd_tune.cpp", "unet.cpp", "dd_visits.hip", "dd_visits_host.cpp", "dd_noalloc.hip",
+           "dd_render.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -30,6 +30,7 @@ struct ArrivalLaunch {
   int R;                    // eval visits per lane (tile = 64 R)
   bool mixed;
   bool near;                // items are near-band items (per-pair regime)
+  bool range = false;       // a visit-range query (its own kernel instantiations)
 };
 hipError_t launch_arrival(const ArrivalLaunch& L, hipStream_t st);
 

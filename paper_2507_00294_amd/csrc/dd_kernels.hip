@@ -36,8 +36,10 @@ __global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, dou
 }
 
 // ---------------------------------------------------------------------------
-// Grid-mapped kernels: wavefront w of block b takes item 4 b + w.
-template <int R>
+// Grid-mapped kernels: wavefront w of block b takes item 4 b + w.  RANGE = 1
+// marks the launches of a visit-range query: the same code as a whole-scan
+// query, instantiated apart so that kernel traces report the two separately.
+template <int R, int RANGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_arrival_far32(const float4* __restrict__ pos,
                                                        const float* __restrict__ rows,
@@ -50,7 +52,7 @@ k_arrival_far32(const float4* __restrict__ pos,
   do_arrival_far32<R, false>(items[it], pos, rows, V, bnd, partial, pstride, pj0);
 }
 
-template <int R>
+template <int R, int RANGE>
 __global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict__ pos,
                                                        const double* __restrict__ rows,
                                                        const ArrItem* __restrict__ items, int n_items,
@@ -62,7 +64,7 @@ __global__ void __launch_bounds__(256) k_arrival_far64(const double2* __restrict
   do_arrival_far64<R>(items[it], pos, rows, V, bnd, partial, pstride, pj0);
 }
 
-template <int R, bool MIXED>
+template <int R, bool MIXED, int RANGE>
 __global__ void __launch_bounds__(256) k_arrival_near(const void* __restrict__ pos_v,
                                                       const double* __restrict__ rows64,
                                                       const float* __restrict__ rows32,
@@ -196,42 +198,44 @@ hipError_t launch_lag_rows(int64_t n0, int64_t count, double f, double kappa, do
   return hipGetLastError();
 }
 
-template <int R>
+template <int R, int RANGE>
 static void launch_arrival_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
   if (L.mixed) {
-    hipLaunchKernelGGL((k_arrival_far32<R>), dim3(blocks), dim3(256), 0, st, L.pos4,
+    hipLaunchKernelGGL((k_arrival_far32<R, RANGE>), dim3(blocks), dim3(256), 0, st, L.pos4,
                        L.rows32, L.items, L.n_items, L.V, L.bounds, L.partial, L.pstride, L.pj0);
   } else {
-    hipLaunchKernelGGL((k_arrival_far64<R>), dim3(blocks), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_arrival_far64<R, RANGE>), dim3(blocks), dim3(256), 0, st,
                        (const double2*)L.pos, L.rows64, L.items, L.n_items, L.V, L.bounds,
                        L.partial, L.pstride, L.pj0);
   }
 }
 
-template <int R>
+template <int R, int RANGE>
 static void launch_arrival_near_r(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
   if (L.mixed)
-    hipLaunchKernelGGL((k_arrival_near<R, true>), dim3(blocks), dim3(256), 0, st, L.pos, L.rows64,
-                       L.rows32, L.items, L.n_items, L.V, L.partial, L.pstride, L.pj0);
-  else
-    hipLaunchKernelGGL((k_arrival_near<R, false>), dim3(blocks), dim3(256), 0, st, L.pos,
+    hipLaunchKernelGGL((k_arrival_near<R, true, RANGE>), dim3(blocks), dim3(256), 0, st, L.pos,
                        L.rows64, L.rows32, L.items, L.n_items, L.V, L.partial, L.pstride, L.pj0);
+  else
+    hipLaunchKernelGGL((k_arrival_near<R, false, RANGE>), dim3(blocks), dim3(256), 0, st, L.pos,
+                       L.rows64, L.rows32, L.items, L.n_items, L.V, L.partial, L.pstride, L.pj0);
+}
+
+template <int R>
+static void launch_arrival_kind(const ArrivalLaunch& L, hipStream_t st, unsigned blocks) {
+  if (L.near)
+    L.range ? launch_arrival_near_r<R, 1>(L, st, blocks) : launch_arrival_near_r<R, 0>(L, st, blocks);
+  else
+    L.range ? launch_arrival_r<R, 1>(L, st, blocks) : launch_arrival_r<R, 0>(L, st, blocks);
 }
 
 // Near-band and far-region items are launched separately (L.near).
 hipError_t launch_arrival(const ArrivalLaunch& L, hipStream_t st) {
   if (L.n_items <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((L.n_items + 3) / 4);
-  const bool near = L.near;
   switch (L.R) {
-    case 2:
-      near ? launch_arrival_near_r<2>(L, st, blocks) : launch_arrival_r<2>(L, st, blocks);
-      break;
-    case 4:
-      near ? launch_arrival_near_r<4>(L, st, blocks) : launch_arrival_r<4>(L, st, blocks);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 2: launch_arrival_kind<2>(L, st, blocks); break;
+    case 4: launch_arrival_kind<4>(L, st, blocks); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

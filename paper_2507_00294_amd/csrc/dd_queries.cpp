@@ -453,6 +453,7 @@ dd_status dd::launch_range(dd_scan* s, bool mixed, const RangePlan& rp, int64_t 
   L.pstride = rp.pstride;
   L.pj0 = rp.pj0;
   L.mixed = mixed;
+  L.range = true;
   L.items = d_items;
   L.n_items = P.n_near;
   L.near = true;

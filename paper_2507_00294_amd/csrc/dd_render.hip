@@ -1,0 +1,207 @@
+// dd_render.hip -- visualisation of damage maps (dd_render_maps): psi maps
+// rendered to 8-bit RGB images on the device, the counterpart of the
+// paper's integrated live and offline 2-D views of the diffusion
+// distribution (Sec. IV).  Any [n][h][w] array of psi values is accepted:
+// the maps of dd_damage_map, the frames of dd_damage_sweep, the final maps
+// of dd_batch_solve or dd_unet_predict.
+//
+// Per pixel, value v of map m with range [lo_m, hi_m]:
+//   t = 0                         if not (v > lo_m) (also NaN, v <= 0 on a log scale)
+//   t = 1                         if v >= hi_m
+//   t = ln(v / lo_m) / ln(hi_m / lo_m)      (log scale)
+//   t = (v - lo_m) / (hi_m - lo_m)          (linear scale)
+//   colour = table[min(255, floor(256 t))]
+// The table interpolates the colour-map anchors of dd.h linearly between
+// anchor bins (FP64, rounded to the nearest integer).  With iso-lines, a
+// pixel whose level min(L - 1, floor(L t)) differs from that of its right
+// or lower neighbour in the same map is drawn white.  An automatic range
+// takes hi_m = the largest finite value of map m and lo_m = max(hi_m
+// 10^-decades, 2^-1022) (log) or 0 (linear); a map whose hi_m <= lo_m (no
+// positive value) renders black.  A t that is not a number (a linear range
+// so wide that hi - lo overflows) is taken as 0.
+// HBM-bound: 8 bytes read and 3 written per pixel (the neighbours' values
+// come from the same cache lines).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <mutex>
+
+#include "../../include/dd.h"
+#include "dd_runtime.h"
+
+namespace dd {
+namespace {
+
+// Colour-map anchors: (bin, r, g, b), bins 0 .. 255 increasing (the table of
+// dd.h).
+constexpr int kAnchors = 7;
+constexpr int kAnchor[kAnchors][4] = {
+    {0, 0, 0, 0},       {38, 32, 12, 96},  {90, 118, 24, 132}, {141, 200, 52, 84},
+    {192, 244, 128, 32}, {230, 250, 208, 64}, {255, 255, 255, 232}};
+
+// One table entry: the linear interpolation between the anchors around bin
+// i, in FP64, rounded to the nearest integer (x >= 0, so x + 0.5 truncates
+// to the rounding).
+struct ColourTable {
+  uint32_t rgb[256];
+  constexpr ColourTable() : rgb() {
+    for (int i = 0; i < 256; ++i) {
+      int a = 0;
+      while (a + 1 < kAnchors - 1 && kAnchor[a + 1][0] <= i) ++a;
+      const int b0 = kAnchor[a][0], b1 = kAnchor[a + 1][0];
+      uint32_t packed = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double c0 = kAnchor[a][c + 1], c1 = kAnchor[a + 1][c + 1];
+        const double x = c0 + (c1 - c0) * (double)(i - b0) / (double)(b1 - b0);
+        packed |= (uint32_t)(int)(x + 0.5) << (8 * c);
+      }
+      rgb[i] = packed;
+    }
+  }
+};
+constexpr ColourTable kTable{};
+
+struct RenderArgs {
+  const double* psi;
+  uint8_t* rgb;
+  const double2* range;  // per map (lo, hi) of the automatic range, else null
+  double lo, hi;         // explicit range
+  int64_t npix, total;   // pixels per map, all pixels
+  int32_t w, h;
+  int32_t log_scale, levels;  // levels = 0: no iso-lines
+  ColourTable table;
+};
+
+// Largest finite value of each map (one block per map, fixed-order tree).
+__global__ void __launch_bounds__(256) k_render_range(const double* __restrict__ psi, int64_t npix,
+                                                      double fac, int32_t log_scale,
+                                                      double2* __restrict__ range) {
+  __shared__ double red[256];
+  const int64_t m = blockIdx.x;
+  const double* p = psi + m * npix;
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < npix; i += 256) {
+    const double v = p[i];
+    if (__builtin_isfinite(v) && v > mx) mx = v;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double hi = red[0];
+    // a log range starts at the smallest normal double at the lowest
+    const double lo = log_scale ? fmax(hi * fac, 2.2250738585072014e-308) : 0.0;
+    range[m] = make_double2(lo, hi);
+  }
+}
+
+__device__ __forceinline__ double scale_t(double v, double lo, double hi, int log_scale) {
+  if (!(v > lo)) return 0.0;
+  if (v >= hi) return 1.0;
+  const double t = log_scale ? ::log(v / lo) / ::log(hi / lo) : (v - lo) / (hi - lo);
+  return fmin(fmax(t, 0.0), 1.0);  // a t that is not a number (overflowed range) is 0
+}
+
+__device__ __forceinline__ int level_of(double t, int L) { return min(L - 1, (int)(t * L)); }
+
+__global__ void __launch_bounds__(256) k_render(RenderArgs A) {
+  __shared__ uint32_t tab[256];
+  tab[threadIdx.x] = A.table.rgb[threadIdx.x];
+  __syncthreads();
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < A.total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = e / A.npix, q = e - m * A.npix;
+    double lo = A.lo, hi = A.hi;
+    if (A.range) {
+      const double2 r = A.range[m];
+      lo = r.x;
+      hi = r.y;
+    }
+    uint32_t c;
+    if (!(hi > lo)) {  // an automatic range over a map with no positive value
+      c = tab[0];
+    } else {
+      const double t = scale_t(A.psi[e], lo, hi, A.log_scale);
+      c = tab[min(255, (int)(t * 256.0))];
+      if (A.levels > 0) {
+        const int x = (int)(q % A.w), y = (int)(q / A.w);
+        const int lv = level_of(t, A.levels);
+        bool edge = false;
+        if (x + 1 < A.w) edge |= level_of(scale_t(A.psi[e + 1], lo, hi, A.log_scale), A.levels) != lv;
+        if (y + 1 < A.h)
+          edge |= level_of(scale_t(A.psi[e + A.w], lo, hi, A.log_scale), A.levels) != lv;
+        if (edge) c = 0xFFFFFFu;
+      }
+    }
+    uint8_t* o = A.rgb + 3 * e;
+    o[0] = (uint8_t)(c & 0xFF);
+    o[1] = (uint8_t)((c >> 8) & 0xFF);
+    o[2] = (uint8_t)((c >> 16) & 0xFF);
+  }
+}
+
+// Per-thread device buffer of the automatic ranges.
+thread_local DevBuf g_range_buf;
+
+}  // namespace
+}  // namespace dd
+
+using namespace dd;
+
+dd_status dd_render_maps(const double* psi, int64_t n, int32_t w, int32_t h,
+                         const dd_render_opts* opt, uint8_t* rgb, void* hip_stream) {
+  if (!opt) return fail(DD_EINVAL, "NULL options");
+  if (n < 0 || w < 1 || h < 1) return fail(DD_EINVAL, "need n >= 0 maps of w, h >= 1 pixels");
+  if ((int64_t)w * h > (1LL << 40) / std::max<int64_t>(n, 1))
+    return fail(DD_EINVAL, "too many pixels");
+  if (n > 0 && (!psi || !rgb)) return fail(DD_EINVAL, "NULL array");
+  if (opt->log_scale != 0 && opt->log_scale != 1) return fail(DD_EINVAL, "log_scale must be 0 or 1");
+  if (opt->levels < 0 || opt->levels > 256) return fail(DD_EINVAL, "levels must be in [0, 256]");
+  const bool autor = opt->lo == 0.0 && opt->hi == 0.0;
+  if (autor) {
+    if (opt->log_scale && !(std::isfinite(opt->decades) && opt->decades > 0 && opt->decades <= 300))
+      return fail(DD_EINVAL, "decades must be in (0, 300]");
+  } else {
+    if (!(std::isfinite(opt->lo) && std::isfinite(opt->hi) && opt->hi > opt->lo))
+      return fail(DD_EINVAL, "need finite lo < hi (or lo = hi = 0 for an automatic range)");
+    if (opt->log_scale && !(opt->lo > 0)) return fail(DD_EINVAL, "a log scale needs lo > 0");
+  }
+  dd_status rc = ensure_device();
+  if (rc != DD_OK) return rc;
+  if (n == 0) return DD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t npix = (int64_t)w * h, total = npix * n;
+  RenderArgs A{};
+  A.psi = psi;
+  A.rgb = rgb;
+  A.lo = opt->lo;
+  A.hi = opt->hi;
+  A.npix = npix;
+  A.total = total;
+  A.w = w;
+  A.h = h;
+  A.log_scale = opt->log_scale;
+  A.levels = opt->levels;
+  A.table = kTable;
+  if (autor) {
+    hipError_t e = g_range_buf.ensure(sizeof(double2) * (size_t)n);
+    if (e != hipSuccess) return hip_fail(e, "device allocation");
+    const double fac = std::pow(10.0, -opt->decades);
+    if (n > 0x7fffffff) return fail(DD_EINVAL, "too many maps");
+    hipLaunchKernelGGL(k_render_range, dim3((unsigned)n), dim3(256), 0, st, psi, npix, fac,
+                       opt->log_scale, g_range_buf.as<double2>());
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "range kernel launch");
+    A.range = g_range_buf.as<double2>();
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_render, dim3(blocks), dim3(256), 0, st, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "render kernel launch");
+  return DD_OK;
+}

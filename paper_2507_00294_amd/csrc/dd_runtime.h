@@ -38,13 +38,21 @@ ProfToken prof_begin(const char* kernel, hipStream_t st);
 void prof_end(ProfToken tok, hipStream_t st, double pairs, double flops);
 bool prof_on();  // whether kernel timing is being recorded
 
-// Floating-point operations per pair of the evaluation form used (FMA = 2):
-// mixed degree <= 3 (powers of a, folded correction) 15 + 2M, mixed degree
-// >= 4 (powers of dx, exact correction) 17 + 2M, FP64 40 + 2M (13-term
-// exp polynomial).
+// Floating-point operations per pair of the evaluation form used, counted as
+// the hardware counters count them (FMA = 2, add, multiply and the
+// transcendental v_exp_f32 = 1), with the FP64 accumulation.  Mixed
+// precision:
+//  * degree M <= 3 (powers of a, folded correction): 13 + 2 max(M, 1) --
+//    a 3, x1 log2(e) and its rounding error 3, 2^-x 1, the polynomial
+//    2 max(M, 1) (degrees 0 and 1 both take one FMA), the correction 2,
+//    the running sum 2 (FMA; every 4th lag a product of 1 and an FP64 add
+//    of 1 every 4 lags);
+//  * degree M >= 4 (powers of dx, exact correction): 17 + 2M.
+// FP64: 33 + 2M (distance 5, dx 1, x1 log2(e) 1, the exponent split 2, the
+// degree-11 exp polynomial 22, the polynomial 2M, the sum 2).
 inline double series_flops(int M, bool mixed) {
-  if (!mixed) return 36.0 + 2.0 * M;  // exp: degree-11 polynomial (22 flops)
-  return (M <= kMaxA ? 15.0 : 17.0) + 2.0 * M;
+  if (!mixed) return 33.0 + 2.0 * M;
+  return M <= kMaxA ? 13.0 + 2.0 * (M > 1 ? M : 1) : 17.0 + 2.0 * M;
 }
 
 // A grow-only device buffer.

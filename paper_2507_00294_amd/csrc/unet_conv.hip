@@ -204,8 +204,15 @@ __device__ __forceinline__ void epilogue(const ConvArgs& p, f32x4 (&acc)[4][NB],
   }
 }
 
-template <typename TIn, int IN, int BN, int EPI, int LG>
+// Input element type as a template integer (kernel names in traces then
+// demangle plainly): TIN_BF16 for activations, TIN_F32 for gradients.
+enum { TIN_BF16 = 0, TIN_F32 = 1 };
+template <int TIN>
+using InType = typename std::conditional<TIN == TIN_BF16, __bf16, float>::type;
+
+template <int TIN, int IN, int BN, int EPI, int LG>
 __global__ void __launch_bounds__(256) k_conv_halo(ConvArgs p) {
+  using TIn = InType<TIN>;
   // weights staged in LDS for BN = 64; for BN = 32 (the one-chunk layers at
   // 64^2, which depend on occupancy) each wave reads them from L2, one tap ahead
   constexpr bool BLDS = BN >= 64;
@@ -457,25 +464,25 @@ __global__ void __launch_bounds__(256) k_conv_first(ConvArgs p) {
   epilogue<2, EPI>(p, acc, m0, 0, wave, lane);
 }
 
-template <typename TIn, int IN, int BN, int EPI>
+template <int TIN, int IN, int BN, int EPI>
 void launch_halo_bn(const ConvArgs& p, dim3 grid, hipStream_t st) {
   switch (p.lg) {
-    case 3: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 3>), grid, dim3(256), 0, st, p); break;
-    case 4: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 4>), grid, dim3(256), 0, st, p); break;
-    case 5: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 5>), grid, dim3(256), 0, st, p); break;
-    default: hipLaunchKernelGGL((k_conv_halo<TIn, IN, BN, EPI, 6>), grid, dim3(256), 0, st, p); break;
+    case 3: hipLaunchKernelGGL((k_conv_halo<TIN, IN, BN, EPI, 3>), grid, dim3(256), 0, st, p); break;
+    case 4: hipLaunchKernelGGL((k_conv_halo<TIN, IN, BN, EPI, 4>), grid, dim3(256), 0, st, p); break;
+    case 5: hipLaunchKernelGGL((k_conv_halo<TIN, IN, BN, EPI, 5>), grid, dim3(256), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_conv_halo<TIN, IN, BN, EPI, 6>), grid, dim3(256), 0, st, p); break;
   }
 }
 
 // Callers have checked 3 <= lg <= 6 (halo_ok).
-template <typename TIn, int IN, int EPI>
+template <int TIN, int IN, int EPI>
 hipError_t launch_halo(const ConvArgs& p, hipStream_t st) {
   const int bn = (EPI == EPI_HEAD) ? 32 : (p.N % 64 == 0) ? 64 : 32;
   dim3 grid((p.M + CBM - 1) / CBM, p.N / bn);
   if (bn == 64)
-    launch_halo_bn<TIn, IN, 64, EPI>(p, grid, st);
+    launch_halo_bn<TIN, IN, 64, EPI>(p, grid, st);
   else
-    launch_halo_bn<TIn, IN, 32, EPI>(p, grid, st);
+    launch_halo_bn<TIN, IN, 32, EPI>(p, grid, st);
   return hipGetLastError();
 }
 
@@ -489,7 +496,7 @@ hipError_t conv3_silu(const __bf16* x, int B, int lg, int ci, const __bf16* wt, 
                       __bf16* act, float* z, int co, __bf16* pool, hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, nullptr, nullptr, co, pool};
   if (!halo_ok(p.M, lg, ci, co) || !act || (pool && lg < 4)) return hipErrorInvalidValue;
-  return launch_halo<__bf16, IN_PLAIN, EPI_SILU>(p, st);
+  return launch_halo<TIN_BF16, IN_PLAIN, EPI_SILU>(p, st);
 }
 
 hipError_t conv3_upcat_silu(const __bf16* coarse, int c1, const __bf16* skip, int c2, int B,
@@ -497,7 +504,7 @@ hipError_t conv3_upcat_silu(const __bf16* coarse, int c1, const __bf16* skip, in
                             int co, hipStream_t st) {
   ConvArgs p{skip, coarse, c1, B << (2 * lg), lg, c1 + c2, wt, bias, act, z, nullptr, nullptr, co};
   if (!halo_ok(p.M, lg, p.ci, co) || c1 % 32 != 0 || lg < 4 || !act) return hipErrorInvalidValue;
-  return launch_halo<__bf16, IN_UPCAT, EPI_SILU>(p, st);
+  return launch_halo<TIN_BF16, IN_UPCAT, EPI_SILU>(p, st);
 }
 
 hipError_t conv3_silu_head(const __bf16* x, int B, int lg, int ci, const __bf16* wt,
@@ -505,14 +512,14 @@ hipError_t conv3_silu_head(const __bf16* x, int B, int lg, int ci, const __bf16*
                            hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, bias, act, z, head, y, 32};
   if (!halo_ok(p.M, lg, ci, 32) || !y || !head) return hipErrorInvalidValue;
-  return launch_halo<__bf16, IN_PLAIN, EPI_HEAD>(p, st);
+  return launch_halo<TIN_BF16, IN_PLAIN, EPI_HEAD>(p, st);
 }
 
 hipError_t conv3_plain(const float* x, int B, int lg, int ci, const __bf16* wt, float* out, int co,
                        hipStream_t st) {
   ConvArgs p{x, nullptr, 0, B << (2 * lg), lg, ci, wt, nullptr, out, nullptr, nullptr, nullptr, co};
   if (!halo_ok(p.M, lg, ci, co) || !out) return hipErrorInvalidValue;
-  return launch_halo<float, IN_PLAIN, EPI_PLAIN>(p, st);
+  return launch_halo<TIN_F32, IN_PLAIN, EPI_PLAIN>(p, st);
 }
 
 hipError_t conv3_first_silu(const float* x, int B, int lg, int ci, const __bf16* wt,

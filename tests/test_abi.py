@@ -328,3 +328,46 @@ def test_handles_created_and_destroyed_in_threads(dd):
     for t in th:
         t.join()
     assert not errors, errors
+
+
+def test_render_arguments_checked_before_device(dd):
+    lib = dd.load_library()
+    o = ctypes.c_void_p(16)
+    ok = dd.RenderOpts(0.0, 0.0, 6.0, 1, 0)
+    assert lib.dd_render_maps(o, 1, 4, 4, None, o, None) == dd.DD_EINVAL
+    for n, w, h in ((-1, 4, 4), (1, 0, 4), (1, 4, 0)):
+        assert lib.dd_render_maps(o, n, w, h, ctypes.byref(ok), o, None) == dd.DD_EINVAL
+    assert lib.dd_render_maps(None, 1, 4, 4, ctypes.byref(ok), o, None) == dd.DD_EINVAL
+    for bad in (dd.RenderOpts(0.0, 0.0, 0.0, 1, 0), dd.RenderOpts(0.0, 0.0, 301.0, 1, 0),
+                dd.RenderOpts(0.0, 0.0, float("nan"), 1, 0), dd.RenderOpts(0.0, 1.0, 6.0, 1, 0),
+                dd.RenderOpts(2.0, 1.0, 6.0, 0, 0), dd.RenderOpts(1.0, float("inf"), 6.0, 0, 0),
+                dd.RenderOpts(0.0, 0.0, 6.0, 2, 0), dd.RenderOpts(0.0, 0.0, 6.0, 1, -1),
+                dd.RenderOpts(0.0, 0.0, 6.0, 1, 257)):
+        assert lib.dd_render_maps(o, 1, 4, 4, ctypes.byref(bad), o, None) == dd.DD_EINVAL
+
+
+def test_save_png_roundtrip(dd, tmp_path):
+    import struct
+    import zlib
+
+    rng = np.random.default_rng(3)
+    img = rng.integers(0, 256, size=(7, 5, 3), dtype=np.uint8)
+    path = str(tmp_path / "x.png")
+    dd.save_png(path, img)
+    data = open(path, "rb").read()
+    assert data[:8] == b"\x89PNG\r\n\x1a\n"
+    pos, chunks = 8, {}
+    while pos < len(data):
+        (n,) = struct.unpack(">I", data[pos:pos + 4])
+        tag, body = data[pos + 4:pos + 8], data[pos + 8:pos + 8 + n]
+        (crc,) = struct.unpack(">I", data[pos + 8 + n:pos + 12 + n])
+        assert crc == zlib.crc32(tag + body) & 0xFFFFFFFF
+        chunks[tag] = body
+        pos += 12 + n
+    w, h, depth, ctype = struct.unpack(">IIBB", chunks[b"IHDR"][:10])
+    assert (w, h, depth, ctype) == (5, 7, 8, 2)
+    raw = zlib.decompress(chunks[b"IDAT"])
+    rows = [raw[y * (1 + 15):(y + 1) * (1 + 15)] for y in range(7)]
+    assert all(r[0] == 0 for r in rows)
+    back = np.frombuffer(b"".join(r[1:] for r in rows), dtype=np.uint8).reshape(7, 5, 3)
+    assert np.array_equal(back, img)
