@@ -32,6 +32,9 @@ def test_forward_loss_and_gradients_match_reference(dd, batch):
     net = dd.UNet(seed=3)
     assert net.num_params == unet_ref.num_params()
     p = net.params()
+    # a random head (the initial one is zero, which would zero every
+    # convolution's gradient)
+    p[dict(unet_ref.layer_slices())["head"]] = np.random.default_rng(5).normal(0, 0.3, 33)
     p[-1] = -0.5
     net.set_params(p)
     rng = np.random.default_rng(7)
@@ -51,8 +54,7 @@ def test_forward_loss_and_gradients_match_reference(dd, batch):
     assert np.linalg.norm(dy - ref_dy) <= 5e-2 * np.linalg.norm(ref_dy)
     for name, s in unet_ref.layer_slices():
         gn = np.linalg.norm(ref_g[s])
-        if gn == 0:
-            continue
+        assert gn > 0, name
         err = np.linalg.norm(g[s] - ref_g[s]) / gn
         assert err <= 6e-2, (name, err)
     cos = float(np.dot(g, ref_g) / (np.linalg.norm(g) * np.linalg.norm(ref_g)))

@@ -1,0 +1,103 @@
+"""The surrogate's forward pass, loss gradient and every parameter gradient
+against the BF16-emulating float64 reference (oracle/unet_ref.py
+forward_bf16 / backward_bf16 / loss_dy), element by element.
+
+The reference rounds the operands of every convolution to BF16 where the
+kernels do and accumulates in float64, so what remains is the kernels' FP32
+accumulation and fast SiLU (~1e-6 relative) and the rare stored value whose
+FP32 result lies on the other side of a BF16 rounding boundary than the
+float64 one (one BF16 step, 2^-8, of one operand).  Per output or parameter
+group the bound is max |g - r| <= tol max |r| with the tolerances below.
+Two settings: the committed trained weights on final maps of real 64x64
+scans (every level, borders included), and a random network whose head and
+biases are random too, so that no gradient is zero."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL_Y = 5e-3       # forward output y, every pixel (measured <= 2.2e-3)
+TOL_DY = 1e-5      # loss and dL/dy of the loss kernel at the GPU's own y (<= 3.2e-6)
+TOL_G = 1e-2       # every weight and bias gradient group, element-wise (<= 2.3e-3)
+TOL_G_NORM = 5e-3  # relative L2 error of every group (<= 1.9e-3)
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_00294_amd as dd
+
+    dd.load_library()
+    return dd
+
+
+def _case(dd, mode):
+    import torch
+
+    from paper_2507_00294_amd import surrogate as sg
+    from paper_2507_00294_amd import workloads as wl
+
+    specs = wl.surrogate_scans(3, seed=6)
+    scans = [dd.Scan(**s.kwargs()) for s in specs]
+    x, own = dd.surrogate_inputs(scans)
+    outs = dd.batch_solve(scans, dd.Q_FINAL_AT_PROBES, "mixed")
+    t = dd.surrogate_targets(scans, torch.stack([o.view(64, 64) for o in outs]))
+    net = dd.UNet(seed=3)
+    if mode == "trained":
+        sg.load_weights(net)
+    else:
+        from oracle import unet_ref as R
+
+        p = net.params()
+        rng = np.random.default_rng(23)
+        for name, s in R.layer_slices():
+            if name.endswith(".b"):
+                p[s] = rng.normal(0, 0.05, s.stop - s.start)
+        hs = dict(R.layer_slices())["head"]
+        p[hs] = rng.normal(0, 0.3, 33)
+        net.set_params(p)
+    return net, x, own, t
+
+
+@pytest.mark.parametrize("mode", ["trained", "random"])
+def test_surrogate_elementwise(dd, mode):
+    import torch
+
+    from oracle import unet_ref as R
+
+    net, x, own, t = _case(dd, mode)
+    p = net.params().astype(np.float64)
+    y = net.forward(x, train=True)
+    loss, dy = net.loss(y, own, t)
+    net.backward(dy)
+    g = net.grads().astype(np.float64)
+    y, dy = y.cpu().numpy().astype(np.float64), dy.cpu().numpy().astype(np.float64)
+    xt = torch.tensor(x.cpu().numpy(), dtype=torch.float64)
+    yr, state = R.forward_bf16(torch.tensor(p), xt)
+    yr = yr.numpy()
+    # forward: every pixel, borders included
+    ey = np.abs(y - yr)
+    report = {"y": float(ey.max() / np.abs(yr).max())}
+    border = np.zeros((64, 64), dtype=bool)
+    border[[0, -1], :] = border[:, [0, -1]] = True
+    report["y_border"] = float(ey[:, border].max() / np.abs(yr).max())
+    # loss and its gradient at the GPU's own y
+    lr, dyr = R.loss_dy(y, own.cpu().numpy(), t.cpu().numpy())
+    report["loss"] = abs(loss - lr) / lr
+    report["dy"] = float(np.abs(dy - dyr).max() / np.abs(dyr).max())
+    # backward from the GPU's dy through the reference's own forward state
+    gr = R.backward_bf16(torch.tensor(p), state, torch.tensor(dy)).numpy()
+    worst = {}
+    for name, s in R.layer_slices():
+        a, b = g[s], gr[s]
+        worst[name] = (float(np.abs(a - b).max() / np.abs(b).max()),
+                       float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+    print("\n" + mode, report, {k: f"{v[0]:.2e}/{v[1]:.2e}" for k, v in worst.items()})
+    assert report["y"] <= TOL_Y, report
+    assert report["loss"] <= TOL_DY and report["dy"] <= TOL_DY, report
+    for name, (emax, enorm) in worst.items():
+        assert emax <= TOL_G and enorm <= TOL_G_NORM, (name, emax, enorm)
+    net.close()

@@ -75,3 +75,81 @@ def test_loss_is_mean_squared_relative_l2():
     t2 = torch.tensor([[[2.0, 4.0]]], dtype=torch.float64)
     want2 = 0.5 * ((0.5 ** 2) * (0 - np.log(1.0)) ** 2 + 1.0 * (0 - np.log(4.0)) ** 2)
     assert float(unet_ref.anchor_term(y0, own2, t2)) == pytest.approx(want2, rel=1e-12)
+
+
+def test_bf16_reference_without_rounding_is_the_network_and_its_autograd():
+    """The BF16 reference with rounding switched off computes the float64
+    network (forward) and, through its hand-written backward (convolution
+    adjoints, pooling, upsampling and concatenation routing, head), the
+    autograd gradient of forward(p, x) . dy; with rounding on it differs only
+    at BF16 level."""
+    import torch
+
+    from oracle import unet_ref as R
+
+    rng = np.random.default_rng(11)
+    p = torch.tensor(rng.normal(0, 0.05, R.num_params()))
+    x = torch.tensor(rng.random((2, 16, 16, R.CIN)))
+    dy = torch.tensor(rng.normal(0, 1, (2, 16, 16)))
+    y0, st0 = R.forward_bf16(p, x, rounding=False)
+    y64 = R.forward(p, x)
+    assert float((y0 - y64).abs().max()) <= 1e-13 * float(y64.abs().max())
+    g0 = R.backward_bf16(p, st0, dy)
+    pa = p.clone().requires_grad_(True)
+    (R.forward(pa, x) * dy).sum().backward()
+    for name, s in R.layer_slices():
+        ref = pa.grad[s]
+        assert float((g0[s] - ref).abs().max()) <= 1e-11 * float(ref.abs().max()), name
+    yb, stb = R.forward_bf16(p, x)
+    gb = R.backward_bf16(p, stb, dy)
+    assert 1e-6 < float((yb - y64).abs().max() / y64.abs().max()) < 1e-2
+    for name, s in R.layer_slices():
+        ref = pa.grad[s]
+        err = float((gb[s] - ref).abs().max() / ref.abs().max())
+        assert err < 5e-2, (name, err)
+    # the rounding itself: BF16 keeps 8 significant bits, ties to even
+    v = torch.tensor([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, 3.0 * 2 ** -100])
+    assert R.bf16(v).tolist() == [1.0, 1.0, 1.0 + 4 * 2 ** -8, 1.0, 3.0 * 2 ** -100]
+
+
+def test_elementwise_bounds_see_a_wrong_tap_or_border():
+    """The element-wise bound of the GPU comparison (5e-3 of max |y|) is far
+    below what a mistake confined to one tap or to one layer's border
+    handling does to the reference's own output."""
+    import torch
+    import torch.nn.functional as F
+
+    from oracle import unet_ref as R
+
+    rng = np.random.default_rng(13)
+    p = torch.tensor(rng.normal(0, 0.08, R.num_params()))
+    x = torch.tensor(rng.random((1, 16, 16, R.CIN)))
+    y, _ = R.forward_bf16(p, x)
+    scale = float(y.abs().max())
+    off = 0
+    offs = []
+    for ci, co in R.CONVS:
+        offs.append(off)
+        off += 9 * ci * co + co
+    # one tap (the centre of layer 9) zeroed
+    q = p.clone()
+    ci, co = R.CONVS[9]
+    q[offs[9] + 4 * ci * co: offs[9] + 5 * ci * co] = 0
+    assert float((R.forward_bf16(q, x)[0] - y).abs().max()) > 10 * 5e-3 * scale
+    # border pixels of the input replicated instead of zero padded, first layer
+    real_conv2d = F.conv2d
+    calls = []
+
+    def replicate_first(inp, w, b=None, padding=0):
+        calls.append(1)
+        if len(calls) == 1:
+            return real_conv2d(F.pad(inp, (1, 1, 1, 1), mode="replicate"), w, b)
+        return real_conv2d(inp, w, b, padding=padding)
+
+    R.F.conv2d = replicate_first
+    try:
+        y2, _ = R.forward_bf16(p, x)
+    finally:
+        R.F.conv2d = real_conv2d
+    d = (y2 - y).abs()[0]
+    assert float(d[[0, -1], :].max()) > 5e-3 * scale or float(d[:, [0, -1]].max()) > 5e-3 * scale
