@@ -602,7 +602,7 @@ def main():
             net = dd.UNet(0)
             sg.load_weights(net)
             res = sg.evaluate(net, wl.surrogate_scans(args.surrogate_maps, seed=6), 0.02, "mixed",
-                              repeats=3)
+                              repeats=3, extra_tols=(0.01,))
             net.close()
             sur = {"metric": "surrogate speedup over the exact batched kernel at <= 1% mean "
                              "relative L2 error", "speedup": res["speedup"],
@@ -612,6 +612,9 @@ def main():
                    "network_only_ms": res["network_only_s"] * 1e3,
                    "network_only_rel_l2_mean": res["network_only_rel_l2_mean"],
                    "maps": res["maps"], "spot_tol": res["spot_tol"],
+                   "judge": "exact values on the 8x8 probe sub-grid of stride 9 per map; "
+                            "rel_l2_max is the worst accepted map (rejected maps are exact)",
+                   "at_spot_tol_0.01": res["at_spot_tol"][0.01],
                    "workload": "final damage maps of 64x64 scans, batched-config sampling "
                                "(seed 6), mixed precision exact path"}
             log(f"[bench] surrogate: x{sur['speedup']:.2f} at rel L2 {sur['rel_l2_mean']:.4f} "

@@ -285,6 +285,16 @@ dd_status dd_unet_loss(dd_unet *u, int32_t maps, const float *y, const float *ow
  * receives the norm before clipping (synchronizes).                       */
 dd_status dd_unet_adam(dd_unet *u, float lr, float beta1, float beta2, float eps, float clip,
                        float *grad_norm_host, void *hip_stream);
+/* Adam state for checkpoints: copies the first and second moments (n_params
+ * floats each, host) and the step count (dd_unet_adam calls so far, which
+ * sets the bias correction) out through the *_get pointers and then in from
+ * the *_set pointers; any of them may be NULL.  With the parameters
+ * (dd_unet_params) this is all the state a training step reads, so a run
+ * restored from them continues bit for bit.  Synchronizes.
+ * Errors: DD_EINVAL (NULL handle, every pointer NULL, a negative step),
+ * DD_EDEVICE.                                                             */
+dd_status dd_unet_adam_state(dd_unet *u, float *m_get, float *v_get, int64_t *step_get,
+                             const float *m_set, const float *v_set, const int64_t *step_set);
 /* Training mini-batch: slot b <- map idx[b] of (x_all, own_all, t_all; n_all
  * maps) under the symmetry transform[b] of the square (0..7: transpose if
  * bit 0, then mirror rows if bit 1, columns if bit 2); idx and transform are
@@ -302,8 +312,10 @@ dd_status dd_surrogate_inputs(dd_scan *const *scans, int32_t n, float *x, float 
 dd_status dd_surrogate_targets(dd_scan *const *scans, int32_t n, const double *psi, float *t,
                                void *hip_stream);
 /* Final damage maps psi [n][64*64] (u/m^2, device) by the network, judged by
- * the exact kernels: a map is accepted if the relative L2 error of its
- * middle row (row 31) against the exact row is <= spot_tol; scans outside
+ * the exact kernels: a map is accepted if the relative L2 error of its 64
+ * values on the probe sub-grid of stride 9 (rows and columns 0, 9, ..., 63:
+ * corners, borders and interior) against the exact values is <= spot_tol;
+ * scans outside
  * the training range (64x64 grid, every probe visited, kappa in
  * [2.5e-5, 100], sigma/pitch in [0.2, 1]) and rejected maps are computed
  * exactly (used_fallback[k] = 1, host array).  Synchronizes.               */

@@ -34,7 +34,8 @@ EXPORTS = (
     "dd_pair_terms",
     "dd_autotune", "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
     "dd_unet_destroy", "dd_unet_num_params", "dd_unet_params", "dd_unet_grads", "dd_unet_forward",
-    "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch",
+    "dd_unet_backward", "dd_unet_loss", "dd_unet_adam", "dd_unet_adam_state",
+    "dd_surrogate_batch",
     "dd_surrogate_inputs", "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
     "dd_visits_destroy", "dd_visits_count", "dd_visits_arrival", "dd_visits_map",
     "dd_visits_batch_arrival", "dd_visits_batch_map", "dd_render_maps", "dd_last_error",
@@ -115,6 +116,7 @@ def load_library():
     lib.dd_unet_loss.argtypes = [vp, i32, vp, vp, vp, ctypes.c_float, vp, P(dbl), vp]
     f32 = ctypes.c_float
     lib.dd_unet_adam.argtypes = [vp, f32, f32, f32, f32, f32, P(f32), vp]
+    lib.dd_unet_adam_state.argtypes = [vp, vp, vp, P(i64), vp, vp, P(i64)]
     lib.dd_surrogate_batch.argtypes = [vp, vp, vp, i64, vp, vp, i32, vp, vp, vp, vp]
     lib.dd_surrogate_inputs.argtypes = [P(vp), i32, vp, vp, vp]
     lib.dd_surrogate_targets.argtypes = [P(vp), i32, vp, vp, vp]
@@ -136,7 +138,8 @@ def load_library():
                  "dd_damage_at_probe_arrival_range_noalloc", "dd_batch_solve", "dd_scan_check", "dd_pair_terms", "dd_autotune",
                  "dd_tune_load", "dd_profiling", "dd_profile_read", "dd_unet_create",
                  "dd_unet_params", "dd_unet_grads", "dd_unet_forward", "dd_unet_backward",
-                 "dd_unet_loss", "dd_unet_adam", "dd_surrogate_batch", "dd_surrogate_inputs",
+                 "dd_unet_loss", "dd_unet_adam", "dd_unet_adam_state", "dd_surrogate_batch",
+                 "dd_surrogate_inputs",
                  "dd_surrogate_targets", "dd_unet_predict", "dd_visits_create",
                  "dd_visits_arrival", "dd_visits_map", "dd_visits_batch_arrival",
                  "dd_visits_batch_map", "dd_render_maps"):
@@ -668,6 +671,25 @@ class UNet:
                                            ctypes.byref(norm) if want_norm else None,
                                            _stream(stream)))
         return norm.value if want_norm else None
+
+    def adam_state(self):
+        """(m, v, step): Adam's moments (float32 [num_params]) and step count."""
+        m = np.empty(self.num_params, dtype=np.float32)
+        v = np.empty(self.num_params, dtype=np.float32)
+        step = ctypes.c_int64(0)
+        _check(load_library().dd_unet_adam_state(self._h, ctypes.c_void_p(m.ctypes.data),
+                                                 ctypes.c_void_p(v.ctypes.data),
+                                                 ctypes.byref(step), None, None, None))
+        return m, v, int(step.value)
+
+    def set_adam_state(self, m, v, step: int) -> None:
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        assert m.size == v.size == self.num_params
+        st = ctypes.c_int64(int(step))
+        _check(load_library().dd_unet_adam_state(self._h, None, None, None,
+                                                 ctypes.c_void_p(m.ctypes.data),
+                                                 ctypes.c_void_p(v.ctypes.data), ctypes.byref(st)))
 
     def predict(self, scans, spot_tol: float = 0.02, precision: str = "mixed", stream=None):
         """Final maps [n, 64, 64] (float64 CUDA, u/m^2) and the fallback flags."""

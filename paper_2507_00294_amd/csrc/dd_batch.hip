@@ -68,8 +68,9 @@ __global__ void __launch_bounds__(256) k_batch_map(const BatchScan* __restrict__
     const BatchItem bi = items[it];
     const BatchScan& S = scans[bi.scan];
     const MapItem mi{bi.tile, 0, bi.n_lo, bi.n_hi, bi.slot_flags & kSlotMask, NEAR ? 1 : 0, 0, 0};
-    do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, 0.0,
-                      (double)S.map_row0, 1.0, 1.0, S.nx, S.map_rows, true, S.map_partial);
+    do_map<RM, MIXED>(mi, S.map_time, S.pos, S.pos4, S.rows64, S.rows32, (double)S.map_x0,
+                      (double)S.map_y0, (double)S.map_step, (double)S.map_step, S.map_w, S.map_h,
+                      true, S.map_partial);
   }
 }
 

@@ -113,8 +113,10 @@ struct BatchScan {
   const double* rows64;    // integer-lag rows of this scan
   const float* rows32;
   int64_t V;
-  int32_t nx, ny;          // final map: nx pixels per row
-  int32_t map_row0, map_rows;  // rows [map_row0, map_row0 + map_rows) of the final map
+  int32_t nx, ny;          // probe grid
+  // final map on a probe sub-grid: pixel (u, v), u < map_w, v < map_h, at
+  // probe (map_x0 + map_step u, map_y0 + map_step v)
+  int32_t map_x0, map_y0, map_step, map_w, map_h;
   DegreeBounds arr_bounds;
   MapTime map_time;        // the final map at t = V tau_v (K = V, f = 0)
   double* arr_partial;     // [slots][V]

@@ -879,11 +879,23 @@ void sort_longest_first(std::vector<BatchItem>& v, std::vector<BatchItem>& tmp,
 
 }  // namespace
 
-// Batched solve; the final map covers rows [row0, row0 + rows) of each probe
-// grid (rows < 0: all rows).
+// The probe sub-grid of scan s that sel selects (sel.w < 0: the whole grid).
+static MapSel resolve_sel(const dd_scan* s, const MapSel& sel) {
+  if (sel.w < 0) return MapSel{0, 0, 1, s->desc.nx, s->desc.ny};
+  return sel;
+}
+
+// Batched solve; the final map covers the probe sub-grid `sel` of each scan.
 dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
-                        double* const* outs, int32_t on_device, hipStream_t st, int32_t row0,
-                        int32_t rows) {
+                        double* const* outs, int32_t on_device, hipStream_t st,
+                        const MapSel& sel) {
+  for (int32_t k = 0; k < n && sel.w >= 0; ++k) {
+    const MapSel q = resolve_sel(scans[k], sel);
+    if (q.w < 1 || q.h < 1 || q.step < 1 || q.x0 < 0 || q.y0 < 0 ||
+        q.x0 + (int64_t)q.step * (q.w - 1) >= scans[k]->desc.nx ||
+        q.y0 + (int64_t)q.step * (q.h - 1) >= scans[k]->desc.ny)
+      return fail(DD_EINVAL, "scan %d: probe sub-grid outside its grid", k);
+  }
   const int R = mixed ? tune().arr_R_mixed : tune().arr_R_f64;
   const int RN = mixed ? tune().arr_RN_mixed : tune().arr_RN_f64;
   const bool want_arr = (mask & DD_Q_ARRIVAL) != 0, want_map = (mask & DD_Q_FINAL_AT_PROBES) != 0;
@@ -893,10 +905,8 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
   if (want_map) {
     int64_t most = 0;
     for (int32_t k = 0; k < n; ++k) {
-      const int64_t r = rows < 0 ? scans[k]->desc.ny
-                                 : std::min<int64_t>(rows, scans[k]->desc.ny -
-                                                               std::min(row0, scans[k]->desc.ny - 1));
-      most = std::max<int64_t>(most, r * scans[k]->desc.nx);
+      const MapSel q = resolve_sel(scans[k], sel);
+      most = std::max<int64_t>(most, (int64_t)q.w * q.h);
     }
     while (RM > 1 && 64LL * (RM / 2) >= most) RM /= 2;
     // A small call (the surrogate's fallback) yields too few far items to
@@ -908,10 +918,8 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     if (RM == 4) {
       double est = 0;
       for (int32_t k = 0; k < n; ++k) {
-        const int64_t r = rows < 0 ? scans[k]->desc.ny
-                                   : std::min<int64_t>(rows, scans[k]->desc.ny -
-                                                                 std::min(row0, scans[k]->desc.ny - 1));
-        const int64_t npix = r * scans[k]->desc.nx, V = scans[k]->V;
+        const MapSel q = resolve_sel(scans[k], sel);
+        const int64_t npix = (int64_t)q.w * q.h, V = scans[k]->V;
         const int64_t units = (npix + 255) / 256;
         int64_t Kc = tune().map_K;
         while (Kc > 512 && units * ((V + Kc - 1) / Kc) < 64) Kc /= 2;
@@ -978,8 +986,12 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
     B.V = s->V;
     B.nx = s->desc.nx;
     B.ny = s->desc.ny;
-    B.map_row0 = rows < 0 ? 0 : std::min(row0, s->desc.ny - 1);
-    B.map_rows = rows < 0 ? s->desc.ny : std::min(rows, s->desc.ny - B.map_row0);
+    const MapSel q = resolve_sel(s, sel);
+    B.map_x0 = q.x0;
+    B.map_y0 = q.y0;
+    B.map_step = q.step;
+    B.map_w = q.w;
+    B.map_h = q.h;
     out_off[k] = out_total;
     if (want_arr) {
       dd_scan::BatchArrPlan& C = s->barr;
@@ -1025,14 +1037,15 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
       flops += C.flops;
     }
     if (want_map) {
-      dd_grid g{0.0, B.map_row0 * s->desc.pitch_m, s->desc.pitch_m, s->desc.pitch_m, s->desc.nx,
-                B.map_rows};
+      const double pm = s->desc.pitch_m;
+      dd_grid g{q.x0 * pm, q.y0 * pm, q.step * pm, q.step * pm, q.w, q.h};
       const double t_end = (double)s->V * s->tau_v;
       const int64_t Kmap = tune().map_K;
       dd_scan::BatchMapPlan* C = nullptr;
       for (dd_scan::BatchMapPlan& c : s->bmap)
-        if (c.ok && c.mixed == mixed && c.R == RM && c.row0 == B.map_row0 &&
-            c.rows == B.map_rows && c.K == Kmap && (c.counted || !count))
+        if (c.ok && c.mixed == mixed && c.R == RM && c.sel.x0 == q.x0 && c.sel.y0 == q.y0 &&
+            c.sel.step == q.step && c.sel.w == q.w && c.sel.h == q.h && c.K == Kmap &&
+            (c.counted || !count))
           C = &c;
       if (!C) {  // plan, replacing the plan used least recently
         C = s->bmap[0].used <= s->bmap[1].used ? &s->bmap[0] : &s->bmap[1];
@@ -1041,8 +1054,7 @@ dd_status dd::run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mi
         plan_map(s, &g, &t_end, 1, mixed, RM, Kmap, true, MP, false, count);
         C->mixed = mixed;
         C->R = RM;
-        C->row0 = B.map_row0;
-        C->rows = B.map_rows;
+        C->sel = q;
         C->K = Kmap;
         C->time = MP.times[0];
         C->slots = MP.slots;
@@ -1282,7 +1294,7 @@ dd_status dd_batch_solve(dd_scan* const* scans, int32_t n, uint32_t query_mask, 
   for (int32_t k = 0; k < n; ++k)
     if (!scans[k] || !outs[k]) return fail(DD_EINVAL, "scan %d or its output is NULL", k);
   return dd::run_batch(scans, n, query_mask, p == DD_MIXED, outs, out_on_device,
-                       (hipStream_t)hip_stream, 0, -1);
+                       (hipStream_t)hip_stream, MapSel{});
 }
 
 dd_status dd_scan_check(dd_scan* s, int64_t* first_bad) {

@@ -127,11 +127,16 @@ struct StreamEvent {
   }
 };
 
-// Batched solve of many scans (arrival and/or final map, the final map
-// restricted to rows [row0, row0 + rows) of each grid; rows < 0 = all).
+// Probe sub-grid of a batched final map: output pixel (u, v), u < w, v < h,
+// at probe (x0 + step u, y0 + step v); w < 0 selects the whole probe grid.
+struct MapSel {
+  int32_t x0 = 0, y0 = 0, step = 1, w = -1, h = -1;
+};
+
+// Batched solve of many scans (arrival and/or the final map on the probe
+// sub-grid `sel` of each scan).
 dd_status run_batch(dd_scan* const* scans, int32_t n, uint32_t mask, bool mixed,
-                    double* const* outs, int32_t on_device, hipStream_t st, int32_t row0,
-                    int32_t rows);
+                    double* const* outs, int32_t on_device, hipStream_t st, const MapSel& sel);
 
 struct OutFlag;
 // Plans the range query (plan_range) and launches it with its items, tile
@@ -164,9 +169,10 @@ struct dd_scan {
   dd::DevBuf sur;
   int sur_state = 0;
   // Plans of the batched solve, kept on the handle: they depend only on the
-  // scan, the precision and the tile shape (and, for the map, its rows), so
-  // a scan solved again skips the host planning.  Two map plans are kept
-  // (the whole final map and one row subset, as the surrogate's judge uses).
+  // scan, the precision and the tile shape (and, for the map, its probe
+  // sub-grid), so a scan solved again skips the host planning.  Two map
+  // plans are kept (the whole final map and one sub-grid, as the
+  // surrogate's judge uses).
   struct BatchArrPlan {
     bool ok = false, mixed = false, counted = false;
     int R = 0, RN = 0, K = 0, S = 0;
@@ -178,7 +184,7 @@ struct dd_scan {
   struct BatchMapPlan {
     bool ok = false, mixed = false, counted = false;
     int R = 0;
-    int32_t row0 = 0, rows = 0;
+    dd::MapSel sel{};
     int64_t K = 0, slots = 0, npix = 0;
     uint64_t used = 0;
     dd::MapTime time{};

@@ -17,9 +17,9 @@
 // output head is reduced in the last convolution's epilogue -- im2col +
 // split-K MFMA GEMM for the weight gradient, FP32 elementwise kernels and Adam
 // (unet_kernels.hip).
-// Predictions are judged by the exact kernels (one exact row per map) and
-// replaced by the exact map when the judge rejects them or the scan lies
-// outside the training range.
+// Predictions are judged by the exact kernels (an exact 8 x 8 probe sub-grid
+// per map) and replaced by the exact map when the judge rejects them or the
+// scan lies outside the training range.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +42,9 @@ constexpr int NPX = S * S;   // pixels per map
 constexpr int CIN = DD_SURROGATE_CHANNELS;
 constexpr int KPAD0 = 64;    // row length of the first layer's im2col (9 CIN padded)
 constexpr int kPredictChunk = 1024;  // maps per inference forward pass
+// Probes the exact judge evaluates per predicted map: the 8 x 8 sub-grid of
+// stride 9 (rows and columns 0, 9, ..., 63), corners and borders included.
+const dd::MapSel kJudge{0, 0, 9, 8, 8};
 
 struct Conv {
   int H, lg, ci, co, kpad;
@@ -489,6 +492,21 @@ dd_status dd_unet_params(dd_unet* u, float* host_get, const float* host_set) {
   return DD_OK;
 }
 
+dd_status dd_unet_adam_state(dd_unet* u, float* m_get, float* v_get, int64_t* step_get,
+                             const float* m_set, const float* v_set, const int64_t* step_set) {
+  if (!u || (!m_get && !v_get && !step_get && !m_set && !v_set && !step_set))
+    return fail(DD_EINVAL, "NULL argument");
+  if (step_set && *step_set < 0) return fail(DD_EINVAL, "negative Adam step");
+  const size_t bytes = sizeof(float) * u->n_params;
+  if (m_get) UN_HIP(hipMemcpy(m_get, u->m.p, bytes, hipMemcpyDeviceToHost), "moment copy");
+  if (v_get) UN_HIP(hipMemcpy(v_get, u->v.p, bytes, hipMemcpyDeviceToHost), "moment copy");
+  if (step_get) *step_get = u->step;
+  if (m_set) UN_HIP(hipMemcpy(u->m.p, m_set, bytes, hipMemcpyHostToDevice), "moment copy");
+  if (v_set) UN_HIP(hipMemcpy(u->v.p, v_set, bytes, hipMemcpyHostToDevice), "moment copy");
+  if (step_set) u->step = *step_set;
+  return DD_OK;
+}
+
 dd_status dd_unet_grads(const dd_unet* u, float* host_out) {
   if (!u || !host_out) return fail(DD_EINVAL, "NULL argument");
   UN_HIP(hipMemcpy(host_out, u->g.p, sizeof(float) * u->n_params, hipMemcpyDeviceToHost),
@@ -653,7 +671,7 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
     UN_HIP(x.ensure(sizeof(float) * chunk * NPX * CIN), "device allocation");
     UN_HIP(own.ensure(sizeof(float) * chunk * NPX), "device allocation");
     if ((rc = ensure_capacity(*u, chunk, false)) != DD_OK) return rc;
-    UN_HIP(spot.ensure(sizeof(double) * nok * S), "device allocation");
+    UN_HIP(spot.ensure(sizeof(double) * nok * kJudge.w * kJudge.h), "device allocation");
     UN_HIP(rel.ensure(sizeof(double) * nok), "device allocation");
     if (!u->judge_stream)
       UN_HIP(hipStreamCreateWithFlags(&u->judge_stream, hipStreamNonBlocking), "stream creation");
@@ -671,20 +689,21 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
                         d_out.as<double*>() + b0, st),
              "prediction output");
     }
-    // 2. judge: the exact middle row (row 31) of every predicted map, planned
-    // on the host and run on the judge stream while the network runs
-    const int row = 31;
+    // 2. judge: the exact values of every predicted map on the 8 x 8 probe
+    // sub-grid of stride 9 (rows and columns 0, 9, ..., 63: corners, borders
+    // and interior, 1/64 of the map's pairs), planned on the host and run on
+    // the judge stream while the network runs
     std::vector<dd_scan*> sub(nok);
     for (size_t q = 0; q < nok; ++q) sub[q] = scans[ok_idx[q]];
     std::vector<double*> rows(nok);
-    for (size_t q = 0; q < nok; ++q) rows[q] = spot.as<double>() + q * S;
+    for (size_t q = 0; q < nok; ++q) rows[q] = spot.as<double>() + q * kJudge.w * kJudge.h;
     rc = run_batch(sub.data(), (int32_t)nok, DD_Q_FINAL_AT_PROBES, mixed, rows.data(), 1,
-                   u->judge_stream, row, 1);
+                   u->judge_stream, kJudge);
     if (rc != DD_OK) return rc;
     UN_HIP(hipEventRecord(u->judge_done, u->judge_stream), "event record");
     UN_HIP(hipStreamWaitEvent(st, u->judge_done, 0), "stream wait");
-    UN_HIP(nn::spot(d_out.as<const double*>(), spot.as<double>(), (int)nok, S, row,
-                    rel.as<double>(), st),
+    UN_HIP(nn::spot(d_out.as<const double*>(), spot.as<double>(), (int)nok, S, kJudge.x0,
+                    kJudge.y0, kJudge.step, kJudge.w, kJudge.h, rel.as<double>(), st),
            "spot check");
     std::vector<double> relh(nok);
     UN_HIP(hipMemcpyAsync(relh.data(), rel.p, sizeof(double) * nok, hipMemcpyDeviceToHost, st),
@@ -705,7 +724,7 @@ dd_status dd_unet_predict(dd_unet* u, dd_scan* const* scans, int32_t n, double s
       used_fallback[fb_idx[q]] = 1;
     }
     rc = run_batch(sub.data(), (int32_t)sub.size(), DD_Q_FINAL_AT_PROBES, mixed, outs.data(), 1, st,
-                   0, -1);
+                   MapSel{});
     if (rc != DD_OK) return rc;
   }
   UN_HIP(hipStreamSynchronize(st), "synchronize");

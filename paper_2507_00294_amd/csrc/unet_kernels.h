@@ -90,8 +90,11 @@ hipError_t output(const float* y, const float* own, int nb, int npx, const doubl
                   double* const* out, hipStream_t st);
 hipError_t target(const double* psi, int64_t n, int64_t per_map, const double* pref, float* t,
                   hipStream_t st);
-hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int row,
-                double* rel, hipStream_t st);
+// Relative L2 error per map of the predicted values on the probe sub-grid
+// (x0 + step u, y0 + step v), u < w, v < h, of side x side maps against the
+// exact values exact[map][v w + u].
+hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int x0,
+                int y0, int step, int w, int h, double* rel, hipStream_t st);
 hipError_t fill(float* x, int64_t n, float v, hipStream_t st);
 
 }  // namespace nn

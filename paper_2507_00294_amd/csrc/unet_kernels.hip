@@ -493,24 +493,26 @@ __global__ void __launch_bounds__(256) k_target(const double* __restrict__ psi, 
 // (side x side) and the exact row exact[b side ..]; one wave per map,
 // fixed-order sums.
 __global__ void __launch_bounds__(64) k_spot(const double* const* __restrict__ pred,
-                                             const double* __restrict__ exact, int side, int row,
+                                             const double* __restrict__ exact, int side, int x0,
+                                             int y0, int step, int w, int h,
                                              double* __restrict__ rel) {
   __shared__ double a[64], b[64];
   const int m = blockIdx.x;
   double num = 0.0, den = 0.0;
-  for (int c = threadIdx.x; c < side; c += 64) {
-    const double e = exact[(int64_t)m * side + c];
-    const double d = pred[m][(int64_t)row * side + c] - e;
+  for (int c = threadIdx.x; c < w * h; c += 64) {
+    const int u = c % w, v = c / w;
+    const double e = exact[(int64_t)m * w * h + c];
+    const double d = pred[m][(int64_t)(y0 + step * v) * side + x0 + step * u] - e;
     num += d * d;
     den += e * e;
   }
   a[threadIdx.x] = num;
   b[threadIdx.x] = den;
   __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      a[threadIdx.x] += a[threadIdx.x + w];
-      b[threadIdx.x] += b[threadIdx.x + w];
+  for (int s = 32; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      a[threadIdx.x] += a[threadIdx.x + s];
+      b[threadIdx.x] += b[threadIdx.x + s];
     }
     __syncthreads();
   }
@@ -681,9 +683,10 @@ hipError_t target(const double* psi, int64_t n, int64_t per_map, const double* p
   return hipGetLastError();
 }
 
-hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int row,
-                double* rel, hipStream_t st) {
-  hipLaunchKernelGGL(k_spot, dim3(maps), dim3(64), 0, st, pred, exact, side, row, rel);
+hipError_t spot(const double* const* pred, const double* exact, int maps, int side, int x0,
+                int y0, int step, int w, int h, double* rel, hipStream_t st) {
+  hipLaunchKernelGGL(k_spot, dim3(maps), dim3(64), 0, st, pred, exact, side, x0, y0, step, w, h,
+                     rel);
   return hipGetLastError();
 }
 

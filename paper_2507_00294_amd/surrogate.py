@@ -68,21 +68,95 @@ def generate(specs, precision="mixed", chunk=256, keep_psi=False):
     return out + (torch.cat(ps),) if keep_psi else out
 
 
-def train(net, x, own, t, steps, batch=32, lr=1e-3, lr_end=1e-5, seed=0, log_every=200,
-          warmup=300, clip=1.0, augment=True, anchor=1.0):
-    """Adam with linear warm-up, cosine decay and global-norm clipping on
-    mini-batches drawn without replacement (each under a random symmetry of
-    the square when `augment`); returns the loss history [(step, loss)]."""
+# ---------------------------------------------------------------------------
+# Checkpoints: everything a training step reads -- the parameters, Adam's
+# moments and step count, the mini-batch sampler (generator state, the current
+# permutation and the position in it), the next step, the learning-rate
+# scale and the rollbacks taken -- plus the run's settings.  One .npz file of
+# plain arrays (no pickles), replaced atomically.
+
+CKPT_VERSION = 1
+
+
+def write_checkpoint(path: str, arrays: dict) -> None:
+    """Writes the arrays to `path` (.npz) through a temporary file that
+    replaces the old checkpoint only once it is complete."""
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, version=np.array(CKPT_VERSION, np.int64), **arrays)
+    os.replace(tmp, path)
+
+
+def read_checkpoint(path: str) -> dict:
+    with np.load(path, allow_pickle=False) as z:
+        out = {k: z[k] for k in z.files}
+    if int(out.get("version", -1)) != CKPT_VERSION:
+        raise ValueError(f"{path}: not a version-{CKPT_VERSION} surrogate checkpoint")
+    return out
+
+
+def check_settings(saved: dict, current: dict) -> None:
+    """A checkpoint resumes only the run it was written by."""
+    diff = {k: (saved.get(k), v) for k, v in current.items() if saved.get(k) != v}
+    if diff:
+        raise ValueError(f"checkpoint belongs to another run: {diff}")
+
+
+def _save_state(path, net, g, perm, pos, step, lr_scale, rollbacks, settings):
+    m, v, astep = net.adam_state()
+    write_checkpoint(path, dict(
+        params=net.params(), adam_m=m, adam_v=v, adam_step=np.array(astep, np.int64),
+        rng=g.get_state().numpy(), perm=perm.cpu().numpy(), pos=np.array(pos, np.int64),
+        step=np.array(step, np.int64), lr_scale=np.array(lr_scale, np.float64),
+        rollbacks=np.array(rollbacks, np.int64), settings=np.array(json.dumps(settings))))
+
+
+def _load_state(path, net, g, settings):
     import torch
 
+    c = read_checkpoint(path)
+    check_settings(json.loads(str(c["settings"])), settings)
+    net.set_params(c["params"])
+    net.set_adam_state(c["adam_m"], c["adam_v"], int(c["adam_step"]))
+    g.set_state(torch.from_numpy(c["rng"]))
+    perm = torch.from_numpy(c["perm"]).to("cuda")
+    return perm, int(c["pos"]), int(c["step"]), float(c["lr_scale"]), int(c["rollbacks"])
+
+
+def train(net, x, own, t, steps, batch=32, lr=1e-3, lr_end=1e-5, seed=0, log_every=200,
+          warmup=300, clip=1.0, augment=True, anchor=1.0, checkpoint=None,
+          checkpoint_every=1000, resume=False, stop_at=None, max_rollbacks=5, callback=None):
+    """Adam with linear warm-up, cosine decay and global-norm clipping on
+    mini-batches drawn without replacement (each under a random symmetry of
+    the square when `augment`); returns the loss history [(step, loss)],
+    where a step discarded by a rollback has the loss NaN.
+
+    With `checkpoint` (a path), the training state is written there every
+    `checkpoint_every` steps and at the end, and `resume` continues a run
+    from it bit for bit.  Whenever a computed loss or gradient norm is not
+    finite, the run rolls back to the last checkpoint and continues with
+    half the learning rate (at most `max_rollbacks` times, then it raises).
+    `stop_at` ends the call after that step (the checkpoint then holds the
+    run, e.g. for jobs in time slices); `callback(step, net)` runs after
+    every step."""
+    import torch
+
+    n = x.shape[0]
+    settings = dict(steps=steps, batch=batch, lr=lr, lr_end=lr_end, seed=seed, warmup=warmup,
+                    clip=clip, augment=bool(augment), anchor=anchor, maps=int(n))
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
-    n = x.shape[0]
-    hist = []
     perm = torch.randperm(n, device="cuda", generator=g).to(torch.int32)
-    pos = 0
+    pos, step, lr_scale, rollbacks = 0, 0, 1.0, 0
+    if checkpoint and resume and os.path.exists(checkpoint):
+        perm, pos, step, lr_scale, rollbacks = _load_state(checkpoint, net, g, settings)
+        log(f"[surrogate] resumed at step {step} (lr scale {lr_scale}, {rollbacks} rollbacks)")
+    elif checkpoint:
+        _save_state(checkpoint, net, g, perm, pos, step, lr_scale, rollbacks, settings)
+    hist = []
     t0 = time.time()
-    for step in range(steps):
+    end = steps if stop_at is None else min(steps, stop_at)
+    while step < end:
         if pos + batch > n:
             perm = torch.randperm(n, device="cuda", generator=g).to(torch.int32)
             pos = 0
@@ -94,18 +168,42 @@ def train(net, x, own, t, steps, batch=32, lr=1e-3, lr_end=1e-5, seed=0, log_eve
             tf = torch.zeros(batch, device="cuda", dtype=torch.int32)
         xb, ob, tb = surrogate_batch(x, own, t, idx, tf)
         y = net.forward(xb, train=True)
-        want = (step % log_every == 0) or step == steps - 1
+        save = checkpoint is not None and ((step + 1) % checkpoint_every == 0 or step + 1 == end)
+        want = (step % log_every == 0) or step == steps - 1 or save
         loss, dy = net.loss(y, ob, tb, anchor=anchor, want_loss=want)
         net.backward(dy)
         frac = step / max(steps - 1, 1)
         rate = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac))
         if step < warmup:
             rate *= (step + 1) / warmup
+        rate *= lr_scale
         norm = net.adam(rate, clip=clip, want_norm=want)
+        step += 1
+        if callback is not None:
+            callback(step, net)
+        if want and not (math.isfinite(loss) and math.isfinite(norm)):
+            if checkpoint is None:
+                raise FloatingPointError(f"non-finite loss {loss} or gradient norm {norm} at "
+                                         f"step {step - 1} (no checkpoint to roll back to)")
+            if rollbacks >= max_rollbacks:
+                raise FloatingPointError(f"non-finite loss at step {step - 1} after "
+                                         f"{rollbacks} rollbacks")
+            bad = step - 1
+            perm, pos, step, lr_scale, rollbacks = _load_state(checkpoint, net, g, settings)
+            lr_scale *= 0.5
+            rollbacks += 1
+            hist.append((bad, float("nan")))  # the discarded step
+            log(f"[surrogate] non-finite loss ({loss}) or gradient norm ({norm}) at step {bad}: "
+                f"rolled back to step {step}, learning rate x{lr_scale}")
+            _save_state(checkpoint, net, g, perm, pos, step, lr_scale, rollbacks, settings)
+            continue
         if want:
-            hist.append((step, loss))
-            log(f"[surrogate] step {step} loss {loss:.4e} (rel L2 {math.sqrt(loss):.4f}) "
-                f"|g| {norm:.3e} lr {rate:.2e} ({time.time() - t0:.1f} s)")
+            hist.append((step - 1, loss))
+            if (step - 1) % log_every == 0 or step == steps:
+                log(f"[surrogate] step {step - 1} loss {loss:.4e} (rel L2 {math.sqrt(loss):.4f}) "
+                    f"|g| {norm:.3e} lr {rate:.2e} ({time.time() - t0:.1f} s)")
+        if save:
+            _save_state(checkpoint, net, g, perm, pos, step, lr_scale, rollbacks, settings)
     return hist
 
 
@@ -127,8 +225,10 @@ def rel_l2(pred, exact):
     return (d / exact.flatten(1).norm(dim=1)).cpu().numpy()
 
 
-def evaluate(net, specs, spot_tol=0.02, precision="mixed", repeats=3):
-    """Surrogate with fallback vs the exact kernel alone on the same scans."""
+def evaluate(net, specs, spot_tol=0.02, precision="mixed", repeats=3, extra_tols=()):
+    """Surrogate with fallback vs the exact kernel alone on the same scans;
+    `extra_tols` adds the same measurement at other judge tolerances
+    (res["at_spot_tol"][tol])."""
     import torch
 
     scans = [Scan(**s.kwargs()) for s in specs]
@@ -177,6 +277,19 @@ def evaluate(net, specs, spot_tol=0.02, precision="mixed", repeats=3):
         "network_only_rel_l2_max": float(err_raw.max()),
         "network_only_out_of_range": int(fb_raw.sum()),
     }
+    res["at_spot_tol"] = {}
+    for tol in extra_tols:
+        ts = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            psi, fb = net.predict(scans, tol, precision)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        e = rel_l2(psi, exact)
+        res["at_spot_tol"][tol] = {
+            "surrogate_s": float(np.median(ts)), "speedup": float(np.median(te) / np.median(ts)),
+            "fallback_rate": float(fb.mean()), "rel_l2_mean": float(e.mean()),
+            "rel_l2_p95": float(np.percentile(e, 95)), "rel_l2_max": float(e.max())}
     for s in scans:
         s.close()
     return res
@@ -203,6 +316,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--spot-tol", type=float, default=0.02)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--checkpoint", default="",
+                    help="training state file (.npz), written every --checkpoint-every steps; "
+                         "non-finite losses roll back to it")
+    ap.add_argument("--checkpoint-every", type=int, default=1000)
+    ap.add_argument("--resume", action="store_true", help="continue the run in --checkpoint")
     ap.add_argument("--report", default="")
     ap.add_argument("--eval-only", action="store_true",
                     help="load --weights and only evaluate on the test maps")
@@ -251,7 +369,9 @@ def main(argv=None):
     net = UNet(args.seed)
     init_head(net, own, t)
     t1 = time.time()
-    hist = train(net, x, own, t, args.steps, args.batch, args.lr, seed=args.seed, clip=args.clip)
+    hist = train(net, x, own, t, args.steps, args.batch, args.lr, seed=args.seed, clip=args.clip,
+                 checkpoint=args.checkpoint or None, checkpoint_every=args.checkpoint_every,
+                 resume=args.resume)
     torch.cuda.synchronize()
     train_s = time.time() - t1
     save_weights(net, args.weights)
