@@ -62,7 +62,15 @@ typedef enum {
   DD_EXPLICIT = 4      /* caller-supplied probe ids, repeats allowed           */
 } dd_order;
 
-typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
+typedef enum {
+  DD_FP64 = 0,
+  DD_MIXED = 1,
+  /* bounds of the type only: every int32 value is a value of dd_precision, so
+   * a call can read whatever the caller passes and rejects values other than
+   * DD_FP64 and DD_MIXED with DD_EINVAL                                    */
+  DD_PRECISION_RANGE_MIN = -2147483647 - 1,
+  DD_PRECISION_RANGE_MAX = 2147483647
+} dd_precision;
 
 /* Scan description (Sec. II assumptions: deposition rate Q0, constant D,
  * Gaussian probe of per-axis standard deviation sigma = r_s).  Visit v

@@ -20,7 +20,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ddo.c")
-_LIB_PATH = os.path.join(_HERE, "libddo.so")
+# DDO_LIBRARY names another build of ddo.c (the sanitizer run); it is used as is
+_LIB_PATH = os.environ.get("DDO_LIBRARY") or os.path.join(_HERE, "libddo.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -29,6 +30,8 @@ RASTER, INTERLEAVED, RANDOM, MULTIFRAME = 0, 1, 2, 3
 
 def build(force: bool = False) -> str:
     """Compile ddo.c with gcc into oracle/libddo.so (plain -O2, no fast-math)."""
+    if os.environ.get("DDO_LIBRARY"):
+        return _LIB_PATH
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
         os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "ddo.h"))
     ):

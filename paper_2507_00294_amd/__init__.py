@@ -18,7 +18,8 @@ from typing import Iterable, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdd.so")
+# DD_LIBRARY names another build of the library (the host-sanitizer run)
+LIB_PATH = os.environ.get("DD_LIBRARY") or os.path.join(_HERE, "libdd.so")
 
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_EUNSUPPORTED = 0, -1, -2, -3, -4
 ORDERS = {"raster": 0, "interleaved": 1, "random": 2, "multiframe": 3, "explicit": 4}
