@@ -1,13 +1,19 @@
-// dd_visits.hip -- FP64 kernels of the general visit list (per-visit
+// dd_visits.hip -- kernels of the general visit list (per-visit
 // position, start time and dwell; Eqs. 1-4 per visit, summed by Eq. 6).
 //
 // Pair term.  With b_hat = 2 + 4 D lag / sigma^2 (the b of Eqs. 1-2 over
 // sigma^2), b0 at the end of the visit's beam-on time seen from t and b1 at
 // its start, x1 = a/b1 < x0 = a/b0 and dx = x0 - x1 = a db / (b0 b1):
 //   E1(x1) - E1(x0) = integral of e^-u / u over [x1, x0]
-// and, at a = 0, ln(b1/b0) (Eqs. 3-4).  Every visit has its own b0 and db,
-// so the per-lag series rows of the uniform scan do not exist here; the
-// term is evaluated per pair in one of four forms:
+// and, at a = 0, ln(b1/b0) (Eqs. 3-4).
+//
+// Maps (k_visit_map): every pixel of a map shares its time, so each visit
+// has one b0 and db for the whole map and its term is a series in dx with
+// coefficients of the visit alone (dd_visit_rows.h), built once per visit
+// and tile, as the scan's lag rows are once per lag.
+//
+// Arrival (k_visit_pairs): every pair has its own b0 and db, and the term
+// is evaluated per pair in one of four forms:
 //   * x1 > 745: zero (both E1 values below the double range);
 //   * dx > 1: the difference of the two E1 values (series or continued
 //     fraction), which differ by more than a factor e^-dx;
@@ -25,46 +31,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
+#include <type_traits>
 
 #include "dd_device.h"
+#include "dd_visit_rows.h"
 #include "dd_visits.h"
 
 namespace dd {
 
 namespace {
-
-// Gauss-Legendre rule of N nodes on [0, 1] (nodes x, weights w summing to
-// 1), computed at compile time: Newton iteration on P_N from the usual
-// cosine estimates, then the weights 1 / ((1 - z^2) P_N'(z)^2) halved.
-constexpr double ccos(double x) {
-  double t = 1.0, s = 1.0;
-  for (int k = 1; k < 30; ++k) {
-    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
-    s += t;
-  }
-  return s;
-}
-template <int N>
-struct GLRule {
-  double x[N], w[N];
-  constexpr GLRule() : x(), w() {
-    for (int i = 0; i < N; ++i) {
-      double z = ccos(3.141592653589793 * (i + 0.75) / (N + 0.5)), dp = 1.0;
-      for (int it = 0; it < 12; ++it) {
-        double p0 = 1.0, p1 = z;
-        for (int k = 1; k < N; ++k) {
-          const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
-          p0 = p1;
-          p1 = p2;
-        }
-        dp = N * (z * p1 - p0) / (z * z - 1.0);
-        if (it < 11) z -= p1 / dp;
-      }
-      x[i] = 0.5 * (1.0 - z);
-      w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
-    }
-  }
-};
 
 // 1/y for normal y > 0: hardware estimate and two Newton steps.
 __device__ __forceinline__ double rcp64(double y) {
@@ -216,6 +192,425 @@ __device__ __forceinline__ double pair_term(bool active, double x1, double dx, d
   return t;
 }
 
+// ---------------------------------------------------------------------------
+// Map query: per-visit series rows.
+//
+// All pixels of a map share its time, so a visit's b0, db and b1 are the
+// same for every pixel and its pair term is the series of dd_visit_rows.h
+// with coefficients of the visit alone.  A wave takes one item: a tile of up
+// to 256 pixels (4 per lane, pixel lane + 64 k) against the item's visits,
+// 64 at a time.  Lane j builds visit j's row in the wave's LDS block, with
+// the degree the tile needs; then every lane adds the 64 visits' terms to
+// its 4 pixels, reading each row as a broadcast.  Per pair: a in metres^2
+// from the positions (the row carries 1/sigma^2), x1 log2(e) and dx as
+// products with the row, the series in dx and exp(-x1).
+//
+// Row degree: the largest dx of a contributing pair of the tile,
+// dx_max = min(a_max c, cull q) (a_max over the tile's bounding box; a pair
+// beyond the cull, x1 > cull, has dx = x1 q > cull q), gives the degree by
+// series_degree at min(dx_max, threshold).  A row with dx_max above the
+// series threshold (1 in FP64, 0.25 mixed) is general: a wave with a
+// contributing pair above the threshold takes the general form (pair_term)
+// for that visit.  Pairs beyond the cull stay in the series with dx clamped
+// to the row's bound, where exp(-x1) makes them vanish (below 2^-1074 in
+// FP64, e^-100 in FP32).  A visit beyond the cull for the whole box of the
+// tile is skipped.
+
+constexpr int kMapWaves = 4;            // waves per block, one item each
+constexpr int kMapPix = kVisTile / 64;   // pixels per lane
+// Row kinds: the degree M (bits 0-4) of a lean row, with flags; negative:
+// no term for the tile.
+constexpr int kRowNotStarted = -1;  // the visit starts at or after t
+constexpr int kRowCulled = -2;      // x1 > cull for the whole tile
+constexpr int kRowCareful = 32;     // clamps, and the per-pair far form
+constexpr int kRowP0 = 64;          // mixed: exponent correction through P_0
+// A lean row: every pixel of the tile has dx <= threshold and
+// x1 log2(e) <= kLeanY (FP64: 2^-y by exp2_lean without a clamp; mixed: y
+// converts to a finite FP32 value), so its pairs need no clamp.
+template <bool MIXED>
+constexpr double kLeanY = MIXED ? 1e30 : 1000.0;
+
+// 1/k (k = 1 .. 63) and (-1)^m / m! (m = 0 .. 23), in constant memory.
+struct RowConst {
+  double inv[64];
+  double sfac[24];
+};
+__constant__ RowConst kRowConst = [] {
+  RowConst c{};
+  for (int k = 1; k < 64; ++k) c.inv[k] = 1.0 / k;
+  double f = 1.0;
+  for (int m = 0; m < 24; ++m) {
+    if (m > 0) f *= m;
+    c.sfac[m] = ((m & 1) ? -1.0 : 1.0) / f;
+  }
+  return c;
+}();
+
+// A visit's row for one tile, in the wave's LDS block.
+template <bool MIXED>
+struct MapRow {
+  using T = typename std::conditional<MIXED, float, double>::type;
+  double vx, vy;  // visit position (m)
+  double R;       // log2(e) / (b1 sigma^2): x1 log2(e) = a_m R
+  double rb1s;    // 1 / (b1 sigma^2): x1 = a_m rb1s
+  T c2;           // db / (b0 b1 sigma^2): dx = a_m c2
+  T zmax;         // dx bound of the series, min(dx_max, threshold)
+  T p0n;          // -ln2 P_0 (mixed)
+  int32_t kind;
+  T P[(MIXED ? kM32 : kM64) + 1];
+};
+
+// Row of visit v for the tile with bounding box (xlo, xhi, ylo, yhi) at
+// time t, written into `row` (LDS) field by field; returns its kind.
+template <bool MIXED>
+__device__ __forceinline__ int build_map_row(const double4 v, double t, double th4, double is2,
+                                             const double4 box, MapRow<MIXED>* row) {
+  constexpr int MM = MIXED ? kM32 : kM64;
+  constexpr double thr = MIXED ? (double)kThr32 : kThr64;
+  constexpr double target = MIXED ? kTrunc32 : kTrunc64;
+  constexpr double cull = MIXED ? kCullX32 : kCullX64;
+  using T = typename MapRow<MIXED>::T;
+  row->vx = v.x;
+  row->vy = v.y;
+  const double dt = t - v.z;
+  if (!(dt > 0.0)) return row->kind = kRowNotStarted;
+  const double on = fmin(dt, v.w), off = dt - on;
+  const double b0 = fma(th4, off, 2.0), db = th4 * on, b1 = b0 + db;
+  const double q = db / b0, rb1s = is2 / b1, c2 = q * rb1s;
+  // nearest point of the box: every pixel beyond the cull (a margin of
+  // 1e-9 keeps roundings on the safe side)
+  const double gx = fmax(0.0, fmax(box.x - v.x, v.x - box.y));
+  const double gy = fmax(0.0, fmax(box.z - v.y, v.y - box.w));
+  if (fma(gx, gx, gy * gy) * rb1s > cull * (1.0 + 1e-9)) return row->kind = kRowCulled;
+  const double fx = fmax(fabs(box.x - v.x), fabs(box.y - v.x));
+  const double fy = fmax(fabs(box.z - v.y), fabs(box.w - v.y));
+  const double amax = fma(fx, fx, fy * fy);
+  const double zmax = fmin(fmin(amax * c2, cull * q), thr);
+  const double R = rb1s * kLog2e;
+  row->R = R;
+  row->rb1s = rb1s;
+  row->c2 = (T)c2;
+  row->zmax = (T)zmax;
+  // P_m = (-1)^m q J_m / m! with J_m by the regime of q (dd_visit_rows.h)
+  if (q <= 0.25) {
+    // downwards from J_N = 1/(N+1), constants from the table (a loop, not
+    // unrolled: 45 FP64 constants held in registers would crowd the pair
+    // loop's)
+    constexpr int N = MM + 28;
+    double j = kRowConst.inv[N + 1];
+#pragma unroll 1
+    for (int m = N - 1; m >= 0; --m) {
+      j = fma(-q, j, kRowConst.inv[m + 1]);
+      if (m <= MM) row->P[m] = (T)(kRowConst.sfac[m] * q * j);
+    }
+  } else if (q <= 1.0) {
+    // 24-node Gauss-Legendre rule on [0, 1], one coefficient at a time
+    constexpr GLRule<24> g{};
+#pragma unroll 1
+    for (int m = 0; m <= MM; ++m) {
+      double J = 0.0;
+#pragma unroll 4
+      for (int k = 0; k < 24; ++k) {
+        const double u = g.x[k];
+        double um = 1.0;
+        for (int i = 0; i < m; ++i) um *= u;
+        J = fma(g.w[k] / fma(q, u, 1.0), um, J);
+      }
+      row->P[m] = (T)(kRowConst.sfac[m] * q * J);
+    }
+  } else {
+    // upwards from J_0 = ln(1 + q)/q
+    const double rq = 1.0 / q;
+    double j = log1p(q) * rq;
+#pragma unroll 1
+    for (int m = 0; m <= MM; ++m) {
+      row->P[m] = (T)(kRowConst.sfac[m] * q * j);
+      j = (kRowConst.inv[m + 1] - j) * rq;
+    }
+  }
+  int kind;
+  if (!(amax * c2 <= thr && amax * R <= kLeanY<MIXED>)) {
+    kind = kRowCareful | MM;
+  } else {
+    kind = series_degree<MM>(zmax, target);
+    // mixed: the P_0 form of the exponent correction (as in the scan's
+    // bulk) where dx <= 0.01: its neglected part is below |eps| dx / 2 < 1e-8
+    if (MIXED && kind <= 3 && zmax <= 0.01) kind |= kRowP0;
+  }
+  row->p0n = (T)(-kLn2 * (double)row->P[0]);
+  return row->kind = kind;
+}
+
+// 2^-y for 0 <= y <= 1000 in double precision: y = n - h, n = rint(y),
+// 2^h = sum_k (h ln2)^k / k! by its Taylor polynomial in h (|h ln2| <=
+// 0.347, degree 11: relative remainder < 1.3e-14, as exp2_neg).
+struct Exp2Coef {
+  double c[12];
+  constexpr Exp2Coef() : c() {
+    double v = 1.0;
+    for (int k = 0; k < 12; ++k) {
+      c[k] = v;
+      v *= kLn2 / (k + 1);
+    }
+  }
+};
+__device__ __forceinline__ double exp2_lean(double y) {
+  constexpr Exp2Coef e{};
+  const double n = __builtin_rint(y);
+  const double h = n - y;
+  double p = e.c[11];
+#pragma unroll
+  for (int k = 10; k >= 0; --k) p = fma(p, h, e.c[k]);
+  return __builtin_ldexp(p, -(int)n);
+}
+
+__device__ __forceinline__ void map_am(const double (&px)[kMapPix], const double (&py)[kMapPix],
+                                       double vx, double vy, double (&am)[kMapPix]) {
+#pragma unroll
+  for (int k = 0; k < kMapPix; ++k) {
+    const double ex = px[k] - vx, ey = py[k] - vy;
+    am[k] = fma(ex, ex, ey * ey);
+  }
+}
+
+// A run of lean rows of one kind (degree M): visits j0 .. j1-1, the terms
+// added to acc (mixed: each term in FP32, converted).
+template <int M, bool MIXED, bool P0C>
+__device__ __forceinline__ void map_lean_run(const MapRow<MIXED>* __restrict__ rows, int j0,
+                                             int j1, const double (&px)[kMapPix],
+                                             const double (&py)[kMapPix],
+                                             double (&acc)[kMapPix]) {
+  using T = typename MapRow<MIXED>::T;
+  for (int j = j0; j < j1; ++j) {
+    const MapRow<MIXED>* r = rows + j;
+    double am[kMapPix];
+    map_am(px, py, r->vx, r->vy, am);
+    const double R = r->R;
+    const T c2 = r->c2;
+    T P[M + 1];
+#pragma unroll
+    for (int m = 0; m <= M; ++m) P[m] = r->P[m];
+#pragma unroll
+    for (int k = 0; k < kMapPix; ++k) {
+      if constexpr (MIXED) {
+        const double y = am[k] * R;
+        const float yh = (float)y;
+        const float yl = (float)(y - (double)yh);
+        const float z = (float)am[k] * c2;
+        float s = P[M];
+#pragma unroll
+        for (int m = M - 1; m >= 0; --m) s = __builtin_fmaf(s, z, P[m]);
+        if constexpr (P0C)
+          s = __builtin_fmaf(r->p0n, yl, s);
+        else
+          s = __builtin_fmaf(s, yl * (float)(-kLn2), s);
+        acc[k] += (double)(__builtin_amdgcn_exp2f(-yh) * s);
+      } else {
+        const double z = am[k] * c2;
+        double s = P[M];
+#pragma unroll
+        for (int m = M - 1; m >= 0; --m) s = fma(s, z, P[m]);
+        acc[k] = fma(exp2_lean(am[k] * R), s, acc[k]);
+      }
+    }
+  }
+}
+
+// A run of careful rows: the clamped series of degree MM at every pixel,
+// and, in each pixel slot where some lane has a contributing pair with dx
+// above the series threshold, the direct difference E1(x1) - E1(x0) for
+// those lanes: the two E1 values differ by more than a factor e^thr there,
+// so the difference keeps its digits (the general form of the scan's lag
+// rows, phi_general_*).
+template <bool MIXED>
+__device__ __forceinline__ void map_careful_run(const MapRow<MIXED>* __restrict__ rows, int j0,
+                                                int j1, const double (&px)[kMapPix],
+                                                const double (&py)[kMapPix],
+                                                const bool (&live)[kMapPix],
+                                                double (&acc)[kMapPix]) {
+  constexpr int MM = MIXED ? kM32 : kM64;
+  constexpr double thr = MIXED ? (double)kThr32 : kThr64;
+  constexpr double cull = MIXED ? kCullX32 : kCullX64;
+  for (int j = j0; j < j1; ++j) {
+    const MapRow<MIXED>* r = rows + j;
+    double am[kMapPix];
+    map_am(px, py, r->vx, r->vy, am);
+    // pixel slot by slot, not unrolled (rare rows, long code)
+#pragma unroll 1
+    for (int k = 0; k < kMapPix; ++k) {
+      double a = am[0];
+      bool l = live[0];
+#pragma unroll
+      for (int i = 1; i < kMapPix; ++i)
+        if (k == i) {
+          a = am[i];
+          l = live[i];
+        }
+      const double x1 = a * r->rb1s, dx = a * (double)r->c2;
+      const bool far = l && dx > thr && x1 <= cull;
+      double term;
+      if constexpr (MIXED) {
+        const double y = fmin(a * r->R, 4096.0);
+        const float yh = (float)y;
+        const float yl = (float)(y - (double)yh);
+        const float z = fminf((float)a * r->c2, r->zmax);
+        float s = r->P[MM];
+#pragma unroll
+        for (int m = MM - 1; m >= 0; --m) s = __builtin_fmaf(s, z, r->P[m]);
+        s = __builtin_fmaf(s, yl * (float)(-kLn2), s);
+        term = (double)(__builtin_amdgcn_exp2f(-yh) * s);
+      } else {
+        const double z = fmin(dx, r->zmax);
+        double s = r->P[MM];
+#pragma unroll
+        for (int m = MM - 1; m >= 0; --m) s = fma(s, z, r->P[m]);
+        term = exp2_neg<11>(a * r->R) * s;
+      }
+      if (__ballot(far) && far) {
+        const double x0 = x1 + dx;
+        if constexpr (MIXED)
+          term = e1_mixed(x1) - (x0 > 745.0 ? 0.0 : e1_mixed(x0));
+        else
+          term = e1_f64(x1) - (x0 > 745.0 ? 0.0 : e1_f64(x0));
+      }
+#pragma unroll
+      for (int i = 0; i < kMapPix; ++i)
+        if (k == i) acc[i] += term;
+    }
+  }
+}
+
+#define DD_LEAN(MV, P0) \
+  case MV:              \
+    map_lean_run<(MV), MIXED, P0>(rows, j0, j1, px, py, acc); \
+    break;
+
+// One run of rows of kind `kind` (uniform).
+template <bool MIXED>
+__device__ __forceinline__ void map_run(int kind, const MapRow<MIXED>* __restrict__ rows, int j0,
+                                        int j1, const double (&px)[kMapPix],
+                                        const double (&py)[kMapPix],
+                                        const bool (&live)[kMapPix], double (&acc)[kMapPix]) {
+  if (kind < 0) return;
+  if (kind & kRowCareful) {
+    map_careful_run<MIXED>(rows, j0, j1, px, py, live, acc);
+    return;
+  }
+  const int M = kind & 31;
+  if constexpr (MIXED) {
+    if (kind & kRowP0) {
+      switch (M) {
+        DD_LEAN(0, true) DD_LEAN(1, true) DD_LEAN(2, true)
+        default: map_lean_run<3, MIXED, true>(rows, j0, j1, px, py, acc);
+      }
+    } else {
+      switch (M) {
+        DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false)
+        DD_LEAN(3, false) DD_LEAN(4, false) DD_LEAN(5, false)
+        default: map_lean_run<6, MIXED, false>(rows, j0, j1, px, py, acc);
+      }
+    }
+  } else {
+    // degrees rounded up to 1, 2, 3, 4, 6, 8, 11, 14, 17 (a higher degree
+    // is as accurate; fewer variants keep the code small)
+    if (M <= 4) {
+      switch (M) {
+        DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false) DD_LEAN(3, false)
+        default: map_lean_run<4, MIXED, false>(rows, j0, j1, px, py, acc);
+      }
+    } else if (M <= 6) {
+      map_lean_run<6, MIXED, false>(rows, j0, j1, px, py, acc);
+    } else if (M <= 8) {
+      map_lean_run<8, MIXED, false>(rows, j0, j1, px, py, acc);
+    } else if (M <= 11) {
+      map_lean_run<11, MIXED, false>(rows, j0, j1, px, py, acc);
+    } else if (M <= 14) {
+      map_lean_run<14, MIXED, false>(rows, j0, j1, px, py, acc);
+    } else {
+      map_lean_run<17, MIXED, false>(rows, j0, j1, px, py, acc);
+    }
+  }
+}
+#undef DD_LEAN
+
+// Orders a wave's LDS writes before its later reads by other lanes (and
+// the reads before later overwrites): the wave's LDS operations complete in
+// order, so a compiler barrier at wavefront scope suffices.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave w of block b takes items 4 b + w, 4 b + w + 4 gridDim.x, ...  The
+// item's visits go 64 at a time: lane j builds visit j's row in the wave's
+// LDS block, and the rows are taken in runs of equal kind (consecutive
+// visits of a long list share their kind almost always), each run by one
+// loop.
+template <bool MIXED>
+__global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
+    const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
+    const VisItem* __restrict__ items, int64_t n_items, double* __restrict__ partial) {
+  __shared__ MapRow<MIXED> s_rows[kMapWaves][64];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  MapRow<MIXED>* rows = s_rows[w];
+  for (int64_t it = (int64_t)blockIdx.x * kMapWaves + w; it < n_items;
+       it += (int64_t)gridDim.x * kMapWaves) {
+    const VisItem item = items[it];
+    const VisTile tile = tiles[item.tile];
+    const VisList& L = lists[tile.list];
+    const VisGrid grid = L.grid;
+    const double t = L.times[tile.m];
+    const double is2 = L.inv_sigma * L.inv_sigma, th4 = L.th4;
+    double px[kMapPix], py[kMapPix];
+    bool live[kMapPix];
+#pragma unroll
+    for (int k = 0; k < kMapPix; ++k) {
+      const int idx = lane + 64 * k;
+      live[k] = idx < tile.n;
+      const int64_t pix = tile.p0 + (live[k] ? idx : 0);
+      px[k] = grid.x0 + (double)(pix % grid.w) * grid.dx;
+      py[k] = grid.y0 + (double)(pix / grid.w) * grid.dy;
+    }
+    // bounding box of the tile's pixels (the same products as the pixels')
+    const int64_t q0 = tile.p0, q1 = tile.p0 + tile.n - 1;
+    const int64_t r0 = q0 / grid.w, r1 = q1 / grid.w;
+    const int64_t u0 = r0 == r1 ? q0 % grid.w : 0, u1 = r0 == r1 ? q1 % grid.w : grid.w - 1;
+    const double xa = grid.x0 + (double)u0 * grid.dx, xb = grid.x0 + (double)u1 * grid.dx;
+    const double ya = grid.y0 + (double)r0 * grid.dy, yb = grid.y0 + (double)r1 * grid.dy;
+    const double4 box = make_double4(fmin(xa, xb), fmax(xa, xb), fmin(ya, yb), fmax(ya, yb));
+    double acc[kMapPix];
+#pragma unroll
+    for (int k = 0; k < kMapPix; ++k) acc[k] = 0.0;
+    bool done = false;
+    for (int64_t v0 = item.v0; v0 < item.v0 + item.nv && !done; v0 += 64) {
+      const int64_t left = item.v0 + item.nv - v0;
+      const int nk = left < 64 ? (int)left : 64;
+      wave_lds_sync();  // the previous stage's rows are no longer read
+      int mykind = kRowNotStarted;
+      if (lane < nk) mykind = build_map_row<MIXED>(L.vis[v0 + lane], t, th4, is2, box, rows + lane);
+      // visits are in start order: the started ones are a prefix
+      const int ns = __popcll(__ballot(mykind != kRowNotStarted));
+      if (ns < nk) done = true;
+      wave_lds_sync();
+      for (int j = 0; j < ns;) {
+        const int kj = __builtin_amdgcn_readlane(mykind, j);
+        // the run of rows j, j+1, ... of kind kj
+        const uint64_t rest = ~(__ballot(mykind == kj) >> j);
+        const int run = rest == 0 ? 64 - j : __builtin_ctzll(rest);
+        const int j1 = min(j + run, ns);
+        map_run<MIXED>(kj, rows, j, j1, px, py, live, acc);
+        j = j1;
+      }
+    }
+    const int64_t pb = tile.pbase + (int64_t)item.slot * kVisTile;
+#pragma unroll
+    for (int k = 0; k < kMapPix; ++k)
+      if (live[k]) partial[pb + lane + 64 * k] = acc[k];
+  }
+}
+
 // One block per item: 256 points (one per thread) against the item's visits,
 // staged 256 at a time in LDS.  Visits are in start order, so the first one
 // that starts at or after the tile's latest time ends the item for the
@@ -324,18 +719,20 @@ hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const 
                               const VisItem* items, int64_t n_items, double* partial,
                               hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
+  if (map) {
+    const unsigned mb =
+        (unsigned)std::min<int64_t>((n_items + kMapWaves - 1) / kMapWaves, 1 << 20);
+    if (mixed)
+      k_visit_map<true><<<mb, 64 * kMapWaves, 0, st>>>(lists, tiles, items, n_items, partial);
+    else
+      k_visit_map<false><<<mb, 64 * kMapWaves, 0, st>>>(lists, tiles, items, n_items, partial);
+    return hipGetLastError();
+  }
   const unsigned blocks = (unsigned)std::min<int64_t>(n_items, 1 << 20);
-#define DD_VISIT_LAUNCH(M, X)                                                                  \
-  k_visit_pairs<M, X><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial)
-  if (map && mixed)
-    DD_VISIT_LAUNCH(true, true);
-  else if (map)
-    DD_VISIT_LAUNCH(true, false);
-  else if (mixed)
-    DD_VISIT_LAUNCH(false, true);
+  if (mixed)
+    k_visit_pairs<false, true><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
   else
-    DD_VISIT_LAUNCH(false, false);
-#undef DD_VISIT_LAUNCH
+    k_visit_pairs<false, false><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
   return hipGetLastError();
 }
 
