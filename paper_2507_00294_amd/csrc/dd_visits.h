@@ -43,15 +43,17 @@ struct VisList {
 };
 
 // A tile of evaluation points of list `list`.  Arrival: the visits p0 ..
-// p0+n-1 in start order, each at its own position and start time.  Map:
-// pixels p0 .. p0+n-1 of the list's grid at its time index m.  Its partial
-// sums sit at pbase + slot * 256.
+// p0+n-1 in start order, each at its own position and start time.  Map: a
+// block of tw columns and n / tw rows of the list's grid at its time index
+// m, with top-left pixel p0 (row-major index); its point i is pixel p0 +
+// (i / tw) w + i % tw.  Its partial sums sit at pbase + slot * 256.
 struct VisTile {
   int64_t p0;
   int64_t pbase;
   int64_t out0;  // map: output index of the first point
   double tmax;   // latest point time of the tile
   int32_t n, m, slots, list;
+  int32_t tw, pad;  // map: block width
 };
 
 // One work item: a tile against visits v0 .. v0+nv-1 (start order).

@@ -12,8 +12,9 @@
 // coefficients of the visit alone (dd_visit_rows.h), built once per visit
 // and tile, as the scan's lag rows are once per lag.
 //
-// Arrival (k_visit_pairs): every pair has its own b0 and db, and the term
-// is evaluated per pair in one of four forms:
+// Arrival (k_visit_arrival): every pair has its own b0 and db; the bulk of
+// a long list takes a short polynomial (see bulk_term), the rest the
+// general form, one of four per pair:
 //   * x1 > 745: zero (both E1 values below the double range);
 //   * dx > 1: the difference of the two E1 values (series or continued
 //     fraction), which differ by more than a factor e^-dx;
@@ -373,15 +374,18 @@ __device__ __forceinline__ void map_am(const double (&px)[kMapPix], const double
   }
 }
 
-// A run of lean rows of one kind (degree M): visits j0 .. j1-1, the terms
-// added to acc (mixed: each term in FP32, converted).
+// The lean rows of a stage (bit j of `mask`: row j), all at degree M (the
+// stage's highest; a higher degree is as accurate), the terms added to acc
+// (mixed: each term in FP32, converted).
 template <int M, bool MIXED, bool P0C>
-__device__ __forceinline__ void map_lean_run(const MapRow<MIXED>* __restrict__ rows, int j0,
-                                             int j1, const double (&px)[kMapPix],
-                                             const double (&py)[kMapPix],
-                                             double (&acc)[kMapPix]) {
+__device__ __forceinline__ void map_lean_rows(const MapRow<MIXED>* __restrict__ rows,
+                                              uint64_t mask, const double (&px)[kMapPix],
+                                              const double (&py)[kMapPix],
+                                              double (&acc)[kMapPix]) {
   using T = typename MapRow<MIXED>::T;
-  for (int j = j0; j < j1; ++j) {
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
     const MapRow<MIXED>* r = rows + j;
     double am[kMapPix];
     map_am(px, py, r->vx, r->vy, am);
@@ -416,22 +420,24 @@ __device__ __forceinline__ void map_lean_run(const MapRow<MIXED>* __restrict__ r
   }
 }
 
-// A run of careful rows: the clamped series of degree MM at every pixel,
+// The careful rows of a stage (bits of `mask`): the clamped series of degree MM at every pixel,
 // and, in each pixel slot where some lane has a contributing pair with dx
 // above the series threshold, the direct difference E1(x1) - E1(x0) for
 // those lanes: the two E1 values differ by more than a factor e^thr there,
 // so the difference keeps its digits (the general form of the scan's lag
 // rows, phi_general_*).
 template <bool MIXED>
-__device__ __forceinline__ void map_careful_run(const MapRow<MIXED>* __restrict__ rows, int j0,
-                                                int j1, const double (&px)[kMapPix],
-                                                const double (&py)[kMapPix],
-                                                const bool (&live)[kMapPix],
-                                                double (&acc)[kMapPix]) {
+__device__ __forceinline__ void map_careful_rows(const MapRow<MIXED>* __restrict__ rows,
+                                                 uint64_t mask, const double (&px)[kMapPix],
+                                                 const double (&py)[kMapPix],
+                                                 const bool (&live)[kMapPix],
+                                                 double (&acc)[kMapPix]) {
   constexpr int MM = MIXED ? kM32 : kM64;
   constexpr double thr = MIXED ? (double)kThr32 : kThr64;
   constexpr double cull = MIXED ? kCullX32 : kCullX64;
-  for (int j = j0; j < j1; ++j) {
+  while (mask) {
+    const int j = __builtin_ctzll(mask);
+    mask &= mask - 1;
     const MapRow<MIXED>* r = rows + j;
     double am[kMapPix];
     map_am(px, py, r->vx, r->vy, am);
@@ -482,54 +488,53 @@ __device__ __forceinline__ void map_careful_run(const MapRow<MIXED>* __restrict_
 
 #define DD_LEAN(MV, P0) \
   case MV:              \
-    map_lean_run<(MV), MIXED, P0>(rows, j0, j1, px, py, acc); \
+    map_lean_rows<(MV), MIXED, P0>(rows, lean, px, py, acc); \
     break;
 
-// One run of rows of kind `kind` (uniform).
+// One stage of rows: the lean rows (bits of `lean`) at degree M with the
+// P_0 correction form if every one allows it (p0), then the careful rows.
 template <bool MIXED>
-__device__ __forceinline__ void map_run(int kind, const MapRow<MIXED>* __restrict__ rows, int j0,
-                                        int j1, const double (&px)[kMapPix],
-                                        const double (&py)[kMapPix],
-                                        const bool (&live)[kMapPix], double (&acc)[kMapPix]) {
-  if (kind < 0) return;
-  if (kind & kRowCareful) {
-    map_careful_run<MIXED>(rows, j0, j1, px, py, live, acc);
-    return;
-  }
-  const int M = kind & 31;
-  if constexpr (MIXED) {
-    if (kind & kRowP0) {
-      switch (M) {
-        DD_LEAN(0, true) DD_LEAN(1, true) DD_LEAN(2, true)
-        default: map_lean_run<3, MIXED, true>(rows, j0, j1, px, py, acc);
+__device__ __forceinline__ void map_stage(const MapRow<MIXED>* __restrict__ rows, uint64_t lean,
+                                          int M, bool p0, uint64_t careful,
+                                          const double (&px)[kMapPix],
+                                          const double (&py)[kMapPix],
+                                          const bool (&live)[kMapPix], double (&acc)[kMapPix]) {
+  if (lean) {
+    if constexpr (MIXED) {
+      if (p0) {
+        switch (M) {
+          DD_LEAN(0, true) DD_LEAN(1, true) DD_LEAN(2, true)
+          default: map_lean_rows<3, MIXED, true>(rows, lean, px, py, acc);
+        }
+      } else {
+        switch (M) {
+          DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false)
+          DD_LEAN(3, false) DD_LEAN(4, false) DD_LEAN(5, false)
+          default: map_lean_rows<6, MIXED, false>(rows, lean, px, py, acc);
+        }
       }
     } else {
-      switch (M) {
-        DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false)
-        DD_LEAN(3, false) DD_LEAN(4, false) DD_LEAN(5, false)
-        default: map_lean_run<6, MIXED, false>(rows, j0, j1, px, py, acc);
+      // degrees rounded up to 1, 2, 3, 4, 6, 8, 11, 14, 17 (fewer variants
+      // keep the code small)
+      if (M <= 4) {
+        switch (M) {
+          DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false) DD_LEAN(3, false)
+          default: map_lean_rows<4, MIXED, false>(rows, lean, px, py, acc);
+        }
+      } else if (M <= 6) {
+        map_lean_rows<6, MIXED, false>(rows, lean, px, py, acc);
+      } else if (M <= 8) {
+        map_lean_rows<8, MIXED, false>(rows, lean, px, py, acc);
+      } else if (M <= 11) {
+        map_lean_rows<11, MIXED, false>(rows, lean, px, py, acc);
+      } else if (M <= 14) {
+        map_lean_rows<14, MIXED, false>(rows, lean, px, py, acc);
+      } else {
+        map_lean_rows<17, MIXED, false>(rows, lean, px, py, acc);
       }
-    }
-  } else {
-    // degrees rounded up to 1, 2, 3, 4, 6, 8, 11, 14, 17 (a higher degree
-    // is as accurate; fewer variants keep the code small)
-    if (M <= 4) {
-      switch (M) {
-        DD_LEAN(0, false) DD_LEAN(1, false) DD_LEAN(2, false) DD_LEAN(3, false)
-        default: map_lean_run<4, MIXED, false>(rows, j0, j1, px, py, acc);
-      }
-    } else if (M <= 6) {
-      map_lean_run<6, MIXED, false>(rows, j0, j1, px, py, acc);
-    } else if (M <= 8) {
-      map_lean_run<8, MIXED, false>(rows, j0, j1, px, py, acc);
-    } else if (M <= 11) {
-      map_lean_run<11, MIXED, false>(rows, j0, j1, px, py, acc);
-    } else if (M <= 14) {
-      map_lean_run<14, MIXED, false>(rows, j0, j1, px, py, acc);
-    } else {
-      map_lean_run<17, MIXED, false>(rows, j0, j1, px, py, acc);
     }
   }
+  if (careful) map_careful_rows<MIXED>(rows, careful, px, py, live, acc);
 }
 #undef DD_LEAN
 
@@ -544,9 +549,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Wave w of block b takes items 4 b + w, 4 b + w + 4 gridDim.x, ...  The
 // item's visits go 64 at a time: lane j builds visit j's row in the wave's
-// LDS block, and the rows are taken in runs of equal kind (consecutive
-// visits of a long list share their kind almost always), each run by one
-// loop.
+// LDS block; then the stage's lean rows are taken by one loop at their
+// highest degree and its careful rows by another.
 template <bool MIXED>
 __global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
     const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
@@ -563,22 +567,23 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
     const VisGrid grid = L.grid;
     const double t = L.times[tile.m];
     const double is2 = L.inv_sigma * L.inv_sigma, th4 = L.th4;
+    // the tile: a block of tw columns from pixel (u0, v0)
+    const int tw = tile.tw;
+    const int64_t u0 = tile.p0 % grid.w, v0 = tile.p0 / grid.w;
     double px[kMapPix], py[kMapPix];
     bool live[kMapPix];
 #pragma unroll
     for (int k = 0; k < kMapPix; ++k) {
       const int idx = lane + 64 * k;
       live[k] = idx < tile.n;
-      const int64_t pix = tile.p0 + (live[k] ? idx : 0);
-      px[k] = grid.x0 + (double)(pix % grid.w) * grid.dx;
-      py[k] = grid.y0 + (double)(pix / grid.w) * grid.dy;
+      const int i = live[k] ? idx : 0;
+      px[k] = grid.x0 + (double)(u0 + i % tw) * grid.dx;
+      py[k] = grid.y0 + (double)(v0 + i / tw) * grid.dy;
     }
     // bounding box of the tile's pixels (the same products as the pixels')
-    const int64_t q0 = tile.p0, q1 = tile.p0 + tile.n - 1;
-    const int64_t r0 = q0 / grid.w, r1 = q1 / grid.w;
-    const int64_t u0 = r0 == r1 ? q0 % grid.w : 0, u1 = r0 == r1 ? q1 % grid.w : grid.w - 1;
+    const int64_t u1 = u0 + tw - 1, v1 = v0 + (tile.n - 1) / tw;
     const double xa = grid.x0 + (double)u0 * grid.dx, xb = grid.x0 + (double)u1 * grid.dx;
-    const double ya = grid.y0 + (double)r0 * grid.dy, yb = grid.y0 + (double)r1 * grid.dy;
+    const double ya = grid.y0 + (double)v0 * grid.dy, yb = grid.y0 + (double)v1 * grid.dy;
     const double4 box = make_double4(fmin(xa, xb), fmax(xa, xb), fmin(ya, yb), fmax(ya, yb));
     double acc[kMapPix];
 #pragma unroll
@@ -594,15 +599,22 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
       const int ns = __popcll(__ballot(mykind != kRowNotStarted));
       if (ns < nk) done = true;
       wave_lds_sync();
-      for (int j = 0; j < ns;) {
-        const int kj = __builtin_amdgcn_readlane(mykind, j);
-        // the run of rows j, j+1, ... of kind kj
-        const uint64_t rest = ~(__ballot(mykind == kj) >> j);
-        const int run = rest == 0 ? 64 - j : __builtin_ctzll(rest);
-        const int j1 = min(j + run, ns);
-        map_run<MIXED>(kj, rows, j, j1, px, py, live, acc);
-        j = j1;
+      // the stage's lean and careful rows; the lean degree is the highest
+      const bool is_lean = mykind >= 0 && !(mykind & kRowCareful);
+      const uint64_t lean = __ballot(is_lean);
+      const uint64_t careful = __ballot(mykind >= 0 && (mykind & kRowCareful));
+      int M = 0;
+      if (lean) {
+        constexpr int MM = MIXED ? kM32 : kM64;
+        const int mine = is_lean ? (mykind & 31) : 0;
+        for (int m = MM; m > 0; --m)
+          if (__ballot(mine >= m)) {
+            M = m;
+            break;
+          }
       }
+      const bool p0 = MIXED && !__ballot(is_lean && !(mykind & kRowP0));
+      map_stage<MIXED>(rows, lean, M, p0, careful, px, py, live, acc);
     }
     const int64_t pb = tile.pbase + (int64_t)item.slot * kVisTile;
 #pragma unroll
@@ -611,33 +623,145 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Arrival query: the bulk form.
+//
+// With u = db/b1 and v = x1 u (so q = u/(1-u), dx = x1 q = v/(1-u)), the
+// term is e^{-x1} u F(u, v) with
+//   F = int_0^1 exp(-v s/(1-u)) / (1 - u(1-s)) ds = sum_{m,n} C_{m,n} v^m u^n,
+//   C_{m,n} = (-1)^m sum_{k=0..n} binom(m+n-k-1, n-k) k! / (m+k+1)!
+// ((1 - u(1-s))^-1 and (1-u)^-m expanded in u, the exponential in v, and
+// int_0^1 s^m (1-s)^k ds = m! k! / (m+k+1)!).  It needs one reciprocal per
+// pair (1/b1), and for small u and v a short polynomial: on u <= 2^-8,
+// v <= 2^-5 (FP64) the degrees in u for m = 0..6 are 5,5,5,4,3,2,1 with a
+// truncation below 1e-14 of the term; on u <= 2^-6, v <= 2^-5 (mixed, in
+// FP32) the degrees for m = 0..3 are 4,3,3,1, below 2e-8.  A wave whose
+// contributing pairs of a visit are all in that domain takes this form (98%
+// of the visit steps of a long raster list); otherwise the general form
+// (pair_term).
+constexpr double binom_d(int a, int b) {
+  if (b == 0) return 1.0;
+  if (a < b || a < 0) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+  return r;
+}
+struct BulkCoef {
+  double c[8][8];  // C_{m,n}
+  constexpr BulkCoef() : c() {
+    for (int m = 0; m < 8; ++m)
+      for (int n = 0; n < 8; ++n) {
+        double sum = 0.0;
+        for (int k = 0; k <= n; ++k) {
+          double f = 1.0;  // k! / (m+k+1)!
+          for (int i = k + 1; i <= m + k + 1; ++i) f /= i;
+          sum += binom_d(m + n - k - 1, n - k) * f;
+        }
+        c[m][n] = (m & 1) ? -sum : sum;
+      }
+  }
+};
+constexpr double kBulkU64 = 1.0 / 256, kBulkV64 = 1.0 / 32;
+constexpr float kBulkU32 = 1.0f / 64, kBulkV32 = 1.0f / 32;
+
+// F(u, v) by Horner in u per power of v, then in v.
+template <typename T, int NM, int D0, int D1, int D2, int D3, int D4 = -1, int D5 = -1,
+          int D6 = -1>
+__device__ __forceinline__ T bulk_f(T u, T v) {
+  constexpr BulkCoef C{};
+  constexpr int deg[7] = {D0, D1, D2, D3, D4, D5, D6};
+  T acc = 0;
+#pragma unroll
+  for (int m = NM - 1; m >= 0; --m) {
+    T cm = (T)C.c[m][deg[m]];
+#pragma unroll
+    for (int n = deg[m] - 1; n >= 0; --n) cm = cm * u + (T)C.c[m][n];
+    acc = (m == NM - 1) ? cm : acc * v + cm;
+  }
+  return acc;
+}
+
+// The bulk term e^{-x1} u F(u, v) (x1 <= cull).
+template <bool MIXED>
+__device__ __forceinline__ double bulk_term(double x1, double u, double v) {
+  if constexpr (MIXED) {
+    const double y = x1 * kLog2e;
+    const float yh = (float)y;
+    const float yl = (float)(y - (double)yh);
+    const float uf = (float)u, vf = (float)v;
+    float g = bulk_f<float, 4, 4, 3, 3, 1>(uf, vf);
+    g = __builtin_fmaf(g, yl * (float)(-kLn2), g);
+    return (double)(__builtin_amdgcn_exp2f(-yh) * (uf * g));
+  } else {
+    const double g = bulk_f<double, 7, 5, 5, 5, 4, 3, 2, 1>(u, v);
+    return exp2_lean(x1 * kLog2e) * (u * g);
+  }
+}
+
+// One arrival pair (point at (px, py) at time pt, visit v): the quantities
+// of both forms and whether the pair contributes (act) and lies in the bulk
+// domain.
+template <bool MIXED>
+struct ArrPair {
+  double x1, u, w, b0, db;
+  bool act, bulk;
+  __device__ __forceinline__ void setup(const double4 v, double px, double py, double pt,
+                                        bool live, double is2, double th4) {
+    constexpr double cull = MIXED ? kCullX32 : kCullX64;
+    const double lag = pt - v.z;
+    const bool started = live && lag > 0.0;
+    const double lg = started ? lag : v.w;  // a valid lag for idle lanes
+    const double on = fmin(lg, v.w), off = lg - on;
+    b0 = fma(th4, off, 2.0);
+    db = th4 * on;
+    const double r1 = rcp64(b0 + db);
+    const double ex = px - v.x, ey = py - v.y;
+    x1 = fma(ex, ex, ey * ey) * (is2 * r1);
+    u = db * r1;
+    w = x1 * u;
+    act = started && x1 <= cull;
+    bulk = MIXED ? ((float)u <= kBulkU32 && (float)w <= kBulkV32)
+                 : (u <= kBulkU64 && w <= kBulkV64);
+  }
+  __device__ __forceinline__ double bulk_value() const {
+    constexpr double cull = MIXED ? kCullX32 : kCullX64;
+    const double t = bulk_term<MIXED>(fmin(x1, cull), u, fmin(w, 1.0));
+    return act ? t : 0.0;
+  }
+};
+
+// The term of one pair: the bulk form if the wave's contributing pairs of
+// this visit are all in its domain, else the general form.
+template <bool MIXED>
+__device__ __forceinline__ double arr_pair_term(const double4 v, double px, double py, double pt,
+                                                bool live, double is2, double th4) {
+  ArrPair<MIXED> pr;
+  pr.setup(v, px, py, pt, live, is2, th4);
+  if (!__ballot(pr.act && !pr.bulk)) return pr.bulk_value();
+  const double q = pr.db / pr.b0;
+  return pair_term<MIXED>(pr.act, pr.x1, pr.x1 * q, q);
+}
+
 // One block per item: 256 points (one per thread) against the item's visits,
 // staged 256 at a time in LDS.  Visits are in start order, so the first one
 // that starts at or after the tile's latest time ends the item for the
-// whole block.  Map tiles share one time: the per-visit factors (1/b1,
-// db/(b0 b1), db/b0) are then formed once per staged visit.
-template <bool MAP, bool MIXED>
-__global__ __launch_bounds__(kVisTile) void k_visit_pairs(
+// whole block.
+template <bool MIXED>
+__global__ __launch_bounds__(kVisTile) void k_visit_arrival(
     const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
     const VisItem* __restrict__ items, int64_t n_items, double* __restrict__ partial) {
+  constexpr double cull = MIXED ? kCullX32 : kCullX64;
   __shared__ double4 s_v[kVisStage];
-  __shared__ double4 s_f[MAP ? kVisStage : 1];
   const int lane = threadIdx.x;
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const VisItem item = items[it];
     const VisTile tile = tiles[item.tile];
     const VisList& L = lists[tile.list];
     const double4* __restrict__ vis = L.vis;
-    const double inv_sigma = L.inv_sigma, th4 = L.th4;
+    const double is2 = L.inv_sigma * L.inv_sigma, th4 = L.th4;
     const bool live = lane < tile.n;
     double px = 0.0, py = 0.0, pt = tile.tmax;
-    if (MAP) {
-      const VisGrid grid = L.grid;
-      const int64_t pix = tile.p0 + (live ? lane : 0);
-      px = grid.x0 + (double)(pix % grid.w) * grid.dx;
-      py = grid.y0 + (double)(pix / grid.w) * grid.dy;
-      pt = L.times[tile.m];
-    } else if (live) {
+    if (live) {
       const double4 me = vis[tile.p0 + lane];
       px = me.x;
       py = me.y;
@@ -649,48 +773,35 @@ __global__ __launch_bounds__(kVisTile) void k_visit_pairs(
       const int64_t left = item.v0 + item.nv - v0;
       const int nk = left < kVisStage ? (int)left : kVisStage;
       __syncthreads();  // the previous stage is no longer read
-      if (lane < nk) {
-        const double4 v = vis[v0 + lane];
-        s_v[lane] = v;
-        if (MAP) {
-          const double dt = pt - v.z;
-          double4 f = make_double4(-1.0, 0.0, 0.0, 0.0);  // rb1 < 0: not started
-          if (dt > 0.0) {
-            const double on = fmin(dt, v.w), off = dt - on;
-            const double b0 = fma(th4, off, 2.0), db = th4 * on, b1 = b0 + db;
-            const double r0 = rcp64(b0), r1 = rcp64(b1);
-            f = make_double4(r1, db * r0 * r1, db * r0, 0.0);
-          }
-          s_f[lane] = f;
+      if (lane < nk) s_v[lane] = vis[v0 + lane];
+      __syncthreads();
+      int j = 0;
+      // four visits at a time (four independent chains per lane) while all
+      // four start before the tile's latest time and the wave's pairs are
+      // all in the bulk domain
+      for (; j + 4 <= nk && s_v[j + 3].z < tile.tmax; j += 4) {
+        ArrPair<MIXED> pr[4];
+        bool out = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          pr[i].setup(s_v[j + i], px, py, pt, live, is2, th4);
+          out |= pr[i].act && !pr[i].bulk;
+        }
+        if (!__ballot(out)) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) sum += pr[i].bulk_value();
+        } else {
+#pragma unroll 1
+          for (int i = 0; i < 4; ++i) sum += arr_pair_term<MIXED>(s_v[j + i], px, py, pt, live, is2, th4);
         }
       }
-      __syncthreads();
-      for (int j = 0; j < nk; ++j) {
+      for (; j < nk; ++j) {
         const double4 v = s_v[j];
-        if (v.z >= pt && MAP) {
-          done = true;  // uniform: one time for the whole tile
-          break;
-        }
-        if (!MAP && v.z >= tile.tmax) {
+        if (v.z >= tile.tmax) {
           done = true;  // uniform: no later visit starts before any point
           break;
         }
-        const double ex = (px - v.x) * inv_sigma, ey = (py - v.y) * inv_sigma;
-        const double a = fma(ex, ex, ey * ey);
-        if (MAP) {
-          const double4 f = s_f[j];
-          const double x1 = a * f.x;
-          sum += pair_term<MIXED>(live && f.x > 0.0 && x1 <= 745.0, x1, a * f.y, f.z);
-        } else {
-          const double dt = pt - v.z;
-          const bool started = live && dt > 0.0;
-          const double on = fmin(dt, v.w), off = dt - on;
-          const double b0 = fma(th4, off, 2.0), db = th4 * on;
-          const double b1 = b0 + db;
-          const double rr = rcp64(started ? b0 * b1 : 4.0);  // 1 / (b0 b1)
-          const double x1 = a * (b0 * rr), q = db * (b1 * rr);
-          sum += pair_term<MIXED>(started && x1 <= 745.0, x1, x1 * q, q);
-        }
+        sum += arr_pair_term<MIXED>(v, px, py, pt, live, is2, th4);
       }
     }
     if (live) partial[tile.pbase + (int64_t)item.slot * kVisTile + lane] = sum;
@@ -707,7 +818,8 @@ __global__ __launch_bounds__(kVisTile) void k_visit_reduce(const VisList* __rest
   if (lane >= tile.n) return;
   double s = 0.0;
   for (int k = 0; k < tile.slots; ++k) s += partial[tile.pbase + (int64_t)k * kVisTile + lane];
-  const int64_t dst = MAP ? tile.out0 + lane : L.perm[tile.p0 + lane];
+  const int64_t dst = MAP ? tile.out0 + (int64_t)(lane / tile.tw) * L.grid.w + lane % tile.tw
+                          : L.perm[tile.p0 + lane];
   const double v = L.pref * s;
   L.out[dst] = v;
   flag_nonfinite(L.fl, v, dst);
@@ -730,9 +842,9 @@ hipError_t launch_visit_pairs(bool map, bool mixed, const VisList* lists, const 
   }
   const unsigned blocks = (unsigned)std::min<int64_t>(n_items, 1 << 20);
   if (mixed)
-    k_visit_pairs<false, true><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
+    k_visit_arrival<true><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
   else
-    k_visit_pairs<false, false><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
+    k_visit_arrival<false><<<blocks, kVisTile, 0, st>>>(lists, tiles, items, n_items, partial);
   return hipGetLastError();
 }
 

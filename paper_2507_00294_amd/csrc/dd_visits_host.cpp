@@ -122,7 +122,7 @@ struct dd_visits {
   void arrival_tiles(int32_t list, std::vector<VisTile>& tiles) const {
     for (int64_t p0 = 0; p0 < n; p0 += kVisTile) {
       const int64_t p1 = std::min(n, p0 + kVisTile);
-      tiles.push_back(VisTile{p0, 0, 0, vis[p1 - 1].z, (int32_t)(p1 - p0), 0, 0, list});
+      tiles.push_back(VisTile{p0, 0, 0, vis[p1 - 1].z, (int32_t)(p1 - p0), 0, 0, list, 0, 0});
     }
   }
   Box tile_box(const VisTile& t) const {
@@ -185,6 +185,25 @@ dd_status check_call_flag(const OutFlag& fl, const std::vector<int64_t>& off, hi
   const int32_t k = (int32_t)(std::upper_bound(off.begin(), off.end(), bad) - off.begin()) - 1;
   return fail(DD_EDEVICE, "list %d: non-finite output value at index %lld", k,
               (long long)(bad - off[k]));
+}
+
+// Items in launch order: the most recent visits relative to the tile's
+// time first (the pairs of short lags take the costlier forms; started
+// early, they overlap the rest instead of trailing it).  Only the schedule
+// changes: every item keeps its slot, so the sums do not.
+void order_items(dd_visits* const* lists) {
+  VisScratch& W = g_vis;
+  std::vector<std::pair<double, int64_t>> key(W.h_items.size());
+  for (size_t i = 0; i < W.h_items.size(); ++i) {
+    const VisItem& it = W.h_items[i];
+    const VisTile& tile = W.h_tiles[it.tile];
+    const dd_visits* v = lists[tile.list];
+    key[i] = {tile.tmax - v->chunk_t0[it.v0 / v->K], (int64_t)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<VisItem> sorted(W.h_items.size());
+  for (size_t i = 0; i < key.size(); ++i) sorted[i] = W.h_items[key[i].second];
+  W.h_items.swap(sorted);
 }
 
 // Partial sums and reduce of the current tiles and items (one launch group);
@@ -262,22 +281,43 @@ dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* c
       const dd_visits* v = lists[tile.list];
       tile.slots = v->plan_tile((int32_t)t, v->tile_box(tile), tile.tmax, W.h_items);
     }
+    order_items(lists);
     rc = launch_group(false, mixed, st);
     if (rc != DD_OK) return rc;
   }
   return check_call_flag(fl, off, st);
 }
 
+// Map tiles of a w x h grid: blocks of tw = min(w, 16) columns and
+// th = min(h, 256 / tw) rows (a narrow grid takes taller blocks), in
+// row-major block order; a square block keeps the spread of distances from
+// a visit to the tile's pixels small.
+struct MapTiling {
+  int32_t w, h, tw, th, bx, by;
+  explicit MapTiling(const dd_grid& g)
+      : w(g.w), h(g.h), tw(std::min(g.w, 16)), th(std::min(g.h, kVisTile / std::min(g.w, 16))),
+        bx((g.w + tw - 1) / tw), by((g.h + th - 1) / th) {}
+  int64_t count() const { return (int64_t)bx * by; }
+  // top-left pixel and size of block b
+  void block(int64_t b, int32_t& u0, int32_t& v0, int32_t& cw, int32_t& ch) const {
+    u0 = (int32_t)(b % bx) * tw;
+    v0 = (int32_t)(b / bx) * th;
+    cw = std::min(tw, w - u0);
+    ch = std::min(th, h - v0);
+  }
+};
+
 // Maps of lists[k] on grids[k] at times t_s[k][0 .. n_t[k]) into outs[k]
 // (device), all in the same launch groups; each list's tiles and items are
-// planned exactly as for a call of its own (tiles time by time, pixel
-// blocks in order), so the results do not depend on the batch.
+// planned exactly as for a call of its own (tiles time by time, blocks in
+// order), so the results do not depend on the batch.
 dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
                    const double* const* t_s, const int32_t* n_t, bool mixed, double* const* outs,
                    hipStream_t st) {
   VisScratch& W = g_vis;
   std::vector<int64_t> npix(n), per(n), off(n, 0);
   std::vector<std::vector<Box>> boxes(n);
+  std::vector<MapTiling> tiling;
   OutFlag fl;
   dd_status rc0 = call_flag(st, fl);
   if (rc0 != DD_OK) return rc0;
@@ -285,8 +325,9 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
   for (int32_t k = 0; k < n; ++k) {
     const dd_grid* g = &grids[k];
     dd_visits* v = lists[k];
+    tiling.emplace_back(*g);
     npix[k] = (int64_t)g->w * g->h;
-    per[k] = (npix[k] + kVisTile - 1) / kVisTile;  // tiles per time
+    per[k] = tiling[k].count();  // tiles per time
     VIS_HIP(v->d_times.ensure(sizeof(double) * n_t[k]), "device allocation");
     VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s[k], sizeof(double) * n_t[k], hipMemcpyHostToDevice,
                            st),
@@ -298,11 +339,11 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
     // pixel boxes of the tiles (the same at every time)
     boxes[k].resize(per[k]);
     for (int64_t b = 0; b < per[k]; ++b) {
-      const int64_t q0 = b * kVisTile, q1 = std::min(npix[k], q0 + kVisTile) - 1;
-      const int64_t v0 = q0 / g->w, v1 = q1 / g->w;
-      const int64_t u0 = v0 == v1 ? q0 % g->w : 0, u1 = v0 == v1 ? q1 % g->w : g->w - 1;
+      int32_t u0, v0, cw, ch;
+      tiling[k].block(b, u0, v0, cw, ch);
       boxes[k][b].add(g->x0_m + (double)u0 * g->dx_m, g->y0_m + (double)v0 * g->dy_m);
-      boxes[k][b].add(g->x0_m + (double)u1 * g->dx_m, g->y0_m + (double)v1 * g->dy_m);
+      boxes[k][b].add(g->x0_m + (double)(u0 + cw - 1) * g->dx_m,
+                      g->y0_m + (double)(v0 + ch - 1) * g->dy_m);
     }
   }
   dd_status rc = upload_lists(st);
@@ -314,9 +355,11 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
     W.h_items.clear();
     while ((int64_t)W.h_tiles.size() < kGroupTiles && k < n) {
       const int64_t m = local / per[k], b = local % per[k];
-      const int64_t p0 = b * kVisTile, p1 = std::min(npix[k], p0 + kVisTile);
+      int32_t u0, v0, cw, ch;
+      tiling[k].block(b, u0, v0, cw, ch);
+      const int64_t p0 = (int64_t)v0 * grids[k].w + u0;
       const double t = t_s[k][m];
-      VisTile tile{p0, 0, m * npix[k] + p0, t, (int32_t)(p1 - p0), (int32_t)m, 0, k};
+      VisTile tile{p0, 0, m * npix[k] + p0, t, cw * ch, (int32_t)m, 0, k, cw, 0};
       tile.slots = lists[k]->plan_tile((int32_t)W.h_tiles.size(), boxes[k][b], t, W.h_items);
       W.h_tiles.push_back(tile);
       if (++local == per[k] * n_t[k]) {
@@ -324,6 +367,7 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
         local = 0;
       }
     }
+    order_items(lists);
     rc = launch_group(true, mixed, st);
     if (rc != DD_OK) return rc;
   }
