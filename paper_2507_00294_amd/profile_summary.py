@@ -12,6 +12,13 @@
         the record bench.py reads (valid while the device sources hash to the
         recorded value).
 
+    python -m paper_2507_00294_amd.profile_summary visits <out.md> <trace_dir> "<command>" \
+        <n_visits> <pass_dir> [<pass_dir> ...]
+        Counters of the general visit list's kernels (arrival and final map of
+        one list of n_visits visits with the map at n_visits pixels), taken
+        from each kernel's largest dispatch (the list's own; the bench's
+        many-list leg launches the same kernels with small grids).
+
 FLOPs are counted from the instruction counters as the FLOP counters count
 them: 2 per FMA, 1 per add, multiply or transcendental, per lane.
 """
@@ -205,11 +212,66 @@ def write_counters(out_md, record, bench_json, trace_dir, fetch_dir, write_dir, 
         f.write("\n".join(lines) + "\n")
 
 
+def counter_max(d: str):
+    """{kernel: {counter: largest per-dispatch value}} over the dispatches in <d>."""
+    acc = defaultdict(lambda: defaultdict(dict))
+    for path in _csvs(d, "counter_collection.csv"):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = short_name(r["Kernel_Name"])
+                did = (path, r.get("Dispatch_Id", r.get("Correlation_Id")))
+                c = acc[k][r["Counter_Name"]]
+                c[did] = c.get(did, 0.0) + float(r["Counter_Value"])
+    return {k: {c: max(v.values()) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def write_visits(out_md, trace_dir, command, n_visits, passes):
+    n = int(n_visits)
+    pairs = {"arrival": n * (n - 1) / 2.0, "map": float(n) * n}
+    merged = defaultdict(dict)
+    for d in passes:
+        for k, cs in counter_max(d).items():
+            merged[k].update(cs)
+    trace = {r["name"]: r for r in kernel_stats(trace_dir)}
+    lines = [f"# Counters: general visit list of {n} visits (arrival and final map)", "",
+             "Commands (each counter pass and the trace its own run):", "",
+             "    " + command, "",
+             "Values are those of each kernel's largest dispatch (the list's own call; the "
+             "many-list leg of the same run launches the same kernels with small grids); the "
+             "duration is the trace's longest launch of the kernel.", "",
+             "| Kernel | pairs | ms | pair-terms/s | VALU / pair | FMA64 / pair | FMA32 / pair | "
+             "CVT / pair | TRANS32 / pair | SALU / wave-step | LDS / wave-step | issue / 3.93e13 |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(merged):
+        if "k_visit_arrival" not in k and "k_visit_map" not in k:
+            continue
+        cs = merged[k]
+        p = pairs["map" if "k_visit_map" in k else "arrival"]
+        t = trace.get(k)
+        ms = t["max_us"] / 1e3 if t else float("nan")
+
+        def per(c):
+            return 64.0 * cs.get(c, 0.0) / p
+        issue = 64.0 * cs.get("SQ_INSTS_VALU", 0.0) / (ms * 1e-3) / (256 * 64 * 2.4e9)
+        lines.append(f"| `{k}` | {p:.4e} | {ms:.3f} | {p / (ms * 1e-3):.3e} | "
+                     f"{per('SQ_INSTS_VALU'):.1f} | {per('SQ_INSTS_VALU_FMA_F64'):.1f} | "
+                     f"{per('SQ_INSTS_VALU_FMA_F32'):.1f} | {per('SQ_INSTS_VALU_CVT'):.1f} | "
+                     f"{per('SQ_INSTS_VALU_TRANS_F32'):.2f} | {per('SQ_INSTS_SALU'):.1f} | "
+                     f"{per('SQ_INSTS_LDS'):.2f} | {issue:.3f} |")
+    lines += ["", "Per pair: lane-instructions per causal pair (counter x 64 / pairs). Per "
+              "wave-step: wave instructions per 64 pairs. The issue rate is VALU lane-instructions "
+              "per second against one per lane per clock on 256 CUs at 2.4 GHz."]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "trace":
         write_trace(argv[1], argv[2], argv[3])
     elif len(argv) >= 8 and argv[0] == "counters":
         write_counters(argv[1], argv[2], argv[3], argv[4], argv[5], argv[6], argv[7:])
+    elif len(argv) >= 6 and argv[0] == "visits":
+        write_visits(argv[1], argv[2], argv[3], argv[4], argv[5:])
     else:
         print(__doc__)
         return 2
