@@ -67,11 +67,20 @@ def test_forward_loss_and_gradients_match_reference(dd):
     assert np.linalg.norm(g - ref_g) <= 1e-1 * np.linalg.norm(ref_g)
 
 
-def test_inference_forward_equals_training_forward(dd):
+@pytest.mark.parametrize("batch", [1, 5, 33])
+@pytest.mark.parametrize("weights", ["random", "trained"])
+def test_inference_forward_equals_training_forward(dd, batch, weights):
+    # inference skips the pre-activations and the last layer's activation
+    # that only the backward pass reads: the outputs are equal bit for bit,
+    # over batch sizes and on the committed weights
     import torch
+    from paper_2507_00294_amd import surrogate as sg
 
     net = dd.UNet(seed=1)
-    x = torch.rand((5, 64, 64, dd.CHANNELS), device="cuda")
+    if weights == "trained":
+        sg.load_weights(net)
+    g = torch.Generator(device="cuda").manual_seed(batch)
+    x = torch.rand((batch, 64, 64, dd.CHANNELS), device="cuda", generator=g)
     a = net.forward(x, train=True)
     b = net.forward(x, train=False)
     assert torch.equal(a, b)
