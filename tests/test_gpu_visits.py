@@ -254,3 +254,69 @@ def test_overlaps_equal_starts_negative_times(dd, ora, prec):
                  prec, "maps")
     z = dd.Visits(x, y, t0, dw, sigma_m=0.4e-9, D_m2s=6e-13, Q0_us=0.0)
     assert np.all(z.arrival(prec).cpu().numpy() == 0.0)
+
+
+def _b_hat(t, t0, dwell, sigma, D):
+    """b0, db, b1 of Eqs. 1-2 over sigma^2 for visits (t0, dwell) seen at time t."""
+    th4 = 4.0 * D / sigma ** 2
+    lag = t - t0
+    on = np.minimum(lag, dwell)
+    b0 = 2.0 + th4 * (lag - on)
+    db = th4 * on
+    return b0, db, b0 + db
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("mixed", 1e-6)])
+def test_arrival_bulk_polynomial_vs_oracle(dd, ora, prec, tol):
+    # a list whose every pair lies in the arrival's bulk domain (u = db/b1 <=
+    # 2^-8 and v = x1 u <= 2^-5, the FP64 one; the mixed one is wider), so
+    # every term takes the two-variable polynomial.  FP64 is held to that
+    # form's own truncation and rounding level, where a wrong high-order
+    # coefficient would show.
+    rng = np.random.default_rng(41)
+    n, sigma, D, tau = 48, 0.5e-9, 2.5e-13, 1e-6
+    t0 = np.cumsum(tau * rng.uniform(500.0, 900.0, n))
+    dwell = tau * rng.uniform(0.5, 1.5, n)
+    x = rng.uniform(0.0, 190.0, n) * sigma
+    y = rng.uniform(0.0, 190.0, n) * sigma
+    for p in range(1, n):
+        b0, db, b1 = _b_hat(t0[p], t0[:p], dwell[:p], sigma, D)
+        a = ((x[p] - x[:p]) ** 2 + (y[p] - y[:p]) ** 2) / sigma ** 2
+        u = db / b1
+        assert np.all(u <= 2.0 ** -8) and np.all(a / b1 * u <= 2.0 ** -5)
+    g = dd.Visits(x, y, t0, dwell, sigma_m=sigma, D_m2s=D)
+    o = ora.Visits(x, y, t0, dwell, sigma, D)
+    got = g.arrival(prec).cpu().numpy()
+    ref = o.psi_arrival()
+    assert got[0] == 0.0 and ref[0] == 0.0
+    err = np.abs(got[1:] - ref[1:]) / ref[1:]
+    assert err.max() <= tol, f"{prec}: max rel err {err.max():.3e} at {int(err.argmax()) + 1}"
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_map_series_rows_vs_oracle(dd, ora, prec, tol):
+    # a map whose rows are all lean (dx <= 1 at every pixel for every visit)
+    # and reach the highest degrees (dx up to ~1): FP64 held to 1e-12, where
+    # a wrong coefficient of the per-visit series would show; lags from 5 to
+    # 60 dwells, so q = db/b0 runs from 0.02 to 0.22
+    rng = np.random.default_rng(42)
+    sigma, D, tau = 0.5e-9, 2.5e-13, 1e-6
+    lags = np.array([5.0, 7.0, 9.0, 12.0, 17.0, 25.0, 40.0, 60.0]) * tau
+    t = 100.0 * tau
+    t0 = t - lags[::-1]
+    dwell = np.full(t0.size, tau)
+    x = rng.uniform(-2.0, 2.0, t0.size) * sigma
+    y = rng.uniform(-2.0, 2.0, t0.size) * sigma
+    w = h = 16
+    x0, d = -5.0 * sigma, 10.0 * sigma / (w - 1)
+    gx, gy = np.meshgrid(x0 + d * np.arange(w), x0 + d * np.arange(h))
+    b0, db, b1 = _b_hat(t, t0, dwell, sigma, D)
+    a = ((gx.ravel()[:, None] - x) ** 2 + (gy.ravel()[:, None] - y) ** 2) / sigma ** 2
+    dx = a * db / (b0 * b1)
+    assert dx.max() <= 1.0 and dx.max() > 0.5 and np.all(db / b0 <= 0.25)
+    g = dd.Visits(x, y, t0, dwell, sigma_m=sigma, D_m2s=D)
+    o = ora.Visits(x, y, t0, dwell, sigma, D)
+    got = g.damage_map(x0, x0, d, d, w, h, [t], prec).cpu().numpy()[0]
+    ref = o.psi_map(x0, x0, d, d, w, h, [t])[0]
+    err = np.abs(got - ref) / ref
+    assert err.max() <= tol, f"{prec}: max rel err {err.max():.3e}"
