@@ -72,10 +72,10 @@ struct dd_visits {
   std::vector<double> chunk_t0;  // first start of each chunk
 
   int dev = -1;
-  DevBuf d_vis, d_perm, d_times, tmp_out;
+  DevBuf d_vis, d_perm, tmp_out;
 
   void release_device() {
-    for (DevBuf* b : {&d_vis, &d_perm, &d_times, &tmp_out})
+    for (DevBuf* b : {&d_vis, &d_perm, &tmp_out})
       b->release();
     dev = -1;
   }
@@ -137,11 +137,37 @@ namespace {
 
 // Per-thread launch tables of the visit-list queries (host vectors reused
 // between calls, device buffers grown as needed).
+// Pinned host memory of the launch tables, grown as needed.
+struct HostStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    const size_t want = std::max(need, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = want;
+    return e;
+  }
+};
+
+// A launch group's tables go to the device in one copy from pinned memory:
+// [map times | list descriptors | tiles | items], each part 256-byte aligned.
+// While a copy or launch may be in flight (`inflight`), the next group waits
+// for the stream before it rewrites the stage or regrows a device buffer; a
+// call ends with the stream synchronized (its non-finite check), which
+// clears the flag, so calls do not overlap on these buffers.
 struct VisScratch {
   std::vector<VisTile> h_tiles;
   std::vector<VisItem> h_items;
   std::vector<VisList> h_lists;
-  DevBuf d_tiles, d_items, d_partial, d_lists;
+  std::vector<const double*> h_times;  // maps: each list's times (host) and count
+  std::vector<int32_t> h_nt;
+  HostStage stage;
+  DevBuf d_stage, d_partial;
+  bool inflight = false;
   // non-finite flag of the thread's calls (see OutFlag), read at the end
   // of each call
   DevBuf flag;
@@ -178,6 +204,7 @@ dd_status check_call_flag(const OutFlag& fl, const std::vector<int64_t>& off, hi
                          st),
           "device-to-host copy");
   VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+  W.inflight = false;
   const unsigned long long w = *W.flag_host;
   constexpr unsigned long long lim = (1ull << kFlagIndexBits) - 1;
   if ((w >> kFlagIndexBits) != fl.seq) return DD_OK;
@@ -206,10 +233,14 @@ void order_items(dd_visits* const* lists) {
   W.h_items.swap(sorted);
 }
 
-// Partial sums and reduce of the current tiles and items (one launch group);
-// the descriptors are already on the device.
+// Partial sums and reduce of the current tiles and items (one launch group),
+// with the tables staged and copied in one transfer.
 dd_status launch_group(bool map, bool mixed, hipStream_t st) {
   VisScratch& W = g_vis;
+  if (W.inflight) {
+    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+    W.inflight = false;
+  }
   int64_t pbase = 0;
   double pairs = 0;
   for (VisTile& t : W.h_tiles) {
@@ -217,38 +248,49 @@ dd_status launch_group(bool map, bool mixed, hipStream_t st) {
     pbase += (int64_t)t.slots * kVisTile;
   }
   for (const VisItem& it : W.h_items) pairs += (double)W.h_tiles[it.tile].n * (double)it.nv;
-  VIS_HIP(W.d_tiles.ensure(sizeof(VisTile) * std::max<size_t>(W.h_tiles.size(), 1)),
-          "device allocation");
-  VIS_HIP(W.d_items.ensure(sizeof(VisItem) * std::max<size_t>(W.h_items.size(), 1)),
-          "device allocation");
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t nl = W.h_lists.size();
+  std::vector<size_t> t_off(nl, 0);
+  size_t off = 0;
+  if (map)
+    for (size_t k = 0; k < nl; ++k) {
+      t_off[k] = off;
+      off = up(off + sizeof(double) * (size_t)W.h_nt[k]);
+    }
+  const size_t l_off = off;
+  off = up(off + sizeof(VisList) * nl);
+  const size_t ti_off = off;
+  off = up(off + sizeof(VisTile) * W.h_tiles.size());
+  const size_t it_off = off;
+  off = up(off + sizeof(VisItem) * std::max<size_t>(W.h_items.size(), 1));
+  VIS_HIP(W.stage.ensure(off), "pinned host allocation");
+  VIS_HIP(W.d_stage.ensure(off), "device allocation");
   VIS_HIP(W.d_partial.ensure(sizeof(double) * std::max<int64_t>(pbase, 1)), "device allocation");
-  VIS_HIP(hipMemcpyAsync(W.d_tiles.p, W.h_tiles.data(), sizeof(VisTile) * W.h_tiles.size(),
-                         hipMemcpyHostToDevice, st),
-          "host-to-device copy");
-  if (!W.h_items.empty())
-    VIS_HIP(hipMemcpyAsync(W.d_items.p, W.h_items.data(), sizeof(VisItem) * W.h_items.size(),
-                           hipMemcpyHostToDevice, st),
-            "host-to-device copy");
+  char* h = static_cast<char*>(W.stage.p);
+  char* d = static_cast<char*>(W.d_stage.p);
+  for (size_t k = 0; k < nl; ++k) {
+    VisList L = W.h_lists[k];
+    if (map) {
+      std::copy(W.h_times[k], W.h_times[k] + W.h_nt[k], reinterpret_cast<double*>(h + t_off[k]));
+      L.times = reinterpret_cast<const double*>(d + t_off[k]);
+    }
+    reinterpret_cast<VisList*>(h + l_off)[k] = L;
+  }
+  std::copy(W.h_tiles.begin(), W.h_tiles.end(), reinterpret_cast<VisTile*>(h + ti_off));
+  std::copy(W.h_items.begin(), W.h_items.end(), reinterpret_cast<VisItem*>(h + it_off));
+  W.inflight = true;
+  VIS_HIP(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st), "host-to-device copy");
+  const VisList* dl = reinterpret_cast<const VisList*>(d + l_off);
+  const VisTile* dt = reinterpret_cast<const VisTile*>(d + ti_off);
+  const VisItem* di = reinterpret_cast<const VisItem*>(d + it_off);
   const ProfToken tok = prof_begin("k_visit_pairs", st);
-  VIS_HIP(launch_visit_pairs(map, mixed, W.d_lists.as<VisList>(), W.d_tiles.as<VisTile>(),
-                             W.d_items.as<VisItem>(), (int64_t)W.h_items.size(),
+  VIS_HIP(launch_visit_pairs(map, mixed, dl, dt, di, (int64_t)W.h_items.size(),
                              W.d_partial.as<double>(), st),
           "k_visit_pairs launch");
   prof_end(tok, st, pairs, 0.0);
-  VIS_HIP(launch_visit_reduce(map, W.d_lists.as<VisList>(), W.d_tiles.as<VisTile>(),
-                              (int64_t)W.h_tiles.size(), W.d_partial.as<double>(), st),
+  VIS_HIP(launch_visit_reduce(map, dl, dt, (int64_t)W.h_tiles.size(), W.d_partial.as<double>(),
+                              st),
           "k_visit_reduce launch");
-  // the host tables are rewritten by the next group: wait for the copies
-  VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
-  return DD_OK;
-}
-
-dd_status upload_lists(hipStream_t st) {
-  VisScratch& W = g_vis;
-  VIS_HIP(W.d_lists.ensure(sizeof(VisList) * W.h_lists.size()), "device allocation");
-  VIS_HIP(hipMemcpyAsync(W.d_lists.p, W.h_lists.data(), sizeof(VisList) * W.h_lists.size(),
-                         hipMemcpyHostToDevice, st),
-          "host-to-device copy");
   return DD_OK;
 }
 
@@ -268,8 +310,6 @@ dd_status run_arrivals(dd_visits* const* lists, int32_t n, bool mixed, double* c
     fl.base = off[k];
     W.h_lists[k] = lists[k]->desc(outs[k], fl);
   }
-  rc = upload_lists(st);
-  if (rc != DD_OK) return rc;
   std::vector<VisTile> all;
   for (int32_t k = 0; k < n; ++k) lists[k]->arrival_tiles(k, all);
   for (size_t g0 = 0; g0 < all.size(); g0 += kGroupTiles) {
@@ -322,20 +362,21 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
   dd_status rc0 = call_flag(st, fl);
   if (rc0 != DD_OK) return rc0;
   W.h_lists.resize(n);
+  W.h_times.resize(n);
+  W.h_nt.resize(n);
   for (int32_t k = 0; k < n; ++k) {
     const dd_grid* g = &grids[k];
     dd_visits* v = lists[k];
     tiling.emplace_back(*g);
     npix[k] = (int64_t)g->w * g->h;
     per[k] = tiling[k].count();  // tiles per time
-    VIS_HIP(v->d_times.ensure(sizeof(double) * n_t[k]), "device allocation");
-    VIS_HIP(hipMemcpyAsync(v->d_times.p, t_s[k], sizeof(double) * n_t[k], hipMemcpyHostToDevice,
-                           st),
-            "host-to-device copy");
     if (k > 0) off[k] = off[k - 1] + (int64_t)n_t[k - 1] * npix[k - 1];
     fl.base = off[k];
-    W.h_lists[k] = v->desc(outs[k], fl, v->d_times.as<double>(),
+    // times: set to the staged copy by launch_group
+    W.h_lists[k] = v->desc(outs[k], fl, nullptr,
                            VisGrid{g->x0_m, g->y0_m, g->dx_m, g->dy_m, g->w, 0});
+    W.h_times[k] = t_s[k];
+    W.h_nt[k] = n_t[k];
     // pixel boxes of the tiles (the same at every time)
     boxes[k].resize(per[k]);
     for (int64_t b = 0; b < per[k]; ++b) {
@@ -346,8 +387,7 @@ dd_status run_maps(dd_visits* const* lists, int32_t n, const dd_grid* grids,
                       g->y0_m + (double)(v0 + ch - 1) * g->dy_m);
     }
   }
-  dd_status rc = upload_lists(st);
-  if (rc != DD_OK) return rc;
+  dd_status rc = DD_OK;
   int32_t k = 0;
   int64_t local = 0;  // next tile of list k
   while (k < n) {
