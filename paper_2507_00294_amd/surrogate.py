@@ -312,6 +312,12 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=80000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-end", type=float, default=1e-5,
+                    help="learning rate at the end of the cosine decay")
+    ap.add_argument("--init", default="",
+                    help="start from these weights (fine-tuning) instead of a fresh network")
+    ap.add_argument("--eval-seed", type=int, default=6,
+                    help="scan seed of the evaluation set (6: the test maps, 7: validation)")
     ap.add_argument("--clip", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--spot-tol", type=float, default=0.02)
@@ -352,7 +358,8 @@ def main(argv=None):
     if args.eval_only:
         net = UNet(args.seed)
         load_weights(net, args.weights)
-        res = evaluate(net, wl.surrogate_scans(args.test, seed=6), args.spot_tol)
+        res = evaluate(net, wl.surrogate_scans(args.test, seed=args.eval_seed), args.spot_tol,
+                       extra_tols=(0.01,))
         line = json.dumps(res)
         print(line, flush=True)
         if args.report:
@@ -361,21 +368,25 @@ def main(argv=None):
         return
     t0 = time.time()
     train_specs = wl.surrogate_scans(args.train, seed=5)
-    test_specs = wl.surrogate_scans(args.test, seed=6)
+    test_specs = wl.surrogate_scans(args.test, seed=args.eval_seed)
     x, own, t = generate(train_specs)
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     log(f"[surrogate] generated {args.train} training maps in {gen_s:.1f} s")
     net = UNet(args.seed)
-    init_head(net, own, t)
+    if args.init:
+        load_weights(net, args.init)
+    else:
+        init_head(net, own, t)
     t1 = time.time()
-    hist = train(net, x, own, t, args.steps, args.batch, args.lr, seed=args.seed, clip=args.clip,
+    hist = train(net, x, own, t, args.steps, args.batch, args.lr, lr_end=args.lr_end,
+                 seed=args.seed, clip=args.clip,
                  checkpoint=args.checkpoint or None, checkpoint_every=args.checkpoint_every,
                  resume=args.resume)
     torch.cuda.synchronize()
     train_s = time.time() - t1
     save_weights(net, args.weights)
-    res = evaluate(net, test_specs, args.spot_tol)
+    res = evaluate(net, test_specs, args.spot_tol, extra_tols=(0.01,))
     res.update({"train_maps": args.train, "steps": args.steps, "batch": args.batch,
                 "train_s": train_s, "generate_s": gen_s, "final_loss": hist[-1][1],
                 "params": net.num_params})
