@@ -198,6 +198,7 @@ class Scan:
         h = ctypes.c_void_p()
         _check(lib.dd_scan_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
+        self._hv = h.value  # plain int for the handle arrays of batched calls
         self.nx, self.ny, self.order = nx, ny, order
         self.pitch_m, self.dwell_s, self.sigma_m, self.D_m2s, self.Q0_us = (
             pitch_m, dwell_s, sigma_m, D_m2s, Q0_us)
@@ -208,6 +209,7 @@ class Scan:
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().dd_scan_destroy(self._h)
             self._h = ctypes.c_void_p()
+            self._hv = 0
 
     def __del__(self):
         try:
@@ -433,7 +435,7 @@ def batch_solve(scans: Sequence[Scan], queries: int = Q_ARRIVAL | Q_FINAL_AT_PRO
     size, any shape), and the call then returns ``out`` itself."""
     torch = _torch()
     n = len(scans)
-    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in scans])
+    hs = _handles(scans)
     if outs is not None:
         ptrs = np.array([o.data_ptr() for o in outs], dtype=np.uint64)
     else:
@@ -550,7 +552,11 @@ def save_png(path: str, rgb) -> None:
 
 
 def _handles(scans):
-    return (ctypes.c_void_p * len(scans))(*[s.handle.value for s in scans])
+    """The scans' handles as a C array (void *[n]); the pointer keeps the array
+    alive.  Built with numpy from plain ints: a ctypes array built element by
+    element costs ~0.1 us per scan, which showed in calls over 2000 scans."""
+    a = np.fromiter((s._hv for s in scans), dtype=np.uintp, count=len(scans))
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p))
 
 
 def _ptr(t):
