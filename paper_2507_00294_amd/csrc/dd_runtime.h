@@ -48,10 +48,10 @@ bool prof_on();  // whether kernel timing is being recorded
 //    the running sum 2 (FMA; every 4th lag a product of 1 and an FP64 add
 //    of 1 every 4 lags);
 //  * degree M >= 4 (powers of dx, exact correction): 17 + 2M.
-// FP64: 33 + 2M (distance 5, dx 1, x1 log2(e) 1, the exponent split 2, the
-// degree-11 exp polynomial 22, the polynomial 2M, the sum 2).
+// FP64: 29 + 2M (distance 5, dx 1, x1 log2(e) 1, the exponent split 2, the
+// degree-9 exp polynomial 18, the polynomial 2M, the sum 2).
 inline double series_flops(int M, bool mixed) {
-  if (!mixed) return 33.0 + 2.0 * M;
+  if (!mixed) return 29.0 + 2.0 * M;
   return M <= kMaxA ? 13.0 + 2.0 * (M > 1 ? M : 1) : 17.0 + 2.0 * M;
 }
 

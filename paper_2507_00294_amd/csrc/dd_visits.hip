@@ -342,26 +342,16 @@ __device__ __forceinline__ int build_map_row(const double4 v, double t, double t
   return row->kind = kind;
 }
 
-// 2^-y for 0 <= y <= 1000 in double precision: y = n - h, n = rint(y),
-// 2^h = sum_k (h ln2)^k / k! by its Taylor polynomial in h (|h ln2| <=
-// 0.347, degree 11: relative remainder < 1.3e-14, as exp2_neg).
-struct Exp2Coef {
-  double c[12];
-  constexpr Exp2Coef() : c() {
-    double v = 1.0;
-    for (int k = 0; k < 12; ++k) {
-      c[k] = v;
-      v *= kLn2 / (k + 1);
-    }
-  }
-};
+// 2^-y for 0 <= y <= 1000 in double precision: y = n - h, n = rint(y), 2^h
+// by the degree-9 Chebyshev interpolant of exp2_neg9 (relative error below
+// 1.9e-14), without exp2_neg9's clamp.
 __device__ __forceinline__ double exp2_lean(double y) {
-  constexpr Exp2Coef e{};
+  constexpr Exp2Cheb<9> e{};
   const double n = __builtin_rint(y);
   const double h = n - y;
-  double p = e.c[11];
+  double p = e.c[9];
 #pragma unroll
-  for (int k = 10; k >= 0; --k) p = fma(p, h, e.c[k]);
+  for (int k = 8; k >= 0; --k) p = fma(p, h, e.c[k]);
   return __builtin_ldexp(p, -(int)n);
 }
 
