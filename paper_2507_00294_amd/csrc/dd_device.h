@@ -167,19 +167,20 @@ struct Exp2Cheb {
   }
 };
 
-// 2^-y for y >= 0 to the FP64 series' per-term budget (1e-13): y -> 2^-n 2^h,
-// n = rint(y), |h| <= 1/2, 2^h by Exp2Cheb<9> (relative error below 1.9e-14,
-// two FMAs fewer than the degree-11 Taylor form of exp2_neg).  Returns 0 for
+// 2^-y for y >= 0 to the FP64 series' per-term budget (1e-13): -y -> m + h,
+// m = rint(-y), |h| <= 1/2, 2^h by Exp2Cheb<9> (relative error below 1.9e-14,
+// two FMAs fewer than the degree-11 Taylor form of exp2_neg); rounding -y
+// rather than y gives the exponent without a negation.  Returns 0 for
 // y > 1100.
 __device__ __forceinline__ double exp2_neg9(double y) {
   constexpr Exp2Cheb<9> e{};
-  y = fmin(y, 1100.0);
-  const double n = __builtin_rint(y);
-  const double h = n - y;
+  const double ny = -fmin(y, 1100.0);
+  const double m = __builtin_rint(ny);
+  const double h = ny - m;
   double p = e.c[9];
 #pragma unroll
   for (int k = 8; k >= 0; --k) p = fma(p, h, e.c[k]);
-  return __builtin_ldexp(p, -(int)n);
+  return __builtin_ldexp(p, (int)m);
 }
 
 // Coefficients (-1)^n / (n n!) of the E1 power series, n = 1..24.

@@ -342,17 +342,17 @@ __device__ __forceinline__ int build_map_row(const double4 v, double t, double t
   return row->kind = kind;
 }
 
-// 2^-y for 0 <= y <= 1000 in double precision: y = n - h, n = rint(y), 2^h
+// 2^-y for 0 <= y <= 1000 in double precision: -y = m + h, m = rint(-y), 2^h
 // by the degree-9 Chebyshev interpolant of exp2_neg9 (relative error below
 // 1.9e-14), without exp2_neg9's clamp.
 __device__ __forceinline__ double exp2_lean(double y) {
   constexpr Exp2Cheb<9> e{};
-  const double n = __builtin_rint(y);
-  const double h = n - y;
+  const double m = __builtin_rint(-y);
+  const double h = -y - m;
   double p = e.c[9];
 #pragma unroll
   for (int k = 8; k >= 0; --k) p = fma(p, h, e.c[k]);
-  return __builtin_ldexp(p, -(int)n);
+  return __builtin_ldexp(p, (int)m);
 }
 
 __device__ __forceinline__ void map_am(const double (&px)[kMapPix], const double (&py)[kMapPix],
