@@ -114,7 +114,7 @@ def far_roofline(prec, kern, side):
         "plan_flops_per_pair": plan_flops / max(pairs_l, 1.0),
     }
     if prec == "mixed":
-        # this build does not emit packed FP32, so 78.6 TFLOP/s is the FLOP ceiling
+        # the kernels are compiled without packed FP32, so 78.6 TFLOP/s is the FLOP ceiling
         roofline["frac_of_fp32_nonpacked"] = round(achieved / FP32_NONPACKED_TFLOPS, 4)
     rec = counter_record(side)
     key = "valu_lane_instructions_per_pair" if prec == "mixed" else \
@@ -378,7 +378,7 @@ def main():
         log(f"[bench] copied {4 * n} bytes three times")
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ typedef enum {
   DD_EINVAL = -1,       /* invalid or non-finite argument                       */
   DD_ENOMEM = -2,       /* host or device allocation failed                     */
   DD_EDEVICE = -3,      /* HIP runtime error or no usable gfx950 device         */
-  DD_EUNSUPPORTED = -4  /* valid request this build does not handle             */
+  DD_EUNSUPPORTED = -4  /* valid request the library does not handle           */
 } dd_status;
 
 /* Visit orders (Sec. I: raster, interleaved/alternating, random and
