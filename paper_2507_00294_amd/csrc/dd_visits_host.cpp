@@ -156,9 +156,11 @@ struct HostStage {
 // A launch group's tables go to the device in one copy from pinned memory:
 // [map times | list descriptors | tiles | items], each part 256-byte aligned.
 // While a copy or launch may be in flight (`inflight`), the next group waits
-// for the stream before it rewrites the stage or regrows a device buffer; a
-// call ends with the stream synchronized (its non-finite check), which
-// clears the flag, so calls do not overlap on these buffers.
+// for the event recorded after the previous group's launches (`done`, on
+// whatever stream those went to) before it rewrites the stage or regrows a
+// device buffer.  A call ends with its stream synchronized (the non-finite
+// check), which clears the flag; a call that failed half-way leaves it set,
+// and the next group, on any stream, still waits.
 struct VisScratch {
   std::vector<VisTile> h_tiles;
   std::vector<VisItem> h_items;
@@ -168,6 +170,7 @@ struct VisScratch {
   HostStage stage;
   DevBuf d_stage, d_partial;
   bool inflight = false;
+  hipEvent_t done = nullptr;  // after the last group's launches; kept until the process ends
   // non-finite flag of the thread's calls (see OutFlag), read at the end
   // of each call
   DevBuf flag;
@@ -238,9 +241,10 @@ void order_items(dd_visits* const* lists) {
 dd_status launch_group(bool map, bool mixed, hipStream_t st) {
   VisScratch& W = g_vis;
   if (W.inflight) {
-    VIS_HIP(hipStreamSynchronize(st), "stream synchronize");
+    VIS_HIP(hipEventSynchronize(W.done), "event synchronize");
     W.inflight = false;
   }
+  if (!W.done) VIS_HIP(hipEventCreateWithFlags(&W.done, hipEventDisableTiming), "event creation");
   int64_t pbase = 0;
   double pairs = 0;
   for (VisTile& t : W.h_tiles) {
@@ -280,6 +284,7 @@ dd_status launch_group(bool map, bool mixed, hipStream_t st) {
   std::copy(W.h_items.begin(), W.h_items.end(), reinterpret_cast<VisItem*>(h + it_off));
   W.inflight = true;
   VIS_HIP(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st), "host-to-device copy");
+  VIS_HIP(hipEventRecord(W.done, st), "event record");  // the stage is read; again after the launches
   const VisList* dl = reinterpret_cast<const VisList*>(d + l_off);
   const VisTile* dt = reinterpret_cast<const VisTile*>(d + ti_off);
   const VisItem* di = reinterpret_cast<const VisItem*>(d + it_off);
@@ -291,6 +296,7 @@ dd_status launch_group(bool map, bool mixed, hipStream_t st) {
   VIS_HIP(launch_visit_reduce(map, dl, dt, (int64_t)W.h_tiles.size(), W.d_partial.as<double>(),
                               st),
           "k_visit_reduce launch");
+  VIS_HIP(hipEventRecord(W.done, st), "event record");
   return DD_OK;
 }
 
