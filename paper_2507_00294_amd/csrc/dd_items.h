@@ -344,6 +344,69 @@ __device__ __forceinline__ void do_arrival_far64(const ArrItem& item, const doub
     if (jl + r < V) partial[base + jl + r] = acc[r];
 }
 
+// Near band, mixed precision: the pairs that need the general form (series
+// variable above the FP32 series' threshold, x1 within the cull) are few and
+// scattered over the lanes; evaluated where they occur, the general form runs
+// with most lanes idle.  They are queued instead, per lane in LDS (a and the
+// lag), and evaluated by the whole wave whenever some lane's queue could
+// overflow, and at the end: the queues are packed into one list at offsets
+// from a prefix sum of their lengths, lane l evaluates list entries l, l + 64,
+// ..., and each lane then adds its own values in the order it queued them
+// (deterministic; the general-form terms of a flush enter the FP64 sum after
+// the series terms of the same lags).
+constexpr int kNearQ = 6;  // queued general-form pairs per lane
+struct NearQueue {
+  float a[kNearQ][64];
+  int32_t n[kNearQ][64];  // lag | (r << 29)
+  float fa[64 * kNearQ];  // the packed list
+  int32_t fn[64 * kNearQ];
+  double fv[64 * kNearQ];
+};
+
+__device__ __forceinline__ void near_wave_sync() {
+  // a wave's LDS operations complete in order: a compiler barrier at
+  // wavefront scope orders its writes before other lanes' reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int R>
+__device__ __forceinline__ void near_flush(NearQueue& Q, int& cnt, const double* __restrict__ rows64,
+                                           const float* __restrict__ rows32, double (&acc)[R]) {
+  const int lane = threadIdx.x & 63;
+  const int c = cnt;
+  int s = c;  // inclusive prefix sum of the queue lengths over the lanes
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(s, d);
+    if (lane >= d) s += t;
+  }
+  const int base = s - c, total = __shfl(s, 63);
+#pragma unroll
+  for (int k = 0; k < kNearQ; ++k)
+    if (k < c) {
+      Q.fa[base + k] = Q.a[k][lane];
+      Q.fn[base + k] = Q.n[k][lane];
+    }
+  near_wave_sync();
+  for (int e = lane; e < total; e += 64) {
+    const int n = Q.fn[e] & 0x1fffffff;
+    Q.fv[e] = phi_general_mixed(Q.fa[e], rows64 + (int64_t)n * kRow64, rows32 + (int64_t)n * kRow32);
+  }
+  near_wave_sync();
+#pragma unroll
+  for (int k = 0; k < kNearQ; ++k)
+    if (k < c) {
+      const int r = Q.fn[base + k] >> 29;
+      const double v = Q.fv[base + k];
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) acc[rr] += (rr == r) ? v : 0.0;  // no indexed registers
+    }
+  near_wave_sync();  // the queues and the list are rewritten next
+  cnt = 0;
+}
+
 // Near band: per-pair regime choice, every pair masked by causality.
 template <int R, bool MIXED>
 __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void* __restrict__ pos_v,
@@ -365,9 +428,13 @@ __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void*
       ex[r] = e.x;
       ey[r] = e.y;
     }
+    static_assert(R <= 4, "the queue entry holds r in two bits");
+    __shared__ NearQueue queues[4];  // one per wave of the 256-thread block
+    NearQueue& Q = queues[threadIdx.x >> 6];
+    int cnt = 0;
     for (int n = item.n_lo; n < item.n_hi; ++n) {
+      if (__ballot(cnt > kNearQ - R)) near_flush<R>(Q, cnt, rows64, rows32, acc);
       const float* r32 = rows32 + (int64_t)n * kRow32;
-      const double* r64 = rows64 + (int64_t)n * kRow64;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int64_t i = jl + r - n;
@@ -375,13 +442,17 @@ __device__ __forceinline__ void do_arrival_near(const ArrItem& item, const void*
           const float2 p = pos[i];
           const float dx = ex[r] - p.x, dy = ey[r] - p.y;
           const float a = __builtin_fmaf(dy, dy, dx * dx);
-          if (a * ldc(r32 + kR32_C) <= kThr32)
+          if (a * ldc(r32 + kR32_C) <= kThr32) {
             acc[r] += (double)series_f32<kMNear32>(a, r32);
-          else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2)
-            acc[r] += phi_general_mixed(a, r64, r32);
+          } else if (a * ldc(r32 + kR32_RHI) <= kCull32Log2) {
+            Q.a[cnt][lane] = a;
+            Q.n[cnt][lane] = n | (r << 29);
+            ++cnt;
+          }
         }
       }
     }
+    if (__ballot(cnt > 0)) near_flush<R>(Q, cnt, rows64, rows32, acc);
   } else {
     const double2* pos = (const double2*)pos_v;
     double ex[R], ey[R];
