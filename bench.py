@@ -37,7 +37,8 @@ METRIC = "pair E1-terms/s at oracle-matched accuracy; surrogate speedup @≤1% L
 # HBM bytes of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # valid only while the device sources hash to the recorded value.
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_arrival_far_512x512_random_record.txt")
-DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip", "dd_queries.cpp")
+DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip", "dd_queries.cpp",
+                  "dd_host.cpp")
 PEAK_TFLOPS = {"mixed": 157.3, "fp64": 78.6}  # MI355X FP32 / FP64 vector peaks
 FP32_NONPACKED_TFLOPS = 78.6  # FP32 vector peak without packed instructions
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: one VALU op per lane per clock

@@ -332,12 +332,12 @@ __device__ __forceinline__ float series_f32(float a, const float* __restrict__ r
 // below |eps| dx / 2, i.e. under 1e-8 of the term at the dx <= 0.01 where
 // degrees <= 3 are used.  P_0 eps enters as -ln2 P_0 rlo added to the linear
 // coefficient (row field PA_1 holds PA_1 - ln2 P_0 rlo) and one fma with e2.
-// `a` is exact.
-template <int M>
+// `a` is exact.  COMP = false leaves out the e2 correction, for rows where
+// y = x1 log2(e) is small enough that fl(a rhi) alone is accurate enough.
+template <int M, bool COMP = true>
 __device__ __forceinline__ float series_f32a_q(float a, const RowA& w, float& t) {
   static_assert(M <= kMaxA, "degree too high for the a-form");
   const float yh = a * w.rhi;
-  const float e2 = __builtin_fmaf(a, w.rhi, -yh);
   t = __builtin_amdgcn_exp2f(-yh);
   float q;
   if constexpr (M == 0) {
@@ -349,13 +349,15 @@ __device__ __forceinline__ float series_f32a_q(float a, const RowA& w, float& t)
     for (int m = M - 1; m >= 1; --m) q = __builtin_fmaf(q, a, pa[m - 1]);
     q = __builtin_fmaf(q, a, w.p0);
   }
+  if constexpr (!COMP) return q;
+  const float e2 = __builtin_fmaf(a, w.rhi, -yh);
   return __builtin_fmaf(w.p0n, e2, q);
 }
 
-template <int M>
+template <int M, bool COMP = true>
 __device__ __forceinline__ float series_f32a(float a, const RowA& w) {
   float t;
-  const float q = series_f32a_q<M>(a, w, t);
+  const float q = series_f32a_q<M, COMP>(a, w, t);
   return t * q;
 }
 

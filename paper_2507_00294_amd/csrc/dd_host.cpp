@@ -304,6 +304,7 @@ static const double* dx_cover(bool mixed) {
 DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
                            bool mixed) {
   DegreeBounds b;
+  b.plain = b.fold = 1 << 30;
   const int mmax = mixed ? kM32 : kM64;
   const double cull = mixed ? kCullX32 : kCullX64;
   const double dx0 = row_dx_bound(f + (double)kf, a_max, cull, kappa, s2);
@@ -319,6 +320,47 @@ DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int6
   // make b nonincreasing in M (b[M] >= b[M+1])
   for (int M = b.m_max - 1; M >= 0; --M) b.b[M] = std::max(b.b[M], b.b[M + 1]);
   return b;
+}
+
+// First rows of the two lighter forms of the mixed arrival series (see
+// DegreeBounds), for the far region from row kf, aligned like the degree
+// segments.  y_max(n) = a_max log2(e) (rb1 + c) bounds a pair's exponent in
+// both forms (RA = log2(e) (rb1 - c P_1/P_0) <= log2(e) (rb1 + c) since
+// |P_1/P_0| < 1); the margin keeps fl(a rhi) and fl(a RA) below the powers
+// of two that the error bounds assume.
+void lean_bounds(DegreeBounds& b, double a_max, double kappa, double s2, int64_t kf, int align) {
+  b.plain = b.fold = 1 << 30;
+  if (a_max <= 0) return;
+  auto ymax = [&](int64_t n) {
+    const double lam = (double)n;
+    const double db = 4.0 * kappa * std::min(lam, 1.0);
+    const double b0 = s2 + 4.0 * kappa * std::max(lam - 1.0, 0.0);
+    return a_max * 1.4426950408889634 * (1.0 / (b0 + db) + db / (b0 * (b0 + db)));
+  };
+  auto first_row = [&](double ylim, double dxlim) {  // both bounds fall with n
+    auto ok = [&](int64_t n) {
+      return ymax(n) <= ylim * (1.0 - 1e-6) &&
+             row_dx_bound((double)n, a_max, kCullX32, kappa, s2) <= dxlim;
+    };
+    int64_t lo = kf, hi = kf;
+    if (!ok(hi)) {
+      while (!ok(hi)) {
+        lo = hi;
+        hi = hi * 2 + 1;
+        if (hi > ((int64_t)1 << 30)) return (int64_t)1 << 30;
+      }
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        (ok(mid) ? hi : lo) = mid;
+      }
+    }
+    if (align > 1) hi = kf + (hi - kf + align - 1) / align * align;
+    return std::min<int64_t>(hi, (int64_t)1 << 30);
+  };
+  const double* cover = dx_cover(true);
+  b.fold = (int32_t)std::max<int64_t>(first_row(4.0, std::min(2e-4, cover[1])), b.b[1]);
+  b.plain = (int32_t)std::max<int64_t>(first_row(8.0, cover[kMaxA]), b.b[kMaxA]);
+  b.plain = std::min(b.plain, b.fold);
 }
 
 }  // namespace dd

@@ -29,12 +29,14 @@ constexpr int kR64_RB1 = 0, kR64_RB0 = 1, kR64_C = 2, kR64_RL2 = 3, kR64_P = 4;
 // FP32 row.  The first 8 floats are everything the bulk (degree <= 3) path
 // reads, so one 32-byte scalar load fetches them: rb1 log2(e) rounded (rhi),
 // P_0, the series coefficients in powers of a itself (PA_m = P_m c^m,
-// m = 1..3), -ln2 P_0, -ln2 P_0 rlo and c.  Then rlo = rb1 log2(e) - rhi and
-// P_1..P_6 for the degree >= 4 form in powers of dx = a c.
+// m = 1..3), -ln2 P_0, -ln2 P_0 rlo and c.  Then rlo = rb1 log2(e) - rhi,
+// P_1..P_6 for the degree >= 4 form in powers of dx = a c, and the exponent
+// rate RA = log2(e) (rb1 - c P_1/P_0) of the folded form (see DegreeBounds).
 constexpr int kR32_RHI = 0, kR32_P0 = 1, kR32_PA = 2, kR32_P0N = 5, kR32_P0NR = 6, kR32_C = 7,
-              kR32_RLO = 8, kR32_P1 = 9;
+              kR32_RLO = 8, kR32_P1 = 9, kR32_RA = 15;
 constexpr int kMaxA = 3;     // highest degree evaluated in powers of a
-static_assert(kR32_PA + kMaxA <= kR32_P0N && kR32_P0NR < kR32_C && kR32_P1 + kM32 - 1 < kRow32,
+static_assert(kR32_PA + kMaxA <= kR32_P0N && kR32_P0NR < kR32_C && kR32_P1 + kM32 - 1 < kR32_RA &&
+                  kR32_RA < kRow32,
               "FP32 row fields overlap");
 // Row fields of the bulk path, loaded together.
 struct RowA {
@@ -89,10 +91,27 @@ struct MapItem {
 
 // Degree segments of the far region: for rows n in [bound[M], bound[M-1]) the
 // series needs P_0..P_M.  bound[-1] is +inf; bound[kMaxSeg] ... bound[0].
+//
+// Two lighter forms of the mixed arrival series take the rows where every
+// pair's exponent y = x1 log2(e) is small, since the rounding of fl(a rhi)
+// then costs little: its error is at most half an ulp of y.
+//  * From row `plain` on (y <= 8 and degree <= 3), the a-form runs without
+//    the correction of that rounding (two operations fewer per pair); the
+//    exponent's error is <= 2^-22, i.e. <= 1.7e-7 of the term.
+//  * From row `fold` on (y <= 4, dx <= 2e-4, degree <= 1), the term is
+//    P_0 2^{-fl(a RA)}: the linear term of the series moves into the exponent,
+//    exp(-x1) (1 + k dx) ~ exp(-x1 + k dx) with k = P_1/P_0, since the two
+//    differ by at most 0.3 dx^2 <= 1.2e-8 (|k| <= 1/(2 ln 2) and
+//    P_2/P_0 <= 1/(6 ln 2) for q = db/b0 <= 1).  Per pair: a, one product, the
+//    exponential and one fused multiply-add into the partial sum.  The
+//    exponent's error, from fl(RA) and fl(a RA), is <= 1.5 2^-22, i.e.
+//    <= 2.5e-7 of the term.
+// Both are >= 2^30 (never) where unused: FP64, maps and short scans.
 constexpr int kMaxSeg = 18;
 struct DegreeBounds {
   int32_t b[kMaxSeg + 1];  // b[M] for M = 0..kMaxSeg; nondecreasing as M falls
   int32_t m_max;           // degree used at the start of the far region
+  int32_t plain, fold;     // first rows of the lighter forms; plain <= fold
 };
 
 struct MapTime {

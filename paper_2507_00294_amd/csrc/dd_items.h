@@ -73,6 +73,7 @@ __device__ inline void make_row(double lam, double kappa, double s2, const GLNod
   r32[kR32_RLO] = rlo;
   for (int m = 1; m <= kM32; ++m) r32[kR32_P1 + m - 1] = (float)P[m];
   for (int k = kR32_P1 + kM32; k < kRow32; ++k) r32[k] = 0.0f;
+  r32[kR32_RA] = (float)(kLog2e * (rb1 - c * (P[1] / P[0])));
 }
 
 
@@ -101,27 +102,52 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // exact FP32 operations (lattice coordinates below 2048).  For degrees <= 3
 // the rows of the next R lags are fetched (scalar loads) while the current R
 // lags are evaluated.
-template <int M>
-struct RowSel {
-  // degree <= 3: the 8 bulk fields; higher degrees read the row in place
-  using type = typename std::conditional<(M <= kMaxA), RowA, const float*>::type;
+// Forms of the far series by row range (see DegreeBounds): the full form,
+// the a-form without the exponent's rounding correction, and the folded
+// single exponential P_0 2^{-a RA}.
+enum { kFormFull = 0, kFormPlain = 1, kFormFold = 2 };
+
+// The two fields of the folded form.
+struct RowF {
+  float ra, p0;
 };
 
-template <int M, bool CAS = true>
-__device__ __forceinline__ typename RowSel<M>::type fetch_row(const float* __restrict__ rows,
-                                                              int64_t n) {
-  if constexpr (M <= kMaxA)
+template <int M, int F = kFormFull>
+struct RowSel {
+  // folded: RA and P_0; degree <= 3: the 8 bulk fields; higher degrees read
+  // the row in place
+  using type = typename std::conditional<
+      F == kFormFold, RowF,
+      typename std::conditional<(M <= kMaxA), RowA, const float*>::type>::type;
+};
+
+template <int M, bool CAS = true, int F = kFormFull>
+__device__ __forceinline__ typename RowSel<M, F>::type fetch_row(const float* __restrict__ rows,
+                                                                 int64_t n) {
+  if constexpr (F == kFormFold) {
+    const float* row = rows + n * kRow32;
+    if constexpr (CAS)
+      return RowF{ldc(row + kR32_RA), ldc(row + kR32_P0)};
+    else
+      return RowF{row[kR32_RA], row[kR32_P0]};
+  } else if constexpr (M <= kMaxA) {
     return load_rowa<CAS>(rows + n * kRow32);
-  else
+  } else {
     return rows + n * kRow32;
+  }
 }
 
-template <int M>
-__device__ __forceinline__ float series_row32(float a, const typename RowSel<M>::type& row) {
-  if constexpr (M <= kMaxA)
-    return series_f32a<M>(a, row);
-  else
+template <int M, int F = kFormFull>
+__device__ __forceinline__ float series_row32(float a, const typename RowSel<M, F>::type& row) {
+  if constexpr (F == kFormFold) {
+    return row.p0 * __builtin_amdgcn_exp2f(-(a * row.ra));
+  } else if constexpr (M <= kMaxA) {
+    static_assert(F == kFormFull || F == kFormPlain, "unknown form");
+    return series_f32a<M, F == kFormFull>(a, row);
+  } else {
+    static_assert(F == kFormFull, "the lighter forms need degree <= 3");
     return series_f32<M>(a, row);
+  }
 }
 
 // The term as its two factors (q returned, t set), for sums that must not
@@ -138,11 +164,11 @@ __device__ __forceinline__ float series_row32_q(float a, const typename RowSel<M
 // One chunk of R lags n0 .. n0+R-1 against window W (see arr_far32); the R
 // terms of each evaluation point are summed in FP32 by fused multiply-adds
 // (R roundings) and then added to its FP64 accumulator.
-template <int M, int R, bool EDGE>
+template <int M, int R, bool EDGE, int F>
 __device__ __forceinline__ void arr_chunk32(int n0, int64_t jl, const float4 (&W)[2 * R - 1],
                                             const float (&ex)[R], const float (&ey)[R],
                                             const float (&ee)[R],
-                                            const typename RowSel<M>::type (&row)[R],
+                                            const typename RowSel<M, F>::type (&row)[R],
                                             double (&acc)[R]) {
   float part[R];
 #pragma unroll
@@ -151,7 +177,7 @@ __device__ __forceinline__ void arr_chunk32(int n0, int64_t jl, const float4 (&W
     for (int r = 0; r < R; ++r) {
       const float4 p = W[r - s + R - 1];
       const float a = __builtin_fmaf(ex[r], p.x, __builtin_fmaf(ey[r], p.y, ee[r] + p.z));
-      float v = series_row32<M>(a, row[s]);
+      float v = series_row32<M, F>(a, row[s]);
       if (EDGE) v = (jl + r >= (int64_t)(n0 + s)) ? v : 0.0f;
       part[r] = (s == 0) ? v : part[r] + v;
     }
@@ -170,12 +196,12 @@ __device__ __forceinline__ float4 ldpos(const float4* p) {
     return *p;
 }
 
-template <int M, int R, bool EDGE, bool CAS>
+template <int M, int R, bool EDGE, bool CAS, int F = kFormFull>
 __device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restrict__ pos, int64_t jl,
                                           const float (&ex)[R], const float (&ey)[R],
                                           const float (&ee)[R], const float* __restrict__ rows,
                                           double (&acc)[R]) {
-  using Row = typename RowSel<M>::type;
+  using Row = typename RowSel<M, F>::type;
   // Two windows alternate so that sliding by R visits needs no register
   // moves: A covers the chunk at n0, B the chunk at n0 + R.
   float4 A[2 * R - 1], B[2 * R - 1];
@@ -183,28 +209,28 @@ __device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restri
   for (int q = 0; q < 2 * R - 1; ++q) A[q] = ldpos<CAS>(pos + (jl - lo - (R - 1) + q));
   Row cur[R];
 #pragma unroll
-  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS>(rows, lo + s);
+  for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS, F>(rows, lo + s);
   int n0 = lo;
   for (; n0 + 2 * R <= hi; n0 += 2 * R) {
     Row nxt[R];
 #pragma unroll
-    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M, CAS>(rows, n0 + R + s);
+    for (int s = 0; s < R; ++s) nxt[s] = fetch_row<M, CAS, F>(rows, n0 + R + s);
 #pragma unroll
     for (int q = R; q < 2 * R - 1; ++q) B[q] = A[q - R];
     const int64_t b1 = jl - (n0 + R) - (R - 1);
 #pragma unroll
     for (int q = 0; q < R; ++q) B[q] = ldpos<CAS>(pos + (b1 + q));
-    arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);
+    arr_chunk32<M, R, EDGE, F>(n0, jl, A, ex, ey, ee, cur, acc);
 #pragma unroll
-    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS>(rows, min(n0 + 2 * R + s, hi - 1));
+    for (int s = 0; s < R; ++s) cur[s] = fetch_row<M, CAS, F>(rows, min(n0 + 2 * R + s, hi - 1));
 #pragma unroll
     for (int q = R; q < 2 * R - 1; ++q) A[q] = B[q - R];
     const int64_t b2 = jl - (n0 + 2 * R) - (R - 1);
 #pragma unroll
     for (int q = 0; q < R; ++q) A[q] = ldpos<CAS>(pos + (b2 + q));
-    arr_chunk32<M, R, EDGE>(n0 + R, jl, B, ex, ey, ee, nxt, acc);
+    arr_chunk32<M, R, EDGE, F>(n0 + R, jl, B, ex, ey, ee, nxt, acc);
   }
-  if (n0 < hi) arr_chunk32<M, R, EDGE>(n0, jl, A, ex, ey, ee, cur, acc);  // one chunk left
+  if (n0 < hi) arr_chunk32<M, R, EDGE, F>(n0, jl, A, ex, ey, ee, cur, acc);  // one chunk left
 }
 
 template <int M, int R, bool EDGE>
@@ -236,12 +262,23 @@ __device__ __forceinline__ void arr_far64(int lo, int hi, const double2* __restr
   }
 }
 
-// Degree dispatch for one segment (uniform branch).
-template <int R, bool EDGE, bool CAS>
+// Degree dispatch for one segment (uniform branch).  PLAIN: the a-form
+// without the exponent's rounding correction (degrees <= 3 only; the planner
+// starts that range below degree 4).
+template <int R, bool EDGE, bool CAS, bool PLAIN = false>
 __device__ __forceinline__ void arr_far32_seg(int M, int lo, int hi, const float4* __restrict__ pos,
                                               int64_t jl, const float (&ex)[R], const float (&ey)[R],
                                               const float (&ee)[R], const float* __restrict__ rows,
                                               double (&acc)[R]) {
+  if constexpr (PLAIN) {
+    switch (M) {
+      case 0: arr_far32<0, R, EDGE, CAS, kFormPlain>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+      case 1: arr_far32<1, R, EDGE, CAS, kFormPlain>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+      case 2: arr_far32<2, R, EDGE, CAS, kFormPlain>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+      default: arr_far32<3, R, EDGE, CAS, kFormPlain>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
+    }
+    return;
+  }
   switch (M) {
     case 0: arr_far32<0, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
     case 1: arr_far32<1, R, EDGE, CAS>(lo, hi, pos, jl, ex, ey, ee, rows, acc); break;
@@ -297,14 +334,27 @@ __device__ __forceinline__ void do_arrival_far32(const ArrItem& item, const floa
     acc[r] = 0.0;
   }
   const bool edge = (item.slot_flags & kItemEdge) != 0;
+  // rows [n_lo, fold) by degree segment, each split at `plain`; then the
+  // folded rows [fold, n_hi) whatever their degree segment
+  const int n_fold = max(item.n_lo, min(item.n_hi, bnd.fold));
   for (int M = bnd.m_max; M >= 0; --M) {
     int lo, hi;
-    seg_range(bnd, M, item.n_lo, item.n_hi, lo, hi);
+    seg_range(bnd, M, item.n_lo, n_fold, lo, hi);
     if (lo >= hi) continue;
+    const int mid = max(lo, min(hi, bnd.plain));
+    if (edge) {
+      if (lo < mid) arr_far32_seg<R, true, CAS>(M, lo, mid, pos, jl, ex, ey, ee, rows, acc);
+      if (mid < hi) arr_far32_seg<R, true, CAS, true>(M, mid, hi, pos, jl, ex, ey, ee, rows, acc);
+    } else {
+      if (lo < mid) arr_far32_seg<R, false, CAS>(M, lo, mid, pos, jl, ex, ey, ee, rows, acc);
+      if (mid < hi) arr_far32_seg<R, false, CAS, true>(M, mid, hi, pos, jl, ex, ey, ee, rows, acc);
+    }
+  }
+  if (n_fold < item.n_hi) {
     if (edge)
-      arr_far32_seg<R, true, CAS>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
+      arr_far32<0, R, true, CAS, kFormFold>(n_fold, item.n_hi, pos, jl, ex, ey, ee, rows, acc);
     else
-      arr_far32_seg<R, false, CAS>(M, lo, hi, pos, jl, ex, ey, ee, rows, acc);
+      arr_far32<0, R, false, CAS, kFormFold>(n_fold, item.n_hi, pos, jl, ex, ey, ee, rows, acc);
   }
   const int64_t base = (int64_t)(item.slot_flags & kSlotMask) * pstride - pj0;
 #pragma unroll

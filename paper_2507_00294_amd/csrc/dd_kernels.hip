@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_lag_rows(int64_t n0, int64_t count, dou
 // marks the launches of a visit-range query: the same code as a whole-scan
 // query, instantiated apart so that kernel traces report the two separately.
 template <int R, int RANGE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_arrival_far32(const float4* __restrict__ pos,
                                                        const float* __restrict__ rows,
                                                        const ArrItem* __restrict__ items, int n_items,

@@ -173,13 +173,20 @@ double arrival_pairs(int64_t A, int64_t B, int64_t lo, int64_t hi) {
 template <typename PairsFn>
 void count_segments(const DegreeBounds& b, int64_t lo, int64_t hi, bool mixed, PairsFn&& pairs,
                     double& p_out, double& f_out) {
+  const int64_t fold = std::max<int64_t>(lo, std::min<int64_t>(hi, b.fold));
   for (int M = b.m_max; M >= 0; --M) {
     const int64_t a = std::max<int64_t>(lo, b.b[M]);
-    const int64_t e = (M == 0) ? hi : std::min<int64_t>(hi, b.b[M - 1]);
+    const int64_t e = (M == 0) ? fold : std::min<int64_t>(fold, b.b[M - 1]);
     if (a >= e) continue;
-    const double pr = pairs(a, e);
+    const int64_t mid = std::max<int64_t>(a, std::min<int64_t>(e, b.plain));
+    const double pf = pairs(a, mid), pp = pairs(mid, e);
+    p_out += pf + pp;
+    f_out += pf * series_flops(M, mixed) + pp * plain_flops(M);
+  }
+  if (fold < hi) {
+    const double pr = pairs(fold, hi);
     p_out += pr;
-    f_out += pr * series_flops(M, mixed);
+    f_out += pr * kFoldFlops;
   }
 }
 
@@ -207,6 +214,7 @@ void plan_arrival(const dd_scan* s, bool mixed, int R, int RN, int K, ArrivalPla
   kf = 1 + (kf - 1 + R - 1) / R * R;
   if (kf > V) kf = V + 1;  // every lag is in the near band
   P.bounds = degree_bounds(a_max, 0.0, s->kappa, s->s2, kf, R, mixed);
+  if (mixed) lean_bounds(P.bounds, a_max, s->kappa, s->s2, kf, R);
   P.near_pairs = P.near_flops = P.far_pairs = P.far_flops = 0;
   const int64_t n_tiles = (V + T - 1) / T;
   const int64_t piece = near_piece > 0 ? near_piece : std::max<int64_t>(1, kf - 1);

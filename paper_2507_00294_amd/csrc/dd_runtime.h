@@ -28,6 +28,7 @@ int64_t first_row_below(double thr, double a_max, double cull, double f, double 
                         int64_t n_start, int64_t n_end);
 DegreeBounds degree_bounds(double a_max, double f, double kappa, double s2, int64_t kf, int align,
                            bool mixed);
+void lean_bounds(DegreeBounds& b, double a_max, double kappa, double s2, int64_t kf, int align);
 
 // Kernel timing (dd_profiling / dd_profile_read): events around a launch on
 // the stream it runs on, plus the launch's algorithmic work.
@@ -54,6 +55,11 @@ inline double series_flops(int M, bool mixed) {
   if (!mixed) return 29.0 + 2.0 * M;
   return M <= kMaxA ? 13.0 + 2.0 * (M > 1 ? M : 1) : 17.0 + 2.0 * M;
 }
+// The lighter mixed forms: the a-form without the rounding correction (two
+// fused multiply-adds fewer) and the folded form (a: 5, product, exponential,
+// fused multiply-add into the partial sum: 9).
+inline double plain_flops(int M) { return series_flops(M, true) - 4.0; }
+constexpr double kFoldFlops = 9.0;
 
 // A grow-only device buffer.
 struct DevBuf {

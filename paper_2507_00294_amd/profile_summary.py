@@ -34,7 +34,8 @@ import sys
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip", "dd_queries.cpp")
+DEVICE_SOURCES = ("dd_device.h", "dd_internal.h", "dd_items.h", "dd_kernels.hip", "dd_queries.cpp",
+                  "dd_host.cpp")
 FAR32 = "k_arrival_far32<4, 0>"
 FAR64 = "k_arrival_far64<2, 0>"
 COPY_BYTES = 1 << 30

@@ -138,6 +138,23 @@ def test_large_random_mixed_vs_fp64(dd, wl):
     assert err.max() <= TOL["mixed"], float(err.max())
 
 
+# The far rows of long lags take the lighter mixed forms: without the
+# exponent's rounding correction where every pair has x1 log2(e) <= 8, and
+# the folded single exponential where it is <= 4 and dx <= 2e-4.  128x128
+# random scans: at D = 1e-13 no row qualifies (the full form alone), at
+# 1e-12 and 1e-11 the rows from about lag 3000 resp. 300 on do.
+@pytest.mark.parametrize("D", [1e-13, 1e-12, 1e-11])
+def test_long_lag_forms(dd, ora, wl, D):
+    spec = wl.ScanSpec(128, 128, "random", 1e-9, 0.5e-6, 0.4e-9, D, 1.0, seed=9)
+    scan = dd.Scan(**spec.kwargs())
+    idx = wl.stratified_visits(spec.n_visits, 512, seed=41)
+    ref = oracle_scan(ora, spec, scan).psi_arrival(idx)
+    got = scan.arrival("mixed").cpu().numpy()
+    assert_close(got[idx], ref, spec, "mixed", f"long-lag forms, D {D}")
+    g64 = scan.arrival("fp64").cpu().numpy()
+    assert rel_err(got, g64, spec, "mixed").max() <= TOL["mixed"]
+
+
 def test_bitwise_reproducible(dd, wl):
     spec = wl.large_random(128)
     scan = dd.Scan(**spec.kwargs())
