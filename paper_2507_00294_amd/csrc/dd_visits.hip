@@ -43,11 +43,15 @@ namespace dd {
 
 namespace {
 
-// 1/y for normal y > 0: hardware estimate and two Newton steps.
+// 1/y for normal y > 0: hardware estimate and STEPS Newton steps (each
+// squares the relative error; one suffices for the mixed path's 1e-9 need
+// from an estimate good to at least FP32's 2^-23).
+template <int STEPS = 2>
 __device__ __forceinline__ double rcp64(double y) {
   double r = __builtin_amdgcn_rcp(y);
-  r = fma(r, fma(-y, r, 1.0), r);
-  return fma(r, fma(-y, r, 1.0), r);
+#pragma unroll
+  for (int k = 0; k < STEPS; ++k) r = fma(r, fma(-y, r, 1.0), r);
+  return r;
 }
 
 // e^-w for 0 <= w <= wmax by its Taylor polynomial of degree DEG (DEG = 7
@@ -73,7 +77,7 @@ __device__ __forceinline__ double near_linear(double x1, double dx) {
   for (int k = 0; k < N; ++k) {
     const double w = dx * g.x[k];
     const double e = EDEG > 0 ? exp_neg_small<EDEG>(w) : ::exp(-w);
-    s = fma(g.w[k], e * rcp64(x1 + w), s);
+    s = fma(g.w[k], e * rcp64<>(x1 + w), s);
   }
   return exp2_neg<11>(x1 * kLog2e) * dx * s;
 }
@@ -704,7 +708,7 @@ struct ArrPair {
     const double on = fmin(lg, v.w), off = lg - on;
     b0 = fma(th4, off, 2.0);
     db = th4 * on;
-    const double r1 = rcp64(b0 + db);
+    const double r1 = rcp64<MIXED ? 1 : 2>(b0 + db);
     const double ex = px - v.x, ey = py - v.y;
     x1 = fma(ex, ex, ey * ey) * (is2 * r1);
     u = db * r1;
@@ -713,9 +717,10 @@ struct ArrPair {
     bulk = MIXED ? ((float)u <= kBulkU32 && (float)w <= kBulkV32)
                  : (u <= kBulkU64 && w <= kBulkV64);
   }
+  // Lanes outside the domain (idle, culled) may compute a non-finite value;
+  // the select drops it.
   __device__ __forceinline__ double bulk_value() const {
-    constexpr double cull = MIXED ? kCullX32 : kCullX64;
-    const double t = bulk_term<MIXED>(fmin(x1, cull), u, fmin(w, 1.0));
+    const double t = bulk_term<MIXED>(x1, u, w);
     return act ? t : 0.0;
   }
 };
