@@ -207,6 +207,59 @@ def cpu_baseline(spec, result, floor, seconds, wl):
     return cpu, float(err.max())
 
 
+def run_oracle_full(j0, j1):
+    """The benchmark scan's arrival on the GPU (both precisions) against the
+    oracle at every visit j0 <= j < j1 (its own visit list, every host CPU),
+    in batches of about 5e8 pairs with a progress line each; one JSON line
+    with the largest relative errors.  Two ranges cover the whole scan."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2507_00294_amd as dd
+    from paper_2507_00294_amd import workloads as wl
+
+    oracle.build()
+    torch.cuda.set_device(0)
+    dd.load_library()
+    spec = wl.large_random()
+    scan = dd.Scan(**spec.kwargs())
+    got = {p: scan.arrival(p).cpu().numpy() for p in ("mixed", "fp64")}
+    ids = oracle.visits(oracle.RANDOM, spec.nx, spec.ny, seed=spec.seed)
+    assert np.array_equal(ids, scan.visits()), "visit lists differ"
+    ora = oracle.Scan(spec.nx, spec.ny, ids, spec.pitch_m, spec.tau_v, spec.sigma_m, spec.D_m2s,
+                      spec.Q0_us)
+    V = ids.size
+    j0, j1 = max(0, j0), min(V, j1)
+    _, usable, model = host_cpu()
+    pref = spec.Q0_us / (4 * np.pi * spec.D_m2s)
+    floors = {"mixed": 1e-30 * pref, "fp64": 1e-250 * pref}
+    worst = {p: (0.0, -1) for p in got}
+    t_all, j, pairs = 0.0, j0, 0.0
+    while j < j1:
+        # visits j .. e-1 hold about 5e8 pairs (visit k has k of them)
+        e = int(min(j1, max(j + 64, np.sqrt(float(j) * j + 1e9))))
+        idx = np.arange(j, e, dtype=np.int64)
+        t0 = time.perf_counter()
+        ref = ora.psi_arrival(idx, nthreads=usable)
+        t_all += time.perf_counter() - t0
+        pairs += float(idx.sum())
+        for p, g in got.items():
+            err = np.abs(g[idx] - ref) / np.maximum(np.abs(ref), floors[p])
+            k = int(err.argmax())
+            if err[k] > worst[p][0]:
+                worst[p] = (float(err[k]), int(idx[k]))
+        log(f"[oracle-full] visits {j}..{e - 1} done, {t_all:.0f} s; max rel err mixed "
+            f"{worst['mixed'][0]:.3e}, fp64 {worst['fp64'][0]:.3e}")
+        j = e
+    print(json.dumps({"workload": "arrival query, 512x512 random-order scan (seed 3), every visit "
+                                  "in the range against the oracle",
+                      "visits": [j0, j1], "pairs": pairs, "oracle_s": t_all, "threads": usable,
+                      "cpu_model": model,
+                      "max_rel_err": {p: w[0] for p, w in worst.items()},
+                      "at_visit": {p: w[1] for p, w in worst.items()}}), flush=True)
+
+
 def _gpu_time(fn, torch, reps=10):
     import numpy as np
 
@@ -363,7 +416,13 @@ def main():
     ap.add_argument("--configs", action="store_true",
                     help="only measure the small, medium and batched configurations against "
                          "the oracle (GPU time, error, oracle time) and print one JSON line")
+    ap.add_argument("--oracle-full", type=int, nargs=2, metavar=("J0", "J1"),
+                    help="only compare the benchmark scan's arrival (both precisions) with the "
+                         "oracle at every visit J0 <= j < J1 and print one JSON line")
     args = ap.parse_args()
+    if args.oracle_full:
+        run_oracle_full(*args.oracle_full)
+        return
     if args.configs:
         run_configs()
         return
