@@ -544,9 +544,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Wave w of block b takes items 4 b + w, 4 b + w + 4 gridDim.x, ...  The
 // item's visits go 64 at a time: lane j builds visit j's row in the wave's
 // LDS block; then the stage's lean rows are taken by one loop at their
-// highest degree and its careful rows by another.
+// highest degree and its careful rows by another.  Mixed: held to 168 VGPRs
+// (3 waves per SIMD instead of 2; the few spilled values are outside the
+// lean loop).
 template <bool MIXED>
-__global__ __launch_bounds__(64 * kMapWaves) void k_visit_map(
+__global__ __launch_bounds__(64 * kMapWaves)
+__attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 1, 8))) void k_visit_map(
     const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
     const VisItem* __restrict__ items, int64_t n_items, double* __restrict__ partial) {
   __shared__ MapRow<MIXED> s_rows[kMapWaves][64];
