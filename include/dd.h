@@ -228,8 +228,8 @@ dd_status dd_tune_load(const char *cache_path);
  * FLOP counters count them (FMA 2; add, multiply, exp 1; per pair of a
  * series of degree M: 13 + 2 max(M, 1) for M <= 3 and 17 + 2M above in
  * mixed precision, 4 fewer in the arrival rows of small exponents that skip
- * the exponent's rounding correction and 9 in those that fold the series'
- * linear term into the exponent; 29 + 2M in FP64).  Kernel names: "arrival_far",
+ * the exponent's rounding correction, 9 in all in those that fold the
+ * series' linear term into the exponent; 29 + 2M in FP64).  Kernel names: "arrival_far",
  * "arrival_near", "map", "batch", "lag_rows", "reduce".                   */
 typedef struct {
   double ms;         /* summed event time of the launches                   */
