@@ -153,6 +153,25 @@ def test_long_lag_forms(dd, ora, wl, D):
     assert_close(got[idx], ref, spec, "mixed", f"long-lag forms, D {D}")
     g64 = scan.arrival("fp64").cpu().numpy()
     assert rel_err(got, g64, spec, "mixed").max() <= TOL["mixed"]
+    # the far launch's algorithmic FLOPs per pair show which forms ran: the
+    # full form takes at least 15 (degree <= 1), the lighter ones 9 + 2M
+    # and 9
+    import torch
+
+    dd.profile_read("arrival_far", reset=True)
+    dd.profiling(True)
+    try:
+        again = scan.arrival("mixed").cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        dd.profiling(False)
+    st = dd.profile_read("arrival_far", reset=True)
+    assert np.array_equal(again, got)
+    fpp = st["flops"] / st["pairs"]
+    if D < 1e-12:
+        assert fpp >= 15.0, fpp
+    else:
+        assert fpp < 14.5, fpp
 
 
 def test_bitwise_reproducible(dd, wl):
