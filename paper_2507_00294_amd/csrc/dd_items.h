@@ -202,8 +202,9 @@ __device__ __forceinline__ void arr_far32(int lo, int hi, const float4* __restri
                                           const float (&ee)[R], const float* __restrict__ rows,
                                           double (&acc)[R]) {
   using Row = typename RowSel<M, F>::type;
-  // Two windows alternate so that sliding by R visits needs no register
-  // moves: A covers the chunk at n0, B the chunk at n0 + R.
+  // Two windows alternate: A covers the chunk at n0, B the chunk at n0 + R.
+  // Each shares R - 1 positions with the other, copied in registers; loading
+  // the whole window per chunk instead costs more than those moves.
   float4 A[2 * R - 1], B[2 * R - 1];
 #pragma unroll
   for (int q = 0; q < 2 * R - 1; ++q) A[q] = ldpos<CAS>(pos + (jl - lo - (R - 1) + q));
