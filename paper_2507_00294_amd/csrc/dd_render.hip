@@ -71,6 +71,7 @@ struct RenderArgs {
   int64_t npix, total;   // pixels per map, all pixels
   int32_t w, h;
   int32_t log_scale, levels;  // levels = 0: no iso-lines
+  int32_t autor;               // k_render_map: automatic range
   ColourTable table;
 };
 
@@ -145,6 +146,79 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs A) {
   }
 }
 
+// Maps of at most kMapPixMax pixels, a multiple of 4, into a 4-byte aligned
+// image: one block per map.  The automatic range (the same reduction as
+// k_render_range), then each pixel's colour bin and level into LDS, so that
+// every pixel takes one logarithm (k_render takes three with iso-lines),
+// then the colours, four pixels (12 bytes) per thread and step as three
+// 4-byte stores.  Per pixel the arithmetic is k_render's, so both give the
+// same image.  The iso-line test reads the neighbours' levels at clamped
+// indices and selects: a short-circuit form of it compiled to code whose
+// vertical comparison did not take effect.
+constexpr int kMapPixMax = 16384;
+
+__global__ void __launch_bounds__(256) k_render_map(RenderArgs A, double fac) {
+  __shared__ uint32_t tab[256];
+  __shared__ double red[256];
+  __shared__ uint8_t s_bin[kMapPixMax], s_lev[kMapPixMax];
+  const int tid = threadIdx.x;
+  const int npix = (int)A.npix, w = A.w, L = A.levels;
+  const int64_t m = blockIdx.x;
+  const double* p = A.psi + m * A.npix;
+  tab[tid] = A.table.rgb[tid];
+  double lo = A.lo, hi = A.hi;
+  if (A.autor) {
+    double mx = 0.0;
+    for (int i = tid; i < npix; i += 256) {
+      const double v = p[i];
+      if (__builtin_isfinite(v) && v > mx) mx = v;
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+      __syncthreads();
+    }
+    hi = red[0];
+    lo = A.log_scale ? fmax(hi * fac, 2.2250738585072014e-308) : 0.0;
+  }
+  const bool blank = !(hi > lo);
+  if (!blank) {
+    for (int i = tid; i < npix; i += 256) {
+      const double t = scale_t(p[i], lo, hi, A.log_scale);
+      s_bin[i] = (uint8_t)min(255, (int)(t * 256.0));
+      if (L > 0) s_lev[i] = (uint8_t)level_of(t, L);
+    }
+  }
+  __syncthreads();
+  uint32_t* out = reinterpret_cast<uint32_t*>(A.rgb + 3 * (m * A.npix));
+  for (int g = tid; 4 * g < npix; g += 256) {
+    uint32_t c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = 4 * g + k;
+      if (blank) {
+        c[k] = tab[0];
+        continue;
+      }
+      c[k] = tab[s_bin[i]];
+      if (L > 0) {
+        // neighbours read at clamped (in-range) indices, then selected
+        const int y = i / w, x = i - y * w;
+        const int lv = s_lev[i];
+        const int lr = s_lev[min(i + 1, npix - 1)], ld = s_lev[min(i + w, npix - 1)];
+        const int er = (x + 1 < w) ? (lr ^ lv) : 0;
+        const int ed = (y + 1 < A.h) ? (ld ^ lv) : 0;
+        c[k] = (er | ed) ? 0xFFFFFFu : c[k];
+      }
+    }
+    // bytes r0 g0 b0 r1 | g1 b1 r2 g2 | b2 r3 g3 b3 (little endian)
+    out[3 * g + 0] = (c[0] & 0xFFFFFFu) | (c[1] << 24);
+    out[3 * g + 1] = ((c[1] >> 8) & 0xFFFFu) | ((c[2] & 0xFFFFu) << 16);
+    out[3 * g + 2] = ((c[2] >> 16) & 0xFFu) | ((c[3] & 0xFFFFFFu) << 8);
+  }
+}
+
 // Per-thread device buffer of the automatic ranges.
 thread_local DevBuf g_range_buf;
 
@@ -188,6 +262,15 @@ dd_status dd_render_maps(const double* psi, int64_t n, int32_t w, int32_t h,
   A.log_scale = opt->log_scale;
   A.levels = opt->levels;
   A.table = kTable;
+  if (npix <= kMapPixMax && npix % 4 == 0 && n <= 0x7fffffff &&
+      reinterpret_cast<uintptr_t>(rgb) % 4 == 0) {
+    A.autor = autor ? 1 : 0;
+    const double fac = autor ? std::pow(10.0, -opt->decades) : 0.0;
+    hipLaunchKernelGGL(k_render_map, dim3((unsigned)n), dim3(256), 0, st, A, fac);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "render kernel launch");
+    return DD_OK;
+  }
   if (autor) {
     hipError_t e = g_range_buf.ensure(sizeof(double2) * (size_t)n);
     if (e != hipSuccess) return hip_fail(e, "device allocation");

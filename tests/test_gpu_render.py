@@ -75,6 +75,30 @@ def test_render_same_values_exact(dd):
             _compare(got, ref, margin, 1e-12)
 
 
+def test_render_block_per_map_equals_general_kernel(dd):
+    """Maps of at most 16384 pixels, a multiple of 4, into an aligned image go
+    to the one-block-per-map kernel; an output one byte off alignment takes
+    the general kernel.  Both must give the same image bit for bit."""
+    import torch
+
+    rng = np.random.default_rng(11)
+    for (n, h, w) in ((3, 128, 128), (8, 64, 64), (2, 60, 20), (5, 1, 4)):
+        v = 10.0 ** rng.uniform(-4, 8, size=(n, h, w))
+        v[rng.random((n, h, w)) < 0.03] = 0.0
+        v[0, 0, :1] = np.nan
+        v[-1] = -1.0  # a map with no positive value
+        psi = torch.tensor(v, device="cuda")
+        size = n * h * w * 3
+        for opts in (dict(), dict(levels=7), dict(decades=2.0, levels=3), dict(lo=1e-2, hi=1e6),
+                     dict(lo=1e-2, hi=1e6, levels=5), dict(log_scale=False, levels=4),
+                     dict(log_scale=False, lo=-1e7, hi=5e7)):
+            fast = dd.render_maps(psi, **opts)
+            buf = torch.empty(size + 1, dtype=torch.uint8, device="cuda")
+            slow = dd.render_maps(psi, out=buf[1:].view(n, h, w, 3), **opts)
+            assert slow.data_ptr() % 4 == 1
+            assert torch.equal(fast, slow), (n, h, w, opts)
+
+
 def test_render_special_values(dd):
     import torch
 
