@@ -10,6 +10,8 @@
 //   t = 1                         if v >= hi_m
 //   t = ln(v / lo_m) / ln(hi_m / lo_m)      (log scale)
 //   t = (v - lo_m) / (hi_m - lo_m)          (linear scale)
+// (evaluated as (ln v - ln lo_m) * (1 / (ln hi_m - ln lo_m)), resp. with the
+// reciprocal of hi_m - lo_m, ln by ln_pos of dd_log.h)
 //   colour = table[min(255, floor(256 t))]
 // The table interpolates the colour-map anchors of dd.h linearly between
 // anchor bins (FP64, rounded to the nearest integer).  With iso-lines, a
@@ -29,6 +31,7 @@
 #include <mutex>
 
 #include "../../include/dd.h"
+#include "dd_log.h"
 #include "dd_runtime.h"
 
 namespace dd {
@@ -101,13 +104,26 @@ __global__ void __launch_bounds__(256) k_render_range(const double* __restrict__
   }
 }
 
-__device__ __forceinline__ double scale_t(double v, double lo, double hi, int log_scale) {
-  if (!(v > lo)) return 0.0;
-  if (v >= hi) return 1.0;
-  const double t = log_scale ? ::log(v / lo) / ::log(hi / lo) : (v - lo) / (hi - lo);
+// The scale of a range [lo, hi]: t = (ln v - ln lo) / (ln hi - ln lo) (log)
+// or (v - lo) / (hi - lo) (linear), the quotient taken as a product with the
+// reciprocal, ln from ln_pos; both kernels use these, so they agree bit for
+// bit.
+struct Scale {
+  double lo, hi, base, inv;
+  int log_scale;
+};
+__device__ __forceinline__ Scale make_scale(double lo, double hi, int log_scale) {
+  Scale s{lo, hi, 0.0, 0.0, log_scale};
+  s.base = log_scale ? ln_pos(lo) : lo;
+  s.inv = 1.0 / ((log_scale ? ln_pos(hi) : hi) - s.base);
+  return s;
+}
+__device__ __forceinline__ double scale_t(double v, const Scale& s) {
+  if (!(v > s.lo)) return 0.0;
+  if (v >= s.hi) return 1.0;
+  const double t = ((s.log_scale ? ln_pos(v) : v) - s.base) * s.inv;
   return fmin(fmax(t, 0.0), 1.0);  // a t that is not a number (overflowed range) is 0
 }
-
 __device__ __forceinline__ int level_of(double t, int L) { return min(L - 1, (int)(t * L)); }
 
 __global__ void __launch_bounds__(256) k_render(RenderArgs A) {
@@ -127,15 +143,16 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs A) {
     if (!(hi > lo)) {  // an automatic range over a map with no positive value
       c = tab[0];
     } else {
-      const double t = scale_t(A.psi[e], lo, hi, A.log_scale);
+      const Scale sc = make_scale(lo, hi, A.log_scale);
+      const double t = scale_t(A.psi[e], sc);
       c = tab[min(255, (int)(t * 256.0))];
       if (A.levels > 0) {
         const int x = (int)(q % A.w), y = (int)(q / A.w);
         const int lv = level_of(t, A.levels);
         bool edge = false;
-        if (x + 1 < A.w) edge |= level_of(scale_t(A.psi[e + 1], lo, hi, A.log_scale), A.levels) != lv;
+        if (x + 1 < A.w) edge |= level_of(scale_t(A.psi[e + 1], sc), A.levels) != lv;
         if (y + 1 < A.h)
-          edge |= level_of(scale_t(A.psi[e + A.w], lo, hi, A.log_scale), A.levels) != lv;
+          edge |= level_of(scale_t(A.psi[e + A.w], sc), A.levels) != lv;
         if (edge) c = 0xFFFFFFu;
       }
     }
@@ -148,19 +165,23 @@ __global__ void __launch_bounds__(256) k_render(RenderArgs A) {
 
 // Maps of at most kMapPixMax pixels, a multiple of 4, into a 4-byte aligned
 // image: one block per map.  The automatic range (the same reduction as
-// k_render_range), then each pixel's colour bin and level into LDS, so that
+// k_render_range), then each pixel's colour bin (kept in registers by the
+// thread that colours it) and level (into LDS, for the neighbours), so that
 // every pixel takes one logarithm (k_render takes three with iso-lines),
 // then the colours, four pixels (12 bytes) per thread and step as three
-// 4-byte stores.  Per pixel the arithmetic is k_render's, so both give the
+// 4-byte stores.  The host sends here only psi arrays that start 16-byte
+// aligned; a map holds a multiple of four values, so four pixels load as two
+// 16-byte vectors.  Per pixel the arithmetic is k_render's, so both give the
 // same image.  The iso-line test reads the neighbours' levels at clamped
 // indices and selects: a short-circuit form of it compiled to code whose
 // vertical comparison did not take effect.
 constexpr int kMapPixMax = 16384;
+constexpr int kMapSteps = kMapPixMax / (4 * 256);  // groups of four pixels per thread
 
 __global__ void __launch_bounds__(256) k_render_map(RenderArgs A, double fac) {
   __shared__ uint32_t tab[256];
   __shared__ double red[256];
-  __shared__ uint8_t s_bin[kMapPixMax], s_lev[kMapPixMax];
+  __shared__ uint8_t s_lev[kMapPixMax];
   const int tid = threadIdx.x;
   const int npix = (int)A.npix, w = A.w, L = A.levels;
   const int64_t m = blockIdx.x;
@@ -183,26 +204,37 @@ __global__ void __launch_bounds__(256) k_render_map(RenderArgs A, double fac) {
     lo = A.log_scale ? fmax(hi * fac, 2.2250738585072014e-308) : 0.0;
   }
   const bool blank = !(hi > lo);
-  if (!blank) {
-    for (int i = tid; i < npix; i += 256) {
-      const double t = scale_t(p[i], lo, hi, A.log_scale);
-      s_bin[i] = (uint8_t)min(255, (int)(t * 256.0));
-      if (L > 0) s_lev[i] = (uint8_t)level_of(t, L);
+  // the thread's pixels 4 g .. 4 g + 3, g = tid + 256 j: colour bins packed
+  // four to a register, levels into LDS for the neighbours' tests
+  uint32_t bins[kMapSteps];
+  const Scale sc = make_scale(lo, hi, A.log_scale);
+#pragma unroll
+  for (int j = 0; j < kMapSteps; ++j) {
+    const int g = tid + 256 * j;
+    bins[j] = 0;
+    if (blank || 4 * g >= npix) continue;
+    const double2 v01 = *reinterpret_cast<const double2*>(p + 4 * g);
+    const double2 v23 = *reinterpret_cast<const double2*>(p + 4 * g + 2);
+    const double v[4] = {v01.x, v01.y, v23.x, v23.y};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double t = scale_t(v[k], sc);
+      bins[j] |= (uint32_t)min(255, (int)(t * 256.0)) << (8 * k);
+      if (L > 0) s_lev[4 * g + k] = (uint8_t)level_of(t, L);
     }
   }
   __syncthreads();
   uint32_t* out = reinterpret_cast<uint32_t*>(A.rgb + 3 * (m * A.npix));
-  for (int g = tid; 4 * g < npix; g += 256) {
+#pragma unroll
+  for (int j = 0; j < kMapSteps; ++j) {
+    const int g = tid + 256 * j;
+    if (4 * g >= npix) continue;
     uint32_t c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int i = 4 * g + k;
-      if (blank) {
-        c[k] = tab[0];
-        continue;
-      }
-      c[k] = tab[s_bin[i]];
-      if (L > 0) {
+      c[k] = tab[blank ? 0 : (bins[j] >> (8 * k)) & 0xFFu];
+      if (!blank && L > 0) {
         // neighbours read at clamped (in-range) indices, then selected
         const int y = i / w, x = i - y * w;
         const int lv = s_lev[i];
@@ -263,7 +295,7 @@ dd_status dd_render_maps(const double* psi, int64_t n, int32_t w, int32_t h,
   A.levels = opt->levels;
   A.table = kTable;
   if (npix <= kMapPixMax && npix % 4 == 0 && n <= 0x7fffffff &&
-      reinterpret_cast<uintptr_t>(rgb) % 4 == 0) {
+      reinterpret_cast<uintptr_t>(rgb) % 4 == 0 && reinterpret_cast<uintptr_t>(psi) % 16 == 0) {
     A.autor = autor ? 1 : 0;
     const double fac = autor ? std::pow(10.0, -opt->decades) : 0.0;
     hipLaunchKernelGGL(k_render_map, dim3((unsigned)n), dim3(256), 0, st, A, fac);

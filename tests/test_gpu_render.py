@@ -97,6 +97,12 @@ def test_render_block_per_map_equals_general_kernel(dd):
             slow = dd.render_maps(psi, out=buf[1:].view(n, h, w, 3), **opts)
             assert slow.data_ptr() % 4 == 1
             assert torch.equal(fast, slow), (n, h, w, opts)
+            # psi 8 bytes off 16-byte alignment also takes the general kernel
+            pbuf = torch.empty(psi.numel() + 1, dtype=torch.float64, device="cuda")
+            psi8 = pbuf[1:].view(n, h, w)
+            psi8.copy_(psi)
+            assert psi8.data_ptr() % 16 == 8
+            assert torch.equal(dd.render_maps(psi8, **opts), fast), (n, h, w, opts)
 
 
 def test_render_special_values(dd):
