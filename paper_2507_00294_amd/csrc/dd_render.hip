@@ -230,18 +230,23 @@ __global__ void __launch_bounds__(256) k_render_map(RenderArgs A, double fac) {
     const int g = tid + 256 * j;
     if (4 * g >= npix) continue;
     uint32_t c[4];
+    // coordinates of the group's first pixel, then stepped pixel by pixel
+    int y = (4 * g) / w, x = 4 * g - y * w;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int i = 4 * g + k;
       c[k] = tab[blank ? 0 : (bins[j] >> (8 * k)) & 0xFFu];
       if (!blank && L > 0) {
         // neighbours read at clamped (in-range) indices, then selected
-        const int y = i / w, x = i - y * w;
         const int lv = s_lev[i];
         const int lr = s_lev[min(i + 1, npix - 1)], ld = s_lev[min(i + w, npix - 1)];
         const int er = (x + 1 < w) ? (lr ^ lv) : 0;
         const int ed = (y + 1 < A.h) ? (ld ^ lv) : 0;
         c[k] = (er | ed) ? 0xFFFFFFu : c[k];
+      }
+      if (++x == w) {
+        x = 0;
+        ++y;
       }
     }
     // bytes r0 g0 b0 r1 | g1 b1 r2 g2 | b2 r3 g3 b3 (little endian)

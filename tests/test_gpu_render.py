@@ -76,13 +76,15 @@ def test_render_same_values_exact(dd):
 
 
 def test_render_block_per_map_equals_general_kernel(dd):
-    """Maps of at most 16384 pixels, a multiple of 4, into an aligned image go
+    """Maps of at most 16384 pixels, a multiple of 4 (any width, 1 and 2
+    included), into an aligned image go
     to the one-block-per-map kernel; an output one byte off alignment takes
     the general kernel.  Both must give the same image bit for bit."""
     import torch
 
     rng = np.random.default_rng(11)
-    for (n, h, w) in ((3, 128, 128), (8, 64, 64), (2, 60, 20), (5, 1, 4)):
+    for (n, h, w) in ((3, 128, 128), (8, 64, 64), (2, 60, 20), (5, 1, 4), (3, 8, 2), (2, 12, 1),
+                      (4, 3, 12)):
         v = 10.0 ** rng.uniform(-4, 8, size=(n, h, w))
         v[rng.random((n, h, w)) < 0.03] = 0.0
         v[0, 0, :1] = np.nan
