@@ -678,6 +678,38 @@ __device__ __forceinline__ T bulk_f(T u, T v) {
   return acc;
 }
 
+// The FP64 bulk's 43 constants (F's coefficients, rows of kBulkStride, and
+// the degree-9 exp2 interpolant) do not fit the scalar registers beside the
+// kernel's own; the arrival kernel keeps them in LDS (kBulkLds doubles) and
+// reads them as wave-uniform loads.  Same values, same operations.
+constexpr int kBulkStride = 6, kBulkE = 7 * kBulkStride, kBulkLds = kBulkE + 10;
+__device__ __forceinline__ double bulk_const64(int k) {
+  constexpr BulkCoef C{};
+  constexpr Exp2Cheb<9> E{};
+  if (k >= kBulkE) return E.c[k - kBulkE];
+  return C.c[k / kBulkStride][k % kBulkStride];
+}
+__device__ __forceinline__ double bulk_term64_lds(double x1, double u, double v,
+                                                  const double* __restrict__ bc) {
+  constexpr int deg[7] = {5, 5, 5, 4, 3, 2, 1};
+  double g = 0;
+#pragma unroll
+  for (int m = 6; m >= 0; --m) {
+    double cm = bc[m * kBulkStride + deg[m]];
+#pragma unroll
+    for (int n = deg[m] - 1; n >= 0; --n) cm = cm * u + bc[m * kBulkStride + n];
+    g = (m == 6) ? cm : g * v + cm;
+  }
+  // exp2_lean with the interpolant's coefficients from bc
+  const double y = x1 * kLog2e;
+  const double mm = __builtin_rint(-y);
+  const double h = -y - mm;
+  double p = bc[kBulkE + 9];
+#pragma unroll
+  for (int k = 8; k >= 0; --k) p = fma(p, h, bc[kBulkE + k]);
+  return __builtin_ldexp(p, (int)mm) * (u * g);
+}
+
 // The bulk term e^{-x1} u F(u, v) (x1 <= cull).
 template <bool MIXED>
 __device__ __forceinline__ double bulk_term(double x1, double u, double v) {
@@ -722,8 +754,12 @@ struct ArrPair {
   }
   // Lanes outside the domain (idle, culled) may compute a non-finite value;
   // the select drops it.
-  __device__ __forceinline__ double bulk_value() const {
-    const double t = bulk_term<MIXED>(x1, u, w);
+  __device__ __forceinline__ double bulk_value(const double* __restrict__ bc) const {
+    double t;
+    if constexpr (MIXED)
+      t = bulk_term<MIXED>(x1, u, w);
+    else
+      t = bulk_term64_lds(x1, u, w, bc);
     return act ? t : 0.0;
   }
 };
@@ -732,10 +768,11 @@ struct ArrPair {
 // this visit are all in its domain, else the general form.
 template <bool MIXED>
 __device__ __forceinline__ double arr_pair_term(const double4 v, double px, double py, double pt,
-                                                bool live, double is2, double th4) {
+                                                bool live, double is2, double th4,
+                                                const double* __restrict__ bc) {
   ArrPair<MIXED> pr;
   pr.setup(v, px, py, pt, live, is2, th4);
-  if (!__ballot(pr.act && !pr.bulk)) return pr.bulk_value();
+  if (!__ballot(pr.act && !pr.bulk)) return pr.bulk_value(bc);
   const double q = pr.db / pr.b0;
   return pair_term<MIXED>(pr.act, pr.x1, pr.x1 * q, q);
 }
@@ -744,13 +781,18 @@ __device__ __forceinline__ double arr_pair_term(const double4 v, double px, doub
 // staged 256 at a time in LDS.  Visits are in start order, so the first one
 // that starts at or after the tile's latest time ends the item for the
 // whole block.
+// FP64: held to 168 VGPRs (3 waves per SIMD; the constants in LDS took it to
+// 182 and 2 waves unhinted).
 template <bool MIXED>
-__global__ __launch_bounds__(kVisTile) void k_visit_arrival(
+__global__ __launch_bounds__(kVisTile)
+__attribute__((amdgpu_waves_per_eu(MIXED ? 1 : 3, 8))) void k_visit_arrival(
     const VisList* __restrict__ lists, const VisTile* __restrict__ tiles,
     const VisItem* __restrict__ items, int64_t n_items, double* __restrict__ partial) {
   constexpr double cull = MIXED ? kCullX32 : kCullX64;
   __shared__ double4 s_v[kVisStage];
+  __shared__ double s_bc[MIXED ? 1 : kBulkLds];
   const int lane = threadIdx.x;
+  if (!MIXED && lane < kBulkLds) s_bc[lane] = bulk_const64(lane);  // read after the stage barrier
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const VisItem item = items[it];
     const VisTile tile = tiles[item.tile];
@@ -787,10 +829,11 @@ __global__ __launch_bounds__(kVisTile) void k_visit_arrival(
         }
         if (!__ballot(out)) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) sum += pr[i].bulk_value();
+          for (int i = 0; i < 4; ++i) sum += pr[i].bulk_value(s_bc);
         } else {
 #pragma unroll 1
-          for (int i = 0; i < 4; ++i) sum += arr_pair_term<MIXED>(s_v[j + i], px, py, pt, live, is2, th4);
+          for (int i = 0; i < 4; ++i)
+            sum += arr_pair_term<MIXED>(s_v[j + i], px, py, pt, live, is2, th4, s_bc);
         }
       }
       for (; j < nk; ++j) {
@@ -799,7 +842,7 @@ __global__ __launch_bounds__(kVisTile) void k_visit_arrival(
           done = true;  // uniform: no later visit starts before any point
           break;
         }
-        sum += arr_pair_term<MIXED>(v, px, py, pt, live, is2, th4);
+        sum += arr_pair_term<MIXED>(v, px, py, pt, live, is2, th4, s_bc);
       }
     }
     if (live) partial[tile.pbase + (int64_t)item.slot * kVisTile + lane] = sum;
